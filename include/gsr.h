@@ -1,0 +1,210 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) differentiable Gaussian-splatting rasterizer that
+ * drives the global Gaussian-map optimisation of RMGS-SLAM (arXiv 2604.12942, Sec. III-C
+ * "Optimization").  The paper renders colour by standard differentiable splatting with
+ * front-to-back alpha compositing, renders depth with the same compositing weights
+ * (Eq. 8), supervises with masked L1 colour / depth terms (Eq. 9, 10, 12) and refines the
+ * visible, unfrozen Gaussians with a sparse gradient optimiser.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller.  The library never
+ *    allocates, frees or synchronises; all work is enqueued on the caller's stream.  Struct
+ *    arguments passed by pointer (gsr_gaussians, gsr_raster, ...) are HOST structs that hold
+ *    device pointers; they are read before the call returns.
+ *  - Gaussian parameters are structure-of-arrays, component-major [c][n] float32:
+ *      means [3][n], log_scales [3][n], quats [4][n] as raw (w, x, y, z), opacity_logits [n],
+ *      sh [3K][n] with row k*3+ch (K = (sh_degree+1)^2, real SH without Condon-Shortley
+ *      phase, ordered (l, m = -l..l), colour = max(0, sum_k Y_k(d) sh_k + 1/2)).
+ *  - Cameras: a device array of gsr_camera, world->camera p = R mu + t, camera looking along
+ *    +z, image x right and y down; every view of a call shares gsr_raster's width / height.
+ *    Pixel (i, j) is sampled at its centre (i + 1/2, j + 1/2).
+ *  - "Projected splat" records are 48-byte gsr_splat structs, one per (view, Gaussian), at
+ *    index v*n + i.
+ *  - Errors: invalid arguments return GSR_E_INVALID before any launch; a failed launch returns
+ *    GSR_E_HIP.  No C++ exception crosses this interface.  Capacity overflow of the instance
+ *    buffer is detected on the device (see gsr_bin_sort).
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_ABI_VERSION 1
+#define GSR_API __attribute__((visibility("default")))
+
+typedef enum {
+    GSR_OK = 0,
+    GSR_E_INVALID = 1,     /* bad argument, nothing launched */
+    GSR_E_CAPACITY = 2,    /* a caller-provided workspace is too small */
+    GSR_E_HIP = 3,         /* a HIP launch or runtime call failed */
+    GSR_E_UNSUPPORTED = 4  /* configuration this build does not handle */
+} gsr_status;
+
+typedef void *gsr_stream; /* a hipStream_t (NULL = the null stream) */
+
+/* One camera, 96 bytes.  R row-major world->camera rotation, t translation, pinhole
+   intrinsics, near plane (Gaussians with camera z <= z_near are culled) and background. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float z_near;
+    float bg[3];
+    int32_t width, height; /* must equal the gsr_raster of the call */
+    int32_t _pad[2];
+} gsr_camera;
+
+typedef struct {
+    const float *means, *log_scales, *quats, *opacity_logits, *sh;
+    int64_t n;
+    int32_t sh_degree; /* 0..3 */
+    int32_t _pad;
+} gsr_gaussians;
+
+typedef struct {
+    float *means, *log_scales, *quats, *opacity_logits, *sh;
+} gsr_param_grads; /* same layouts as gsr_gaussians; ACCUMULATED into */
+
+/* Image size shared by the views of a call and the screen tile shape.  Supported tile
+   shapes (tile_w x tile_h): 16x16, 8x32, 32x8.  Images are identical for every shape. */
+typedef struct {
+    int32_t width, height;
+    int32_t tile_w, tile_h;
+} gsr_raster;
+
+/* Projected splat of one (view, Gaussian): 48 bytes.
+     u, v      pixel-space mean (double so a tile can re-centre it without rounding loss)
+     l11,l21,l22  lower Cholesky factor L of (log2(e)/2) * Q, Q = inverse screen covariance:
+               the blend weight exponent at offset D is |L^T D|^2, alpha = o * 2^-(|L^T D|^2)
+     opacity   o = sigmoid(logit)
+     depth     camera-frame z (ordering key and Eq. 8 depth)
+     r, g, b   view-dependent colour after the clamp at 0                                  */
+typedef struct {
+    double u, v;
+    float l11, l21, l22;
+    float opacity;
+    float depth;
+    float r, g, b;
+} gsr_splat;
+
+/* Screen-space gradient of one (view, Gaussian), 10 floats in this order:
+   dL/du, dL/dv, dL/dQa, dL/dQb, dL/dQc (Q = [[Qa, Qb], [Qb, Qc]], Qb counted once),
+   dL/do, dL/dr, dL/dg, dL/db, dL/dz. */
+#define GSR_SPLAT_GRAD_FLOATS 10
+
+GSR_API int gsr_abi_version(void);
+GSR_API const char *gsr_status_str(int status);
+
+/* Number of screen tiles per view for a raster. */
+GSR_API int64_t gsr_tiles_per_view(const gsr_raster *r);
+
+/* ---- project ---------------------------------------------------------------------------------
+ * EWA projection of every Gaussian into every view (Sec. III-C: standard splatting; Eq. 8's
+ * camera-frame depth).  Per (view v, Gaussian i): p = R mu + t; culled if z <= z_near;
+ * Sigma = Rq S S^T Rq^T, Sigma' = J R Sigma R^T J^T + 0.3 I with the perspective Jacobian J
+ * (x/z, y/z clamped to 1.3x the half field of view), Q = Sigma'^-1, opacity sigmoid, SH colour
+ * in the viewing direction from the camera centre -R^T t.  A pair contributes to a pixel iff
+ * o exp(-D^T Q D / 2) >= 1/255, so the footprint is the ellipse D^T Q D <= 2 ln(255 o).
+ * Outputs:  splats [V*n] gsr_splat;  tile_info uint32 [4][V*n] (component-major):
+ *   row 0  n_tiles: number of tiles the pair is emitted to (0 = not visible in that view)
+ *   row 1  depth key: the float32 bit pattern of the camera-frame depth (monotone for z > 0)
+ *   row 2  tx0 | ty0 << 16, row 3  tx1 | ty1 << 16: inclusive tile rectangle that
+ *          conservatively covers every pixel centre of the footprint.
+ * cams: device [n_views].  Errors: GSR_E_INVALID for NULL pointers, n < 0, sh_degree outside
+ * 0..3, n_views < 1, width/height <= 0, an unsupported tile shape, or V*n >= 2^32. */
+GSR_API gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
+                       gsr_splat *splats, uint32_t *tile_info, gsr_stream stream);
+
+/* ---- bin / sort ------------------------------------------------------------------------------
+ * Tile binning with a radix sort on (tile, depth) keys.  Emits one instance per (view, tile,
+ * Gaussian) that project's rectangle covers and orders them lexicographically by
+ * (view, tile index ty*ntx+tx, float32 depth bits, Gaussian index): visible pairs are first
+ * radix-sorted stably by depth bits (index order breaks ties), then instances are emitted in
+ * that order and radix-sorted stably by (view, tile).  Outputs inst_gid [capacity] (v*n + i of
+ * each instance, in that order), tile_ranges [V*T][2] ([start, end) per view-tile) and
+ * *n_instances (device uint32: the REQUIRED instance count M).  If M > capacity nothing
+ * beyond capacity is written and the results are incomplete: the caller compares
+ * *n_instances with capacity after synchronising and re-runs with more room.
+ * ws: device workspace of at least gsr_bin_sort_workspace(n, n_views, capacity, r) bytes,
+ * 256-byte aligned.  Errors: GSR_E_INVALID (bad pointers or sizes, capacity >= 2^32),
+ * GSR_E_CAPACITY (ws_bytes too small). */
+GSR_API size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t capacity, const gsr_raster *r);
+GSR_API gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
+                        uint32_t *inst_gid, int64_t capacity, uint32_t *tile_ranges, uint32_t *n_instances,
+                        void *ws, size_t ws_bytes, gsr_stream stream);
+
+/* ---- render forward --------------------------------------------------------------------------
+ * Front-to-back alpha compositing per pixel (Sec. III-C; Eq. 8).  For each view-tile's
+ * instances in order: a = min(0.99, alpha), skipped if alpha < 1/255; T' = T (1 - a); the
+ * pixel stops when T' < 1e-4 (that Gaussian is not composited); C += a T rgb, D += a T z.
+ * Outputs (images [V][...][H][W]): rgb [V][3][H][W] = C + T bg, depth [V][H][W] = D (no
+ * background term), T_final [V][H][W], last [V][H][W] = number of the tile's instances up to
+ * and including the pixel's last composited one (the backward re-walks exactly these). */
+GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
+                          const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb, float *depth,
+                          float *T_final, uint32_t *last, gsr_stream stream);
+
+/* ---- render backward -------------------------------------------------------------------------
+ * Exact gradient of the forward's outputs (every discrete decision held) given dL/drgb
+ * [V][3][H][W] and dL/ddepth [V][H][W] (may be NULL).  Walks each pixel's instances back to
+ * front, recovering transmittance by division, and ACCUMULATES the screen-space gradient of
+ * every (view, Gaussian) into dsplat [V*n][10] (layout GSR_SPLAT_GRAD_FLOATS; the caller
+ * zeroes it).  Float atomics make the summation order, not the result, run-dependent. */
+GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
+                          const gsr_camera *cams, int32_t n_views, const gsr_raster *r, const float *T_final,
+                          const uint32_t *last, const float *dL_drgb, const float *dL_ddepth, float *dsplat,
+                          gsr_stream stream);
+
+/* ---- project backward ------------------------------------------------------------------------
+ * Chain rule from the screen-space gradients to every parameter, summed over views, plus the
+ * per-view camera-pose gradient for a left perturbation T <- Exp(xi) T, xi = (rho, phi)
+ * (translation first): p -> p + rho + phi x p.  Gradients are ACCUMULATED into out;
+ * dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  ws: gsr_project_bwd_workspace bytes. */
+GSR_API size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views);
+GSR_API gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
+                           const float *dsplat, const gsr_param_grads *out, double *dpose, void *ws,
+                           size_t ws_bytes, gsr_stream stream);
+
+/* ---- sparse Adam -----------------------------------------------------------------------------
+ * Sparse gradient optimiser of Sec. III-C (visible and unfrozen Gaussians only).  Up to 8
+ * parameter groups, each a [cols][rows] component-major float32 tensor sharing the row count
+ * `rows` (one row per Gaussian).  For rows with row_mask != 0 (row_mask NULL = every row):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step))
+ * + eps).  Masked-out rows keep p, m, v.  Every gradient element is zeroed.  step >= 1. */
+#define GSR_MAX_GROUPS 8
+typedef struct {
+    float *param[GSR_MAX_GROUPS];
+    float *grad[GSR_MAX_GROUPS];
+    float *m[GSR_MAX_GROUPS];
+    float *v[GSR_MAX_GROUPS];
+    int32_t cols[GSR_MAX_GROUPS];
+    float lr[GSR_MAX_GROUPS];
+    int32_t n_groups;
+    int32_t _pad;
+} gsr_adam_groups;
+GSR_API gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, const uint8_t *row_mask, float beta1,
+                         float beta2, float eps, int32_t step, gsr_stream stream);
+
+/* ---- L1 loss ---------------------------------------------------------------------------------
+ * Eq. 9, 10, 12 with lambda_rgb = 1, lambda_ssim = 0 and the all-ones mask, per view v:
+ * L_v = (1/P) sum_x sum_ch |C - C~| + lambda_depth (1/P) sum_x |D - D~|, P = W H; the loss is
+ * summed over views into *loss (device float64, ACCUMULATED).  Writes dL_drgb [V][3][H][W] and,
+ * if dL_ddepth is not NULL, dL_ddepth [V][H][W] (sign(0) = 0).  target_depth may be NULL
+ * (then lambda_depth is ignored and dL_ddepth, if given, is zeroed). */
+GSR_API gsr_status gsr_loss_l1(const float *rgb, const float *depth, const float *target_rgb, const float *target_depth,
+                       int32_t n_views, const gsr_raster *r, float lambda_depth, double *loss, float *dL_drgb,
+                       float *dL_ddepth, gsr_stream stream);
+
+/* Fill n 32-bit words with a value (graph-capture safe replacement for memset). */
+GSR_API gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

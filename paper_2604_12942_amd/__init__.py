@@ -1,0 +1,258 @@
+"""MI355X-native differentiable Gaussian-splatting rasterizer (binding over libgsr.so).
+
+Every step of the path -- projection, binning and radix sort, compositing, the backward, the
+pose gradient, the L1 loss and sparse Adam -- runs in the HIP kernels of ``csrc/`` behind the C
+ABI of ``include/gsr.h``.  This module only allocates device memory through torch, marshals
+pointers and sizes, and enqueues on torch's current stream.  There is no CPU fallback: if
+``libgsr.so`` is missing every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import GsrError, check
+
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def lib():
+    return _abi.load()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Raster:
+    """Image size shared by the views of a call plus the screen tile shape (16x16, 8x32, 32x8)."""
+
+    def __init__(self, width, height, tile_w=16, tile_h=16):
+        self.width, self.height, self.tile_w, self.tile_h = int(width), int(height), int(tile_w), int(tile_h)
+        self.c = _abi.Raster(self.width, self.height, self.tile_w, self.tile_h)
+        self.ntx = -(-self.width // self.tile_w)
+        self.nty = -(-self.height // self.tile_h)
+        self.tiles = self.ntx * self.nty
+
+    def with_tile(self, tw, th):
+        return Raster(self.width, self.height, tw, th)
+
+
+def camera_tensor(cams, device="cuda"):
+    """Pack camera dicts (R, t, fx, fy, cx, cy, width, height, z_near, bg) into a device array of
+    gsr_camera records (96 bytes each)."""
+    arr = (_abi.Camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k].R[:] = [float(v) for v in np.asarray(c["R"], np.float32).ravel()]
+        arr[k].t[:] = [float(v) for v in np.asarray(c["t"], np.float32).ravel()]
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = c["fx"], c["fy"], c["cx"], c["cy"]
+        arr[k].z_near = c.get("z_near", 0.2)
+        arr[k].bg[:] = [float(v) for v in np.asarray(c.get("bg", (0, 0, 0)), np.float32).ravel()]
+        arr[k].width, arr[k].height = int(c["width"]), int(c["height"])
+    raw = np.frombuffer(bytes(arr), np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+def gaussians_to_device(g, device="cuda"):
+    out = {k: torch.as_tensor(np.ascontiguousarray(g[k], np.float32)).to(device) for k in PARAM_NAMES}
+    out["sh_degree"] = int(g["sh_degree"])
+    return out
+
+
+_ROWS = dict(means=3, log_scales=3, quats=4, opacity_logits=1)
+
+
+def _gauss_struct(P, sh_degree):
+    n = P["means"].shape[-1]
+    if not 0 <= int(sh_degree) <= 3:
+        raise GsrError("sh_degree must be 0..3")
+    rows = dict(_ROWS, sh=3 * (int(sh_degree) + 1) ** 2)
+    for k in PARAM_NAMES:
+        t = P[k]
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise GsrError("parameter %s must be a contiguous float32 device tensor" % k)
+        if t.numel() != rows[k] * n:
+            raise GsrError("parameter %s must hold %d x n values" % (k, rows[k]))
+    return _abi.Gaussians(*[P[k].data_ptr() for k in PARAM_NAMES], n, int(sh_degree), 0)
+
+
+# ------------------------------------------------------------------------------------------
+# thin wrappers with the C names
+# ------------------------------------------------------------------------------------------
+
+def project(P, sh_degree, cams, n_views, raster, splats=None, tile_info=None):
+    n = P["means"].shape[-1]
+    dev = P["means"].device
+    if splats is None:
+        splats = torch.empty(n_views * n * 12, dtype=torch.float32, device=dev)
+    if tile_info is None:
+        tile_info = torch.empty(4 * n_views * n, dtype=torch.int32, device=dev)
+    g = _gauss_struct(P, sh_degree)
+    check(lib().gsr_project(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(tile_info),
+                            _stream()), "gsr_project")
+    return splats, tile_info
+
+
+def bin_sort_workspace(n, n_views, capacity, raster):
+    return int(lib().gsr_bin_sort_workspace(n, n_views, capacity, C.byref(raster.c)))
+
+
+def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_instances, ws):
+    check(lib().gsr_bin_sort(_ptr(tile_info), n, n_views, C.byref(raster.c), _ptr(inst_gid), capacity,
+                             _ptr(tile_ranges), _ptr(n_instances), _ptr(ws), ws.numel() * ws.element_size(),
+                             _stream()), "gsr_bin_sort")
+
+
+def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last):
+    check(lib().gsr_render_fwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(cams), n_views,
+                               C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last), _stream()),
+          "gsr_render_fwd")
+
+
+def render_bwd(splats, inst_gid, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth, dsplat):
+    check(lib().gsr_render_bwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(cams), n_views,
+                               C.byref(raster.c), _ptr(T_final), _ptr(last), _ptr(dL_drgb), _ptr(dL_ddepth),
+                               _ptr(dsplat), _stream()), "gsr_render_bwd")
+
+
+def project_bwd_workspace(n, n_views):
+    return int(lib().gsr_project_bwd_workspace(n, n_views))
+
+
+def project_bwd(P, sh_degree, cams, n_views, raster, dsplat, grads, dpose, ws):
+    g = _gauss_struct(P, sh_degree)
+    gr = _abi.ParamGrads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+    check(lib().gsr_project_bwd(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(dsplat), C.byref(gr),
+                                _ptr(dpose), _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
+                                _stream()), "gsr_project_bwd")
+
+
+def adam_step(groups, rows, row_mask, beta1=0.9, beta2=0.999, eps=1e-15, step=1):
+    """groups: list of (param, grad, m, v, lr) float32 [cols, rows] device tensors."""
+    G = _abi.AdamGroups()
+    if not 1 <= len(groups) <= _abi.MAX_GROUPS:
+        raise GsrError("1..8 parameter groups")
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        cols = p.numel() // rows if rows else 0
+        G.param[k], G.grad[k], G.m[k], G.v[k] = p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr()
+        G.cols[k] = cols
+        G.lr[k] = lr
+    G.n_groups = len(groups)
+    check(lib().gsr_adam_step(C.byref(G), rows, _ptr(row_mask), beta1, beta2, eps, step, _stream()),
+          "gsr_adam_step")
+
+
+def loss_l1(rgb, depth, target_rgb, target_depth, n_views, raster, lambda_depth, loss, dL_drgb, dL_ddepth):
+    check(lib().gsr_loss_l1(_ptr(rgb), _ptr(depth), _ptr(target_rgb), _ptr(target_depth), n_views,
+                            C.byref(raster.c), lambda_depth, _ptr(loss), _ptr(dL_drgb), _ptr(dL_ddepth), _stream()),
+          "gsr_loss_l1")
+
+
+def fill_u32(t, value):
+    check(lib().gsr_fill_u32(_ptr(t), value & 0xFFFFFFFF, t.numel() * t.element_size() // 4, _stream()),
+          "gsr_fill_u32")
+
+
+# ------------------------------------------------------------------------------------------
+# rasterizer state: buffers sized once, grown on demand
+# ------------------------------------------------------------------------------------------
+
+class Rasterizer:
+    """Owns the device buffers of one (n Gaussians, V views, raster) configuration and runs the
+    forward and backward of the hot path through the C ABI."""
+
+    def __init__(self, n, n_views, raster, capacity=None, device="cuda"):
+        self.n, self.V, self.raster, self.device = int(n), int(n_views), raster, device
+        VN = self.V * self.n
+        f32, i32 = torch.float32, torch.int32
+        self.splats = torch.empty(VN * 12, dtype=f32, device=device)
+        self.tile_info = torch.empty(4 * VN, dtype=i32, device=device)
+        self.tile_ranges = torch.empty(2 * self.V * raster.tiles, dtype=i32, device=device)
+        self.n_instances = torch.zeros(1, dtype=i32, device=device)
+        P = raster.width * raster.height
+        self.rgb = torch.empty(self.V, 3, raster.height, raster.width, dtype=f32, device=device)
+        self.depth = torch.empty(self.V, raster.height, raster.width, dtype=f32, device=device)
+        self.T_final = torch.empty(self.V, raster.height, raster.width, dtype=f32, device=device)
+        self.last = torch.empty(self.V, raster.height, raster.width, dtype=i32, device=device)
+        self.dsplat = torch.zeros(VN * _abi.SPLAT_GRAD_FLOATS, dtype=f32, device=device)
+        self.pose_ws = torch.empty(max(1, project_bwd_workspace(self.n, self.V) // 8), dtype=torch.float64,
+                                   device=device)
+        self.dpose = torch.zeros(self.V, 6, dtype=torch.float64, device=device)
+        self._alloc_instances(capacity if capacity else max(1 << 16, 4 * VN))
+
+    def _alloc_instances(self, cap):
+        self.capacity = int(min(cap, (1 << 32) - 2))
+        self.inst_gid = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        wsb = bin_sort_workspace(self.n, self.V, self.capacity, self.raster)
+        self.bin_ws = torch.empty((wsb + 255) // 256 * 64, dtype=torch.int32, device=self.device)
+
+    def forward(self, P, sh_degree, cams, check_capacity=True):
+        """project -> bin/sort -> render; returns (rgb, depth, T_final) views of the buffers."""
+        project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
+        self.bin(check_capacity)
+        render_fwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb, self.depth,
+                   self.T_final, self.last)
+        return self.rgb, self.depth, self.T_final
+
+    def bin(self, check_capacity=True):
+        bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity, self.tile_ranges,
+                 self.n_instances, self.bin_ws)
+        if check_capacity:
+            m = int(self.n_instances.item()) & 0xFFFFFFFF
+            if m > self.capacity:
+                self._alloc_instances(int(m * 1.25) + 1024)
+                bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity,
+                         self.tile_ranges, self.n_instances, self.bin_ws)
+
+    def instances(self):
+        return int(self.n_instances.item()) & 0xFFFFFFFF
+
+    def backward(self, P, sh_degree, cams, dL_drgb, dL_ddepth, grads, want_pose=True):
+        """render bwd -> project bwd; parameter gradients are accumulated into grads."""
+        self.dsplat.zero_()
+        render_bwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.T_final, self.last,
+                   dL_drgb.contiguous(), dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dsplat)
+        project_bwd(P, sh_degree, cams, self.V, self.raster, self.dsplat, grads,
+                    self.dpose if want_pose else None, self.pose_ws)
+        return self.dpose
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rast, sh_degree, cams, pose_delta, means, log_scales, quats, opacity_logits, sh):
+        P = dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=quats.contiguous(),
+                 opacity_logits=opacity_logits.contiguous(), sh=sh.contiguous())
+        rgb, depth, Tf = rast.forward(P, sh_degree, cams)
+        ctx.rast, ctx.sh_degree, ctx.cams = rast, sh_degree, cams
+        ctx.P = P
+        ctx.save_for_backward(means, log_scales, quats, opacity_logits, sh)
+        alpha = 1.0 - Tf
+        ctx.mark_non_differentiable(alpha)
+        return rgb.clone(), depth.clone(), alpha
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_alpha):
+        rast = ctx.rast
+        P = ctx.P
+        grads = {k: torch.zeros_like(P[k]) for k in PARAM_NAMES}
+        if g_rgb is None:
+            g_rgb = torch.zeros_like(rast.rgb)
+        dpose = rast.backward(P, ctx.sh_degree, ctx.cams, g_rgb, g_depth, grads, want_pose=True)
+        return (None, None, None, dpose.to(torch.float32).clone(), grads["means"], grads["log_scales"],
+                grads["quats"], grads["opacity_logits"], grads["sh"])
+
+
+def rasterize(rast, means, log_scales, quats, opacity_logits, sh, sh_degree, cams, pose_delta=None):
+    """Differentiable render of all views of `rast`.  Returns (rgb [V,3,H,W], depth [V,H,W],
+    alpha [V,H,W]).  If pose_delta ([V,6], zeros, requires_grad) is given, its .grad receives the
+    se(3) gradient of a left perturbation (rho, phi) at the current poses."""
+    if pose_delta is None:
+        pose_delta = torch.zeros(rast.V, 6, device=means.device, requires_grad=False)
+    return _RasterizeFn.apply(rast, sh_degree, cams, pose_delta, means, log_scales, quats, opacity_logits, sh)

@@ -1,0 +1,88 @@
+"""ctypes declarations of include/gsr.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsr.so")
+
+P = C.c_void_p
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("z_near", C.c_float), ("bg", C.c_float * 3),
+                ("width", C.c_int32), ("height", C.c_int32), ("_pad", C.c_int32 * 2)]
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("means", P), ("log_scales", P), ("quats", P), ("opacity_logits", P), ("sh", P),
+                ("n", C.c_int64), ("sh_degree", C.c_int32), ("_pad", C.c_int32)]
+
+
+class ParamGrads(C.Structure):
+    _fields_ = [("means", P), ("log_scales", P), ("quats", P), ("opacity_logits", P), ("sh", P)]
+
+
+class Raster(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+
+
+MAX_GROUPS = 8
+
+
+class AdamGroups(C.Structure):
+    _fields_ = [("param", P * MAX_GROUPS), ("grad", P * MAX_GROUPS), ("m", P * MAX_GROUPS), ("v", P * MAX_GROUPS),
+                ("cols", C.c_int32 * MAX_GROUPS), ("lr", C.c_float * MAX_GROUPS), ("n_groups", C.c_int32),
+                ("_pad", C.c_int32)]
+
+
+assert C.sizeof(Camera) == 96
+assert C.sizeof(Gaussians) == 56
+
+SPLAT_BYTES = 48
+SPLAT_GRAD_FLOATS = 10
+
+_SIGS = {
+    "gsr_abi_version": ([], C.c_int),
+    "gsr_status_str": ([C.c_int], C.c_char_p),
+    "gsr_tiles_per_view": ([C.POINTER(Raster)], C.c_int64),
+    "gsr_project": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, P], C.c_int),
+    "gsr_bin_sort_workspace": ([C.c_int64, C.c_int32, C.c_int64, C.POINTER(Raster)], C.c_size_t),
+    "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.c_int64, P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_render_fwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P], C.c_int),
+    "gsr_render_bwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
+    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, C.POINTER(ParamGrads), P, P,
+                         C.c_size_t, P], C.c_int),
+    "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
+    "gsr_loss_l1": ([P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
+    "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
+}
+
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def load():
+    """Load libgsr.so; fail loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgsr.so is not built: run __graft_entry__.build() (hipcc for gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class GsrError(RuntimeError):
+    pass
+
+
+def check(status, what):
+    if status != 0:
+        raise GsrError("%s failed: %s (status %d)" % (what, load().gsr_status_str(status).decode(), status))

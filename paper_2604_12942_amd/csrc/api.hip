@@ -1,0 +1,151 @@
+// C ABI entry points: argument validation, then launches on the caller's stream.
+#include "gsr_internal.h"
+
+using namespace gsr;
+
+extern "C" gsr_status gsr_project_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
+                                         gsr_splat *, uint32_t *, hipStream_t);
+extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
+                                             const float *, const gsr_param_grads *, double *, void *, hipStream_t);
+extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap);
+extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, int64_t, uint32_t *,
+                                          uint32_t *, void *, hipStream_t);
+extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
+                                            const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
+                                            uint32_t *, hipStream_t);
+extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
+                                            const gsr_camera *, int, const gsr_raster *, const float *,
+                                            const uint32_t *, const float *, const float *, float *, hipStream_t);
+extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const uint8_t *, float, float, float, int,
+                                      hipStream_t);
+extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, int,
+                                         const gsr_raster *, float, double *, float *, float *, hipStream_t);
+extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+
+namespace {
+
+bool raster_ok(const gsr_raster *r) {
+    return r && r->width > 0 && r->height > 0 && r->width <= 65535 * 8 && r->height <= 65535 * 8 &&
+           valid_tile(r->tile_w, r->tile_h);
+}
+
+bool gauss_ok(const gsr_gaussians *g) {
+    if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return false;
+    if (g->n == 0) return true;
+    return g->means && g->log_scales && g->quats && g->opacity_logits && g->sh;
+}
+
+int64_t tiles(const gsr_raster *r) {
+    return ceil_div(r->width, r->tile_w) * ceil_div(r->height, r->tile_h);
+}
+
+hipStream_t S(gsr_stream s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" int gsr_abi_version(void) { return GSR_ABI_VERSION; }
+
+extern "C" const char *gsr_status_str(int status) {
+    switch (status) {
+        case GSR_OK: return "ok";
+        case GSR_E_INVALID: return "invalid argument";
+        case GSR_E_CAPACITY: return "workspace too small";
+        case GSR_E_HIP: return "HIP launch or runtime error";
+        case GSR_E_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int64_t gsr_tiles_per_view(const gsr_raster *r) { return raster_ok(r) ? tiles(r) : -1; }
+
+extern "C" gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                  const gsr_raster *r, gsr_splat *splats, uint32_t *tile_info, gsr_stream stream) {
+    if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams) return GSR_E_INVALID;
+    if ((int64_t)n_views * g->n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (g->n > 0 && (!splats || !tile_info)) return GSR_E_INVALID;
+    if (ceil_div(r->width, r->tile_w) > 65535 || ceil_div(r->height, r->tile_h) > 65535) return GSR_E_UNSUPPORTED;
+    return gsr_project_launch(g, cams, n_views, r, splats, tile_info, S(stream));
+}
+
+extern "C" size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t capacity, const gsr_raster *r) {
+    (void)r;
+    if (n < 0 || n_views < 1 || capacity < 0) return 0;
+    return gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity);
+}
+
+extern "C" gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
+                                   uint32_t *inst_gid, int64_t capacity, uint32_t *tile_ranges,
+                                   uint32_t *n_instances, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (!raster_ok(r) || n < 0 || n_views < 1 || capacity < 1 || capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if ((int64_t)n_views * n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (!tile_info && n > 0) return GSR_E_INVALID;
+    if (!inst_gid || !tile_ranges || !n_instances || !ws) return GSR_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
+    if (ws_bytes < gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity)) return GSR_E_CAPACITY;
+    if ((int64_t)n_views * tiles(r) > (int64_t)(1u << 24)) return GSR_E_UNSUPPORTED;
+    const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
+    if (n == 0) {
+        gsr_status s = gsr_fill_u32_launch(tile_ranges, 0u, 2 * (int64_t)n_views * ntx * nty, S(stream));
+        if (s != GSR_OK) return s;
+        return gsr_fill_u32_launch(n_instances, 0u, 1, S(stream));
+    }
+    return gsr_bin_sort_launch(tile_info, n, n_views, ntx, nty, inst_gid, capacity, tile_ranges, n_instances, ws,
+                               S(stream));
+}
+
+extern "C" gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
+                                     const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb,
+                                     float *depth, float *T_final, uint32_t *last, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !rgb || !depth || !T_final || !last)
+        return GSR_E_INVALID;
+    return gsr_render_fwd_launch(splats, inst_gid, tile_ranges, cams, n_views, r, rgb, depth, T_final, last,
+                                 S(stream));
+}
+
+extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
+                                     const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
+                                     const float *T_final, const uint32_t *last, const float *dL_drgb,
+                                     const float *dL_ddepth, float *dsplat, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !T_final || !last || !dL_drgb || !dsplat)
+        return GSR_E_INVALID;
+    return gsr_render_bwd_launch(splats, inst_gid, tile_ranges, cams, n_views, r, T_final, last, dL_drgb, dL_ddepth,
+                                 dsplat, S(stream));
+}
+
+extern "C" gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                      const gsr_raster *r, const float *dsplat, const gsr_param_grads *out,
+                                      double *dpose, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams || !out) return GSR_E_INVALID;
+    if (g->n > 0 && (!dsplat || !out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh))
+        return GSR_E_INVALID;
+    if (dpose && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
+    return gsr_project_bwd_launch(g, cams, n_views, r, dsplat, out, dpose, ws, S(stream));
+}
+
+extern "C" gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, const uint8_t *row_mask, float beta1,
+                                    float beta2, float eps, int32_t step, gsr_stream stream) {
+    if (!groups || groups->n_groups < 1 || groups->n_groups > GSR_MAX_GROUPS || rows < 0 || step < 1)
+        return GSR_E_INVALID;
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return GSR_E_INVALID;
+    for (int k = 0; k < groups->n_groups; k++) {
+        if (groups->cols[k] < 0) return GSR_E_INVALID;
+        if (rows > 0 && groups->cols[k] > 0 &&
+            (!groups->param[k] || !groups->grad[k] || !groups->m[k] || !groups->v[k]))
+            return GSR_E_INVALID;
+    }
+    return gsr_adam_launch(groups, rows, row_mask, beta1, beta2, eps, step, S(stream));
+}
+
+extern "C" gsr_status gsr_loss_l1(const float *rgb, const float *depth, const float *target_rgb,
+                                  const float *target_depth, int32_t n_views, const gsr_raster *r, float lambda_depth,
+                                  double *loss, float *dL_drgb, float *dL_ddepth, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !rgb || !target_rgb || !loss || !dL_drgb) return GSR_E_INVALID;
+    if (target_depth && !depth) return GSR_E_INVALID;
+    return gsr_loss_l1_launch(rgb, depth, target_rgb, target_depth, n_views, r, lambda_depth, loss, dL_drgb,
+                              dL_ddepth, S(stream));
+}
+
+extern "C" gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream) {
+    if (n_words < 0 || (n_words > 0 && !dst)) return GSR_E_INVALID;
+    return gsr_fill_u32_launch(dst, value, n_words, S(stream));
+}

@@ -1,0 +1,359 @@
+// Tile binning: ordered compaction of the visible (view, Gaussian) pairs, a stable LSD radix sort
+// of them by float32 depth bits, depth-ordered emission of (view-tile, pair) instances and a
+// stable LSD radix sort of the instances by view-tile.  The result equals a lexicographic sort by
+// (view, tile, depth bits, Gaussian index) while the expensive instance sort only moves the
+// ceil(log2(V*T)) tile bits (two 8-bit passes for up to 65,536 view-tiles) instead of all 47+.
+//
+// Every kernel reads the live element count from device memory and is launched over the
+// capacity, so the whole pipeline runs without a host round-trip (and can be graph-captured).
+#include "gsr_internal.h"
+
+namespace gsr {
+
+__device__ __forceinline__ uint32_t dev_count(const uint32_t *n_dev, uint32_t n_host, uint32_t cap) {
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    return n < cap ? n : cap;
+}
+
+// ---- generic helpers -------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *__restrict__ dst, uint32_t value, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = value;
+}
+
+// Exclusive scan in place of nb (small) block sums by one 1024-thread block; writes the total.
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *__restrict__ v, int nb, uint32_t *__restrict__ total) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int idx = base + threadIdx.x;
+        const uint32_t x = idx < nb ? v[idx] : 0u;
+        uint32_t inc = wave_incl_scan(x);
+        const int w = threadIdx.x >> 6;
+        if (__lane_id() == 63) s_w[w] = inc;
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (int k = 0; k < 16; k++) {
+            wb += k < w ? s_w[k] : 0u;
+            tot += s_w[k];
+        }
+        const uint32_t carry = s_carry;
+        if (idx < nb) v[idx] = carry + wb + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = s_carry;
+}
+
+// ---- ordered compaction of visible pairs ---------------------------------------------------------
+// block b covers pairs [b*4096, (b+1)*4096); thread t owns the 16 consecutive pairs t*16..t*16+15
+__global__ __launch_bounds__(256) void k_vis_count(const uint32_t *__restrict__ ntiles, uint32_t VN,
+                                                   uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) c += (base + k < VN && ntiles[base + k] > 0) ? 1u : 0u;
+    uint32_t tot;
+    block_excl_scan256(c, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *__restrict__ info, uint32_t VN,
+                                                     const uint32_t *__restrict__ boff, uint32_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ vals) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) c += (base + k < VN && info[base + k] > 0) ? 1u : 0u;
+    uint32_t pos = boff[blockIdx.x] + block_excl_scan256(c, s_w, nullptr);
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) {
+        const uint32_t gid = base + k;
+        if (gid < VN && info[gid] > 0) {
+            keys[pos] = info[VN + gid];
+            vals[pos] = gid;
+            pos++;
+        }
+    }
+}
+
+// ---- stable LSD radix sort, 8-bit digits -----------------------------------------------------
+// Block b sorts items [b*4096, (b+1)*4096) in round-major order: item r*256 + t is held by
+// thread t in round r, so stability follows (round, thread) order.
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
+                                                    uint32_t n_host, uint32_t cap, int shift, int nblocks,
+                                                    uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[kRadix];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = dev_count(n_dev, n_host, cap);
+    const uint32_t base = blockIdx.x * kSortTile;
+    if (base < n) {
+        for (int r = 0; r < kSortItems; r++) {
+            const uint32_t idx = base + r * kSortThreads + threadIdx.x;
+            const bool valid = idx < n;
+            const uint32_t d = valid ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
+            const uint64_t peers = match_digit8(d, valid);
+            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Row d of hist (one row per digit, nblocks entries) is scanned exclusively in place; the row
+// total goes to totals[d].
+__global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ hist, int nblocks,
+                                                         uint32_t *__restrict__ totals) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_carry;
+    uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 256) {
+        const int idx = base + threadIdx.x;
+        const uint32_t x = idx < nblocks ? row[idx] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan256(x, s_w, &tot);
+        const uint32_t carry = s_carry;
+        if (idx < nblocks) row[idx] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = s_carry;
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                       const uint32_t *n_dev, uint32_t n_host, uint32_t cap, int shift,
+                                                       int nblocks, const uint32_t *__restrict__ hist,
+                                                       const uint32_t *__restrict__ totals) {
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[4][kRadix];
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_lstart[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_w[4];
+    const uint32_t n = dev_count(n_dev, n_host, cap);
+    const uint32_t base = blockIdx.x * kSortTile;
+    if (base >= n) return;
+    const int t = threadIdx.x, w = t >> 6;
+    // global start of digit t for this block
+    const uint32_t dtot = totals[t];
+    const uint32_t dstart = block_excl_scan256(dtot, s_w, nullptr);
+    s_gbase[t] = dstart + hist[t * nblocks + blockIdx.x];
+    s_run[t] = 0;
+    for (int k = 0; k < 4; k++) s_wcnt[k][t] = 0;
+    __syncthreads();
+    uint32_t mk[kSortItems], mv[kSortItems], mpos[kSortItems];
+    const uint64_t lt = lanemask_lt();
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t idx = base + r * kSortThreads + t;
+        const bool valid = idx < n;
+        mk[r] = valid ? kin[idx] : 0u;
+        mv[r] = valid ? vin[idx] : 0u;
+        const uint32_t d = (mk[r] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit8(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t prior = s_run[d];
+            for (int k = 0; k < w; k++) prior += s_wcnt[k][d];
+            mpos[r] = prior + rank;
+        }
+        __syncthreads();
+        s_run[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
+        s_wcnt[0][t] = s_wcnt[1][t] = s_wcnt[2][t] = s_wcnt[3][t] = 0;
+        __syncthreads();
+    }
+    s_lstart[t] = block_excl_scan256(s_run[t], s_w, nullptr);
+    __syncthreads();
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t idx = base + r * kSortThreads + t;
+        if (idx < n) {
+            const uint32_t d = (mk[r] >> shift) & (kRadix - 1);
+            const uint32_t p = s_lstart[d] + mpos[r];
+            s_keys[p] = mk[r];
+            s_vals[p] = mv[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t bn = (n - base) < (uint32_t)kSortTile ? (n - base) : (uint32_t)kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t p = r * kSortThreads + t;
+        if (p < bn) {
+            const uint32_t k = s_keys[p];
+            const uint32_t d = (k >> shift) & (kRadix - 1);
+            const uint32_t dst = s_gbase[d] + (p - s_lstart[d]);
+            kout[dst] = k;
+            vout[dst] = s_vals[p];
+        }
+    }
+}
+
+// ---- instance emission in depth order --------------------------------------------------------
+__global__ __launch_bounds__(256) void k_inst_count(const uint32_t *__restrict__ sorted_gid, const uint32_t *n_vis,
+                                                    uint32_t cap, const uint32_t *__restrict__ ntiles,
+                                                    uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t n = dev_count(n_vis, 0, cap);
+    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    uint32_t c = 0;
+    for (int k = 0; k < kSortItems; k++)
+        if (base + k < n) c += ntiles[sorted_gid[base + k]];
+    uint32_t tot;
+    block_excl_scan256(c, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_inst_emit(const uint32_t *__restrict__ sorted_gid, const uint32_t *n_vis,
+                                                   uint32_t cap_vis, const uint32_t *__restrict__ info, uint32_t VN,
+                                                   uint32_t n, uint32_t T, uint32_t ntx,
+                                                   const uint32_t *__restrict__ boff, uint32_t *__restrict__ ikey,
+                                                   uint32_t *__restrict__ ival, uint32_t cap) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t nv = dev_count(n_vis, 0, cap_vis);
+    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    uint32_t c = 0;
+    for (int k = 0; k < kSortItems; k++)
+        if (base + k < nv) c += info[sorted_gid[base + k]];
+    uint32_t pos = boff[blockIdx.x] + block_excl_scan256(c, s_w, nullptr);
+    for (int k = 0; k < kSortItems; k++) {
+        if (base + k >= nv) break;
+        const uint32_t gid = sorted_gid[base + k];
+        const uint32_t v = gid / n;
+        const uint32_t r0 = info[2 * VN + gid], r1 = info[3 * VN + gid];
+        const uint32_t tx0 = r0 & 0xffffu, ty0 = r0 >> 16, tx1 = r1 & 0xffffu, ty1 = r1 >> 16;
+        const uint32_t vb = v * T;
+        for (uint32_t ty = ty0; ty <= ty1; ty++)
+            for (uint32_t tx = tx0; tx <= tx1; tx++) {
+                if (pos < cap) {
+                    ikey[pos] = vb + ty * ntx + tx;
+                    ival[pos] = gid;
+                }
+                pos++;
+            }
+    }
+}
+
+__global__ void k_tile_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_inst, uint32_t cap,
+                              uint32_t *__restrict__ ranges) {
+    const uint32_t m = dev_count(n_inst, 0, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        if (i == 0 || keys[i - 1] != k) ranges[2 * k] = i;
+        if (i + 1 == m || keys[i + 1] != k) ranges[2 * k + 1] = i + 1;
+    }
+}
+
+}  // namespace gsr
+
+using namespace gsr;
+
+namespace {
+
+struct BinWs {
+    uint32_t *zk0, *zv0, *zk1, *zv1;  // depth sort ping-pong [VN]
+    uint32_t *vis_b, *cnt_b;          // block sums [nb_vn]
+    uint32_t *n_vis;                  // 1
+    uint32_t *ik0, *ik1, *iv1;        // instance sort [cap]
+    uint32_t *hist;                   // [256][max nb]
+    uint32_t *totals;                 // [256]
+    size_t bytes;
+};
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+BinWs layout(void *base, int64_t VN, int64_t cap) {
+    BinWs w{};
+    const int64_t nb_vn = ceil_div(VN > 0 ? VN : 1, kSortTile), nb_cap = ceil_div(cap > 0 ? cap : 1, kSortTile);
+    const int64_t nbm = nb_vn > nb_cap ? nb_vn : nb_cap;
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t words) {
+        uint32_t *r = reinterpret_cast<uint32_t *>(p ? p + off : nullptr);
+        off += al(words * 4);
+        return r;
+    };
+    w.zk0 = take(VN); w.zv0 = take(VN); w.zk1 = take(VN); w.zv1 = take(VN);
+    w.vis_b = take(nb_vn); w.cnt_b = take(nb_vn); w.n_vis = take(1);
+    w.ik0 = take(cap); w.ik1 = take(cap); w.iv1 = take(cap);
+    w.hist = take((size_t)kRadix * nbm); w.totals = take(kRadix);
+    w.bytes = off;
+    return w;
+}
+
+gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, const uint32_t *n_dev, uint32_t cap,
+                      int bits, uint32_t *hist, uint32_t *totals, hipStream_t st) {
+    const int nb = (int)ceil_div(cap, kSortTile);
+    for (int shift = 0; shift < bits; shift += kRadixBits) {
+        k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, 0, cap, shift, nb, hist);
+        k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals);
+        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, n_dev, 0, cap, shift, nb, hist, totals);
+        uint32_t *tk = k, *tv = v;
+        k = k2; v = v2; k2 = tk; v2 = tv;
+    }
+    return last_launch();
+}
+
+int bit_length(uint64_t x) {
+    int b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+}  // namespace
+
+extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap) { return layout(nullptr, VN, cap).bytes; }
+
+extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V, int ntx, int nty,
+                                          uint32_t *inst_gid, int64_t cap, uint32_t *ranges, uint32_t *n_inst,
+                                          void *ws, hipStream_t st) {
+    const int64_t VN = (int64_t)V * n;
+    const uint32_t T = (uint32_t)(ntx * nty);
+    BinWs w = layout(ws, VN, cap);
+    const int nb_vn = (int)ceil_div(VN > 0 ? VN : 1, kSortTile);
+    // 1. ordered compaction of visible pairs: keys = depth bits, values = v*n + i
+    k_vis_count<<<nb_vn, 256, 0, st>>>(info, (uint32_t)VN, w.vis_b);
+    k_scan_small<<<1, 1024, 0, st>>>(w.vis_b, nb_vn, w.n_vis);
+    k_vis_compact<<<nb_vn, 256, 0, st>>>(info, (uint32_t)VN, w.vis_b, w.zk0, w.zv0);
+    // 2. stable sort by depth bits (32 bits, 4 passes: result back in zk0 / zv0)
+    uint32_t *k = w.zk0, *v = w.zv0, *k2 = w.zk1, *v2 = w.zv1;
+    gsr_status s = radix_sort(k, v, k2, v2, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), 32, w.hist, w.totals, st);
+    if (s != GSR_OK) return s;
+    // 3. instance counts in depth order, scan, emission
+    k_inst_count<<<nb_vn, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, w.cnt_b);
+    k_scan_small<<<1, 1024, 0, st>>>(w.cnt_b, nb_vn, n_inst);
+    // the instance sort runs ceil(bits/8) passes; emit into the buffer that makes the last
+    // pass land in inst_gid
+    const int tbits = bit_length((uint64_t)V * T - 1) > 0 ? bit_length((uint64_t)V * T - 1) : 1;
+    const int passes = (tbits + kRadixBits - 1) / kRadixBits;
+    uint32_t *ek = w.ik0, *ev = (passes % 2 == 0) ? inst_gid : w.iv1;
+    uint32_t *ok = w.ik1, *ov = (passes % 2 == 0) ? w.iv1 : inst_gid;
+    k_inst_emit<<<nb_vn, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, (uint32_t)VN, (uint32_t)n, T,
+                                       (uint32_t)ntx, w.cnt_b, ek, ev, (uint32_t)cap);
+    // 4. stable sort by view-tile
+    s = radix_sort(ek, ev, ok, ov, n_inst, (uint32_t)cap, passes * kRadixBits, w.hist, w.totals, st);
+    if (s != GSR_OK) return s;
+    // 5. per view-tile [start, end)
+    k_fill_u32<<<(int)ceil_div(2 * (int64_t)V * T, 256) < 4096 ? (int)ceil_div(2 * (int64_t)V * T, 256) : 4096, 256, 0,
+                 st>>>(ranges, 0u, 2 * (int64_t)V * T);
+    const int nr = (int)(ceil_div(cap, 256) < 8192 ? ceil_div(cap, 256) : 8192);
+    k_tile_ranges<<<nr, 256, 0, st>>>(ek, n_inst, (uint32_t)cap, ranges);
+    return last_launch();
+}
+
+extern "C" gsr_status gsr_fill_u32_launch(void *dst, uint32_t value, int64_t n, hipStream_t st) {
+    if (n <= 0) return GSR_OK;
+    const int nb = (int)(ceil_div(n, 256) < 8192 ? ceil_div(n, 256) : 8192);
+    k_fill_u32<<<nb, 256, 0, st>>>(static_cast<uint32_t *>(dst), value, n);
+    return last_launch();
+}
