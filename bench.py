@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Throughput of the batched global-map optimisation step on one MI355X.
+
+Workload (the headline configuration): the 200 m loop-corridor LiDAR scene with 1.5M Gaussians
+at SH degree 3; every step renders 8 keyframe views at 1280x720 (4 from the recent window, 4
+from the history window), takes the L1 colour + 0.2 L1 depth loss against ray-traced targets,
+back-propagates to every parameter and the per-view pose, and applies sparse Adam to the
+visible Gaussians of the 5 latest segments.  A step is one pass of the whole hot path:
+project, bin/sort, render forward, loss, render backward, project backward, Adam.
+
+Prints one JSON line: iterations/s with blends/s, the roofline of the dominant kernel (from HIP
+events on the launch stream) and the FP64 oracle timed on host cores as a baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic float operations per composited (pixel, Gaussian) pair
+FLOP_PER_BLEND_FWD = 23
+FLOP_PER_BLEND_BWD = 48
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--points", type=int, default=1_500_000)
+    return ap.parse_args()
+
+
+def _render_target(args):
+    scene, cam = args
+    return scene.render_gt(cam)
+
+
+def build_workload(n_points, workers):
+    c = synth.config3(n_points=n_points)
+    cams = c["cameras"]
+    nk = len(cams)
+    # keyframe pool: the 8 most recent keyframes (recent window) and 8 spread over the rest
+    recent = list(range(nk - 8, nk))
+    history = [int(round(x)) for x in np.linspace(0, nk - 12, 8)]
+    pool = recent + history
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        tg = list(ex.map(_render_target, [(c["scene"], cams[k]) for k in pool]))
+    return c, [cams[k] for k in pool], tg
+
+
+def views_for_step(step):
+    rng = np.random.default_rng(step)
+    return np.concatenate([rng.choice(8, 4, replace=False), 8 + rng.choice(8, 4, replace=False)])
+
+
+def cpu_baseline(c, pool_cams, tg):
+    """FP64 oracle on one of the 8 views of a step (forward + backward over all 1.5M Gaussians at
+    1280x720), scaled to a whole step."""
+    import oracle
+    oracle.lib()
+    g = c["gaussians"]
+    cam = pool_cams[0]
+    t0 = time.perf_counter()
+    r = oracle.render(g, cam)
+    _, gC, gD = oracle.l1_loss(r["rgb"], r["depth"], tg[0][0], tg[0][1], 0.2)
+    oracle.render_bwd(g, cam, gC, gD)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=1.0 / (8.0 * dt), unit="iters/s", cores=threads, kind="oracle",
+                sample="1 of 8 views of one step (forward + L1 loss + backward incl. pose, all %d Gaussians, "
+                       "1280x720), %.1f s, scaled x8 views" % (g["means"].shape[1], dt))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    t_gen = time.perf_counter()
+    workers = min(8, os.cpu_count() or 1)
+    c, pool_cams, tg = build_workload(a.points, workers)
+    print("workload built in %.1f s" % (time.perf_counter() - t_gen), file=sys.stderr, flush=True)
+
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    from paper_2604_12942_amd.optimize import MapOptimizer
+
+    dev = "cuda"
+    g = c["gaussians"]
+    n = g["means"].shape[1]
+    V = 8
+    H, W = pool_cams[0]["height"], pool_cams[0]["width"]
+    trgb = torch.from_numpy(np.stack([x[0] for x in tg])).to(dev)
+    tdep = torch.from_numpy(np.stack([x[1] for x in tg])).to(dev)
+    cam_pool = gsr.camera_tensor(pool_cams, dev)
+    seg = torch.from_numpy(c["segment_id"]).to(dev)
+    min_seg = int(c["n_segments"]) - 5
+
+    def make_opt(tile):
+        P = gsr.gaussians_to_device(g, dev)
+        raster = gsr.Raster(W, H, *tile)
+        return MapOptimizer(P, g["sh_degree"], cam_pool, trgb, tdep, raster, V, lambda_depth=0.2, segment_id=seg,
+                            min_segment=min_seg, device=dev)
+
+    # the view schedule of every step, resident on the device (no host round-trip per step)
+    sched = torch.from_numpy(np.stack([views_for_step(s) for s in range(a.warmup + a.steps)] +
+                                      [views_for_step(10_000 + s) for s in range(2)] +
+                                      [views_for_step(10_100 + s) for s in range(3)])).to(dev)
+    row_of = {s: s for s in range(a.warmup + a.steps)}
+    row_of.update({10_000 + s: a.warmup + a.steps + s for s in range(2)})
+    row_of.update({10_100 + s: a.warmup + a.steps + 2 + s for s in range(3)})
+
+    def sv(o, step):
+        o.set_views(sched[row_of[step]])
+
+    def timed_steps(opt, k, first_step):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(k):
+            sv(opt, first_step + s)
+            opt.step(check_capacity=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    # project-written autotuner: the same warm state timed under each tile shape
+    shapes = [(16, 16), (8, 32), (32, 8)] if a.tile == "auto" else [tuple(int(x) for x in a.tile.split("x"))]
+    tune = {}
+    if len(shapes) > 1:
+        for sh in shapes:
+            o = make_opt(sh)
+            for s in range(2):
+                sv(o, 10_000 + s)
+                o.step(check_capacity=True)
+            tune["%dx%d" % sh] = timed_steps(o, 3, 10_100)
+            del o
+            torch.cuda.empty_cache()
+        tile = min(shapes, key=lambda s: tune["%dx%d" % s])
+    else:
+        tile = shapes[0]
+    print("tile autotune (s/step): %s -> %dx%d" % (tune, *tile), file=sys.stderr, flush=True)
+
+    opt = make_opt(tile)
+    # warmup with capacity checks (instance buffer grows to fit), then fix the capacity
+    m_max = 0
+    for s in range(a.warmup):
+        sv(opt, s)
+        opt.step(check_capacity=True)
+        m_max = max(m_max, opt.rast.instances())
+    if opt.rast.capacity < int(m_max * 1.3):
+        opt.rast._alloc_instances(int(m_max * 1.3))
+
+    # timed region: K steps, per-stage HIP events on the launch stream
+    stream = torch.cuda.current_stream()
+    stages = ["gather", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "adam"]
+    ev = []
+    m_seen = torch.zeros(a.steps, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        e_start = torch.cuda.Event(enable_timing=True)
+        e_start.record(stream)
+        evs = {}
+
+        def mark(name, evs=evs):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            evs[name] = e
+
+        sv(opt, a.warmup + s)
+        opt.step(check_capacity=False, timer=mark)
+        m_seen[s:s + 1].copy_(opt.rast.n_instances)
+        ev.append((e_start, evs))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / a.steps
+    m_all = m_seen.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    if m_all.max() > opt.rast.capacity:
+        print("instance capacity exceeded in the timed region", file=sys.stderr)
+        sys.exit(3)
+    stage_ms = {k: 0.0 for k in stages}
+    for e_start, evs in ev:
+        prev = e_start
+        for k in stages:
+            stage_ms[k] += prev.elapsed_time(evs[k])
+            prev = evs[k]
+    stage_ms = {k: v / a.steps for k, v in stage_ms.items()}
+
+    # workload statistics of one representative step (same views as the last timed step)
+    sv(opt, a.warmup + a.steps - 1)
+    r = opt.rast
+    ncon = torch.empty(V, H, W, dtype=torch.int32, device=dev)
+    gsr.project(opt.P, opt.sh_degree, opt.cams, V, opt.raster, r.splats, r.tile_info)
+    r.bin(True)
+    gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, opt.cams, V, opt.raster, r.rgb, r.depth, r.T_final, r.last,
+                   ncon)
+    torch.cuda.synchronize()
+    blends = int(ncon.sum().item())
+    M = r.instances()
+    ti = r.tile_info.view(4, -1)
+    Nv = int((ti[0] > 0).sum().item())
+    Nu = int(opt.row_mask.sum().item())
+    Pf = 59
+    P = W * H
+    T = opt.raster.tiles
+    B = dict(project=V * 12 * n + (4 * Pf - 12) * Nv + 52 * Nv,
+             bin_sort=8 * Nv + 12 * M + 24 * M + 8 * M + 8 * V * T,
+             render_fwd=44 * M + 24 * V * P,
+             render_bwd=44 * M + 40 * V * P + 40 * Nv,
+             project_bwd=Nv * (40 + 4 * Pf + 8 * Pf),
+             adam=Nu * 4 * Pf * 8)
+    B_alg = sum(B.values())
+    step_s = ms_per_step / 1000.0
+    dom = max(stage_ms, key=stage_ms.get)
+    if dom in ("render_fwd", "render_bwd"):
+        fl = blends * (FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
+        ach = fl / (stage_ms[dom] / 1000.0) / 1e12
+        roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None, kernel=dom)
+    else:
+        ach = B[dom] / (stage_ms[dom] / 1000.0) / 1e9
+        roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=dom)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(c, pool_cams, tg)
+
+    out = {
+        "metric": "fwd+bwd iters/s @1.5M Gaussians, 8x720p",
+        "value": round(1.0 / step_s, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "loop corridor, %d Gaussians SH3, 8 views 1280x720 per step, L1 rgb + 0.2 L1 depth, "
+                               "sparse Adam over 5 latest segments" % n, "gaussians": n, "views_per_step": V,
+                   "width": W, "height": H, "tile": "%dx%d" % tile},
+        "blends_per_s": round(blends / step_s, 1),
+        "blends_per_step": blends,
+        "instances_per_step": M,
+        "visible_pairs_per_step": Nv,
+        "updated_rows": Nu,
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "step_alg_bytes": B_alg,
+        "step_hbm_frac": round(B_alg / step_s / (HBM_PEAK_GBS * 1e9), 4),
+        "tile_autotune_s_per_step": {k: round(v, 5) for k, v in tune.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "loss_last": float(opt.loss.item()),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

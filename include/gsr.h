@@ -145,10 +145,11 @@ GSR_API gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_
  * pixel stops when T' < 1e-4 (that Gaussian is not composited); C += a T rgb, D += a T z.
  * Outputs (images [V][...][H][W]): rgb [V][3][H][W] = C + T bg, depth [V][H][W] = D (no
  * background term), T_final [V][H][W], last [V][H][W] = number of the tile's instances up to
- * and including the pixel's last composited one (the backward re-walks exactly these). */
+ * and including the pixel's last composited one (the backward re-walks exactly these), and,
+ * if n_contrib is not NULL, n_contrib [V][H][W] = the number of composited Gaussians. */
 GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
                           const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb, float *depth,
-                          float *T_final, uint32_t *last, gsr_stream stream);
+                          float *T_final, uint32_t *last, uint32_t *n_contrib, gsr_stream stream);
 
 /* ---- render backward -------------------------------------------------------------------------
  * Exact gradient of the forward's outputs (every discrete decision held) given dL/drgb
@@ -165,10 +166,18 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
  * Chain rule from the screen-space gradients to every parameter, summed over views, plus the
  * per-view camera-pose gradient for a left perturbation T <- Exp(xi) T, xi = (rho, phi)
  * (translation first): p -> p + rho + phi x p.  Gradients are ACCUMULATED into out;
- * dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  ws: gsr_project_bwd_workspace bytes. */
+ * dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  ws: gsr_project_bwd_workspace bytes.
+ * tile_info (as written by gsr_project, may be NULL): when given, only the pairs with
+ * n_tiles > 0 are read -- the others must hold zeros, which render_bwd never changes -- and the
+ * pairs read are reset to zero, so dsplat is left all-zero for the next backward.
+ * Optional sparse-update mask (Sec. III-C: only visible Gaussians of the latest segments are
+ * updated): if row_mask [n] is not NULL (requires tile_info) it receives 1 for Gaussians that
+ * are visible in at least one view and whose segment_id [n] is >= min_segment (segment_id
+ * NULL = no freezing), else 0. */
 GSR_API size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views);
 GSR_API gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
-                           const float *dsplat, const gsr_param_grads *out, double *dpose, void *ws,
+                           float *dsplat, const gsr_param_grads *out, double *dpose, const uint32_t *tile_info,
+                           const int32_t *segment_id, int32_t min_segment, uint8_t *row_mask, void *ws,
                            size_t ws_bytes, gsr_stream stream);
 
 /* ---- sparse Adam -----------------------------------------------------------------------------
@@ -195,11 +204,13 @@ GSR_API gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, co
  * Eq. 9, 10, 12 with lambda_rgb = 1, lambda_ssim = 0 and the all-ones mask, per view v:
  * L_v = (1/P) sum_x sum_ch |C - C~| + lambda_depth (1/P) sum_x |D - D~|, P = W H; the loss is
  * summed over views into *loss (device float64, ACCUMULATED).  Writes dL_drgb [V][3][H][W] and,
- * if dL_ddepth is not NULL, dL_ddepth [V][H][W] (sign(0) = 0).  target_depth may be NULL
- * (then lambda_depth is ignored and dL_ddepth, if given, is zeroed). */
+ * if dL_ddepth is not NULL, dL_ddepth [V][H][W] (sign(0) = 0).  Targets are read from slot
+ * target_index[v] (device int32 [V]; NULL = slot v) of target_rgb [S][3][H][W] and
+ * target_depth [S][H][W]; target_depth may be NULL (then lambda_depth is ignored and
+ * dL_ddepth, if given, is zeroed). */
 GSR_API gsr_status gsr_loss_l1(const float *rgb, const float *depth, const float *target_rgb, const float *target_depth,
-                       int32_t n_views, const gsr_raster *r, float lambda_depth, double *loss, float *dL_drgb,
-                       float *dL_ddepth, gsr_stream stream);
+                       const int32_t *target_index, int32_t n_views, const gsr_raster *r, float lambda_depth,
+                       double *loss, float *dL_drgb, float *dL_ddepth, gsr_stream stream);
 
 /* Fill n 32-bit words with a value (graph-capture safe replacement for memset). */
 GSR_API gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream);

@@ -27,7 +27,8 @@
  *            c = -R^T t; Y_k real orthonormal SH without Condon-Shortley phase.
  *   alpha    a_raw = o exp(-1/2 D^T Q D), D = pixel centre - (u, v); a pair
  *            contributes iff a_raw >= 1/255; a = min(0.99, a_raw).
- *   order    contributors by ascending (z, Gaussian index).
+ *   order    contributors by ascending (depth key, Gaussian index), the depth key being the
+ *            camera depth rounded to float32 (the 32-bit key of the tile binning sort).
  *   blend    T = 1; for each: T' = T (1 - a); stop if T' < 1e-4 (that one is
  *            not composited); C += a T rgb; D += a T z (Eq. 8); T = T'.
  *            Output C + T bg, D, T.
@@ -326,20 +327,27 @@ typedef struct {
     double z, a_raw, a, dx, dy, T;   /* T = transmittance before this contributor */
 } orc_contrib;
 
+/* Compositing order: ascending depth key, then Gaussian index.  The depth key is the camera
+   depth rounded to float32 (round to nearest), the 32-bit key tile binning sorts on; equal
+   keys fall back to the index. */
 static int cmp_contrib(const void *pa, const void *pb) {
     const orc_contrib *a = pa, *b = pb;
-    if (a->z < b->z) return -1;
-    if (a->z > b->z) return 1;
+    const float za = (float)a->z, zb = (float)b->z;
+    if (za < zb) return -1;
+    if (za > zb) return 1;
     return (a->id > b->id) - (a->id < b->id);
 }
 
 static double rel_margin(double v, double ref) { return fabs(v / ref - 1.0); }
 
-/* ulp of a float32 value near |z| (for the depth-tie test) */
-static double f32_ulp(double z) {
-    int e;
-    frexp(fabs(z), &e);
-    return ldexp(1.0, e - 24);
+/* relative distance of z to the nearest float32 rounding midpoint: below ~1e-13 the depth
+   key could round either way under a different (equally exact) evaluation order */
+static double f32_round_margin(double z) {
+    const float zf = (float)z;
+    const double up = 0.5 * ((double)zf + (double)nextafterf(zf, INFINITY));
+    const double dn = 0.5 * ((double)zf + (double)nextafterf(zf, -INFINITY));
+    const double m = fabs(z - up) < fabs(z - dn) ? fabs(z - up) : fabs(z - dn);
+    return m / fabs(z);
 }
 
 typedef struct {
@@ -378,15 +386,14 @@ static int64_t pixel_composite(const orc_pg *P, const orc_cells *C, const orc_ca
     qsort(s->buf, m, sizeof(orc_contrib), cmp_contrib);
     double T = 1, Cc[3] = {0, 0, 0}, D = 0;
     int64_t n = 0;
-    double zprev = NAN;
     for (int64_t k = 0; k < m; k++) {
         orc_contrib c = s->buf[k];
         double mth = rel_margin(c.a_raw * 255.0, 1.0);
         if (mth < mg) mg = mth;
         if (c.a_raw < ORC_ALPHA_MIN) continue;
         const orc_pg *G = &P[c.id];
-        /* depth tie within 4 float32 ulps between consecutive contributors */
-        if (n > 0 && fabs(c.z - zprev) <= 4 * f32_ulp(c.z)) mg = 0;
+        /* depth key at a float32 rounding midpoint */
+        if (f32_round_margin(c.z) < 1e-13) mg = 0;
         double mcl = rel_margin(c.a_raw, ORC_ALPHA_MAX);
         if (mcl < mg) mg = mcl;
         double a = c.a_raw < ORC_ALPHA_MAX ? c.a_raw : ORC_ALPHA_MAX;
@@ -406,7 +413,6 @@ static int64_t pixel_composite(const orc_pg *P, const orc_cells *C, const orc_ca
         c.a = a; c.T = T;
         s->buf[n++] = c;
         T = Tn;
-        zprev = c.z;
     }
     for (int ch = 0; ch < 3; ch++) rgb[ch] = Cc[ch] + T * cam->bg[ch];
     *depth = D;

@@ -110,10 +110,10 @@ def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_i
                              _stream()), "gsr_bin_sort")
 
 
-def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last):
+def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last, n_contrib=None):
     check(lib().gsr_render_fwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(cams), n_views,
-                               C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last), _stream()),
-          "gsr_render_fwd")
+                               C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
+                               _ptr(n_contrib), _stream()), "gsr_render_fwd")
 
 
 def render_bwd(splats, inst_gid, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth, dsplat):
@@ -126,12 +126,14 @@ def project_bwd_workspace(n, n_views):
     return int(lib().gsr_project_bwd_workspace(n, n_views))
 
 
-def project_bwd(P, sh_degree, cams, n_views, raster, dsplat, grads, dpose, ws):
+def project_bwd(P, sh_degree, cams, n_views, raster, dsplat, grads, dpose, ws, tile_info=None, segment_id=None,
+                min_segment=0, row_mask=None):
     g = _gauss_struct(P, sh_degree)
     gr = _abi.ParamGrads(*[grads[k].data_ptr() for k in PARAM_NAMES])
     check(lib().gsr_project_bwd(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(dsplat), C.byref(gr),
-                                _ptr(dpose), _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
-                                _stream()), "gsr_project_bwd")
+                                _ptr(dpose), _ptr(tile_info), _ptr(segment_id), int(min_segment), _ptr(row_mask),
+                                _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
+          "gsr_project_bwd")
 
 
 def adam_step(groups, rows, row_mask, beta1=0.9, beta2=0.999, eps=1e-15, step=1):
@@ -149,10 +151,11 @@ def adam_step(groups, rows, row_mask, beta1=0.9, beta2=0.999, eps=1e-15, step=1)
           "gsr_adam_step")
 
 
-def loss_l1(rgb, depth, target_rgb, target_depth, n_views, raster, lambda_depth, loss, dL_drgb, dL_ddepth):
-    check(lib().gsr_loss_l1(_ptr(rgb), _ptr(depth), _ptr(target_rgb), _ptr(target_depth), n_views,
-                            C.byref(raster.c), lambda_depth, _ptr(loss), _ptr(dL_drgb), _ptr(dL_ddepth), _stream()),
-          "gsr_loss_l1")
+def loss_l1(rgb, depth, target_rgb, target_depth, n_views, raster, lambda_depth, loss, dL_drgb, dL_ddepth,
+            target_index=None):
+    check(lib().gsr_loss_l1(_ptr(rgb), _ptr(depth), _ptr(target_rgb), _ptr(target_depth), _ptr(target_index),
+                            n_views, C.byref(raster.c), lambda_depth, _ptr(loss), _ptr(dL_drgb), _ptr(dL_ddepth),
+                            _stream()), "gsr_loss_l1")
 
 
 def fill_u32(t, value):
@@ -185,6 +188,7 @@ class Rasterizer:
         self.pose_ws = torch.empty(max(1, project_bwd_workspace(self.n, self.V) // 8), dtype=torch.float64,
                                    device=device)
         self.dpose = torch.zeros(self.V, 6, dtype=torch.float64, device=device)
+        self.keep_dsplat = False  # tests: keep a copy of the screen-space gradients
         self._alloc_instances(capacity if capacity else max(1 << 16, 4 * VN))
 
     def _alloc_instances(self, cap):
@@ -214,13 +218,17 @@ class Rasterizer:
     def instances(self):
         return int(self.n_instances.item()) & 0xFFFFFFFF
 
-    def backward(self, P, sh_degree, cams, dL_drgb, dL_ddepth, grads, want_pose=True):
-        """render bwd -> project bwd; parameter gradients are accumulated into grads."""
-        self.dsplat.zero_()
+    def backward(self, P, sh_degree, cams, dL_drgb, dL_ddepth, grads, want_pose=True, segment_id=None,
+                 min_segment=0, row_mask=None):
+        """render bwd -> project bwd; parameter gradients are accumulated into grads.  The
+        screen-space gradient buffer is consumed (left zeroed) by project bwd."""
         render_bwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.T_final, self.last,
                    dL_drgb.contiguous(), dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dsplat)
+        if self.keep_dsplat:
+            self.dsplat_copy = self.dsplat.clone()
         project_bwd(P, sh_degree, cams, self.V, self.raster, self.dsplat, grads,
-                    self.dpose if want_pose else None, self.pose_ws)
+                    self.dpose if want_pose else None, self.pose_ws, self.tile_info, segment_id, min_segment,
+                    row_mask)
         return self.dpose
 
 

@@ -49,13 +49,13 @@ _SIGS = {
     "gsr_project": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, P], C.c_int),
     "gsr_bin_sort_workspace": ([C.c_int64, C.c_int32, C.c_int64, C.POINTER(Raster)], C.c_size_t),
     "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.c_int64, P, P, P, C.c_size_t, P], C.c_int),
-    "gsr_render_fwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P], C.c_int),
+    "gsr_render_fwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
     "gsr_render_bwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
     "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
-    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, C.POINTER(ParamGrads), P, P,
-                         C.c_size_t, P], C.c_int),
+    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, C.POINTER(ParamGrads), P, P, P,
+                         C.c_int32, P, P, C.c_size_t, P], C.c_int),
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
-    "gsr_loss_l1": ([P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
+    "gsr_loss_l1": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
 }
 

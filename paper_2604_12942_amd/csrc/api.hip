@@ -6,20 +6,21 @@ using namespace gsr;
 extern "C" gsr_status gsr_project_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
                                          gsr_splat *, uint32_t *, hipStream_t);
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
-                                             const float *, const gsr_param_grads *, double *, void *, hipStream_t);
+                                             float *, const gsr_param_grads *, double *, const uint32_t *,
+                                             const int32_t *, int32_t, uint8_t *, void *, hipStream_t);
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap);
 extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, int64_t, uint32_t *,
                                           uint32_t *, void *, hipStream_t);
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
-                                            uint32_t *, hipStream_t);
+                                            uint32_t *, uint32_t *, hipStream_t);
 extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, const float *,
                                             const uint32_t *, const float *, const float *, float *, hipStream_t);
 extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const uint8_t *, float, float, float, int,
                                       hipStream_t);
-extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, int,
-                                         const gsr_raster *, float, double *, float *, float *, hipStream_t);
+extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
+                                         int, const gsr_raster *, float, double *, float *, float *, hipStream_t);
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
 
 namespace {
@@ -95,11 +96,12 @@ extern "C" gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t
 
 extern "C" gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
                                      const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb,
-                                     float *depth, float *T_final, uint32_t *last, gsr_stream stream) {
+                                     float *depth, float *T_final, uint32_t *last, uint32_t *n_contrib,
+                                     gsr_stream stream) {
     if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !rgb || !depth || !T_final || !last)
         return GSR_E_INVALID;
     return gsr_render_fwd_launch(splats, inst_gid, tile_ranges, cams, n_views, r, rgb, depth, T_final, last,
-                                 S(stream));
+                                 n_contrib, S(stream));
 }
 
 extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
@@ -113,13 +115,17 @@ extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *in
 }
 
 extern "C" gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
-                                      const gsr_raster *r, const float *dsplat, const gsr_param_grads *out,
-                                      double *dpose, void *ws, size_t ws_bytes, gsr_stream stream) {
+                                      const gsr_raster *r, float *dsplat, const gsr_param_grads *out,
+                                      double *dpose, const uint32_t *tile_info, const int32_t *segment_id,
+                                      int32_t min_segment, uint8_t *row_mask, void *ws, size_t ws_bytes,
+                                      gsr_stream stream) {
     if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams || !out) return GSR_E_INVALID;
     if (g->n > 0 && (!dsplat || !out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh))
         return GSR_E_INVALID;
+    if (row_mask && !tile_info && g->n > 0) return GSR_E_INVALID;
     if (dpose && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
-    return gsr_project_bwd_launch(g, cams, n_views, r, dsplat, out, dpose, ws, S(stream));
+    return gsr_project_bwd_launch(g, cams, n_views, r, dsplat, out, dpose, tile_info, segment_id, min_segment,
+                                  row_mask, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, const uint8_t *row_mask, float beta1,
@@ -137,12 +143,13 @@ extern "C" gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows,
 }
 
 extern "C" gsr_status gsr_loss_l1(const float *rgb, const float *depth, const float *target_rgb,
-                                  const float *target_depth, int32_t n_views, const gsr_raster *r, float lambda_depth,
-                                  double *loss, float *dL_drgb, float *dL_ddepth, gsr_stream stream) {
+                                  const float *target_depth, const int32_t *target_index, int32_t n_views,
+                                  const gsr_raster *r, float lambda_depth, double *loss, float *dL_drgb,
+                                  float *dL_ddepth, gsr_stream stream) {
     if (!raster_ok(r) || n_views < 1 || !rgb || !target_rgb || !loss || !dL_drgb) return GSR_E_INVALID;
     if (target_depth && !depth) return GSR_E_INVALID;
-    return gsr_loss_l1_launch(rgb, depth, target_rgb, target_depth, n_views, r, lambda_depth, loss, dL_drgb,
-                              dL_ddepth, S(stream));
+    return gsr_loss_l1_launch(rgb, depth, target_rgb, target_depth, target_index, n_views, r, lambda_depth, loss,
+                              dL_drgb, dL_ddepth, S(stream));
 }
 
 extern "C" gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream) {

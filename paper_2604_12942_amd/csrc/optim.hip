@@ -29,7 +29,8 @@ __global__ void k_adam(gsr_adam_groups G, int64_t rows, const uint8_t *__restric
 
 __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ rgb, const float *__restrict__ depth,
                                                  const float *__restrict__ trgb, const float *__restrict__ tdepth,
-                                                 int64_t P, int V, float lam, float *__restrict__ grgb,
+                                                 const int32_t *__restrict__ tidx, int64_t P, int V, float lam,
+                                                 float *__restrict__ grgb,
                                                  float *__restrict__ gdepth, double *__restrict__ loss) {
     __shared__ double s_red[4];
     const float invP = 1.0f / (float)P;
@@ -37,16 +38,17 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ rgb, 
     const int64_t total = (int64_t)V * P;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = e / P, pix = e % P;
-        const int64_t base = v * 3 * P + pix;
+        const int64_t slot = tidx ? (int64_t)tidx[v] : v;
+        const int64_t base = v * 3 * P + pix, tbase = slot * 3 * P + pix;
         float l = 0.f;
         for (int ch = 0; ch < 3; ch++) {
-            const float d = rgb[base + ch * P] - trgb[base + ch * P];
+            const float d = rgb[base + ch * P] - trgb[tbase + ch * P];
             l += fabsf(d);
             grgb[base + ch * P] = (d > 0.f ? invP : (d < 0.f ? -invP : 0.f));
         }
         float gd = 0.f;
         if (tdepth) {
-            const float d = depth[e] - tdepth[e];
+            const float d = depth[e] - tdepth[slot * P + pix];
             l += lam * fabsf(d);
             gd = lam * (d > 0.f ? invP : (d < 0.f ? -invP : 0.f));
         }
@@ -76,11 +78,11 @@ extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *g, int64_t rows, co
 }
 
 extern "C" gsr_status gsr_loss_l1_launch(const float *rgb, const float *depth, const float *trgb, const float *tdepth,
-                                         int V, const gsr_raster *r, float lam, double *loss, float *grgb,
-                                         float *gdepth, hipStream_t st) {
+                                         const int32_t *tidx, int V, const gsr_raster *r, float lam, double *loss,
+                                         float *grgb, float *gdepth, hipStream_t st) {
     const int64_t P = (int64_t)r->width * r->height;
     const int64_t total = (int64_t)V * P;
     const int nb = (int)(ceil_div(total, 256) < 2048 ? ceil_div(total, 256) : 2048);
-    k_loss_l1<<<nb, 256, 0, st>>>(rgb, depth, trgb, tdepth, P, V, lam, grgb, gdepth, loss);
+    k_loss_l1<<<nb, 256, 0, st>>>(rgb, depth, trgb, tdepth, tidx, P, V, lam, grgb, gdepth, loss);
     return last_launch();
 }

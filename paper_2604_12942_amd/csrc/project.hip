@@ -206,15 +206,18 @@ __global__ __launch_bounds__(256) void k_project(gsr_gaussians g, const gsr_came
                 rec2 = make_float4(zf, col[0], col[1], col[2]);
             }
         }
-        double2 *dst = reinterpret_cast<double2 *>(splats + gid);
-        dst[0] = make_double2(rec0.x, rec0.y);
-        float4 *dstf = reinterpret_cast<float4 *>(splats + gid) + 1;
-        dstf[0] = rec1;
-        dstf[1] = rec2;
+        // only visible pairs are ever read back: skip the record writes of the others
         info[gid] = ntiles;
-        info[VN + gid] = zbits;
-        info[2 * VN + gid] = r0;
-        info[3 * VN + gid] = r1;
+        if (ntiles) {
+            double2 *dst = reinterpret_cast<double2 *>(splats + gid);
+            dst[0] = make_double2(rec0.x, rec0.y);
+            float4 *dstf = reinterpret_cast<float4 *>(splats + gid) + 1;
+            dstf[0] = rec1;
+            dstf[1] = rec2;
+            info[VN + gid] = zbits;
+            info[2 * VN + gid] = r0;
+            info[3 * VN + gid] = r1;
+        }
     }
 }
 
@@ -239,8 +242,11 @@ __device__ __forceinline__ void block_sum6_d(double v[6], double *s_red /*[4][6]
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_camera *__restrict__ cams, int V,
-                                                     int W, int H, const float *__restrict__ dsplat,
-                                                     gsr_param_grads out, double *__restrict__ pose_part) {
+                                                     int W, int H, float *__restrict__ dsplat,
+                                                     gsr_param_grads out, double *__restrict__ pose_part,
+                                                     const uint32_t *__restrict__ tile_info,
+                                                     const int32_t *__restrict__ seg, int32_t min_seg,
+                                                     uint8_t *__restrict__ row_mask) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ double s_red[4 * 6];
     const int64_t n = g.n;
@@ -260,18 +266,32 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
     float gh[3 * K];
 #pragma unroll
     for (int e = 0; e < 3 * K; e++) gh[e] = 0.f;
-    bool touched = false;
+    bool touched = false, visible = false;
 
     for (int vi = 0; vi < V; vi++) {
         double pose[6] = {0, 0, 0, 0, 0, 0};
         float gs[10];
         bool any = false;
         if (live) {
-            const float *src = dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS;
+            // with tile_info, only the pairs that were rendered can hold gradients: read those and
+            // reset them, leaving dsplat zeroed for the next backward without a separate fill
+            const bool vis = tile_info ? tile_info[(int64_t)vi * n + i] > 0 : true;
+            visible |= vis;
+            if (vis) {
+                float *src = dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS;
+                float2 *s2 = reinterpret_cast<float2 *>(src);
 #pragma unroll
-            for (int e = 0; e < 10; e++) {
-                gs[e] = src[e];
-                any |= gs[e] != 0.f;
+                for (int e = 0; e < 5; e++) {
+                    const float2 q = s2[e];
+                    gs[2 * e] = q.x;
+                    gs[2 * e + 1] = q.y;
+                }
+#pragma unroll
+                for (int e = 0; e < 10; e++) any |= gs[e] != 0.f;
+                if (tile_info && any) {
+#pragma unroll
+                    for (int e = 0; e < 5; e++) s2[e] = make_float2(0.f, 0.f);
+                }
             }
         }
         Cam k;
@@ -374,6 +394,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
             block_sum6_d(pose, s_red, pose_part + ((int64_t)blockIdx.x * V + vi) * 6);
         }
     }
+    if (live && row_mask) row_mask[i] = (visible && (!seg || seg[i] >= min_seg)) ? 1 : 0;
     if (!live || !touched) return;
     // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 dL/dSigma M
     double gRq[3][3];
@@ -445,8 +466,9 @@ extern "C" size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views) {
 }
 
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_camera *cams, int V,
-                                             const gsr_raster *r, const float *dsplat, const gsr_param_grads *out,
-                                             double *dpose, void *ws, hipStream_t st) {
+                                             const gsr_raster *r, float *dsplat, const gsr_param_grads *out,
+                                             double *dpose, const uint32_t *tile_info, const int32_t *seg,
+                                             int32_t min_seg, uint8_t *row_mask, void *ws, hipStream_t st) {
     const int nb = (int)ceil_div(g->n, 256);
     if (nb == 0) {
         if (dpose) {
@@ -456,7 +478,9 @@ extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_c
         return last_launch();
     }
     double *part = dpose ? static_cast<double *>(ws) : nullptr;
-#define GSR_PB(D) k_project_bwd<D><<<nb, 256, 0, st>>>(*g, cams, V, r->width, r->height, dsplat, *out, part)
+#define GSR_PB(D)                                                                                          \
+    k_project_bwd<D><<<nb, 256, 0, st>>>(*g, cams, V, r->width, r->height, dsplat, *out, part, tile_info, seg, \
+                                         min_seg, row_mask)
     switch (g->sh_degree) {
         case 0: GSR_PB(0); break;
         case 1: GSR_PB(1); break;

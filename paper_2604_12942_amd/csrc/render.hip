@@ -2,7 +2,7 @@
 //
 // One 256-lane workgroup (four wave64s) per (view, screen tile); one pixel per lane.  The tile's
 // depth-ordered instances are staged through LDS in batches of 256: each lane gathers one
-// projected splat (48 B), re-centres its double-precision mean on the tile origin and stores
+// projected splat (48 B), re-centres its double-precision mean near the tile and stores
 // the float32 fields the blend loop needs; every lane then walks the batch reading the staged
 // values as LDS broadcasts.  The blend exponent is evaluated in the whitened form
 // |L^T D|^2 (L the Cholesky factor of (log2(e)/2) Q): two fused products per pair and no
@@ -12,7 +12,7 @@
 namespace gsr {
 
 struct Staged {
-    float4 A;  // mx, my (mean relative to the tile origin), l11, l21
+    float4 A;  // mx, my (mean relative to the 32-aligned block origin), l11, l21
     float4 B;  // l22, cut = log2(255 o), o, z
     float4 C;  // r, g, b, (unused)
 };
@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
                                                     const uint32_t *__restrict__ ranges,
                                                     const gsr_camera *__restrict__ cams, int W, int H, int ntx,
                                                     int T, float *__restrict__ rgb, float *__restrict__ depth,
-                                                    float *__restrict__ Tfin, uint32_t *__restrict__ last) {
+                                                    float *__restrict__ Tfin, uint32_t *__restrict__ last,
+                                                    uint32_t *__restrict__ ncon) {
     static_assert(TW * TH == 256, "one pixel per lane");
     __shared__ float4 sA[256], sB[256], sC[256];
     const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
@@ -54,10 +55,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < W && py < H;
     const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
-    const double ox = (double)(tx * TW), oy = (double)(ty * TH);
-    const float fx = lx + 0.5f, fy = ly + 0.5f;
+    // means are re-centred on the 32x32-aligned block holding the tile: the same origin for
+    // every tile shape, so images are bit-identical across 16x16, 8x32 and 32x8 tiles
+    const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
+    const double ox = (double)bx, oy = (double)by;
+    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;
     float Tr = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dd = 0.f;
-    uint32_t lst = 0;
+    uint32_t lst = 0, nc = 0;
     bool done = !inside;
     for (uint32_t b = start; b < end; b += 256) {
         if (__syncthreads_count(!done) == 0) break;
@@ -92,6 +96,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
             dd = __builtin_fmaf(wgt, B.w, dd);
             Tr = Tn;
             lst = b - start + j + 1;
+            nc++;
         }
     }
     if (!inside) return;
@@ -104,6 +109,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     depth[(int64_t)v * P + pix] = dd;
     Tfin[(int64_t)v * P + pix] = Tr;
     last[(int64_t)v * P + pix] = lst;
+    if (ncon) ncon[(int64_t)v * P + pix] = nc;
 }
 
 template <int TW, int TH>
@@ -126,8 +132,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < W && py < H;
     const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
-    const double ox = (double)(tx * TW), oy = (double)(ty * TH);
-    const float fx = lx + 0.5f, fy = ly + 0.5f;
+    const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
+    const double ox = (double)bx, oy = (double)by;
+    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;
     const int64_t P = (int64_t)W * H;
     const int64_t pix = (int64_t)py * W + px;
     float Tr = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f;
@@ -220,12 +227,14 @@ using namespace gsr;
 
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *splats, const uint32_t *inst, const uint32_t *ranges,
                                             const gsr_camera *cams, int V, const gsr_raster *r, float *rgb,
-                                            float *depth, float *Tfin, uint32_t *last, hipStream_t st) {
+                                            float *depth, float *Tfin, uint32_t *last, uint32_t *ncon,
+                                            hipStream_t st) {
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     const int T = ntx * nty;
     const int nb = V * T;
 #define GSR_RF(TW, TH) \
-    k_render_fwd<TW, TH><<<nb, 256, 0, st>>>(splats, inst, ranges, cams, r->width, r->height, ntx, T, rgb, depth, Tfin, last)
+    k_render_fwd<TW, TH><<<nb, 256, 0, st>>>(splats, inst, ranges, cams, r->width, r->height, ntx, T, rgb, depth, Tfin, last, \
+                                             ncon)
     if (r->tile_w == 16) GSR_RF(16, 16);
     else if (r->tile_w == 8) GSR_RF(8, 32);
     else GSR_RF(32, 8);

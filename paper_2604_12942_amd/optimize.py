@@ -1,0 +1,95 @@
+"""Global Gaussian-map optimisation step (paper Sec. III-C), batched over keyframe views.
+
+One step: the views chosen for this iteration are projected and binned together, rendered
+(colour + depth, Eq. 8), supervised with the L1 colour + lambda_depth L1 depth loss (Eq. 9, 10,
+12 with the all-ones mask), differentiated back to every parameter (and the per-view pose), and
+the visible Gaussians of the unfrozen segments take a sparse Adam step.  Every stage is a
+libgsr kernel on torch's current stream; this class only owns buffers.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import PARAM_NAMES, Rasterizer, adam_step, loss_l1
+
+# learning rates per parameter group: means (m), log-scales, quaternions, opacity logits,
+# SH DC, SH rest
+DEFAULT_LR = dict(means=5e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4)
+
+
+class MapOptimizer:
+    def __init__(self, params, sh_degree, cam_pool, target_rgb, target_depth, raster, n_views, lambda_depth=0.2,
+                 lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda"):
+        """params: dict of float32 [c, n] device tensors (optimised in place); cam_pool: device
+        uint8 [S*96] gsr_camera records; target_rgb [S,3,H,W], target_depth [S,H,W] (or None)."""
+        self.P = params
+        self.sh_degree = int(sh_degree)
+        self.n = params["means"].shape[1]
+        self.V = int(n_views)
+        self.raster = raster
+        self.cam_pool = cam_pool.view(-1, 96)
+        self.target_rgb, self.target_depth = target_rgb, target_depth
+        self.lambda_depth = float(lambda_depth)
+        self.lr = dict(DEFAULT_LR, **(lr or {}))
+        self.segment_id, self.min_segment = segment_id, int(min_segment)
+        self.rast = Rasterizer(self.n, self.V, raster, capacity=capacity, device=device)
+        self.grads = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        H, W = raster.height, raster.width
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.g_rgb = torch.empty(self.V, 3, H, W, device=device)
+        self.g_depth = torch.empty(self.V, H, W, device=device)
+        self.row_mask = torch.zeros(self.n, dtype=torch.uint8, device=device)
+        self.view_idx = torch.zeros(self.V, dtype=torch.int64, device=device)
+        self.view_idx32 = torch.zeros(self.V, dtype=torch.int32, device=device)
+        self.cams = torch.empty(self.V * 96, dtype=torch.uint8, device=device)
+        self.t = 0
+
+    def set_views(self, idx):
+        """Choose this iteration's keyframes (slots of the camera / target pool).  A device
+        tensor is copied on the stream without a host round-trip."""
+        if isinstance(idx, torch.Tensor) and idx.is_cuda:
+            self.view_idx.copy_(idx)
+        else:
+            self.view_idx.copy_(torch.as_tensor(idx, dtype=torch.int64), non_blocking=False)
+
+    def _groups(self):
+        P, G, M, Vv, lr = self.P, self.grads, self.m, self.v, self.lr
+        gs = [(P[k], G[k], M[k], Vv[k], lr[k]) for k in ("means", "log_scales", "quats", "opacity_logits")]
+        gs.append((P["sh"][0:3], G["sh"][0:3], M["sh"][0:3], Vv["sh"][0:3], lr["sh_dc"]))
+        if P["sh"].shape[0] > 3:
+            gs.append((P["sh"][3:], G["sh"][3:], M["sh"][3:], Vv["sh"][3:], lr["sh_rest"]))
+        return gs
+
+    def step(self, check_capacity=True, timer=None):
+        """One optimisation iteration over the chosen views.  timer(stage) is called between
+        stages (e.g. to record events)."""
+        mark = timer or (lambda s: None)
+        r = self.rast
+        torch.index_select(self.cam_pool, 0, self.view_idx, out=self.cams.view(-1, 96))
+        self.view_idx32.copy_(self.view_idx)
+        mark("gather")
+        from . import project, bin_sort, render_fwd, render_bwd, project_bwd
+        project(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.tile_info)
+        mark("project")
+        r.bin(check_capacity)
+        mark("bin_sort")
+        render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth, r.T_final,
+                   r.last)
+        mark("render_fwd")
+        self.loss.zero_()
+        loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
+                self.loss, self.g_rgb, self.g_depth if self.target_depth is not None else None,
+                target_index=self.view_idx32)
+        mark("loss")
+        render_bwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.T_final, r.last,
+                   self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dsplat)
+        mark("render_bwd")
+        project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.dsplat, self.grads, r.dpose,
+                    r.pose_ws, r.tile_info, self.segment_id, self.min_segment, self.row_mask)
+        mark("project_bwd")
+        self.t += 1
+        adam_step(self._groups(), self.n, self.row_mask, step=self.t)
+        mark("adam")
+        return self.loss

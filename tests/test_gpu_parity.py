@@ -174,13 +174,15 @@ def test_render_backward_matches_oracle(name):
     GC, GD = _upstream(cam, 5)
     o = oracle.render_bwd(g, cam, GC.astype(np.float64), GD.astype(np.float64))
     grads = {k: torch.zeros_like(P[k]) for k in gsr.PARAM_NAMES}
+    rast.keep_dsplat = True
     dpose = rast.backward(P, g["sh_degree"], ct, torch.from_numpy(GC[None]).cuda(),
                           torch.from_numpy(GD[None]).cuda(), grads)
     torch.cuda.synchronize()
+    assert torch.count_nonzero(rast.dsplat).item() == 0  # consumed by project bwd
     keep = ~o["knife_g"]
     # screen-space gradients per Gaussian (u, v, Qa, Qb, Qc, o, r, g, b, z)
     n = g["means"].shape[1]
-    ds = rast.dsplat.cpu().numpy().reshape(-1, 10)[:n].astype(np.float64)
+    ds = rast.dsplat_copy.cpu().numpy().reshape(-1, 10)[:n].astype(np.float64)
     for e in range(10):
         bad = grad_close(ds[:, e], o["screen"][:, e], mask=keep)
         assert bad.sum() == 0, ("screen", e, bad.sum(), np.nonzero(bad)[0][:5])

@@ -243,3 +243,20 @@ def test_l1_loss_and_psnr_closed_forms(orc):
     _, gC0, _ = orc.l1_loss(tgt, dep, tgt, None, 0.0)
     assert np.all(gC0 == 0)
     assert orc.psnr(rgb, tgt) == pytest.approx(10 * math.log10(1 / 0.0625), rel=1e-14)
+
+
+def test_order_uses_float32_depth_key_then_index(orc):
+    # Two coincident Gaussians whose depths differ by less than half a float32 ulp share the
+    # depth key: the lower index composites first even though it is (in float64) farther away.
+    z = 3.0
+    a = one_gaussian([0, 0, z + 1e-8], [math.log(0.01)] * 3, logit=logit(0.6), sh=(1.0, 0.0, 0.0))
+    b = one_gaussian([0, 0, z], [math.log(0.01)] * 3, logit=logit(0.3), sh=(0.0, 1.0, 0.0))
+    c = cam(21, 21, f=100.0)
+    r = orc.render(stack([a, b]), c, pixels=[[10, 10]])
+    k = 1 / (2 * math.sqrt(math.pi))
+    ca, cb = np.array([0.5 + k, 0.5, 0.5]), np.array([0.5, 0.5 + k, 0.5])
+    np.testing.assert_allclose(r["rgb"][0], 0.6 * ca + 0.4 * 0.3 * cb, rtol=1e-13)
+    # once the keys differ, depth decides
+    a2 = one_gaussian([0, 0, z + 1e-5], [math.log(0.01)] * 3, logit=logit(0.6), sh=(1.0, 0.0, 0.0))
+    r2 = orc.render(stack([a2, b]), c, pixels=[[10, 10]])
+    np.testing.assert_allclose(r2["rgb"][0], 0.3 * cb + 0.7 * 0.6 * ca, rtol=1e-13)
