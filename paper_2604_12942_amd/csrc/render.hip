@@ -112,6 +112,43 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     if (ncon) ncon[(int64_t)v * P + pix] = nc;
 }
 
+// ---- wave64 inclusive scans over lane order (DPP row shifts, then row broadcasts) -------------
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_or(float src, float ident) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(ident), __float_as_int(src), CTRL, ROWS, 0xf,
+                                                      false));
+}
+__device__ __forceinline__ float wave_incl_prod(float v) {
+    v *= dpp_or<0x111, 0xf>(v, 1.0f);  // row_shr:1
+    v *= dpp_or<0x112, 0xf>(v, 1.0f);  // row_shr:2
+    v *= dpp_or<0x114, 0xf>(v, 1.0f);  // row_shr:4
+    v *= dpp_or<0x118, 0xf>(v, 1.0f);  // row_shr:8
+    v *= dpp_or<0x142, 0xa>(v, 1.0f);  // row_bcast:15 into rows 1 and 3
+    v *= dpp_or<0x143, 0xc>(v, 1.0f);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+__device__ __forceinline__ float wave_incl_sum(float v) {
+    v += dpp_or<0x111, 0xf>(v, 0.0f);
+    v += dpp_or<0x112, 0xf>(v, 0.0f);
+    v += dpp_or<0x114, 0xf>(v, 0.0f);
+    v += dpp_or<0x118, 0xf>(v, 0.0f);
+    v += dpp_or<0x142, 0xa>(v, 0.0f);
+    v += dpp_or<0x143, 0xc>(v, 0.0f);
+    return v;
+}
+__device__ __forceinline__ float rdl(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ float wrl(float v, int lane, float old) { return __lane_id() == lane ? v : old; }
+
+// Backward, Gaussian-major.  The tile's instances up to the deepest pixel's last contributor are
+// staged back to front in batches of 256 and cut into chunks of 64.  Within a chunk, lane l
+// holds the Gaussian at chunk slot 63-l (lane 0 = deepest), and each wave walks its own 64
+// pixels: for one pixel, every lane evaluates its Gaussian, a wave-wide inclusive product scan
+// of (1 - a) recovers the transmittance in front of each Gaussian from the pixel's transmittance
+// behind the chunk, and an inclusive sum scan of w (dL/dC . c + dL/dD z) gives the colour behind
+// it.  Gradients accumulate in the lanes' registers across pixels, so the only reductions are
+// one 4-wave LDS sum per chunk and one atomic per (tile, Gaussian, component).
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
@@ -124,6 +161,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                                                     float *__restrict__ dsplat) {
     __shared__ float4 sA[256], sB[256], sC[256];
     __shared__ uint32_t sG[256];
+    __shared__ float sRed[4][10][64];
     __shared__ uint32_t s_max;
     const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
     const int v = item / T, tile = item % T;
@@ -134,6 +172,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
     const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
     const double ox = (double)bx, oy = (double)by;
+    // per-pixel state, one pixel per lane (read by the wave with readlane)
     const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;
     const int64_t P = (int64_t)W * H;
     const int64_t pix = (int64_t)py * W + px;
@@ -148,14 +187,16 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
         if (dLddepth) GD = dLddepth[(int64_t)v * P + pix];
     }
     const gsr_camera &cam = cams[v];
-    // S = sum over later contributors of w_j (G . c_j + GD z_j) plus the background term
+    // S = sum over contributors behind of w_j (dL/dC . c_j + dL/dD z_j) plus the background term
     float S = Tr * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
     if (mylast) atomicMax(&s_max, mylast);
     __syncthreads();
     const uint32_t nl = min(s_max, end - start);
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
     const float kap = (float)GSR_KAPPA;
+    const float ln2 = (float)GSR_LN2;
     for (int bend = (int)nl; bend > 0; bend -= 256) {
         const int b0 = bend > 256 ? bend - 256 : 0;
         const int cnt = bend - b0;
@@ -170,53 +211,69 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
             sG[threadIdx.x] = gid;
         }
         __syncthreads();
-        for (int j = cnt - 1; j >= 0; j--) {
-            float g[10];
+        for (int k = (cnt - 1) >> 6; k >= 0; k--) {
+            const int slot = k * 64 + 63 - lane;
+            const bool gvalid = slot < cnt;
+            const float4 A = gvalid ? sA[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 B = gvalid ? sB[slot] : make_float4(0.f, -1.f, 0.f, 0.f);
+            const float4 C = gvalid ? sC[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const uint32_t pos = (uint32_t)(b0 + slot);
+            const uint32_t cbase = (uint32_t)(b0 + k * 64);
+            float acc[10];
 #pragma unroll
-            for (int e = 0; e < 10; e++) g[e] = 0.f;
-            bool contrib = false;
-            if ((uint32_t)(b0 + j) < mylast) {
-                const float4 A = sA[j];
-                const float4 B = sB[j];
+            for (int e = 0; e < 10; e++) acc[e] = 0.f;
+            for (int p = 0; p < 64; p++) {
+                const uint32_t lastp = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
+                if (cbase >= lastp) continue;
+                const float pfx = rdl(fx, p), pfy = rdl(fy, p);
                 float dx, dy, u1, u2;
-                const float Pw = blend_exponent(A, B.x, fx, fy, dx, dy, u1, u2);
-                if (Pw <= B.y) {
-                    contrib = true;
-                    const float e2 = __builtin_amdgcn_exp2f(-Pw);
-                    const float ar = B.z * e2;
-                    const float a = fminf(ar, GSR_ALPHA_MAX);
-                    const float om = 1.0f - a;
-                    const float Tk = Tr / om;  // transmittance in front of this contributor
-                    const float wgt = a * Tk;
-                    const float4 C = sC[j];
-                    const float gsum = G0 * C.x + G1 * C.y + G2 * C.z + GD * B.w;
-                    const float dLda = Tk * gsum - S / om;
-                    S = __builtin_fmaf(wgt, gsum, S);
-                    Tr = Tk;
-                    g[6] = G0 * wgt;
-                    g[7] = G1 * wgt;
-                    g[8] = G2 * wgt;
-                    g[9] = GD * wgt;
+                const float Pw = blend_exponent(A, B.x, pfx, pfy, dx, dy, u1, u2);
+                const bool act = gvalid && pos < lastp && Pw <= B.y;
+                if (__ballot(act) == 0) continue;  // no Gaussian of the chunk reaches this pixel
+                const float e2 = act ? __builtin_amdgcn_exp2f(-Pw) : 0.f;
+                const float ar = B.z * e2;
+                const float a = fminf(ar, GSR_ALPHA_MAX);
+                const float om = 1.0f - a;
+                const float Te = rdl(Tr, p), Se = rdl(S, p);
+                const float g0 = rdl(G0, p), g1 = rdl(G1, p), g2 = rdl(G2, p), gd = rdl(GD, p);
+                const float Pt = wave_incl_prod(om);
+                const float Tb = Te * __builtin_amdgcn_rcpf(Pt);  // transmittance in front of it
+                const float wgt = a * Tb;
+                const float gsum = g0 * C.x + g1 * C.y + g2 * C.z + gd * B.w;
+                const float wg = wgt * gsum;
+                const float incl = wave_incl_sum(wg);
+                const float Sa = Se + (incl - wg);  // everything behind it
+                const float dLda = Tb * gsum - Sa * __builtin_amdgcn_rcpf(om);
+                if (act) {
+                    acc[6] = __builtin_fmaf(g0, wgt, acc[6]);
+                    acc[7] = __builtin_fmaf(g1, wgt, acc[7]);
+                    acc[8] = __builtin_fmaf(g2, wgt, acc[8]);
+                    acc[9] = __builtin_fmaf(gd, wgt, acc[9]);
                     if (ar <= GSR_ALPHA_MAX) {
                         // alpha_raw = o 2^-P: d/dP = -ln2 alpha_raw, d/do = 2^-P
-                        const float dP = -(float)GSR_LN2 * ar * dLda;
-                        g[0] = -2.0f * dP * (A.z * u1);
-                        g[1] = -2.0f * dP * (A.w * u1 + B.x * u2);
-                        g[2] = dP * kap * dx * dx;
-                        g[3] = dP * 2.0f * kap * dx * dy;
-                        g[4] = dP * kap * dy * dy;
-                        g[5] = dLda * e2;
+                        const float dP = -ln2 * ar * dLda;
+                        acc[0] -= 2.0f * dP * (A.z * u1);
+                        acc[1] -= 2.0f * dP * (A.w * u1 + B.x * u2);
+                        acc[2] += dP * kap * dx * dx;
+                        acc[3] += dP * 2.0f * kap * dx * dy;
+                        acc[4] += dP * kap * dy * dy;
+                        acc[5] = __builtin_fmaf(dLda, e2, acc[5]);
                     }
                 }
+                // the pixel's state in front of this chunk (lane 63 holds the frontmost slot)
+                Tr = wrl(rdl(Tb, 63), p, Tr);
+                S = wrl(Se + rdl(incl, 63), p, S);
             }
-            if (__ballot(contrib)) {
-                const uint32_t gid = sG[j];
 #pragma unroll
-                for (int e = 0; e < 10; e++) {
-                    const float s = wave_sum(g[e]);
-                    if (__lane_id() == 0 && s != 0.f) atomicAdd(dsplat + (int64_t)gid * 10 + e, s);
-                }
+            for (int e = 0; e < 10; e++) sRed[w][e][63 - lane] = acc[e];
+            __syncthreads();
+            for (int q = threadIdx.x; q < 640; q += 256) {
+                const int e = q >> 6, j = q & 63;
+                const float sum = sRed[0][e][j] + sRed[1][e][j] + sRed[2][e][j] + sRed[3][e][j];
+                const int sl = k * 64 + j;
+                if (sl < cnt && sum != 0.f) atomicAdd(dsplat + (int64_t)sG[sl] * 10 + e, sum);
             }
+            __syncthreads();
         }
     }
 }
