@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--points", type=int, default=1_500_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -86,6 +88,15 @@ def cpu_baseline(c, pool_cams, tg):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        import torch
+        x = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes)",
               file=sys.stderr)
@@ -207,7 +218,7 @@ def main():
     gsr.project(opt.P, opt.sh_degree, opt.cams, V, opt.raster, r.splats, r.tile_info)
     r.bin(True)
     gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, opt.cams, V, opt.raster, r.rgb, r.depth, r.T_final, r.last,
-                   ncon)
+                   ncon, tile_order=r.tile_order)
     torch.cuda.synchronize()
     blends = int(ncon.sum().item())
     M = r.instances()

@@ -131,13 +131,16 @@ GSR_API gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams, i
  * *n_instances (device uint32: the REQUIRED instance count M).  If M > capacity nothing
  * beyond capacity is written and the results are incomplete: the caller compares
  * *n_instances with capacity after synchronising and re-runs with more room.
+ * tile_order (device uint32 [V*T], may be NULL) receives the view-tiles sorted by descending
+ * instance count (ties by index): the longest-processing-time-first launch order the render
+ * kernels use to keep heavy tiles off the tail of the grid.
  * ws: device workspace of at least gsr_bin_sort_workspace(n, n_views, capacity, r) bytes,
  * 256-byte aligned.  Errors: GSR_E_INVALID (bad pointers or sizes, capacity >= 2^32),
  * GSR_E_CAPACITY (ws_bytes too small). */
 GSR_API size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t capacity, const gsr_raster *r);
 GSR_API gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
                         uint32_t *inst_gid, int64_t capacity, uint32_t *tile_ranges, uint32_t *n_instances,
-                        void *ws, size_t ws_bytes, gsr_stream stream);
+                        uint32_t *tile_order, void *ws, size_t ws_bytes, gsr_stream stream);
 
 /* ---- render forward --------------------------------------------------------------------------
  * Front-to-back alpha compositing per pixel (Sec. III-C; Eq. 8).  For each view-tile's
@@ -146,9 +149,10 @@ GSR_API gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_
  * Outputs (images [V][...][H][W]): rgb [V][3][H][W] = C + T bg, depth [V][H][W] = D (no
  * background term), T_final [V][H][W], last [V][H][W] = number of the tile's instances up to
  * and including the pixel's last composited one (the backward re-walks exactly these), and,
- * if n_contrib is not NULL, n_contrib [V][H][W] = the number of composited Gaussians. */
+ * if n_contrib is not NULL, n_contrib [V][H][W] = the number of composited Gaussians.
+ * tile_order (from gsr_bin_sort, may be NULL = natural order) only sets the launch order. */
 GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
-                          const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb, float *depth,
+                          const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb, float *depth,
                           float *T_final, uint32_t *last, uint32_t *n_contrib, gsr_stream stream);
 
 /* ---- render backward -------------------------------------------------------------------------
@@ -158,7 +162,7 @@ GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_
  * every (view, Gaussian) into dsplat [V*n][10] (layout GSR_SPLAT_GRAD_FLOATS; the caller
  * zeroes it).  Float atomics make the summation order, not the result, run-dependent. */
 GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
-                          const gsr_camera *cams, int32_t n_views, const gsr_raster *r, const float *T_final,
+                          const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r, const float *T_final,
                           const uint32_t *last, const float *dL_drgb, const float *dL_ddepth, float *dsplat,
                           gsr_stream stream);
 

@@ -104,22 +104,24 @@ def bin_sort_workspace(n, n_views, capacity, raster):
     return int(lib().gsr_bin_sort_workspace(n, n_views, capacity, C.byref(raster.c)))
 
 
-def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_instances, ws):
+def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_instances, ws, tile_order=None):
     check(lib().gsr_bin_sort(_ptr(tile_info), n, n_views, C.byref(raster.c), _ptr(inst_gid), capacity,
-                             _ptr(tile_ranges), _ptr(n_instances), _ptr(ws), ws.numel() * ws.element_size(),
-                             _stream()), "gsr_bin_sort")
+                             _ptr(tile_ranges), _ptr(n_instances), _ptr(tile_order), _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream()), "gsr_bin_sort")
 
 
-def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last, n_contrib=None):
-    check(lib().gsr_render_fwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(cams), n_views,
-                               C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
+def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last, n_contrib=None,
+               tile_order=None):
+    check(lib().gsr_render_fwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
+                               n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
                                _ptr(n_contrib), _stream()), "gsr_render_fwd")
 
 
-def render_bwd(splats, inst_gid, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth, dsplat):
-    check(lib().gsr_render_bwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(cams), n_views,
-                               C.byref(raster.c), _ptr(T_final), _ptr(last), _ptr(dL_drgb), _ptr(dL_ddepth),
-                               _ptr(dsplat), _stream()), "gsr_render_bwd")
+def render_bwd(splats, inst_gid, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth, dsplat,
+               tile_order=None):
+    check(lib().gsr_render_bwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
+                               n_views, C.byref(raster.c), _ptr(T_final), _ptr(last), _ptr(dL_drgb),
+                               _ptr(dL_ddepth), _ptr(dsplat), _stream()), "gsr_render_bwd")
 
 
 def project_bwd_workspace(n, n_views):
@@ -178,6 +180,7 @@ class Rasterizer:
         self.splats = torch.empty(VN * 12, dtype=f32, device=device)
         self.tile_info = torch.empty(4 * VN, dtype=i32, device=device)
         self.tile_ranges = torch.empty(2 * self.V * raster.tiles, dtype=i32, device=device)
+        self.tile_order = torch.empty(self.V * raster.tiles, dtype=i32, device=device)
         self.n_instances = torch.zeros(1, dtype=i32, device=device)
         P = raster.width * raster.height
         self.rgb = torch.empty(self.V, 3, raster.height, raster.width, dtype=f32, device=device)
@@ -202,18 +205,18 @@ class Rasterizer:
         project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
         self.bin(check_capacity)
         render_fwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb, self.depth,
-                   self.T_final, self.last)
+                   self.T_final, self.last, tile_order=self.tile_order)
         return self.rgb, self.depth, self.T_final
 
     def bin(self, check_capacity=True):
         bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity, self.tile_ranges,
-                 self.n_instances, self.bin_ws)
+                 self.n_instances, self.bin_ws, self.tile_order)
         if check_capacity:
             m = int(self.n_instances.item()) & 0xFFFFFFFF
             if m > self.capacity:
                 self._alloc_instances(int(m * 1.25) + 1024)
                 bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity,
-                         self.tile_ranges, self.n_instances, self.bin_ws)
+                         self.tile_ranges, self.n_instances, self.bin_ws, self.tile_order)
 
     def instances(self):
         return int(self.n_instances.item()) & 0xFFFFFFFF
@@ -223,7 +226,8 @@ class Rasterizer:
         """render bwd -> project bwd; parameter gradients are accumulated into grads.  The
         screen-space gradient buffer is consumed (left zeroed) by project bwd."""
         render_bwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.T_final, self.last,
-                   dL_drgb.contiguous(), dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dsplat)
+                   dL_drgb.contiguous(), dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dsplat,
+                   tile_order=self.tile_order)
         if self.keep_dsplat:
             self.dsplat_copy = self.dsplat.clone()
         project_bwd(P, sh_degree, cams, self.V, self.raster, self.dsplat, grads,

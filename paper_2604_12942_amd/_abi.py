@@ -48,9 +48,9 @@ _SIGS = {
     "gsr_tiles_per_view": ([C.POINTER(Raster)], C.c_int64),
     "gsr_project": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, P], C.c_int),
     "gsr_bin_sort_workspace": ([C.c_int64, C.c_int32, C.c_int64, C.POINTER(Raster)], C.c_size_t),
-    "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.c_int64, P, P, P, C.c_size_t, P], C.c_int),
-    "gsr_render_fwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
-    "gsr_render_bwd": ([P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.c_int64, P, P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_render_fwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_render_bwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
     "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
     "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, C.POINTER(ParamGrads), P, P, P,
                          C.c_int32, P, P, C.c_size_t, P], C.c_int),

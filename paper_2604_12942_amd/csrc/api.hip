@@ -8,13 +8,13 @@ extern "C" gsr_status gsr_project_launch(const gsr_gaussians *, const gsr_camera
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
                                              float *, const gsr_param_grads *, double *, const uint32_t *,
                                              const int32_t *, int32_t, uint8_t *, void *, hipStream_t);
-extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap);
+extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT);
 extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, int64_t, uint32_t *,
-                                          uint32_t *, void *, hipStream_t);
-extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
+                                          uint32_t *, uint32_t *, void *, hipStream_t);
+extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
                                             uint32_t *, uint32_t *, hipStream_t);
-extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
+extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, const float *,
                                             const uint32_t *, const float *, const float *, float *, hipStream_t);
 extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const uint8_t *, float, float, float, int,
@@ -22,6 +22,7 @@ extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const ui
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
                                          int, const gsr_raster *, float, double *, float *, float *, hipStream_t);
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+extern "C" gsr_status gsr_tile_order_identity(uint32_t *, int64_t, hipStream_t);
 
 namespace {
 
@@ -69,49 +70,55 @@ extern "C" gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams
 }
 
 extern "C" size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t capacity, const gsr_raster *r) {
-    (void)r;
-    if (n < 0 || n_views < 1 || capacity < 0) return 0;
-    return gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity);
+    if (n < 0 || n_views < 1 || capacity < 0 || !raster_ok(r)) return 0;
+    return gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity, (int64_t)n_views * tiles(r));
 }
 
 extern "C" gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
                                    uint32_t *inst_gid, int64_t capacity, uint32_t *tile_ranges,
-                                   uint32_t *n_instances, void *ws, size_t ws_bytes, gsr_stream stream) {
+                                   uint32_t *n_instances, uint32_t *tile_order, void *ws, size_t ws_bytes,
+                                   gsr_stream stream) {
     if (!raster_ok(r) || n < 0 || n_views < 1 || capacity < 1 || capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
     if ((int64_t)n_views * n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
     if (!tile_info && n > 0) return GSR_E_INVALID;
     if (!inst_gid || !tile_ranges || !n_instances || !ws) return GSR_E_INVALID;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
-    if (ws_bytes < gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity)) return GSR_E_CAPACITY;
+    if (ws_bytes < gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity, (int64_t)n_views * tiles(r)))
+        return GSR_E_CAPACITY;
     if ((int64_t)n_views * tiles(r) > (int64_t)(1u << 24)) return GSR_E_UNSUPPORTED;
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     if (n == 0) {
         gsr_status s = gsr_fill_u32_launch(tile_ranges, 0u, 2 * (int64_t)n_views * ntx * nty, S(stream));
         if (s != GSR_OK) return s;
+        if (tile_order) {
+            // no instances: any order of the view-tiles; identity
+            s = gsr_tile_order_identity(tile_order, (int64_t)n_views * ntx * nty, S(stream));
+            if (s != GSR_OK) return s;
+        }
         return gsr_fill_u32_launch(n_instances, 0u, 1, S(stream));
     }
-    return gsr_bin_sort_launch(tile_info, n, n_views, ntx, nty, inst_gid, capacity, tile_ranges, n_instances, ws,
-                               S(stream));
+    return gsr_bin_sort_launch(tile_info, n, n_views, ntx, nty, inst_gid, capacity, tile_ranges, n_instances,
+                               tile_order, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
-                                     const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb,
+                                     const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb,
                                      float *depth, float *T_final, uint32_t *last, uint32_t *n_contrib,
                                      gsr_stream stream) {
     if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !rgb || !depth || !T_final || !last)
         return GSR_E_INVALID;
-    return gsr_render_fwd_launch(splats, inst_gid, tile_ranges, cams, n_views, r, rgb, depth, T_final, last,
-                                 n_contrib, S(stream));
+    return gsr_render_fwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, rgb, depth, T_final,
+                                 last, n_contrib, S(stream));
 }
 
 extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
-                                     const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
+                                     const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
                                      const float *T_final, const uint32_t *last, const float *dL_drgb,
                                      const float *dL_ddepth, float *dsplat, gsr_stream stream) {
     if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !T_final || !last || !dL_drgb || !dsplat)
         return GSR_E_INVALID;
-    return gsr_render_bwd_launch(splats, inst_gid, tile_ranges, cams, n_views, r, T_final, last, dL_drgb, dL_ddepth,
-                                 dsplat, S(stream));
+    return gsr_render_bwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, T_final, last, dL_drgb,
+                                 dL_ddepth, dsplat, S(stream));
 }
 
 extern "C" gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,

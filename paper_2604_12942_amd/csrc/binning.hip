@@ -244,6 +244,16 @@ __global__ __launch_bounds__(256) void k_inst_emit(const uint32_t *__restrict__ 
     }
 }
 
+// LPT key of every view-tile: descending instance count (ascending 0xffff - count), ties by index
+__global__ void k_tile_keys(const uint32_t *__restrict__ ranges, uint32_t VT, uint32_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT; i += gridDim.x * blockDim.x) {
+        const uint32_t c = ranges[2 * i + 1] - ranges[2 * i];
+        keys[i] = 0xffffu - (c < 0xffffu ? c : 0xffffu);
+        vals[i] = i;
+    }
+}
+
 __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_inst, uint32_t cap,
                               uint32_t *__restrict__ ranges) {
     const uint32_t m = dev_count(n_inst, 0, cap);
@@ -265,6 +275,7 @@ struct BinWs {
     uint32_t *vis_b, *cnt_b;          // block sums [nb_vn]
     uint32_t *n_vis;                  // 1
     uint32_t *ik0, *ik1, *iv1;        // instance sort [cap]
+    uint32_t *tk0, *tk1, *tv1;        // tile-order sort [VT]
     uint32_t *hist;                   // [256][max nb]
     uint32_t *totals;                 // [256]
     size_t bytes;
@@ -272,10 +283,12 @@ struct BinWs {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-BinWs layout(void *base, int64_t VN, int64_t cap) {
+BinWs layout(void *base, int64_t VN, int64_t cap, int64_t VT) {
     BinWs w{};
     const int64_t nb_vn = ceil_div(VN > 0 ? VN : 1, kSortTile), nb_cap = ceil_div(cap > 0 ? cap : 1, kSortTile);
-    const int64_t nbm = nb_vn > nb_cap ? nb_vn : nb_cap;
+    const int64_t nb_vt = ceil_div(VT > 0 ? VT : 1, kSortTile);
+    int64_t nbm = nb_vn > nb_cap ? nb_vn : nb_cap;
+    nbm = nbm > nb_vt ? nbm : nb_vt;
     char *p = static_cast<char *>(base);
     size_t off = 0;
     auto take = [&](size_t words) {
@@ -286,18 +299,19 @@ BinWs layout(void *base, int64_t VN, int64_t cap) {
     w.zk0 = take(VN); w.zv0 = take(VN); w.zk1 = take(VN); w.zv1 = take(VN);
     w.vis_b = take(nb_vn); w.cnt_b = take(nb_vn); w.n_vis = take(1);
     w.ik0 = take(cap); w.ik1 = take(cap); w.iv1 = take(cap);
+    w.tk0 = take(VT); w.tk1 = take(VT); w.tv1 = take(VT);
     w.hist = take((size_t)kRadix * nbm); w.totals = take(kRadix);
     w.bytes = off;
     return w;
 }
 
-gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, const uint32_t *n_dev, uint32_t cap,
-                      int bits, uint32_t *hist, uint32_t *totals, hipStream_t st) {
+gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, const uint32_t *n_dev,
+                      uint32_t n_host, uint32_t cap, int bits, uint32_t *hist, uint32_t *totals, hipStream_t st) {
     const int nb = (int)ceil_div(cap, kSortTile);
     for (int shift = 0; shift < bits; shift += kRadixBits) {
-        k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, 0, cap, shift, nb, hist);
+        k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, n_host, cap, shift, nb, hist);
         k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals);
-        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, n_dev, 0, cap, shift, nb, hist, totals);
+        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, n_dev, n_host, cap, shift, nb, hist, totals);
         uint32_t *tk = k, *tv = v;
         k = k2; v = v2; k2 = tk; v2 = tv;
     }
@@ -312,14 +326,15 @@ int bit_length(uint64_t x) {
 
 }  // namespace
 
-extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap) { return layout(nullptr, VN, cap).bytes; }
+extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT) { return layout(nullptr, VN, cap, VT).bytes; }
 
 extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V, int ntx, int nty,
                                           uint32_t *inst_gid, int64_t cap, uint32_t *ranges, uint32_t *n_inst,
-                                          void *ws, hipStream_t st) {
+                                          uint32_t *tile_order, void *ws, hipStream_t st) {
     const int64_t VN = (int64_t)V * n;
     const uint32_t T = (uint32_t)(ntx * nty);
-    BinWs w = layout(ws, VN, cap);
+    const int64_t VT = (int64_t)V * T;
+    BinWs w = layout(ws, VN, cap, VT);
     const int nb_vn = (int)ceil_div(VN > 0 ? VN : 1, kSortTile);
     // 1. ordered compaction of visible pairs: keys = depth bits, values = v*n + i
     k_vis_count<<<nb_vn, 256, 0, st>>>(info, (uint32_t)VN, w.vis_b);
@@ -327,7 +342,7 @@ extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V
     k_vis_compact<<<nb_vn, 256, 0, st>>>(info, (uint32_t)VN, w.vis_b, w.zk0, w.zv0);
     // 2. stable sort by depth bits (32 bits, 4 passes: result back in zk0 / zv0)
     uint32_t *k = w.zk0, *v = w.zv0, *k2 = w.zk1, *v2 = w.zv1;
-    gsr_status s = radix_sort(k, v, k2, v2, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), 32, w.hist, w.totals, st);
+    gsr_status s = radix_sort(k, v, k2, v2, w.n_vis, 0, (uint32_t)(VN > 0 ? VN : 1), 32, w.hist, w.totals, st);
     if (s != GSR_OK) return s;
     // 3. instance counts in depth order, scan, emission
     k_inst_count<<<nb_vn, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, w.cnt_b);
@@ -341,13 +356,21 @@ extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V
     k_inst_emit<<<nb_vn, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, (uint32_t)VN, (uint32_t)n, T,
                                        (uint32_t)ntx, w.cnt_b, ek, ev, (uint32_t)cap);
     // 4. stable sort by view-tile
-    s = radix_sort(ek, ev, ok, ov, n_inst, (uint32_t)cap, passes * kRadixBits, w.hist, w.totals, st);
+    s = radix_sort(ek, ev, ok, ov, n_inst, 0, (uint32_t)cap, passes * kRadixBits, w.hist, w.totals, st);
     if (s != GSR_OK) return s;
     // 5. per view-tile [start, end)
     k_fill_u32<<<(int)ceil_div(2 * (int64_t)V * T, 256) < 4096 ? (int)ceil_div(2 * (int64_t)V * T, 256) : 4096, 256, 0,
                  st>>>(ranges, 0u, 2 * (int64_t)V * T);
     const int nr = (int)(ceil_div(cap, 256) < 8192 ? ceil_div(cap, 256) : 8192);
     k_tile_ranges<<<nr, 256, 0, st>>>(ek, n_inst, (uint32_t)cap, ranges);
+    // 6. longest-processing-time order of the view-tiles (descending instance count)
+    if (tile_order) {
+        const int nt = (int)(ceil_div(VT, 256) < 4096 ? ceil_div(VT, 256) : 4096);
+        k_tile_keys<<<nt, 256, 0, st>>>(ranges, (uint32_t)VT, w.tk0, tile_order);
+        uint32_t *a = w.tk0, *b = tile_order, *c = w.tk1, *d = w.tv1;
+        s = radix_sort(a, b, c, d, nullptr, (uint32_t)VT, (uint32_t)VT, 16, w.hist, w.totals, st);
+        if (s != GSR_OK) return s;
+    }
     return last_launch();
 }
 
@@ -355,5 +378,17 @@ extern "C" gsr_status gsr_fill_u32_launch(void *dst, uint32_t value, int64_t n, 
     if (n <= 0) return GSR_OK;
     const int nb = (int)(ceil_div(n, 256) < 8192 ? ceil_div(n, 256) : 8192);
     k_fill_u32<<<nb, 256, 0, st>>>(static_cast<uint32_t *>(dst), value, n);
+    return last_launch();
+}
+
+__global__ void k_iota_u32(uint32_t *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (uint32_t)i;
+}
+
+extern "C" gsr_status gsr_tile_order_identity(uint32_t *dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return GSR_OK;
+    const int nb = (int)(ceil_div(n, 256) < 4096 ? ceil_div(n, 256) : 4096);
+    k_iota_u32<<<nb, 256, 0, st>>>(dst, n);
     return last_launch();
 }

@@ -76,7 +76,7 @@ class MapOptimizer:
         r.bin(check_capacity)
         mark("bin_sort")
         render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth, r.T_final,
-                   r.last)
+                   r.last, tile_order=r.tile_order)
         mark("render_fwd")
         self.loss.zero_()
         loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
@@ -84,7 +84,8 @@ class MapOptimizer:
                 target_index=self.view_idx32)
         mark("loss")
         render_bwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.T_final, r.last,
-                   self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dsplat)
+                   self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dsplat,
+                   tile_order=r.tile_order)
         mark("render_bwd")
         project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.dsplat, self.grads, r.dpose,
                     r.pose_ws, r.tile_info, self.segment_id, self.min_segment, self.row_mask)
