@@ -30,6 +30,30 @@ FP32_PEAK_TFLOPS = 157.3
 # algorithmic float operations per composited (pixel, Gaussian) pair
 FLOP_PER_BLEND_FWD = 23
 FLOP_PER_BLEND_BWD = 48
+# the kernel each timed stage launches (its name in rocprofv3 kernel traces)
+KERNEL_OF_STAGE = dict(project="k_project", bin_sort="gsr_bin_sort (11 kernels)", render_fwd="k_render_fwd",
+                       loss="k_loss_l1", render_bwd="k_render_bwd", project_bwd="k_project_bwd")
+# HBM bytes per launch of a kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counters on this
+# workload, each scaled by the counter's reading for a 256 MiB device copy (fetch x1.9997, write x1.0);
+# keyed by (kernel, tile), with the SHA-256 prefix of the kernel's sources at measurement time: a
+# figure whose sources have changed since is reported as null.
+TRAFFIC = {("k_render_bwd", "8x32"): (5356241813, "8570516a2f3a930b")}
+KERNEL_SOURCES = {"k_render_bwd": ["csrc/gsr_internal.h", "csrc/render.hip"],
+                  "k_render_fwd": ["csrc/gsr_internal.h", "csrc/render.hip"],
+                  "k_project_bwd": ["csrc/gsr_internal.h", "csrc/project.hip"]}
+
+
+def traffic_of(kernel, tile):
+    """Measured HBM bytes per launch, or None when unmeasured or measured on other sources."""
+    import hashlib
+    ent = TRAFFIC.get((kernel, tile))
+    if ent is None or kernel not in KERNEL_SOURCES:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2604_12942_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return ent[0] if h.hexdigest()[:16] == ent[1] else None
 
 
 def parse():
@@ -68,22 +92,24 @@ def views_for_step(step):
     return np.concatenate([rng.choice(8, 4, replace=False), 8 + rng.choice(8, 4, replace=False)])
 
 
-def cpu_baseline(c, pool_cams, tg):
-    """FP64 oracle on one of the 8 views of a step (forward + backward over all 1.5M Gaussians at
-    1280x720), scaled to a whole step."""
+def cpu_baseline(c, pool_cams, tg, step_views, n_sample=4):
+    """FP64 oracle on n_sample of the 8 views of one step (forward + L1 loss + backward incl. pose,
+    over all Gaussians at full resolution), scaled to a whole step."""
     import oracle
     oracle.lib()
     g = c["gaussians"]
-    cam = pool_cams[0]
     t0 = time.perf_counter()
-    r = oracle.render(g, cam)
-    _, gC, gD = oracle.l1_loss(r["rgb"], r["depth"], tg[0][0], tg[0][1], 0.2)
-    oracle.render_bwd(g, cam, gC, gD)
+    for k in step_views[:n_sample]:
+        cam = pool_cams[k]
+        r = oracle.render(g, cam)
+        _, gC, gD = oracle.l1_loss(r["rgb"], r["depth"], tg[k][0], tg[k][1], 0.2)
+        oracle.render_bwd(g, cam, gC, gD)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=1.0 / (8.0 * dt), unit="iters/s", cores=threads, kind="oracle",
-                sample="1 of 8 views of one step (forward + L1 loss + backward incl. pose, all %d Gaussians, "
-                       "1280x720), %.1f s, scaled x8 views" % (g["means"].shape[1], dt))
+    V = len(step_views)
+    return dict(value=round(n_sample / (V * dt), 5), unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+                sample="%d of the %d views of one step (forward + L1 loss + backward incl. pose, all %d Gaussians, "
+                       "%dx%d), %.1f s, scaled to %d views" % (n_sample, V, g["means"].shape[1], pool_cams[0]["width"],
+                                                              pool_cams[0]["height"], dt, V))
 
 
 def main():
@@ -129,12 +155,13 @@ def main():
                             min_segment=min_seg, device=dev)
 
     # the view schedule of every step, resident on the device (no host round-trip per step)
-    sched = torch.from_numpy(np.stack([views_for_step(s) for s in range(a.warmup + a.steps)] +
+    n_main = max(a.warmup + a.steps, 10)
+    sched = torch.from_numpy(np.stack([views_for_step(s) for s in range(n_main)] +
                                       [views_for_step(10_000 + s) for s in range(2)] +
                                       [views_for_step(10_100 + s) for s in range(3)])).to(dev)
-    row_of = {s: s for s in range(a.warmup + a.steps)}
-    row_of.update({10_000 + s: a.warmup + a.steps + s for s in range(2)})
-    row_of.update({10_100 + s: a.warmup + a.steps + 2 + s for s in range(3)})
+    row_of = {s: s for s in range(n_main)}
+    row_of.update({10_000 + s: n_main + s for s in range(2)})
+    row_of.update({10_100 + s: n_main + 2 + s for s in range(3)})
 
     def sv(o, step):
         o.set_views(sched[row_of[step]])
@@ -166,6 +193,31 @@ def main():
     print("tile autotune (s/step): %s -> %dx%d" % (tune, *tile), file=sys.stderr, flush=True)
 
     opt = make_opt(tile)
+    stages = ["gather", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "adam"]
+    stream = torch.cuda.current_stream()
+
+    def staged_steps(o, k, first_step, stage_pair=None):
+        """k steps with HIP events on the launch stream: after every stage, or (stage_pair =
+        (before, stage)) only around one stage.  Returns per-stage ms summed over the steps."""
+        recs = []
+        for s in range(k):
+            evs = {}
+
+            def mark(name, evs=evs):
+                if stage_pair is None or name in stage_pair:
+                    e = torch.cuda.Event(enable_timing=True)
+                    e.record(stream)
+                    evs[name] = e
+
+            e0 = torch.cuda.Event(enable_timing=True)
+            if stage_pair is None:
+                e0.record(stream)
+            sv(o, first_step + s)
+            o.step(check_capacity=False, timer=mark)
+            recs.append((e0, evs))
+        return recs
+
+    opt = make_opt(tile)
     # warmup with capacity checks (instance buffer grows to fit), then fix the capacity
     m_max = 0
     for s in range(a.warmup):
@@ -175,41 +227,35 @@ def main():
     if opt.rast.capacity < int(m_max * 1.3):
         opt.rast._alloc_instances(int(m_max * 1.3))
 
-    # timed region: K steps, per-stage HIP events on the launch stream
-    stream = torch.cuda.current_stream()
-    stages = ["gather", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "adam"]
-    ev = []
+    # per-stage breakdown (its own pass: events between every stage perturb the wall clock)
+    recs = staged_steps(opt, max(3, min(a.steps, 10)), 0)
+    torch.cuda.synchronize()
+    stage_ms = {k: 0.0 for k in stages}
+    for e0, evs in recs:
+        prev = e0
+        for k in stages:
+            stage_ms[k] += prev.elapsed_time(evs[k])
+            prev = evs[k]
+    stage_ms = {k: v / len(recs) for k, v in stage_ms.items()}
+    dom = max(stage_ms, key=stage_ms.get)
+    before = stages[stages.index(dom) - 1]
+
+    # timed region: K steps; HIP events only around the dominant kernel's stage
     m_seen = torch.zeros(a.steps, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    recs = []
     for s in range(a.steps):
-        e_start = torch.cuda.Event(enable_timing=True)
-        e_start.record(stream)
-        evs = {}
-
-        def mark(name, evs=evs):
-            e = torch.cuda.Event(enable_timing=True)
-            e.record(stream)
-            evs[name] = e
-
-        sv(opt, a.warmup + s)
-        opt.step(check_capacity=False, timer=mark)
+        recs += staged_steps(opt, 1, a.warmup + s, stage_pair=(before, dom))
         m_seen[s:s + 1].copy_(opt.rast.n_instances)
-        ev.append((e_start, evs))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / a.steps
+    dom_ms = sum(evs[before].elapsed_time(evs[dom]) for _, evs in recs) / a.steps
     m_all = m_seen.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
     if m_all.max() > opt.rast.capacity:
         print("instance capacity exceeded in the timed region", file=sys.stderr)
         sys.exit(3)
-    stage_ms = {k: 0.0 for k in stages}
-    for e_start, evs in ev:
-        prev = e_start
-        for k in stages:
-            stage_ms[k] += prev.elapsed_time(evs[k])
-            prev = evs[k]
-    stage_ms = {k: v / a.steps for k, v in stage_ms.items()}
 
     # workload statistics of one representative step (same views as the last timed step)
     sv(opt, a.warmup + a.steps - 1)
@@ -236,20 +282,23 @@ def main():
              adam=Nu * 4 * Pf * 8)
     B_alg = sum(B.values())
     step_s = ms_per_step / 1000.0
-    dom = max(stage_ms, key=stage_ms.get)
+    kname = KERNEL_OF_STAGE[dom]
     if dom in ("render_fwd", "render_bwd"):
         fl = blends * (FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
-        ach = fl / (stage_ms[dom] / 1000.0) / 1e12
+        ach = fl / (dom_ms / 1000.0) / 1e12
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None, kernel=dom)
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
+                    kernel=kname, launch_ms=round(dom_ms, 4), units_per_launch=blends, unit_kind="blend",
+                    flop_per_unit=FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
     else:
-        ach = B[dom] / (stage_ms[dom] / 1000.0) / 1e9
+        ach = B[dom] / (dom_ms / 1000.0) / 1e9
         roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=dom)
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
+                    kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(c, pool_cams, tg)
+        cpu = cpu_baseline(c, pool_cams, tg, views_for_step(a.warmup + a.steps - 1))
 
     out = {
         "metric": "fwd+bwd iters/s @1.5M Gaussians, 8x720p",

@@ -170,7 +170,9 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
  * Chain rule from the screen-space gradients to every parameter, summed over views, plus the
  * per-view camera-pose gradient for a left perturbation T <- Exp(xi) T, xi = (rho, phi)
  * (translation first): p -> p + rho + phi x p.  Gradients are ACCUMULATED into out;
- * dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  ws: gsr_project_bwd_workspace bytes.
+ * dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  splats: the records gsr_project wrote for
+ * these parameters (their clamped colours fix the colour clamp decisions).  ws:
+ * gsr_project_bwd_workspace bytes.
  * tile_info (as written by gsr_project, may be NULL): when given, only the pairs with
  * n_tiles > 0 are read -- the others must hold zeros, which render_bwd never changes -- and the
  * pairs read are reset to zero, so dsplat is left all-zero for the next backward.
@@ -180,9 +182,42 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
  * NULL = no freezing), else 0. */
 GSR_API size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views);
 GSR_API gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
-                           float *dsplat, const gsr_param_grads *out, double *dpose, const uint32_t *tile_info,
+                           const gsr_splat *splats, float *dsplat, const gsr_param_grads *out, double *dpose, const uint32_t *tile_info,
                            const int32_t *segment_id, int32_t min_segment, uint8_t *row_mask, void *ws,
                            size_t ws_bytes, gsr_stream stream);
+
+/* ---- project backward fused with sparse Adam ---------------------------------------------------
+ * The optimisation step's form of gsr_project_bwd followed by gsr_adam_step (Sec. III-C: visible
+ * Gaussians of the latest segments are refined by a sparse gradient optimiser): the parameter
+ * gradients never leave registers.  For every Gaussian visible in at least one view (tile_info
+ * row 0 > 0; tile_info required) whose segment_id >= min_segment (segment_id NULL = all), the
+ * Adam update of gsr_adam_step is applied IN PLACE to the parameter arrays of g, with the moments
+ * in adam->m / adam->v (same layouts), per-group learning rates adam->lr = {means, log_scales,
+ * quats, opacity_logits, sh rows 0-2 (DC), sh rows 3.. (rest)} and the 1-based step number read
+ * from device memory (*adam->step, so a captured graph can replay with an incremented step).
+ * All other rows are untouched.  dsplat is consumed (left zeroed) as in gsr_project_bwd; dpose
+ * and row_mask as in gsr_project_bwd. */
+typedef struct {
+    gsr_param_grads m, v;
+    float lr[6];
+    float beta1, beta2, eps;
+    const int32_t *step;
+} gsr_adam_fused;
+GSR_API gsr_status gsr_project_bwd_adam(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                        const gsr_raster *r, const gsr_splat *splats, float *dsplat, const uint32_t *tile_info,
+                                        const uint32_t *visible_list, const uint32_t *visible_count,
+                                        const int32_t *segment_id, int32_t min_segment, const gsr_adam_fused *adam,
+                                        double *dpose, uint8_t *row_mask, void *ws, size_t ws_bytes,
+                                        gsr_stream stream);
+
+/* Ordered list of the Gaussians visible in at least one view (tile_info row 0 > 0 for some
+ * view): list [n] receives their indices in ascending order and *count (device) their number.
+ * Passing it to gsr_project_bwd_adam (visible_list, visible_count; both or neither) makes the
+ * backward launch dense work over the visible Gaussians only; row_mask is then written for the
+ * listed rows only.  ws: gsr_visible_list_workspace(n) bytes. */
+GSR_API size_t gsr_visible_list_workspace(int64_t n);
+GSR_API gsr_status gsr_visible_list(const uint32_t *tile_info, int64_t n, int32_t n_views, uint32_t *list,
+                                    uint32_t *count, void *ws, size_t ws_bytes, gsr_stream stream);
 
 /* ---- sparse Adam -----------------------------------------------------------------------------
  * Sparse gradient optimiser of Sec. III-C (visible and unfrozen Gaussians only).  Up to 8

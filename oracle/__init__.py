@@ -58,10 +58,16 @@ def lib():
         L.orc_render_bwd.argtypes = [C.POINTER(_Gauss), C.POINTER(_Cam), P, P, P, P, P, P, P, P, P,
                                      C.c_double, P, P]
         L.orc_render_bwd.restype = C.c_int64
+        L.orc_num_threads.restype = C.c_int
         L.orc_adam.argtypes = [P, P, P, P, C.c_int64, C.c_int64, P, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int]
         _lib = L
     return _lib
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops run on."""
+    return int(lib().orc_num_threads())
 
 
 def _ptr(a):

@@ -749,3 +749,12 @@ void orc_adam(double *param, double *grad, double *m, double *v, int64_t rows, i
             grad[e] = 0;
         }
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use (1 without OpenMP). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

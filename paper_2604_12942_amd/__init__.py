@@ -128,14 +128,43 @@ def project_bwd_workspace(n, n_views):
     return int(lib().gsr_project_bwd_workspace(n, n_views))
 
 
-def project_bwd(P, sh_degree, cams, n_views, raster, dsplat, grads, dpose, ws, tile_info=None, segment_id=None,
-                min_segment=0, row_mask=None):
+def project_bwd(P, sh_degree, cams, n_views, raster, splats, dsplat, grads, dpose, ws, tile_info=None,
+                segment_id=None, min_segment=0, row_mask=None):
     g = _gauss_struct(P, sh_degree)
     gr = _abi.ParamGrads(*[grads[k].data_ptr() for k in PARAM_NAMES])
-    check(lib().gsr_project_bwd(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(dsplat), C.byref(gr),
+    check(lib().gsr_project_bwd(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(dsplat),
+                                C.byref(gr),
                                 _ptr(dpose), _ptr(tile_info), _ptr(segment_id), int(min_segment), _ptr(row_mask),
                                 _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
           "gsr_project_bwd")
+
+
+def visible_list_workspace(n):
+    return int(lib().gsr_visible_list_workspace(n))
+
+
+def visible_list(tile_info, n, n_views, out_list, out_count, ws):
+    check(lib().gsr_visible_list(_ptr(tile_info), n, n_views, _ptr(out_list), _ptr(out_count), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream()), "gsr_visible_list")
+
+
+def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dsplat, tile_info, m, v, lr, step_dev, dpose, ws,
+                     segment_id=None, min_segment=0, row_mask=None, beta1=0.9, beta2=0.999, eps=1e-15,
+                     vis_list=None, vis_count=None):
+    """Projection backward fused with sparse Adam: P (parameters) is updated in place.
+    lr: (means, log_scales, quats, opacity_logits, sh_dc, sh_rest); step_dev: device int32 [1]."""
+    g = _gauss_struct(P, sh_degree)
+    A = _abi.AdamFused()
+    A.m = _abi.ParamGrads(*[m[k].data_ptr() for k in PARAM_NAMES])
+    A.v = _abi.ParamGrads(*[v[k].data_ptr() for k in PARAM_NAMES])
+    A.lr[:] = [float(x) for x in lr]
+    A.beta1, A.beta2, A.eps = beta1, beta2, eps
+    A.step = step_dev.data_ptr()
+    check(lib().gsr_project_bwd_adam(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(dsplat),
+                                     _ptr(tile_info), _ptr(vis_list), _ptr(vis_count), _ptr(segment_id),
+                                     int(min_segment), C.byref(A), _ptr(dpose),
+                                     _ptr(row_mask), _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+          "gsr_project_bwd_adam")
 
 
 def adam_step(groups, rows, row_mask, beta1=0.9, beta2=0.999, eps=1e-15, step=1):
@@ -230,7 +259,7 @@ class Rasterizer:
                    tile_order=self.tile_order)
         if self.keep_dsplat:
             self.dsplat_copy = self.dsplat.clone()
-        project_bwd(P, sh_degree, cams, self.V, self.raster, self.dsplat, grads,
+        project_bwd(P, sh_degree, cams, self.V, self.raster, self.splats, self.dsplat, grads,
                     self.dpose if want_pose else None, self.pose_ws, self.tile_info, segment_id, min_segment,
                     row_mask)
         return self.dpose

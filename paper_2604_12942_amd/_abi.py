@@ -27,6 +27,11 @@ class Raster(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
 
 
+class AdamFused(C.Structure):
+    _fields_ = [("m", ParamGrads), ("v", ParamGrads), ("lr", C.c_float * 6), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("step", P)]
+
+
 MAX_GROUPS = 8
 
 
@@ -52,8 +57,12 @@ _SIGS = {
     "gsr_render_fwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
     "gsr_render_bwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
     "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
-    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, C.POINTER(ParamGrads), P, P, P,
-                         C.c_int32, P, P, C.c_size_t, P], C.c_int),
+    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, C.POINTER(ParamGrads), P, P,
+                         P, C.c_int32, P, P, C.c_size_t, P], C.c_int),
+    "gsr_project_bwd_adam": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P, C.c_int32,
+                              C.POINTER(AdamFused), P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_visible_list_workspace": ([C.c_int64], C.c_size_t),
+    "gsr_visible_list": ([P, C.c_int64, C.c_int32, P, P, P, C.c_size_t, P], C.c_int),
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
     "gsr_loss_l1": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),

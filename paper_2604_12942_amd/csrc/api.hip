@@ -6,8 +6,12 @@ using namespace gsr;
 extern "C" gsr_status gsr_project_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
                                          gsr_splat *, uint32_t *, hipStream_t);
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
-                                             float *, const gsr_param_grads *, double *, const uint32_t *,
-                                             const int32_t *, int32_t, uint8_t *, void *, hipStream_t);
+                                             const gsr_splat *, float *, const gsr_param_grads *, double *, const uint32_t *,
+                                             const int32_t *, int32_t, uint8_t *, const gsr_adam_fused *,
+                                             const uint32_t *, const uint32_t *, void *, hipStream_t);
+extern "C" size_t gsr_visible_list_ws_bytes(int64_t n);
+extern "C" gsr_status gsr_visible_list_launch(const uint32_t *, int64_t, int, uint32_t *, uint32_t *, void *,
+                                              hipStream_t);
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT);
 extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, int64_t, uint32_t *,
                                           uint32_t *, uint32_t *, void *, hipStream_t);
@@ -122,17 +126,46 @@ extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *in
 }
 
 extern "C" gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
-                                      const gsr_raster *r, float *dsplat, const gsr_param_grads *out,
+                                      const gsr_raster *r, const gsr_splat *splats, float *dsplat, const gsr_param_grads *out,
                                       double *dpose, const uint32_t *tile_info, const int32_t *segment_id,
                                       int32_t min_segment, uint8_t *row_mask, void *ws, size_t ws_bytes,
                                       gsr_stream stream) {
     if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams || !out) return GSR_E_INVALID;
-    if (g->n > 0 && (!dsplat || !out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh))
+    if (g->n > 0 && (!splats || !dsplat || !out->means || !out->log_scales || !out->quats || !out->opacity_logits ||
+                     !out->sh))
         return GSR_E_INVALID;
     if (row_mask && !tile_info && g->n > 0) return GSR_E_INVALID;
     if (dpose && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
-    return gsr_project_bwd_launch(g, cams, n_views, r, dsplat, out, dpose, tile_info, segment_id, min_segment,
-                                  row_mask, ws, S(stream));
+    return gsr_project_bwd_launch(g, cams, n_views, r, splats, dsplat, out, dpose, tile_info, segment_id,
+                                  min_segment, row_mask, nullptr, nullptr, nullptr, ws, S(stream));
+}
+
+extern "C" gsr_status gsr_project_bwd_adam(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                           const gsr_raster *r, const gsr_splat *splats, float *dsplat, const uint32_t *tile_info,
+                                           const uint32_t *visible_list, const uint32_t *visible_count,
+                                           const int32_t *segment_id, int32_t min_segment,
+                                           const gsr_adam_fused *adam, double *dpose, uint8_t *row_mask, void *ws,
+                                           size_t ws_bytes, gsr_stream stream) {
+    if ((visible_list == nullptr) != (visible_count == nullptr)) return GSR_E_INVALID;
+    if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams || !adam) return GSR_E_INVALID;
+    if (g->n > 0 && (!splats || !dsplat || !tile_info || !adam->step || !adam->m.means || !adam->m.log_scales ||
+                     !adam->m.quats || !adam->m.opacity_logits || !adam->m.sh || !adam->v.means ||
+                     !adam->v.log_scales || !adam->v.quats || !adam->v.opacity_logits || !adam->v.sh))
+        return GSR_E_INVALID;
+    if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f && adam->eps >= 0.f))
+        return GSR_E_INVALID;
+    if (dpose && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
+    return gsr_project_bwd_launch(g, cams, n_views, r, splats, dsplat, nullptr, dpose, tile_info, segment_id,
+                                  min_segment, row_mask, adam, visible_list, visible_count, ws, S(stream));
+}
+
+extern "C" size_t gsr_visible_list_workspace(int64_t n) { return n < 0 ? 0 : gsr_visible_list_ws_bytes(n); }
+
+extern "C" gsr_status gsr_visible_list(const uint32_t *tile_info, int64_t n, int32_t n_views, uint32_t *list,
+                                       uint32_t *count, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (n < 0 || n_views < 1 || !count || (n > 0 && (!tile_info || !list)) || !ws) return GSR_E_INVALID;
+    if (ws_bytes < gsr_visible_list_ws_bytes(n)) return GSR_E_CAPACITY;
+    return gsr_visible_list_launch(tile_info, n, n_views, list, count, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, const uint8_t *row_mask, float beta1,

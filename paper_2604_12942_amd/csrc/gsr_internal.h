@@ -20,7 +20,7 @@ namespace gsr {
 // Launch bookkeeping: every entry point returns GSR_E_HIP if a launch failed.
 inline gsr_status last_launch() { return hipGetLastError() == hipSuccess ? GSR_OK : GSR_E_HIP; }
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline bool valid_tile(int tw, int th) {
     return (tw == 16 && th == 16) || (tw == 8 && th == 32) || (tw == 32 && th == 8);

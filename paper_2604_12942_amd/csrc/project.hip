@@ -8,53 +8,87 @@
 
 namespace gsr {
 
-// Real spherical harmonics without Condon-Shortley phase, orthonormal, (l, m=-l..l) order, as
-// polynomials of the unit direction (x, y, z); dY gets the polynomial gradient.
-template <int DEG, bool GRAD>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y, double (*dY)[3]) {
-    Y[0] = 0.28209479177387814;
-    if (GRAD) { dY[0][0] = dY[0][1] = dY[0][2] = 0.0; }
-    if (DEG >= 1) {
-        const double a = 0.4886025119029199;
-        Y[1] = a * y; Y[2] = a * z; Y[3] = a * x;
-        if (GRAD) {
-            dY[1][0] = 0; dY[1][1] = a; dY[1][2] = 0;
-            dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = a;
-            dY[3][0] = a; dY[3][1] = 0; dY[3][2] = 0;
-        }
+// Real spherical harmonics without Condon-Shortley phase, orthonormal, ordered (l, m = -l..l),
+// as polynomials of the unit direction (x, y, z).
+// Term k in float, with its polynomial gradient.  k is wave-uniform and the callers loop over it
+// without unrolling, so one term (three coefficients) is live at a time: unrolling the basis
+// would keep every coefficient load in flight and cap occupancy.
+__device__ __forceinline__ float sh_term(int k, float x, float y, float z, float &gx, float &gy, float &gz) {
+    constexpr float a = 0.4886025119029199f;
+    constexpr float b = 1.0925484305920792f, c = 0.31539156525252005f, d = 0.5462742152960396f;
+    constexpr float e = 0.5900435899266435f, f = 2.890611442640554f, g = 0.4570457994644658f;
+    constexpr float h = 0.3731763325901154f, m = 1.445305721320277f;
+    gx = gy = gz = 0.f;
+    switch (k) {
+        case 0: return 0.28209479177387814f;
+        case 1: gy = a; return a * y;
+        case 2: gz = a; return a * z;
+        case 3: gx = a; return a * x;
+        case 4: gx = b * y; gy = b * x; return b * x * y;
+        case 5: gy = b * z; gz = b * y; return b * y * z;
+        case 6: gz = 6.0f * c * z; return c * (3.0f * z * z - 1.0f);
+        case 7: gx = b * z; gz = b * x; return b * x * z;
+        case 8: gx = 2.0f * d * x; gy = -2.0f * d * y; return d * (x * x - y * y);
+        case 9: gx = 6.0f * e * x * y; gy = 3.0f * e * (x * x - y * y); return e * y * (3.0f * x * x - y * y);
+        case 10: gx = f * y * z; gy = f * x * z; gz = f * x * y; return f * x * y * z;
+        case 11: gy = g * (5.0f * z * z - 1.0f); gz = 10.0f * g * y * z; return g * y * (5.0f * z * z - 1.0f);
+        case 12: gz = h * (15.0f * z * z - 3.0f); return h * z * (5.0f * z * z - 3.0f);
+        case 13: gx = g * (5.0f * z * z - 1.0f); gz = 10.0f * g * x * z; return g * x * (5.0f * z * z - 1.0f);
+        case 14:
+            gx = 2.0f * m * x * z; gy = -2.0f * m * y * z; gz = m * (x * x - y * y);
+            return m * z * (x * x - y * y);
+        default:
+            gx = 3.0f * e * (x * x - y * y); gy = -6.0f * e * x * y;
+            return e * x * (x * x - 3.0f * y * y);
     }
-    if (DEG >= 2) {
-        const double b = 1.0925484305920792, c = 0.31539156525252005, d = 0.5462742152960396;
-        Y[4] = b * x * y; Y[5] = b * y * z; Y[6] = c * (3.0 * z * z - 1.0); Y[7] = b * x * z;
-        Y[8] = d * (x * x - y * y);
-        if (GRAD) {
-            dY[4][0] = b * y; dY[4][1] = b * x; dY[4][2] = 0;
-            dY[5][0] = 0; dY[5][1] = b * z; dY[5][2] = b * y;
-            dY[6][0] = 0; dY[6][1] = 0; dY[6][2] = 6.0 * c * z;
-            dY[7][0] = b * z; dY[7][1] = 0; dY[7][2] = b * x;
-            dY[8][0] = 2.0 * d * x; dY[8][1] = -2.0 * d * y; dY[8][2] = 0;
-        }
+}
+
+// pre-clamp colour 1/2 + sum_k Y_k(d) h_k, coefficients read from the component-major array
+template <int K>
+__device__ __forceinline__ void sh_colour(float x, float y, float z, const float *__restrict__ sh, int64_t n,
+                                          int64_t i, float pre[3]) {
+#pragma unroll 1
+    for (int k = 0; k < K; k++) {
+        float gx, gy, gz;
+        const float Yk = sh_term(k, x, y, z, gx, gy, gz);
+        pre[0] = __builtin_fmaf(Yk, sh[(3 * k + 0) * n + i], pre[0]);
+        pre[1] = __builtin_fmaf(Yk, sh[(3 * k + 1) * n + i], pre[1]);
+        pre[2] = __builtin_fmaf(Yk, sh[(3 * k + 2) * n + i], pre[2]);
     }
-    if (DEG >= 3) {
-        const double e = 0.5900435899266435, f = 2.890611442640554, g = 0.4570457994644658;
-        const double h = 0.3731763325901154, k = 1.445305721320277;
-        const double x2 = x * x, y2 = y * y, z2 = z * z;
-        Y[9] = e * y * (3.0 * x2 - y2);
-        Y[10] = f * x * y * z;
-        Y[11] = g * y * (5.0 * z2 - 1.0);
-        Y[12] = h * z * (5.0 * z2 - 3.0);
-        Y[13] = g * x * (5.0 * z2 - 1.0);
-        Y[14] = k * z * (x2 - y2);
-        Y[15] = e * x * (x2 - 3.0 * y2);
-        if (GRAD) {
-            dY[9][0] = 6.0 * e * x * y; dY[9][1] = 3.0 * e * (x2 - y2); dY[9][2] = 0;
-            dY[10][0] = f * y * z; dY[10][1] = f * x * z; dY[10][2] = f * x * y;
-            dY[11][0] = 0; dY[11][1] = g * (5.0 * z2 - 1.0); dY[11][2] = 10.0 * g * y * z;
-            dY[12][0] = 0; dY[12][1] = 0; dY[12][2] = h * (15.0 * z2 - 3.0);
-            dY[13][0] = g * (5.0 * z2 - 1.0); dY[13][1] = 0; dY[13][2] = 10.0 * g * x * z;
-            dY[14][0] = 2.0 * k * x * z; dY[14][1] = -2.0 * k * y * z; dY[14][2] = k * (x2 - y2);
-            dY[15][0] = 3.0 * e * (x2 - y2); dY[15][1] = -6.0 * e * x * y; dY[15][2] = 0;
+}
+
+// the same sum fully unrolled (the forward projection has registers to spare for it)
+template <int K, int k = 0>
+__device__ __forceinline__ void sh_colour_unrolled(float x, float y, float z, const float *__restrict__ sh, int64_t n,
+                                                   int64_t i, float pre[3]) {
+    if constexpr (k < K) {
+        float gx, gy, gz;
+        const float Yk = sh_term(k, x, y, z, gx, gy, gz);
+        pre[0] = __builtin_fmaf(Yk, sh[(3 * k + 0) * n + i], pre[0]);
+        pre[1] = __builtin_fmaf(Yk, sh[(3 * k + 1) * n + i], pre[1]);
+        pre[2] = __builtin_fmaf(Yk, sh[(3 * k + 2) * n + i], pre[2]);
+        sh_colour_unrolled<K, k + 1>(x, y, z, sh, n, i, pre);
+    }
+}
+
+// backward of the colour: gh[k][ch] += gcol[ch] Y_k, gdir += (sum_ch gcol[ch] h_k,ch) grad Y_k
+template <int K>
+__device__ __forceinline__ void sh_colour_bwd(float x, float y, float z, const float *__restrict__ sh, int64_t n,
+                                              int64_t i, const float gcol[3], float *gh, int stride, float gdir[3]) {
+#pragma unroll 1
+    for (int k = 0; k < K; k++) {
+        float gx, gy, gz;
+        const float Yk = sh_term(k, x, y, z, gx, gy, gz);
+        float sk = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            float &acc = gh[(3 * k + ch) * stride];
+            acc = __builtin_fmaf(gcol[ch], Yk, acc);
+            sk = __builtin_fmaf(gcol[ch], sh[(3 * k + ch) * n + i], sk);
         }
+        gdir[0] = __builtin_fmaf(sk, gx, gdir[0]);
+        gdir[1] = __builtin_fmaf(sk, gy, gdir[1]);
+        gdir[2] = __builtin_fmaf(sk, gz, gdir[2]);
     }
 }
 
@@ -82,10 +116,51 @@ __device__ __forceinline__ void load_cam(const gsr_camera &c, Cam &k) {
     for (int a = 0; a < 3; a++) k.C[a] = -(k.R[0][a] * k.t[0] + k.R[1][a] * k.t[1] + k.R[2][a] * k.t[2]);
 }
 
+// symmetric 3x3: xx, xy, xz, yy, yz, zz
+struct Sym3 {
+    double xx, xy, xz, yy, yz, zz;
+};
+
+__device__ __forceinline__ double sym_at(const Sym3 &S, int a, int b) {
+    const int k = a < b ? a * 3 + b : b * 3 + a;  // 0 1 2 / 4 5 / 8
+    switch (k) {
+        case 0: return S.xx;
+        case 1: return S.xy;
+        case 2: return S.xz;
+        case 4: return S.yy;
+        case 5: return S.yz;
+        default: return S.zz;
+    }
+}
+
+// R S R^T for a symmetric S
+__device__ __forceinline__ Sym3 rot_sym(const double R[3][3], const Sym3 &S) {
+    double RS[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            RS[a][b] = R[a][0] * sym_at(S, 0, b) + R[a][1] * sym_at(S, 1, b) + R[a][2] * sym_at(S, 2, b);
+    Sym3 o;
+    o.xx = RS[0][0] * R[0][0] + RS[0][1] * R[0][1] + RS[0][2] * R[0][2];
+    o.xy = RS[0][0] * R[1][0] + RS[0][1] * R[1][1] + RS[0][2] * R[1][2];
+    o.xz = RS[0][0] * R[2][0] + RS[0][1] * R[2][1] + RS[0][2] * R[2][2];
+    o.yy = RS[1][0] * R[1][0] + RS[1][1] * R[1][1] + RS[1][2] * R[1][2];
+    o.yz = RS[1][0] * R[2][0] + RS[1][1] * R[2][1] + RS[1][2] * R[2][2];
+    o.zz = RS[2][0] * R[2][0] + RS[2][1] * R[2][1] + RS[2][2] * R[2][2];
+    return o;
+}
+
+// R^T S R for a symmetric S
+__device__ __forceinline__ Sym3 rot_sym_t(const double R[3][3], const Sym3 &S) {
+    double Rt[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) Rt[a][b] = R[b][a];
+    return rot_sym(Rt, S);
+}
+
 // Everything the forward and backward share for one (view, Gaussian).
 struct ViewGeom {
     double p[3];        // camera-frame mean
-    double Sc[3][3];    // camera-frame covariance
+    Sym3 Sc;            // camera-frame covariance
     double j00, j02, j11, j12, tx, ty;
     bool clx, cly;
     double a, b, c;     // Sigma' = [[a, b], [b, c]]
@@ -94,16 +169,12 @@ struct ViewGeom {
     double dir[3], dist;
 };
 
-__device__ __forceinline__ bool view_geom(const double mu[3], const double Sig[3][3], const Cam &k, int W, int H,
+__device__ __forceinline__ bool view_geom(const double mu[3], const Sym3 &Sig, const Cam &k, int W, int H,
                                           ViewGeom &G) {
     for (int a = 0; a < 3; a++) G.p[a] = k.R[a][0] * mu[0] + k.R[a][1] * mu[1] + k.R[a][2] * mu[2] + k.t[a];
     const double z = G.p[2];
     if (!(z > k.znear)) return false;
-    double RS[3][3];
-    for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) RS[a][b] = k.R[a][0] * Sig[0][b] + k.R[a][1] * Sig[1][b] + k.R[a][2] * Sig[2][b];
-    for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) G.Sc[a][b] = RS[a][0] * k.R[b][0] + RS[a][1] * k.R[b][1] + RS[a][2] * k.R[b][2];
+    G.Sc = rot_sym(k.R, Sig);
     const double limx = GSR_GUARD * W / (2.0 * k.fx), limy = GSR_GUARD * H / (2.0 * k.fy);
     const double rx = G.p[0] / z, ry = G.p[1] / z;
     G.clx = fabs(rx) > limx;
@@ -114,38 +185,46 @@ __device__ __forceinline__ bool view_geom(const double mu[3], const double Sig[3
     G.j00 = k.fx * iz; G.j02 = -k.fx * G.tx * iz;
     G.j11 = k.fy * iz; G.j12 = -k.fy * G.ty * iz;
     // Sigma' = J Sc J^T + 0.3 I with J = [[j00, 0, j02], [0, j11, j12]]
-    const double r0[3] = {G.j00 * G.Sc[0][0] + G.j02 * G.Sc[2][0], G.j00 * G.Sc[0][1] + G.j02 * G.Sc[2][1],
-                          G.j00 * G.Sc[0][2] + G.j02 * G.Sc[2][2]};
-    const double r1[3] = {G.j11 * G.Sc[1][0] + G.j12 * G.Sc[2][0], G.j11 * G.Sc[1][1] + G.j12 * G.Sc[2][1],
-                          G.j11 * G.Sc[1][2] + G.j12 * G.Sc[2][2]};
-    G.a = r0[0] * G.j00 + r0[2] * G.j02 + GSR_LOWPASS;
-    G.b = r0[1] * G.j11 + r0[2] * G.j12;
-    G.c = r1[1] * G.j11 + r1[2] * G.j12 + GSR_LOWPASS;
+    const Sym3 &S = G.Sc;
+    G.a = G.j00 * (G.j00 * S.xx + G.j02 * S.xz) + G.j02 * (G.j00 * S.xz + G.j02 * S.zz) + GSR_LOWPASS;
+    G.b = G.j00 * (G.j11 * S.xy + G.j12 * S.xz) + G.j02 * (G.j11 * S.yz + G.j12 * S.zz);
+    G.c = G.j11 * (G.j11 * S.yy + G.j12 * S.yz) + G.j12 * (G.j11 * S.yz + G.j12 * S.zz) + GSR_LOWPASS;
     G.det = G.a * G.c - G.b * G.b;
     G.u = k.fx * G.p[0] * iz + k.cx;
     G.v = k.fy * G.p[1] * iz + k.cy;
     double d[3] = {mu[0] - k.C[0], mu[1] - k.C[1], mu[2] - k.C[2]};
     G.dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    for (int a = 0; a < 3; a++) G.dir[a] = d[a] / G.dist;
+    const double idist = 1.0 / G.dist;
+    for (int a = 0; a < 3; a++) G.dir[a] = d[a] * idist;
     return true;
 }
 
-__device__ __forceinline__ void gaussian_cov(const gsr_gaussians &g, int64_t i, double mu[3], double Rq[3][3],
-                                             double s[3], double qn[4], double &qnorm, double Sig[3][3]) {
+__device__ __forceinline__ void load_quat(const gsr_gaussians &g, int64_t i, double qn[4], double &qnorm) {
     const int64_t n = g.n;
-    for (int a = 0; a < 3; a++) mu[a] = g.means[a * n + i];
     double q[4];
     for (int a = 0; a < 4; a++) q[a] = g.quats[a * n + i];
     qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     for (int a = 0; a < 4; a++) qn[a] = q[a] / qnorm;
+}
+
+// Sigma = Rq S S^T Rq^T
+__device__ __forceinline__ Sym3 gaussian_sigma(const gsr_gaussians &g, int64_t i) {
+    const int64_t n = g.n;
+    double qn[4], qnorm, Rq[3][3], s2[3];
+    load_quat(g, i, qn, qnorm);
     quat_rot(qn[0], qn[1], qn[2], qn[3], Rq);
-    for (int a = 0; a < 3; a++) s[a] = exp((double)g.log_scales[a * n + i]);
-    for (int a = 0; a < 3; a++)
-        for (int b = 0; b <= a; b++) {
-            double acc = 0;
-            for (int k = 0; k < 3; k++) acc += Rq[a][k] * Rq[b][k] * s[k] * s[k];
-            Sig[a][b] = Sig[b][a] = acc;
-        }
+    for (int a = 0; a < 3; a++) {
+        const double sa = exp((double)g.log_scales[a * n + i]);
+        s2[a] = sa * sa;
+    }
+    Sym3 S;
+    S.xx = Rq[0][0] * Rq[0][0] * s2[0] + Rq[0][1] * Rq[0][1] * s2[1] + Rq[0][2] * Rq[0][2] * s2[2];
+    S.xy = Rq[0][0] * Rq[1][0] * s2[0] + Rq[0][1] * Rq[1][1] * s2[1] + Rq[0][2] * Rq[1][2] * s2[2];
+    S.xz = Rq[0][0] * Rq[2][0] * s2[0] + Rq[0][1] * Rq[2][1] * s2[1] + Rq[0][2] * Rq[2][2] * s2[2];
+    S.yy = Rq[1][0] * Rq[1][0] * s2[0] + Rq[1][1] * Rq[1][1] * s2[1] + Rq[1][2] * Rq[1][2] * s2[2];
+    S.yz = Rq[1][0] * Rq[2][0] * s2[0] + Rq[1][1] * Rq[2][1] * s2[1] + Rq[1][2] * Rq[2][2] * s2[2];
+    S.zz = Rq[2][0] * Rq[2][0] * s2[0] + Rq[2][1] * Rq[2][1] * s2[1] + Rq[2][2] * Rq[2][2] * s2[2];
+    return S;
 }
 
 template <int DEG>
@@ -157,31 +236,21 @@ __global__ __launch_bounds__(256) void k_project(gsr_gaussians g, const gsr_came
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t VN = (int64_t)V * n;
-    double mu[3], Rq[3][3], s[3], qn[4], qnorm, Sig[3][3];
-    gaussian_cov(g, i, mu, Rq, s, qn, qnorm, Sig);
+    const double mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    const Sym3 Sig = gaussian_sigma(g, i);
     const double o = 1.0 / (1.0 + exp(-(double)g.opacity_logits[i]));
-    float h[3 * K];
-#pragma unroll
-    for (int e = 0; e < 3 * K; e++) h[e] = g.sh[e * n + i];
+#pragma unroll 1
     for (int vi = 0; vi < V; vi++) {
+        // keep the SH coefficients out of registers across views: they are re-read (cached) per view
+        __asm__ __volatile__("" ::: "memory");
         Cam k;
         load_cam(cams[vi], k);
         const int64_t gid = vi * n + i;
         ViewGeom G;
         uint32_t ntiles = 0, zbits = 0, r0 = 0, r1 = 0;
-        double4 rec0 = make_double4(0, 0, 0, 0);
+        double2 rec0 = make_double2(0, 0);
         float4 rec1 = make_float4(0, 0, 0, 0), rec2 = make_float4(0, 0, 0, 0);
         if (view_geom(mu, Sig, k, W, H, G) && 255.0 * o >= 1.0) {
-            // colour in the viewing direction
-            double Y[K];
-            sh_basis<DEG, false>(G.dir[0], G.dir[1], G.dir[2], Y, nullptr);
-            float col[3];
-            for (int ch = 0; ch < 3; ch++) {
-                double acc = 0.5;
-#pragma unroll
-                for (int kk = 0; kk < K; kk++) acc += Y[kk] * (double)h[3 * kk + ch];
-                col[ch] = (float)(acc > 0.0 ? acc : 0.0);
-            }
             // footprint: D^T Q D <= r2, bounding box half-extents sqrt(r2 a), sqrt(r2 c)
             const double r2 = 2.0 * log(255.0 * o);
             const double ex = sqrt(r2 * G.a), ey = sqrt(r2 * G.c);
@@ -197,20 +266,22 @@ __global__ __launch_bounds__(256) void k_project(gsr_gaussians g, const gsr_came
                 r1 = tx1 | (ty1 << 16);
                 const float zf = (float)G.p[2];
                 zbits = __float_as_uint(zf);
+                // colour in the viewing direction
+                float col[3] = {0.5f, 0.5f, 0.5f};
+                sh_colour_unrolled<K>((float)G.dir[0], (float)G.dir[1], (float)G.dir[2], g.sh, n, i, col);
                 // Cholesky factor of kappa Q, Q = [[c, -b], [-b, a]] / det:
                 // l11 = sqrt(kappa c / det), l21 = -kappa b / (det l11), l22 = sqrt(kappa / c)
                 const double qa = GSR_KAPPA * G.c / G.det, qb = -GSR_KAPPA * G.b / G.det;
                 const double l11 = sqrt(qa);
-                rec0 = make_double4(G.u, G.v, 0, 0);
+                rec0 = make_double2(G.u, G.v);
                 rec1 = make_float4((float)l11, (float)(qb / l11), (float)sqrt(GSR_KAPPA / G.c), (float)o);
-                rec2 = make_float4(zf, col[0], col[1], col[2]);
+                rec2 = make_float4(zf, fmaxf(col[0], 0.f), fmaxf(col[1], 0.f), fmaxf(col[2], 0.f));
             }
         }
         // only visible pairs are ever read back: skip the record writes of the others
         info[gid] = ntiles;
         if (ntiles) {
-            double2 *dst = reinterpret_cast<double2 *>(splats + gid);
-            dst[0] = make_double2(rec0.x, rec0.y);
+            *reinterpret_cast<double2 *>(splats + gid) = rec0;
             float4 *dstf = reinterpret_cast<float4 *>(splats + gid) + 1;
             dstf[0] = rec1;
             dstf[1] = rec2;
@@ -224,62 +295,99 @@ __global__ __launch_bounds__(256) void k_project(gsr_gaussians g, const gsr_came
 // ---------------------------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ void block_sum6_d(double v[6], double *s_red /*[4][6]*/, double *out) {
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int e = 0; e < 6; e++) {
-        double r = wave_sum_d(v[e]);
-        if (__lane_id() == 0) s_red[w * 6 + e] = r;
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        double acc = 0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); k++) acc += s_red[k * 6 + threadIdx.x];
-        out[threadIdx.x] = acc;
-    }
-    __syncthreads();
+// Sum over the wave in float (DPP row shifts, then row broadcasts): the total lands in lane 63.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+__device__ __forceinline__ float wave_total_f(float v) {
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-template <int DEG>
+// In-place Adam on one element (the same float expression as the standalone optimiser kernel).
+__device__ __forceinline__ void adam_elem(float *p, float *m, float *v, int64_t e, float g, float lr, float b1,
+                                          float b2, float eps, float bc1, float bc2) {
+    const float mm = b1 * m[e] + (1.0f - b1) * g;
+    const float vv = b2 * v[e] + (1.0f - b2) * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+struct FusedAdam {
+    gsr_param_grads m, v;
+    float lr[6];
+    float b1, b2, eps;
+    const int32_t *step;
+};
+
+// Chain rule from the screen-space gradients to the parameters and the per-view pose.  With
+// tile_info, a Gaussian that no view rendered costs V 4-byte reads and nothing else.  FUSED:
+// instead of accumulating gradients, visible Gaussians of unfrozen segments take their sparse
+// Adam step directly from the register-held gradient (no gradient buffer round trip).  The SH
+// coefficient gradients accumulate across views in LDS ([coefficient][thread], conflict-free).
+template <int DEG, bool FUSED>
 __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_camera *__restrict__ cams, int V,
-                                                     int W, int H, float *__restrict__ dsplat,
+                                                     int W, int H, const gsr_splat *__restrict__ splats,
+                                                     float *__restrict__ dsplat,
                                                      gsr_param_grads out, double *__restrict__ pose_part,
                                                      const uint32_t *__restrict__ tile_info,
                                                      const int32_t *__restrict__ seg, int32_t min_seg,
-                                                     uint8_t *__restrict__ row_mask) {
+                                                     uint8_t *__restrict__ row_mask, FusedAdam adam,
+                                                     const uint32_t *__restrict__ vlist,
+                                                     const uint32_t *__restrict__ vcount) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    __shared__ double s_red[4 * 6];
+    __shared__ float s_gh[3 * K][256];
     const int64_t n = g.n;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < n;
-    double mu[3] = {0, 0, 0}, Rq[3][3], s[3] = {1, 1, 1}, qn[4] = {1, 0, 0, 0}, qnorm = 1, Sig[3][3];
-    double o = 0;
-    float h[3 * K];
-    if (live) {
-        gaussian_cov(g, i, mu, Rq, s, qn, qnorm, Sig);
-        o = 1.0 / (1.0 + exp(-(double)g.opacity_logits[i]));
-#pragma unroll
-        for (int e = 0; e < 3 * K; e++) h[e] = g.sh[e * n + i];
+    // thread -> Gaussian: directly, or through the compacted list of visible Gaussians
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cnt = vlist ? (int64_t)*vcount : n;
+    if ((int64_t)blockIdx.x * blockDim.x >= cnt) {
+        // past the end of the (visible) list: the pose reduction reads only the partials of
+        // the blocks below this one
+        return;
     }
-    double gSig[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double gmu[3] = {0, 0, 0}, gop = 0;
-    float gh[3 * K];
+    const bool live = t < cnt;
+    const int64_t i = live ? (vlist ? (int64_t)vlist[t] : t) : 0;
+    bool anyvis = live;
+    if (live && tile_info) {
+        anyvis = false;
+        for (int vi = 0; vi < V; vi++) anyvis |= tile_info[(int64_t)vi * n + i] > 0;
+    }
+    float *gh = &s_gh[0][threadIdx.x];
 #pragma unroll
-    for (int e = 0; e < 3 * K; e++) gh[e] = 0.f;
+    for (int e = 0; e < 3 * K; e++) gh[e * 256] = 0.f;
+    double mu[3] = {0, 0, 0};
+    Sym3 Sig{1, 0, 0, 1, 0, 1};
+    double o = 0;
+    if (anyvis) {
+        for (int a = 0; a < 3; a++) mu[a] = g.means[a * n + i];
+        Sig = gaussian_sigma(g, i);
+        o = 1.0 / (1.0 + exp(-(double)g.opacity_logits[i]));
+    }
+    Sym3 gSig{0, 0, 0, 0, 0, 0};
+    double gmu[3] = {0, 0, 0}, gop = 0;
     bool touched = false, visible = false;
 
+#pragma unroll 1
     for (int vi = 0; vi < V; vi++) {
+        __asm__ __volatile__("" ::: "memory");
         double pose[6] = {0, 0, 0, 0, 0, 0};
         float gs[10];
         bool any = false;
-        if (live) {
+        if (anyvis) {
             // with tile_info, only the pairs that were rendered can hold gradients: read those and
             // reset them, leaving dsplat zeroed for the next backward without a separate fill
             const bool vis = tile_info ? tile_info[(int64_t)vi * n + i] > 0 : true;
             visible |= vis;
             if (vis) {
-                float *src = dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS;
-                float2 *s2 = reinterpret_cast<float2 *>(src);
+                float2 *s2 = reinterpret_cast<float2 *>(dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS);
 #pragma unroll
                 for (int e = 0; e < 5; e++) {
                     const float2 q = s2[e];
@@ -301,30 +409,33 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
             touched = true;
             const double x = G.p[0], y = G.p[1], z = G.p[2], iz = 1.0 / z;
             // conic Q = [[c, -b], [-b, a]] / det
-            const double Qa = G.c / G.det, Qb = -G.b / G.det, Qc = G.a / G.det;
+            const double idet = 1.0 / G.det;
+            const double Qa = G.c * idet, Qb = -G.b * idet, Qc = G.a * idet;
             // dL/dSigma' = -Q dL/dQ Q with the symmetric dL/dQ = [[ga, gb/2], [gb/2, gc]]
             const double ga = gs[2], gb = 0.5 * gs[3], gc = gs[4];
             const double m00 = Qa * ga + Qb * gb, m01 = Qa * gb + Qb * gc;
             const double m10 = Qb * ga + Qc * gb, m11 = Qb * gb + Qc * gc;
             const double S00 = -(m00 * Qa + m01 * Qb), S01 = -(m00 * Qb + m01 * Qc);
             const double S11 = -(m10 * Qb + m11 * Qc);
-            // J rows: J0 = (j00, 0, j02), J1 = (0, j11, j12)
+            // J rows: J0 = (j00, 0, j02), J1 = (0, j11, j12); dL/dSc = J^T dL/dSigma' J
             const double J0[3] = {G.j00, 0.0, G.j02}, J1[3] = {0.0, G.j11, G.j12};
-            // dL/dSc = J^T dL/dSigma' J
-            double gSc[3][3];
-            for (int a = 0; a < 3; a++)
-                for (int b = 0; b < 3; b++)
-                    gSc[a][b] = J0[a] * (S00 * J0[b] + S01 * J1[b]) + J1[a] * (S01 * J0[b] + S11 * J1[b]);
+            Sym3 gSc;
+            gSc.xx = J0[0] * (S00 * J0[0] + S01 * J1[0]) + J1[0] * (S01 * J0[0] + S11 * J1[0]);
+            gSc.xy = J0[0] * (S00 * J0[1] + S01 * J1[1]) + J1[0] * (S01 * J0[1] + S11 * J1[1]);
+            gSc.xz = J0[0] * (S00 * J0[2] + S01 * J1[2]) + J1[0] * (S01 * J0[2] + S11 * J1[2]);
+            gSc.yy = J0[1] * (S00 * J0[1] + S01 * J1[1]) + J1[1] * (S01 * J0[1] + S11 * J1[1]);
+            gSc.yz = J0[1] * (S00 * J0[2] + S01 * J1[2]) + J1[1] * (S01 * J0[2] + S11 * J1[2]);
+            gSc.zz = J0[2] * (S00 * J0[2] + S01 * J1[2]) + J1[2] * (S01 * J0[2] + S11 * J1[2]);
             // dL/dJ = 2 dL/dSigma' J Sc (rows 0 and 1)
-            double JS0[3], JS1[3];
-            for (int b = 0; b < 3; b++) {
-                JS0[b] = J0[0] * G.Sc[0][b] + J0[2] * G.Sc[2][b];
-                JS1[b] = J1[1] * G.Sc[1][b] + J1[2] * G.Sc[2][b];
-            }
-            const double gJ00 = 2.0 * (S00 * JS0[0] + S01 * JS1[0]);
-            const double gJ02 = 2.0 * (S00 * JS0[2] + S01 * JS1[2]);
-            const double gJ11 = 2.0 * (S01 * JS0[1] + S11 * JS1[1]);
-            const double gJ12 = 2.0 * (S01 * JS0[2] + S11 * JS1[2]);
+            const Sym3 &Sc = G.Sc;
+            const double JS0x = J0[0] * Sc.xx + J0[2] * Sc.xz, JS0y = J0[0] * Sc.xy + J0[2] * Sc.yz;
+            const double JS0z = J0[0] * Sc.xz + J0[2] * Sc.zz;
+            const double JS1x = J1[1] * Sc.xy + J1[2] * Sc.xz, JS1y = J1[1] * Sc.yy + J1[2] * Sc.yz;
+            const double JS1z = J1[1] * Sc.yz + J1[2] * Sc.zz;
+            const double gJ00 = 2.0 * (S00 * JS0x + S01 * JS1x);
+            const double gJ02 = 2.0 * (S00 * JS0z + S01 * JS1z);
+            const double gJ11 = 2.0 * (S01 * JS0y + S11 * JS1y);
+            const double gJ12 = 2.0 * (S01 * JS0z + S11 * JS1z);
             // camera-frame point
             double gp[3];
             gp[0] = gs[0] * k.fx * iz;
@@ -344,18 +455,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
                 gp[2] += gJ12 * 2.0 * k.fy * y * iz * iz * iz;
             }
             // world covariance: dL/dSigma += R^T dL/dSc R
-            double T1[3][3];
-            for (int a = 0; a < 3; a++)
-                for (int b = 0; b < 3; b++)
-                    T1[a][b] = k.R[0][a] * gSc[0][b] + k.R[1][a] * gSc[1][b] + k.R[2][a] * gSc[2][b];
-            for (int a = 0; a < 3; a++)
-                for (int b = 0; b < 3; b++)
-                    gSig[a][b] += T1[a][0] * k.R[0][b] + T1[a][1] * k.R[1][b] + T1[a][2] * k.R[2][b];
+            const Sym3 gw = rot_sym_t(k.R, gSc);
+            gSig.xx += gw.xx; gSig.xy += gw.xy; gSig.xz += gw.xz;
+            gSig.yy += gw.yy; gSig.yz += gw.yz; gSig.zz += gw.zz;
             // pose, rotation part through Sc: <dL/dSc, [e]x Sc - Sc [e]x> = 2 tr([e]x Sc dL/dSc)
             double A[3][3];
             for (int a = 0; a < 3; a++)
                 for (int b = 0; b < 3; b++)
-                    A[a][b] = G.Sc[a][0] * gSc[0][b] + G.Sc[a][1] * gSc[1][b] + G.Sc[a][2] * gSc[2][b];
+                    A[a][b] = sym_at(Sc, a, 0) * sym_at(gSc, 0, b) + sym_at(Sc, a, 1) * sym_at(gSc, 1, b) +
+                              sym_at(Sc, a, 2) * sym_at(gSc, 2, b);
             pose[3] += 2.0 * (A[1][2] - A[2][1]);
             pose[4] += 2.0 * (A[2][0] - A[0][2]);
             pose[5] += 2.0 * (A[0][1] - A[1][0]);
@@ -365,47 +473,56 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
             pose[3] += y * gp[2] - z * gp[1];
             pose[4] += z * gp[0] - x * gp[2];
             pose[5] += x * gp[1] - y * gp[0];
-            // colour: clamp at zero, SH coefficients, viewing direction
-            double Y[K], dY[K][3];
-            sh_basis<DEG, true>(G.dir[0], G.dir[1], G.dir[2], Y, dY);
-            double gdir[3] = {0, 0, 0};
-            for (int ch = 0; ch < 3; ch++) {
-                double pre = 0.5;
-#pragma unroll
-                for (int kk = 0; kk < K; kk++) pre += Y[kk] * (double)h[3 * kk + ch];
-                if (!(pre > 0.0)) continue;
-                const double gcol = gs[6 + ch];
-#pragma unroll
-                for (int kk = 0; kk < K; kk++) {
-                    gh[3 * kk + ch] += (float)(gcol * Y[kk]);
-                    for (int a = 0; a < 3; a++) gdir[a] += gcol * h[3 * kk + ch] * dY[kk][a];
-                }
-            }
+            // colour: clamp at zero, SH coefficients, viewing direction.  The forward stored
+            // max(0, pre-clamp colour) in the splat, so a zero channel is exactly a clamped one.
+            const float dxf = (float)G.dir[0], dyf = (float)G.dir[1], dzf = (float)G.dir[2];
+            const float4 rgbz = *(reinterpret_cast<const float4 *>(splats + (int64_t)vi * n + i) + 2);
+            float gcol[3], gdirf[3] = {0.f, 0.f, 0.f};
+            gcol[0] = rgbz.y > 0.f ? gs[6] : 0.f;
+            gcol[1] = rgbz.z > 0.f ? gs[7] : 0.f;
+            gcol[2] = rgbz.w > 0.f ? gs[8] : 0.f;
+            sh_colour_bwd<K>(dxf, dyf, dzf, g.sh, n, i, gcol, gh, 256, gdirf);
+            const double gdir[3] = {gdirf[0], gdirf[1], gdirf[2]};
             const double dd = G.dir[0] * gdir[0] + G.dir[1] * gdir[1] + G.dir[2] * gdir[2];
             double gd[3];
-            for (int a = 0; a < 3; a++) gd[a] = (gdir[a] - G.dir[a] * dd) / G.dist;
+            const double idist = 1.0 / G.dist;
+            for (int a = 0; a < 3; a++) gd[a] = (gdir[a] - G.dir[a] * dd) * idist;
             for (int a = 0; a < 3; a++) gmu[a] += gd[a];
             // camera centre -R^T t moves by -R^T rho: dL/drho += R dL/d(mu - C)
             for (int a = 0; a < 3; a++) pose[a] += k.R[a][0] * gd[0] + k.R[a][1] * gd[1] + k.R[a][2] * gd[2];
             gop += gs[5];
         }
         if (pose_part) {
-            // deterministic per-block partial sums of the pose gradient of this view
-            block_sum6_d(pose, s_red, pose_part + ((int64_t)blockIdx.x * V + vi) * 6);
+            // per-wave partial sums of the pose gradient of this view, component-major
+            // [V][6][waves] so that the fixed-order reduction reads them contiguously
+            const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+            const int64_t nw = (int64_t)gridDim.x * 4;
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                const float tot = wave_total_f((float)pose[e]);
+                if (__lane_id() == e) pose_part[((int64_t)vi * 6 + e) * nw + wid] = (double)tot;
+            }
         }
     }
-    if (live && row_mask) row_mask[i] = (visible && (!seg || seg[i] >= min_seg)) ? 1 : 0;
-    if (!live || !touched) return;
+    const bool unfrozen = !seg || (live && seg[i] >= min_seg);
+    if (live && row_mask) row_mask[i] = (visible && unfrozen) ? 1 : 0;
+    if (!anyvis || !(touched || (FUSED && visible && unfrozen))) return;
     // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 dL/dSigma M
+    double qn[4], qnorm, Rq[3][3], sc[3];
+    load_quat(g, i, qn, qnorm);
+    quat_rot(qn[0], qn[1], qn[2], qn[3], Rq);
+    for (int a = 0; a < 3; a++) sc[a] = exp((double)g.log_scales[a * n + i]);
     double gRq[3][3];
+    float gls[3];
     for (int c = 0; c < 3; c++) {
         double gsc = 0;
         for (int a = 0; a < 3; a++) {
-            const double gm = 2.0 * (gSig[a][0] * Rq[0][c] + gSig[a][1] * Rq[1][c] + gSig[a][2] * Rq[2][c]) * s[c];
+            const double gm = 2.0 * (sym_at(gSig, a, 0) * Rq[0][c] + sym_at(gSig, a, 1) * Rq[1][c] +
+                                     sym_at(gSig, a, 2) * Rq[2][c]) * sc[c];
             gsc += gm * Rq[a][c];
-            gRq[a][c] = gm * s[c];
+            gRq[a][c] = gm * sc[c];
         }
-        out.log_scales[c * n + i] += (float)(gsc * s[c]);
+        gls[c] = (float)(gsc * sc[c]);
     }
     // R(q) = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]_x on the unit sphere
     const double w = qn[0], vx = qn[1], vy = qn[2], vz = qn[3];
@@ -423,22 +540,103 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
         gq[1 + a] = -2.0 * vv[a] * tr + 2.0 * (Gv + GTv) + 2.0 * w * ax[a];
     }
     const double qd = qn[0] * gq[0] + qn[1] * gq[1] + qn[2] * gq[2] + qn[3] * gq[3];
-    for (int a = 0; a < 4; a++) out.quats[a * n + i] += (float)((gq[a] - qn[a] * qd) / qnorm);
-    for (int a = 0; a < 3; a++) out.means[a * n + i] += (float)gmu[a];
-    out.opacity_logits[i] += (float)(gop * o * (1.0 - o));
+    float gqf[4];
+    for (int a = 0; a < 4; a++) gqf[a] = (float)((gq[a] - qn[a] * qd) / qnorm);
+    const float gomf = (float)(gop * o * (1.0 - o));
+    if (!FUSED) {
+        for (int c = 0; c < 3; c++) out.log_scales[c * n + i] += gls[c];
+        for (int a = 0; a < 4; a++) out.quats[a * n + i] += gqf[a];
+        for (int a = 0; a < 3; a++) out.means[a * n + i] += (float)gmu[a];
+        out.opacity_logits[i] += gomf;
 #pragma unroll
-    for (int e = 0; e < 3 * K; e++) out.sh[e * n + i] += gh[e];
+        for (int e = 0; e < 3 * K; e++) out.sh[e * n + i] += gh[e * 256];
+    } else if (visible && unfrozen) {
+        const int step = *adam.step;
+        const float bc1 = (float)(1.0 - pow((double)adam.b1, step)), bc2 = (float)(1.0 - pow((double)adam.b2, step));
+        float *P0 = const_cast<float *>(g.means), *P1 = const_cast<float *>(g.log_scales);
+        float *P2 = const_cast<float *>(g.quats), *P3 = const_cast<float *>(g.opacity_logits);
+        float *P4 = const_cast<float *>(g.sh);
+        const float b1 = adam.b1, b2 = adam.b2, eps = adam.eps;
+        for (int a = 0; a < 3; a++)
+            adam_elem(P0, adam.m.means, adam.v.means, a * n + i, (float)gmu[a], adam.lr[0], b1, b2, eps, bc1, bc2);
+        for (int c = 0; c < 3; c++)
+            adam_elem(P1, adam.m.log_scales, adam.v.log_scales, c * n + i, gls[c], adam.lr[1], b1, b2, eps, bc1, bc2);
+        for (int a = 0; a < 4; a++)
+            adam_elem(P2, adam.m.quats, adam.v.quats, a * n + i, gqf[a], adam.lr[2], b1, b2, eps, bc1, bc2);
+        adam_elem(P3, adam.m.opacity_logits, adam.v.opacity_logits, i, gomf, adam.lr[3], b1, b2, eps, bc1, bc2);
+        for (int e = 0; e < 3 * K; e++)
+            adam_elem(P4, adam.m.sh, adam.v.sh, e * n + i, gh[e * 256], e < 3 ? adam.lr[4] : adam.lr[5], b1, b2, eps,
+                      bc1, bc2);
+    }
 }
 
-// dpose[v][e] = sum over blocks of the partial sums (fixed order: deterministic)
-__global__ void k_pose_reduce(const double *__restrict__ part, int nblocks, int V, double *__restrict__ dpose) {
-    const int v = blockIdx.x;
-    const int e = threadIdx.x >> 6;  // 6 waves, one per component
-    if (e >= 6) return;
+// ---- ordered list of the Gaussians visible in at least one view ---------------------------------
+__global__ __launch_bounds__(256) void k_vis_any_count(const uint32_t *__restrict__ info, int64_t n, int V,
+                                                       uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t s_w[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool vis = false;
+    if (i < n)
+        for (int v = 0; v < V; v++) vis |= info[(int64_t)v * n + i] > 0;
+    uint32_t tot;
+    block_excl_scan256(vis ? 1u : 0u, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_vis_any_write(const uint32_t *__restrict__ info, int64_t n, int V,
+                                                       const uint32_t *__restrict__ boff, uint32_t *__restrict__ list) {
+    __shared__ uint32_t s_w[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool vis = false;
+    if (i < n)
+        for (int v = 0; v < V; v++) vis |= info[(int64_t)v * n + i] > 0;
+    const uint32_t pos = boff[blockIdx.x] + block_excl_scan256(vis ? 1u : 0u, s_w, nullptr);
+    if (vis) list[pos] = (uint32_t)i;
+}
+
+// exclusive scan in place of nb block sums by one 1024-thread block; total -> *total
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ v, int nb, uint32_t *__restrict__ total) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int idx = base + threadIdx.x;
+        const uint32_t x = idx < nb ? v[idx] : 0u;
+        const uint32_t inc = wave_incl_scan(x);
+        const int w = threadIdx.x >> 6;
+        if (__lane_id() == 63) s_w[w] = inc;
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (int k = 0; k < 16; k++) {
+            wb += k < w ? s_w[k] : 0u;
+            tot += s_w[k];
+        }
+        const uint32_t carry = s_carry;
+        if (idx < nb) v[idx] = carry + wb + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = s_carry;
+}
+
+// dpose[v][e] = sum over waves of the partial sums (fixed order: deterministic)
+// One workgroup per (view, component): the sum of the per-wave partials of the waves that ran
+// (all nw waves, or those covering the first *vcount entries of the visible list), in a fixed
+// order, so the pose gradient is reproducible.
+__global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ part, int64_t nw,
+                                                     const uint32_t *__restrict__ vcount,
+                                                     double *__restrict__ dpose) {
+    __shared__ double s_w[4];
+    const int64_t live = vcount ? 4 * ceil_div((int64_t)*vcount, 256) : nw;
+    const double *p = part + (int64_t)blockIdx.x * nw;
     double acc = 0;
-    for (int b = __lane_id(); b < nblocks; b += 64) acc += part[((int64_t)b * V + v) * 6 + e];
+    for (int64_t w = threadIdx.x; w < live; w += 256) acc += p[w];
     acc = wave_sum_d(acc);
-    if (__lane_id() == 0) dpose[v * 6 + e] = acc;
+    if (__lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) dpose[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
 }
 
 }  // namespace gsr
@@ -461,33 +659,66 @@ extern "C" gsr_status gsr_project_launch(const gsr_gaussians *g, const gsr_camer
 }
 
 extern "C" size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views) {
-    const int64_t nb = ceil_div(n > 0 ? n : 1, 256);
-    return (size_t)(nb * (n_views > 0 ? n_views : 1) * 6 * sizeof(double) + 256);
+    const int64_t nw = 4 * ceil_div(n > 0 ? n : 1, 256);  // per-wave pose partials
+    return (size_t)(nw * (n_views > 0 ? n_views : 1) * 6 * sizeof(double) + 256);
 }
 
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_camera *cams, int V,
-                                             const gsr_raster *r, float *dsplat, const gsr_param_grads *out,
+                                             const gsr_raster *r, const gsr_splat *splats, float *dsplat, const gsr_param_grads *out,
                                              double *dpose, const uint32_t *tile_info, const int32_t *seg,
-                                             int32_t min_seg, uint8_t *row_mask, void *ws, hipStream_t st) {
+                                             int32_t min_seg, uint8_t *row_mask, const gsr_adam_fused *fa,
+                                             const uint32_t *vlist, const uint32_t *vcount, void *ws,
+                                             hipStream_t st) {
     const int nb = (int)ceil_div(g->n, 256);
     if (nb == 0) {
         if (dpose) {
             // no Gaussians: zero pose gradient
-            k_pose_reduce<<<V, 384, 0, st>>>(static_cast<double *>(ws), 0, V, dpose);
+            k_pose_reduce<<<V * 6, 256, 0, st>>>(static_cast<double *>(ws), 0, nullptr, dpose);
         }
         return last_launch();
     }
     double *part = dpose ? static_cast<double *>(ws) : nullptr;
-#define GSR_PB(D)                                                                                          \
-    k_project_bwd<D><<<nb, 256, 0, st>>>(*g, cams, V, r->width, r->height, dsplat, *out, part, tile_info, seg, \
-                                         min_seg, row_mask)
-    switch (g->sh_degree) {
-        case 0: GSR_PB(0); break;
-        case 1: GSR_PB(1); break;
-        case 2: GSR_PB(2); break;
-        default: GSR_PB(3); break;
+    FusedAdam A{};
+    gsr_param_grads none{};
+    if (fa) {
+        A.m = fa->m;
+        A.v = fa->v;
+        for (int k = 0; k < 6; k++) A.lr[k] = fa->lr[k];
+        A.b1 = fa->beta1;
+        A.b2 = fa->beta2;
+        A.eps = fa->eps;
+        A.step = fa->step;
     }
+    const gsr_param_grads &O = out ? *out : none;
+#define GSR_PB(D, F)                                                                                          \
+    k_project_bwd<D, F><<<nb, 256, 0, st>>>(*g, cams, V, r->width, r->height, splats, dsplat, O, part, tile_info, seg, \
+                                            min_seg, row_mask, A, vlist, vcount)
+#define GSR_PBD(F)                   \
+    switch (g->sh_degree) {          \
+        case 0: GSR_PB(0, F); break; \
+        case 1: GSR_PB(1, F); break; \
+        case 2: GSR_PB(2, F); break; \
+        default: GSR_PB(3, F); break; \
+    }
+    if (fa) {
+        GSR_PBD(true)
+    } else {
+        GSR_PBD(false)
+    }
+#undef GSR_PBD
 #undef GSR_PB
-    if (dpose) k_pose_reduce<<<V, 384, 0, st>>>(part, nb, V, dpose);
+    if (dpose) k_pose_reduce<<<V * 6, 256, 0, st>>>(part, 4 * (int64_t)nb, vlist ? vcount : nullptr, dpose);
+    return last_launch();
+}
+
+extern "C" size_t gsr_visible_list_ws_bytes(int64_t n) { return (size_t)(ceil_div(n > 0 ? n : 1, 256) * 4 + 256); }
+
+extern "C" gsr_status gsr_visible_list_launch(const uint32_t *info, int64_t n, int V, uint32_t *list, uint32_t *count,
+                                              void *ws, hipStream_t st) {
+    const int nb = (int)ceil_div(n > 0 ? n : 1, 256);
+    uint32_t *bsum = static_cast<uint32_t *>(ws);
+    k_vis_any_count<<<nb, 256, 0, st>>>(info, n, V, bsum);
+    k_scan_blocks<<<1, 1024, 0, st>>>(bsum, nb, count);
+    k_vis_any_write<<<nb, 256, 0, st>>>(info, n, V, bsum, list);
     return last_launch();
 }

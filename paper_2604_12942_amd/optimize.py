@@ -19,7 +19,7 @@ DEFAULT_LR = dict(means=5e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, 
 
 class MapOptimizer:
     def __init__(self, params, sh_degree, cam_pool, target_rgb, target_depth, raster, n_views, lambda_depth=0.2,
-                 lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda"):
+                 lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda", fused=True):
         """params: dict of float32 [c, n] device tensors (optimised in place); cam_pool: device
         uint8 [S*96] gsr_camera records; target_rgb [S,3,H,W], target_depth [S,H,W] (or None)."""
         self.P = params
@@ -44,6 +44,12 @@ class MapOptimizer:
         self.view_idx = torch.zeros(self.V, dtype=torch.int64, device=device)
         self.view_idx32 = torch.zeros(self.V, dtype=torch.int32, device=device)
         self.cams = torch.empty(self.V * 96, dtype=torch.uint8, device=device)
+        self.fused = fused
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        from . import visible_list_workspace
+        self.vis_list = torch.empty(max(1, self.n), dtype=torch.int32, device=device)
+        self.vis_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.vis_ws = torch.empty((visible_list_workspace(self.n) + 3) // 4, dtype=torch.int32, device=device)
         self.t = 0
 
     def set_views(self, idx):
@@ -70,7 +76,7 @@ class MapOptimizer:
         torch.index_select(self.cam_pool, 0, self.view_idx, out=self.cams.view(-1, 96))
         self.view_idx32.copy_(self.view_idx)
         mark("gather")
-        from . import project, bin_sort, render_fwd, render_bwd, project_bwd
+        from . import project, render_fwd, render_bwd, project_bwd, project_bwd_adam, visible_list
         project(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.tile_info)
         mark("project")
         r.bin(check_capacity)
@@ -87,10 +93,22 @@ class MapOptimizer:
                    self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dsplat,
                    tile_order=r.tile_order)
         mark("render_bwd")
-        project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.dsplat, self.grads, r.dpose,
-                    r.pose_ws, r.tile_info, self.segment_id, self.min_segment, self.row_mask)
-        mark("project_bwd")
         self.t += 1
-        adam_step(self._groups(), self.n, self.row_mask, step=self.t)
-        mark("adam")
+        if self.fused:
+            self.step_dev += 1
+            lr = self.lr
+            visible_list(r.tile_info, self.n, self.V, self.vis_list, self.vis_count, self.vis_ws)
+            self.row_mask.zero_()
+            lrs = (lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"], lr["sh_rest"])
+            project_bwd_adam(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dsplat, r.tile_info,
+                             self.m, self.v, lrs, self.step_dev, r.dpose, r.pose_ws, self.segment_id,
+                             self.min_segment, self.row_mask, vis_list=self.vis_list, vis_count=self.vis_count)
+            mark("project_bwd")
+            mark("adam")
+        else:
+            project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dsplat, self.grads, r.dpose,
+                        r.pose_ws, r.tile_info, self.segment_id, self.min_segment, self.row_mask)
+            mark("project_bwd")
+            adam_step(self._groups(), self.n, self.row_mask, step=self.t)
+            mark("adam")
         return self.loss
