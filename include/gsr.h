@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 1
+#define GSR_ABI_VERSION 2
 #define GSR_API __attribute__((visibility("default")))
 
 typedef enum {
@@ -126,21 +126,33 @@ GSR_API gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams, i
  * Gaussian) that project's rectangle covers and orders them lexicographically by
  * (view, tile index ty*ntx+tx, float32 depth bits, Gaussian index): visible pairs are first
  * radix-sorted stably by depth bits (index order breaks ties), then instances are emitted in
- * that order and radix-sorted stably by (view, tile).  Outputs inst_gid [capacity] (v*n + i of
- * each instance, in that order), tile_ranges [V*T][2] ([start, end) per view-tile) and
- * *n_instances (device uint32: the REQUIRED instance count M).  If M > capacity nothing
- * beyond capacity is written and the results are incomplete: the caller compares
- * *n_instances with capacity after synchronising and re-runs with more room.
+ * that order ("emission order": a pair's tiles row-major and consecutive) and radix-sorted
+ * stably by (view, tile).  Outputs, all device memory:
+ *   inst_gid    [capacity]  v*n + i of each instance, in sorted order
+ *   tile_ranges [V*T][2]    [start, end) of each view-tile's instances
+ *   *n_instances            (uint32) the REQUIRED instance count M.
+ * If M > capacity nothing beyond capacity is written and the results are incomplete: the caller
+ * compares *n_instances with capacity after synchronising and re-runs with more room.
  * tile_order (device uint32 [V*T], may be NULL) receives the view-tiles sorted by descending
  * instance count (ties by index): the longest-processing-time-first launch order the render
  * kernels use to keep heavy tiles off the tail of the grid.
+ * em (may be NULL; needed by the backward) receives the emission bookkeeping, see gsr_emission.
  * ws: device workspace of at least gsr_bin_sort_workspace(n, n_views, capacity, r) bytes,
  * 256-byte aligned.  Errors: GSR_E_INVALID (bad pointers or sizes, capacity >= 2^32),
  * GSR_E_CAPACITY (ws_bytes too small). */
+typedef struct {
+    uint32_t *inst_emit;  /* [capacity]: emission index of each sorted instance (where
+                             gsr_render_bwd stores its gradient record)                      */
+    uint32_t *pair_gid;   /* [V*n]: the visible pairs (v*n + i) in emission order             */
+    uint32_t *pair_first; /* [V*n]: emission index of each listed pair's first instance; the
+                             pair has tile_info row 0 many instances                          */
+    uint32_t *n_pairs;    /* [1]: number of listed pairs                                      */
+} gsr_emission;
 GSR_API size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t capacity, const gsr_raster *r);
 GSR_API gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
-                        uint32_t *inst_gid, int64_t capacity, uint32_t *tile_ranges, uint32_t *n_instances,
-                        uint32_t *tile_order, void *ws, size_t ws_bytes, gsr_stream stream);
+                                uint32_t *inst_gid, const gsr_emission *em, int64_t capacity,
+                                uint32_t *tile_ranges, uint32_t *n_instances, uint32_t *tile_order, void *ws,
+                                size_t ws_bytes, gsr_stream stream);
 
 /* ---- render forward --------------------------------------------------------------------------
  * Front-to-back alpha compositing per pixel (Sec. III-C; Eq. 8).  For each view-tile's
@@ -158,45 +170,57 @@ GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_
 /* ---- render backward -------------------------------------------------------------------------
  * Exact gradient of the forward's outputs (every discrete decision held) given dL/drgb
  * [V][3][H][W] and dL/ddepth [V][H][W] (may be NULL).  Walks each pixel's instances back to
- * front, recovering transmittance by division, and ACCUMULATES the screen-space gradient of
- * every (view, Gaussian) into dsplat [V*n][10] (layout GSR_SPLAT_GRAD_FLOATS; the caller
- * zeroes it).  Float atomics make the summation order, not the result, run-dependent. */
-GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
-                          const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r, const float *T_final,
-                          const uint32_t *last, const float *dL_drgb, const float *dL_ddepth, float *dsplat,
-                          gsr_stream stream);
+ * front, recovering transmittance by division.  For EVERY instance k < M of gsr_bin_sort it
+ * stores, at dinst[inst_emit[k]][0..9] (inst_emit = gsr_emission.inst_emit) (float32 [capacity][GSR_SPLAT_GRAD_FLOATS]), the
+ * screen-space gradient that its tile's pixels give its (view, Gaussian) pair: plain stores, no
+ * accumulation and no clearing needed.  A pair's gradient is the sum of its instances' records
+ * (gsr_pair_grads, or inside gsr_project_bwd), taken in a fixed order, so results repeat
+ * bit-for-bit from run to run. */
+GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                  const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
+                                  int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,
+                                  const float *dL_drgb, const float *dL_ddepth, float *dinst, gsr_stream stream);
+
+/* Screen-space gradient per (view, Gaussian): dsplat [V*n][10] (OVERWRITTEN) = the sum, in
+ * emission order, of the pair's instance records in dinst (from gsr_render_bwd); the pairs and
+ * their first records come from em (gsr_bin_sort), their counts from tile_info row 0
+ * (gsr_project); zero for pairs that were not rendered. */
+GSR_API gsr_status gsr_pair_grads(const float *dinst, const gsr_emission *em, const uint32_t *tile_info, int64_t n,
+                                  int32_t n_views, float *dsplat, gsr_stream stream);
 
 /* ---- project backward ------------------------------------------------------------------------
  * Chain rule from the screen-space gradients to every parameter, summed over views, plus the
  * per-view camera-pose gradient for a left perturbation T <- Exp(xi) T, xi = (rho, phi)
- * (translation first): p -> p + rho + phi x p.  Gradients are ACCUMULATED into out;
- * dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  splats: the records gsr_project wrote for
- * these parameters (their clamped colours fix the colour clamp decisions).  ws:
- * gsr_project_bwd_workspace bytes.
- * tile_info (as written by gsr_project, may be NULL): when given, only the pairs with
- * n_tiles > 0 are read -- the others must hold zeros, which render_bwd never changes -- and the
- * pairs read are reset to zero, so dsplat is left all-zero for the next backward.
+ * (translation first): p -> p + rho + phi x p.  The screen-space gradient of each rendered pair
+ * (tile_info row 0 > 0) is the sum of its instance records dinst (gsr_render_bwd), located by
+ * em (gsr_bin_sort); tile_info is the one gsr_project wrote.  Gradients are
+ * ACCUMULATED into out; dpose [V][6] (float64, may be NULL) is OVERWRITTEN.  splats: the records
+ * gsr_project wrote for these parameters (their clamped colours fix the colour clamp
+ * decisions).  ws: device workspace of gsr_project_bwd_workspace(n, V) bytes, 256-byte aligned,
+ * required when n > 0 (it holds the per-pair sums of the instance records and the pose
+ * partials; GSR_E_CAPACITY if smaller).
  * Optional sparse-update mask (Sec. III-C: only visible Gaussians of the latest segments are
- * updated): if row_mask [n] is not NULL (requires tile_info) it receives 1 for Gaussians that
- * are visible in at least one view and whose segment_id [n] is >= min_segment (segment_id
- * NULL = no freezing), else 0. */
+ * updated): if row_mask [n] is not NULL it receives 1 for Gaussians that are visible in at
+ * least one view and whose segment_id [n] is >= min_segment (segment_id NULL = no freezing),
+ * else 0. */
 GSR_API size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views);
-GSR_API gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
-                           const gsr_splat *splats, float *dsplat, const gsr_param_grads *out, double *dpose, const uint32_t *tile_info,
-                           const int32_t *segment_id, int32_t min_segment, uint8_t *row_mask, void *ws,
-                           size_t ws_bytes, gsr_stream stream);
+GSR_API gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                                   const gsr_raster *r, const gsr_splat *splats, const float *dinst,
+                                   const gsr_emission *em, const uint32_t *tile_info, const gsr_param_grads *out,
+                                   double *dpose, const int32_t *segment_id, int32_t min_segment, uint8_t *row_mask,
+                                   void *ws, size_t ws_bytes, gsr_stream stream);
 
 /* ---- project backward fused with sparse Adam ---------------------------------------------------
  * The optimisation step's form of gsr_project_bwd followed by gsr_adam_step (Sec. III-C: visible
  * Gaussians of the latest segments are refined by a sparse gradient optimiser): the parameter
  * gradients never leave registers.  For every Gaussian visible in at least one view (tile_info
- * row 0 > 0; tile_info required) whose segment_id >= min_segment (segment_id NULL = all), the
+ * row 0 > 0) whose segment_id >= min_segment (segment_id NULL = all), the
  * Adam update of gsr_adam_step is applied IN PLACE to the parameter arrays of g, with the moments
  * in adam->m / adam->v (same layouts), per-group learning rates adam->lr = {means, log_scales,
  * quats, opacity_logits, sh rows 0-2 (DC), sh rows 3.. (rest)} and the 1-based step number read
  * from device memory (*adam->step, so a captured graph can replay with an incremented step).
- * All other rows are untouched.  dsplat is consumed (left zeroed) as in gsr_project_bwd; dpose
- * and row_mask as in gsr_project_bwd. */
+ * All other rows are untouched.  dinst, em, tile_info, dpose and row_mask as in
+ * gsr_project_bwd. */
 typedef struct {
     gsr_param_grads m, v;
     float lr[6];
@@ -204,7 +228,8 @@ typedef struct {
     const int32_t *step;
 } gsr_adam_fused;
 GSR_API gsr_status gsr_project_bwd_adam(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
-                                        const gsr_raster *r, const gsr_splat *splats, float *dsplat, const uint32_t *tile_info,
+                                        const gsr_raster *r, const gsr_splat *splats, const float *dinst,
+                                        const gsr_emission *em, const uint32_t *tile_info,
                                         const uint32_t *visible_list, const uint32_t *visible_count,
                                         const int32_t *segment_id, int32_t min_segment, const gsr_adam_fused *adam,
                                         double *dpose, uint8_t *row_mask, void *ws, size_t ws_bytes,

@@ -104,8 +104,18 @@ def bin_sort_workspace(n, n_views, capacity, raster):
     return int(lib().gsr_bin_sort_workspace(n, n_views, capacity, C.byref(raster.c)))
 
 
-def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_instances, ws, tile_order=None):
-    check(lib().gsr_bin_sort(_ptr(tile_info), n, n_views, C.byref(raster.c), _ptr(inst_gid), capacity,
+def emission(inst_emit, pair_gid, pair_first, n_pairs):
+    """gsr_emission struct over four device int32 tensors (see gsr_bin_sort)."""
+    return _abi.Emission(_ptr(inst_emit), _ptr(pair_gid), _ptr(pair_first), _ptr(n_pairs))
+
+
+def _em(em):
+    return C.byref(em) if em is not None else None
+
+
+def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_instances, ws, tile_order=None,
+             em=None):
+    check(lib().gsr_bin_sort(_ptr(tile_info), n, n_views, C.byref(raster.c), _ptr(inst_gid), _em(em), capacity,
                              _ptr(tile_ranges), _ptr(n_instances), _ptr(tile_order), _ptr(ws),
                              ws.numel() * ws.element_size(), _stream()), "gsr_bin_sort")
 
@@ -117,25 +127,30 @@ def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth,
                                _ptr(n_contrib), _stream()), "gsr_render_fwd")
 
 
-def render_bwd(splats, inst_gid, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth, dsplat,
-               tile_order=None):
-    check(lib().gsr_render_bwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
-                               n_views, C.byref(raster.c), _ptr(T_final), _ptr(last), _ptr(dL_drgb),
-                               _ptr(dL_ddepth), _ptr(dsplat), _stream()), "gsr_render_bwd")
+def render_bwd(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth,
+               dinst, tile_order=None):
+    check(lib().gsr_render_bwd(_ptr(splats), _ptr(inst_gid), _ptr(inst_emit), _ptr(tile_ranges), _ptr(tile_order),
+                               _ptr(cams), n_views, C.byref(raster.c), _ptr(T_final), _ptr(last), _ptr(dL_drgb),
+                               _ptr(dL_ddepth), _ptr(dinst), _stream()), "gsr_render_bwd")
+
+
+def pair_grads(dinst, em, tile_info, n, n_views, dsplat):
+    check(lib().gsr_pair_grads(_ptr(dinst), _em(em), _ptr(tile_info), n, n_views, _ptr(dsplat), _stream()),
+          "gsr_pair_grads")
 
 
 def project_bwd_workspace(n, n_views):
     return int(lib().gsr_project_bwd_workspace(n, n_views))
 
 
-def project_bwd(P, sh_degree, cams, n_views, raster, splats, dsplat, grads, dpose, ws, tile_info=None,
+def project_bwd(P, sh_degree, cams, n_views, raster, splats, dinst, em, tile_info, grads, dpose, ws,
                 segment_id=None, min_segment=0, row_mask=None):
     g = _gauss_struct(P, sh_degree)
     gr = _abi.ParamGrads(*[grads[k].data_ptr() for k in PARAM_NAMES])
-    check(lib().gsr_project_bwd(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(dsplat),
-                                C.byref(gr),
-                                _ptr(dpose), _ptr(tile_info), _ptr(segment_id), int(min_segment), _ptr(row_mask),
-                                _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
+    check(lib().gsr_project_bwd(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(dinst),
+                                _em(em), _ptr(tile_info), C.byref(gr), _ptr(dpose), _ptr(segment_id),
+                                int(min_segment), _ptr(row_mask), _ptr(ws),
+                                ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
           "gsr_project_bwd")
 
 
@@ -148,7 +163,8 @@ def visible_list(tile_info, n, n_views, out_list, out_count, ws):
                                  ws.numel() * ws.element_size(), _stream()), "gsr_visible_list")
 
 
-def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dsplat, tile_info, m, v, lr, step_dev, dpose, ws,
+def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dinst, em, tile_info, m, v, lr, step_dev,
+                     dpose, ws,
                      segment_id=None, min_segment=0, row_mask=None, beta1=0.9, beta2=0.999, eps=1e-15,
                      vis_list=None, vis_count=None):
     """Projection backward fused with sparse Adam: P (parameters) is updated in place.
@@ -160,8 +176,8 @@ def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dsplat, tile_i
     A.lr[:] = [float(x) for x in lr]
     A.beta1, A.beta2, A.eps = beta1, beta2, eps
     A.step = step_dev.data_ptr()
-    check(lib().gsr_project_bwd_adam(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(dsplat),
-                                     _ptr(tile_info), _ptr(vis_list), _ptr(vis_count), _ptr(segment_id),
+    check(lib().gsr_project_bwd_adam(C.byref(g), _ptr(cams), n_views, C.byref(raster.c), _ptr(splats), _ptr(dinst),
+                                     _em(em), _ptr(tile_info), _ptr(vis_list), _ptr(vis_count), _ptr(segment_id),
                                      int(min_segment), C.byref(A), _ptr(dpose),
                                      _ptr(row_mask), _ptr(ws), ws.numel() * ws.element_size(), _stream()),
           "gsr_project_bwd_adam")
@@ -216,16 +232,21 @@ class Rasterizer:
         self.depth = torch.empty(self.V, raster.height, raster.width, dtype=f32, device=device)
         self.T_final = torch.empty(self.V, raster.height, raster.width, dtype=f32, device=device)
         self.last = torch.empty(self.V, raster.height, raster.width, dtype=i32, device=device)
-        self.dsplat = torch.zeros(VN * _abi.SPLAT_GRAD_FLOATS, dtype=f32, device=device)
+        self.pair_gid = torch.empty(max(1, VN), dtype=i32, device=device)
+        self.pair_first = torch.empty(max(1, VN), dtype=i32, device=device)
+        self.n_pairs = torch.zeros(1, dtype=i32, device=device)
         self.pose_ws = torch.empty(max(1, project_bwd_workspace(self.n, self.V) // 8), dtype=torch.float64,
                                    device=device)
         self.dpose = torch.zeros(self.V, 6, dtype=torch.float64, device=device)
-        self.keep_dsplat = False  # tests: keep a copy of the screen-space gradients
+        self.keep_dsplat = False  # tests: keep the per-pair screen-space gradients
         self._alloc_instances(capacity if capacity else max(1 << 16, 4 * VN))
 
     def _alloc_instances(self, cap):
         self.capacity = int(min(cap, (1 << 32) - 2))
         self.inst_gid = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        self.inst_emit = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        self.dinst = torch.empty(self.capacity * _abi.SPLAT_GRAD_FLOATS, dtype=torch.float32, device=self.device)
+        self.em = emission(self.inst_emit, self.pair_gid, self.pair_first, self.n_pairs)
         wsb = bin_sort_workspace(self.n, self.V, self.capacity, self.raster)
         self.bin_ws = torch.empty((wsb + 255) // 256 * 64, dtype=torch.int32, device=self.device)
 
@@ -238,31 +259,36 @@ class Rasterizer:
         return self.rgb, self.depth, self.T_final
 
     def bin(self, check_capacity=True):
-        bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity, self.tile_ranges,
-                 self.n_instances, self.bin_ws, self.tile_order)
+        def run():
+            bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity, self.tile_ranges,
+                     self.n_instances, self.bin_ws, self.tile_order, self.em)
+        run()
         if check_capacity:
             m = int(self.n_instances.item()) & 0xFFFFFFFF
             if m > self.capacity:
                 self._alloc_instances(int(m * 1.25) + 1024)
-                bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity,
-                         self.tile_ranges, self.n_instances, self.bin_ws, self.tile_order)
+                run()
 
     def instances(self):
         return int(self.n_instances.item()) & 0xFFFFFFFF
 
     def backward(self, P, sh_degree, cams, dL_drgb, dL_ddepth, grads, want_pose=True, segment_id=None,
                  min_segment=0, row_mask=None):
-        """render bwd -> project bwd; parameter gradients are accumulated into grads.  The
-        screen-space gradient buffer is consumed (left zeroed) by project bwd."""
-        render_bwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.T_final, self.last,
-                   dL_drgb.contiguous(), dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dsplat,
-                   tile_order=self.tile_order)
+        """render bwd -> project bwd; parameter gradients are accumulated into grads."""
+        render_bwd(self.splats, self.inst_gid, self.inst_emit, self.tile_ranges, cams, self.V, self.raster,
+                   self.T_final, self.last, dL_drgb.contiguous(),
+                   dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dinst, tile_order=self.tile_order)
         if self.keep_dsplat:
-            self.dsplat_copy = self.dsplat.clone()
-        project_bwd(P, sh_degree, cams, self.V, self.raster, self.splats, self.dsplat, grads,
-                    self.dpose if want_pose else None, self.pose_ws, self.tile_info, segment_id, min_segment,
+            self.dsplat_copy = self.screen_grads()
+        project_bwd(P, sh_degree, cams, self.V, self.raster, self.splats, self.dinst, self.em, self.tile_info, grads, self.dpose if want_pose else None, self.pose_ws, segment_id, min_segment,
                     row_mask)
         return self.dpose
+
+    def screen_grads(self):
+        """Per-pair screen-space gradients [V*n*10] of the last backward."""
+        out = torch.empty(self.V * self.n * _abi.SPLAT_GRAD_FLOATS, dtype=torch.float32, device=self.device)
+        pair_grads(self.dinst, self.em, self.tile_info, self.n, self.V, out)
+        return out
 
 
 class _RasterizeFn(torch.autograd.Function):

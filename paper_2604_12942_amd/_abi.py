@@ -41,6 +41,11 @@ class AdamGroups(C.Structure):
                 ("_pad", C.c_int32)]
 
 
+class Emission(C.Structure):
+    _fields_ = [("inst_emit", C.c_void_p), ("pair_gid", C.c_void_p), ("pair_first", C.c_void_p),
+                ("n_pairs", C.c_void_p)]
+
+
 assert C.sizeof(Camera) == 96
 assert C.sizeof(Gaussians) == 56
 
@@ -53,14 +58,16 @@ _SIGS = {
     "gsr_tiles_per_view": ([C.POINTER(Raster)], C.c_int64),
     "gsr_project": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, P], C.c_int),
     "gsr_bin_sort_workspace": ([C.c_int64, C.c_int32, C.c_int64, C.POINTER(Raster)], C.c_size_t),
-    "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.c_int64, P, P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.POINTER(Emission), C.c_int64, P, P, P, P,
+                      C.c_size_t, P], C.c_int),
     "gsr_render_fwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
-    "gsr_render_bwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_render_bwd": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_pair_grads": ([P, C.POINTER(Emission), P, C.c_int64, C.c_int32, P, P], C.c_int),
     "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
-    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, C.POINTER(ParamGrads), P, P,
-                         P, C.c_int32, P, P, C.c_size_t, P], C.c_int),
-    "gsr_project_bwd_adam": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P, C.c_int32,
-                              C.POINTER(AdamFused), P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, C.POINTER(Emission), P,
+                         C.POINTER(ParamGrads), P, P, C.c_int32, P, P, C.c_size_t, P], C.c_int),
+    "gsr_project_bwd_adam": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, C.POINTER(Emission), P,
+                              P, P, P, C.c_int32, C.POINTER(AdamFused), P, P, P, C.c_size_t, P], C.c_int),
     "gsr_visible_list_workspace": ([C.c_int64], C.c_size_t),
     "gsr_visible_list": ([P, C.c_int64, C.c_int32, P, P, P, C.c_size_t, P], C.c_int),
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),

@@ -6,21 +6,24 @@ using namespace gsr;
 extern "C" gsr_status gsr_project_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
                                          gsr_splat *, uint32_t *, hipStream_t);
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *, const gsr_camera *, int, const gsr_raster *,
-                                             const gsr_splat *, float *, const gsr_param_grads *, double *, const uint32_t *,
-                                             const int32_t *, int32_t, uint8_t *, const gsr_adam_fused *,
-                                             const uint32_t *, const uint32_t *, void *, hipStream_t);
+                                             const gsr_splat *, const float *, const gsr_emission *,
+                                             const gsr_param_grads *, double *, const uint32_t *, const int32_t *,
+                                             int32_t, uint8_t *, const gsr_adam_fused *, const uint32_t *,
+                                             const uint32_t *, void *, hipStream_t);
 extern "C" size_t gsr_visible_list_ws_bytes(int64_t n);
 extern "C" gsr_status gsr_visible_list_launch(const uint32_t *, int64_t, int, uint32_t *, uint32_t *, void *,
                                               hipStream_t);
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT);
-extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, int64_t, uint32_t *,
-                                          uint32_t *, uint32_t *, void *, hipStream_t);
+extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, const gsr_emission *,
+                                          int64_t, uint32_t *, uint32_t *, uint32_t *, void *, hipStream_t);
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
                                             uint32_t *, uint32_t *, hipStream_t);
 extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
-                                            const gsr_camera *, int, const gsr_raster *, const float *,
+                                            const uint32_t *, const gsr_camera *, int, const gsr_raster *, const float *,
                                             const uint32_t *, const float *, const float *, float *, hipStream_t);
+extern "C" gsr_status gsr_pair_grads_launch(const float *, const gsr_emission *, const uint32_t *, int64_t, float *,
+                                            bool, hipStream_t);
 extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const uint8_t *, float, float, float, int,
                                       hipStream_t);
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
@@ -46,6 +49,8 @@ int64_t tiles(const gsr_raster *r) {
 }
 
 hipStream_t S(gsr_stream s) { return static_cast<hipStream_t>(s); }
+
+bool emission_ok(const gsr_emission *em) { return em && em->pair_gid && em->pair_first && em->n_pairs; }
 
 }  // namespace
 
@@ -79,13 +84,14 @@ extern "C" size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t cap
 }
 
 extern "C" gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
-                                   uint32_t *inst_gid, int64_t capacity, uint32_t *tile_ranges,
-                                   uint32_t *n_instances, uint32_t *tile_order, void *ws, size_t ws_bytes,
-                                   gsr_stream stream) {
+                                   uint32_t *inst_gid, const gsr_emission *em, int64_t capacity,
+                                   uint32_t *tile_ranges, uint32_t *n_instances, uint32_t *tile_order, void *ws,
+                                   size_t ws_bytes, gsr_stream stream) {
     if (!raster_ok(r) || n < 0 || n_views < 1 || capacity < 1 || capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
     if ((int64_t)n_views * n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
     if (!tile_info && n > 0) return GSR_E_INVALID;
     if (!inst_gid || !tile_ranges || !n_instances || !ws) return GSR_E_INVALID;
+    if (em && (!em->inst_emit || !em->pair_gid || !em->pair_first || !em->n_pairs)) return GSR_E_INVALID;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
     if (ws_bytes < gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity, (int64_t)n_views * tiles(r)))
         return GSR_E_CAPACITY;
@@ -99,9 +105,13 @@ extern "C" gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t
             s = gsr_tile_order_identity(tile_order, (int64_t)n_views * ntx * nty, S(stream));
             if (s != GSR_OK) return s;
         }
+        if (em) {
+            s = gsr_fill_u32_launch(em->n_pairs, 0u, 1, S(stream));
+            if (s != GSR_OK) return s;
+        }
         return gsr_fill_u32_launch(n_instances, 0u, 1, S(stream));
     }
-    return gsr_bin_sort_launch(tile_info, n, n_views, ntx, nty, inst_gid, capacity, tile_ranges, n_instances,
+    return gsr_bin_sort_launch(tile_info, n, n_views, ntx, nty, inst_gid, em, capacity, tile_ranges, n_instances,
                                tile_order, ws, S(stream));
 }
 
@@ -115,48 +125,62 @@ extern "C" gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *in
                                  last, n_contrib, S(stream));
 }
 
-extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
-                                     const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
-                                     const float *T_final, const uint32_t *last, const float *dL_drgb,
-                                     const float *dL_ddepth, float *dsplat, gsr_stream stream) {
-    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !T_final || !last || !dL_drgb || !dsplat)
+extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                     const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
+                                     int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,
+                                     const float *dL_drgb, const float *dL_ddepth, float *dinst, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !T_final || !last || !dL_drgb || !dinst ||
+        !inst_emit || !inst_gid || !splats)
         return GSR_E_INVALID;
-    return gsr_render_bwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, T_final, last, dL_drgb,
-                                 dL_ddepth, dsplat, S(stream));
+    return gsr_render_bwd_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, T_final, last,
+                                 dL_drgb, dL_ddepth, dinst, S(stream));
+}
+
+extern "C" gsr_status gsr_pair_grads(const float *dinst, const gsr_emission *em, const uint32_t *tile_info, int64_t n,
+                                     int32_t n_views, float *dsplat, gsr_stream stream) {
+    if (n < 0 || n_views < 1) return GSR_E_INVALID;
+    if ((int64_t)n_views * n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (n > 0 && (!dinst || !emission_ok(em) || !tile_info || !dsplat)) return GSR_E_INVALID;
+    return gsr_pair_grads_launch(dinst, em, tile_info, (int64_t)n_views * n, dsplat, true, S(stream));
 }
 
 extern "C" gsr_status gsr_project_bwd(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
-                                      const gsr_raster *r, const gsr_splat *splats, float *dsplat, const gsr_param_grads *out,
-                                      double *dpose, const uint32_t *tile_info, const int32_t *segment_id,
+                                      const gsr_raster *r, const gsr_splat *splats, const float *dinst,
+                                      const gsr_emission *em, const uint32_t *tile_info, const gsr_param_grads *out, double *dpose, const int32_t *segment_id,
                                       int32_t min_segment, uint8_t *row_mask, void *ws, size_t ws_bytes,
                                       gsr_stream stream) {
     if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams || !out) return GSR_E_INVALID;
-    if (g->n > 0 && (!splats || !dsplat || !out->means || !out->log_scales || !out->quats || !out->opacity_logits ||
-                     !out->sh))
+    if ((int64_t)n_views * g->n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (g->n > 0 && (!splats || !dinst || !emission_ok(em) || !tile_info || !out->means || !out->log_scales ||
+                     !out->quats || !out->opacity_logits || !out->sh))
         return GSR_E_INVALID;
-    if (row_mask && !tile_info && g->n > 0) return GSR_E_INVALID;
-    if (dpose && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
-    return gsr_project_bwd_launch(g, cams, n_views, r, splats, dsplat, out, dpose, tile_info, segment_id,
+    if (g->n > 0 && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
+    return gsr_project_bwd_launch(g, cams, n_views, r, splats, dinst, em, out, dpose, tile_info, segment_id,
                                   min_segment, row_mask, nullptr, nullptr, nullptr, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_project_bwd_adam(const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
-                                           const gsr_raster *r, const gsr_splat *splats, float *dsplat, const uint32_t *tile_info,
+                                           const gsr_raster *r, const gsr_splat *splats, const float *dinst,
+                                           const gsr_emission *em, const uint32_t *tile_info,
                                            const uint32_t *visible_list, const uint32_t *visible_count,
                                            const int32_t *segment_id, int32_t min_segment,
                                            const gsr_adam_fused *adam, double *dpose, uint8_t *row_mask, void *ws,
                                            size_t ws_bytes, gsr_stream stream) {
     if ((visible_list == nullptr) != (visible_count == nullptr)) return GSR_E_INVALID;
     if (!gauss_ok(g) || !raster_ok(r) || n_views < 1 || !cams || !adam) return GSR_E_INVALID;
-    if (g->n > 0 && (!splats || !dsplat || !tile_info || !adam->step || !adam->m.means || !adam->m.log_scales ||
-                     !adam->m.quats || !adam->m.opacity_logits || !adam->m.sh || !adam->v.means ||
-                     !adam->v.log_scales || !adam->v.quats || !adam->v.opacity_logits || !adam->v.sh))
+    if ((int64_t)n_views * g->n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (g->n > 0 && (!splats || !dinst || !emission_ok(em) || !tile_info || !adam->step || !adam->m.means ||
+                     !adam->m.log_scales || !adam->m.quats || !adam->m.opacity_logits || !adam->m.sh ||
+                     !adam->v.means || !adam->v.log_scales || !adam->v.quats || !adam->v.opacity_logits ||
+                     !adam->v.sh))
         return GSR_E_INVALID;
     if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f && adam->eps >= 0.f))
         return GSR_E_INVALID;
-    if (dpose && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
-    return gsr_project_bwd_launch(g, cams, n_views, r, splats, dsplat, nullptr, dpose, tile_info, segment_id,
-                                  min_segment, row_mask, adam, visible_list, visible_count, ws, S(stream));
+    if (g->n > 0 && (!ws || ws_bytes < gsr_project_bwd_workspace(g->n, n_views))) return GSR_E_CAPACITY;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
+    return gsr_project_bwd_launch(g, cams, n_views, r, splats, dinst, em, nullptr, dpose, tile_info,
+                                  segment_id, min_segment, row_mask, adam, visible_list, visible_count, ws, S(stream));
 }
 
 extern "C" size_t gsr_visible_list_workspace(int64_t n) { return n < 0 ? 0 : gsr_visible_list_ws_bytes(n); }

@@ -16,6 +16,10 @@ __device__ __forceinline__ uint32_t dev_count(const uint32_t *n_dev, uint32_t n_
 }
 
 // ---- generic helpers -------------------------------------------------------------------------
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ dst, uint32_t value, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = value;
@@ -131,6 +135,7 @@ __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ 
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                        uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                       const uint32_t *__restrict__ vin2, uint32_t *__restrict__ vout2,
                                                        const uint32_t *n_dev, uint32_t n_host, uint32_t cap, int shift,
                                                        int nblocks, const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ totals) {
@@ -152,13 +157,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     s_run[t] = 0;
     for (int k = 0; k < 4; k++) s_wcnt[k][t] = 0;
     __syncthreads();
-    uint32_t mk[kSortItems], mv[kSortItems], mpos[kSortItems];
+    uint32_t mk[kSortItems], mv[kSortItems], mpos[kSortItems], mv2[kSortItems];
     const uint64_t lt = lanemask_lt();
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + t;
         const bool valid = idx < n;
         mk[r] = valid ? kin[idx] : 0u;
         mv[r] = valid ? vin[idx] : 0u;
+        mv2[r] = (valid && vin2) ? vin2[idx] : 0u;
         const uint32_t d = (mk[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit8(d, valid);
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
@@ -197,50 +203,94 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
             vout[dst] = s_vals[p];
         }
     }
+    if (vin2) {
+        // the second payload takes the same permutation through the same LDS staging
+        __syncthreads();
+        for (int r = 0; r < kSortItems; r++) {
+            const uint32_t idx = base + r * kSortThreads + t;
+            if (idx < n) s_vals[s_lstart[(mk[r] >> shift) & (kRadix - 1)] + mpos[r]] = mv2[r];
+        }
+        __syncthreads();
+        for (int r = 0; r < kSortItems; r++) {
+            const uint32_t p = r * kSortThreads + t;
+            if (p < bn) {
+                const uint32_t d = (s_keys[p] >> shift) & (kRadix - 1);
+                vout2[s_gbase[d] + (p - s_lstart[d])] = s_vals[p];
+            }
+        }
+    }
 }
 
 // ---- instance emission in depth order --------------------------------------------------------
+// Instance count of each block of 256 depth-ordered visible pairs.
 __global__ __launch_bounds__(256) void k_inst_count(const uint32_t *__restrict__ sorted_gid, const uint32_t *n_vis,
                                                     uint32_t cap, const uint32_t *__restrict__ ntiles,
                                                     uint32_t *__restrict__ bsum) {
     __shared__ uint32_t s_w[4];
     const uint32_t n = dev_count(n_vis, 0, cap);
-    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
-    uint32_t c = 0;
-    for (int k = 0; k < kSortItems; k++)
-        if (base + k < n) c += ntiles[sorted_gid[base + k]];
+    const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x * 256 >= n) {
+        if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
+        return;
+    }
+    const uint32_t c = idx < n ? ntiles[sorted_gid[idx]] : 0u;
     uint32_t tot;
     block_excl_scan256(c, s_w, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
+// Emission of the instances of 256 depth-ordered visible pairs per block, load-balanced: the
+// block's instances are spread over its threads (instance k of the block goes to thread
+// k mod 256, which finds its pair by binary search over the pairs' offsets in LDS), so the
+// writes are coalesced.  A pair's tiles are emitted row-major and consecutively ("emission
+// order").  With pair_gid: the emission-ordered list of visible pairs and the emission index of
+// each pair's first instance, and the sort's second payload (each instance's emission index).
 __global__ __launch_bounds__(256) void k_inst_emit(const uint32_t *__restrict__ sorted_gid, const uint32_t *n_vis,
                                                    uint32_t cap_vis, const uint32_t *__restrict__ info, uint32_t VN,
                                                    uint32_t n, uint32_t T, uint32_t ntx,
                                                    const uint32_t *__restrict__ boff, uint32_t *__restrict__ ikey,
-                                                   uint32_t *__restrict__ ival, uint32_t cap) {
+                                                   uint32_t *__restrict__ ival, uint32_t *__restrict__ iemit,
+                                                   uint32_t *__restrict__ pair_gid, uint32_t *__restrict__ pair_first,
+                                                   uint32_t cap) {
     __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_off[256], s_gid[256], s_r0[256], s_r1[256];
     const uint32_t nv = dev_count(n_vis, 0, cap_vis);
-    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
-    uint32_t c = 0;
-    for (int k = 0; k < kSortItems; k++)
-        if (base + k < nv) c += info[sorted_gid[base + k]];
-    uint32_t pos = boff[blockIdx.x] + block_excl_scan256(c, s_w, nullptr);
-    for (int k = 0; k < kSortItems; k++) {
-        if (base + k >= nv) break;
-        const uint32_t gid = sorted_gid[base + k];
-        const uint32_t v = gid / n;
-        const uint32_t r0 = info[2 * VN + gid], r1 = info[3 * VN + gid];
-        const uint32_t tx0 = r0 & 0xffffu, ty0 = r0 >> 16, tx1 = r1 & 0xffffu, ty1 = r1 >> 16;
-        const uint32_t vb = v * T;
-        for (uint32_t ty = ty0; ty <= ty1; ty++)
-            for (uint32_t tx = tx0; tx <= tx1; tx++) {
-                if (pos < cap) {
-                    ikey[pos] = vb + ty * ntx + tx;
-                    ival[pos] = gid;
-                }
-                pos++;
-            }
+    if (blockIdx.x * 256 >= nv) return;
+    const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = idx < nv;
+    const uint32_t gid = valid ? sorted_gid[idx] : 0u;
+    const uint32_t c = valid ? info[gid] : 0u;
+    uint32_t tot;
+    const uint32_t excl = block_excl_scan256(c, s_w, &tot);
+    const uint32_t base = boff[blockIdx.x];
+    s_off[threadIdx.x] = excl;
+    s_gid[threadIdx.x] = gid;
+    s_r0[threadIdx.x] = valid ? info[2 * VN + gid] : 0u;
+    s_r1[threadIdx.x] = valid ? info[3 * VN + gid] : 0u;
+    if (valid && pair_gid) {
+        pair_gid[idx] = gid;
+        pair_first[idx] = base + excl;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < tot; k += 256) {
+        // the last pair whose offset is <= k (pairs without instances share the next one's offset)
+        uint32_t lo = 0, hi = 256;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= k) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t g = s_gid[lo], r0 = s_r0[lo], r1 = s_r1[lo];
+        const uint32_t local = k - s_off[lo];
+        const uint32_t tx0 = r0 & 0xffffu, ty0 = r0 >> 16, tx1 = r1 & 0xffffu;
+        const uint32_t wdt = tx1 - tx0 + 1;
+        const uint32_t ly = local / wdt, lx = local - ly * wdt;
+        const uint32_t pos = base + k;
+        if (pos < cap) {
+            ikey[pos] = (g / n) * T + (ty0 + ly) * ntx + tx0 + lx;
+            ival[pos] = g;
+            if (iemit) iemit[pos] = pos;
+        }
     }
 }
 
@@ -272,9 +322,9 @@ namespace {
 
 struct BinWs {
     uint32_t *zk0, *zv0, *zk1, *zv1;  // depth sort ping-pong [VN]
-    uint32_t *vis_b, *cnt_b;          // block sums [nb_vn]
+    uint32_t *vis_b, *cnt_b;          // block sums [nb_vn], [VN / 256]
     uint32_t *n_vis;                  // 1
-    uint32_t *ik0, *ik1, *iv1;        // instance sort [cap]
+    uint32_t *ik0, *ik1, *iv1, *iw1;  // instance sort [cap]
     uint32_t *tk0, *tk1, *tv1;        // tile-order sort [VT]
     uint32_t *hist;                   // [256][max nb]
     uint32_t *totals;                 // [256]
@@ -297,8 +347,8 @@ BinWs layout(void *base, int64_t VN, int64_t cap, int64_t VT) {
         return r;
     };
     w.zk0 = take(VN); w.zv0 = take(VN); w.zk1 = take(VN); w.zv1 = take(VN);
-    w.vis_b = take(nb_vn); w.cnt_b = take(nb_vn); w.n_vis = take(1);
-    w.ik0 = take(cap); w.ik1 = take(cap); w.iv1 = take(cap);
+    w.vis_b = take(nb_vn); w.cnt_b = take(ceil_div(VN > 0 ? VN : 1, 256)); w.n_vis = take(1);
+    w.ik0 = take(cap); w.ik1 = take(cap); w.iv1 = take(cap); w.iw1 = take(cap);
     w.tk0 = take(VT); w.tk1 = take(VT); w.tv1 = take(VT);
     w.hist = take((size_t)kRadix * nbm); w.totals = take(kRadix);
     w.bytes = off;
@@ -306,14 +356,21 @@ BinWs layout(void *base, int64_t VN, int64_t cap, int64_t VT) {
 }
 
 gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, const uint32_t *n_dev,
-                      uint32_t n_host, uint32_t cap, int bits, uint32_t *hist, uint32_t *totals, hipStream_t st) {
+                      uint32_t n_host, uint32_t cap, int bits, uint32_t *hist, uint32_t *totals, hipStream_t st,
+                      uint32_t **w = nullptr, uint32_t **w2 = nullptr) {
     const int nb = (int)ceil_div(cap, kSortTile);
     for (int shift = 0; shift < bits; shift += kRadixBits) {
         k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, n_host, cap, shift, nb, hist);
         k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals);
-        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, n_dev, n_host, cap, shift, nb, hist, totals);
+        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, w ? *w : nullptr, w ? *w2 : nullptr, n_dev,
+                                                     n_host, cap, shift, nb, hist, totals);
         uint32_t *tk = k, *tv = v;
         k = k2; v = v2; k2 = tk; v2 = tv;
+        if (w) {
+            uint32_t *tw = *w;
+            *w = *w2;
+            *w2 = tw;
+        }
     }
     return last_launch();
 }
@@ -329,8 +386,9 @@ int bit_length(uint64_t x) {
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT) { return layout(nullptr, VN, cap, VT).bytes; }
 
 extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V, int ntx, int nty,
-                                          uint32_t *inst_gid, int64_t cap, uint32_t *ranges, uint32_t *n_inst,
-                                          uint32_t *tile_order, void *ws, hipStream_t st) {
+                                          uint32_t *inst_gid, const gsr_emission *em, int64_t cap,
+                                          uint32_t *ranges, uint32_t *n_inst, uint32_t *tile_order, void *ws,
+                                          hipStream_t st) {
     const int64_t VN = (int64_t)V * n;
     const uint32_t T = (uint32_t)(ntx * nty);
     const int64_t VT = (int64_t)V * T;
@@ -345,18 +403,25 @@ extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V
     gsr_status s = radix_sort(k, v, k2, v2, w.n_vis, 0, (uint32_t)(VN > 0 ? VN : 1), 32, w.hist, w.totals, st);
     if (s != GSR_OK) return s;
     // 3. instance counts in depth order, scan, emission
-    k_inst_count<<<nb_vn, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, w.cnt_b);
-    k_scan_small<<<1, 1024, 0, st>>>(w.cnt_b, nb_vn, n_inst);
+    const int nb_p = (int)ceil_div(VN > 0 ? VN : 1, 256);
+    k_inst_count<<<nb_p, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, w.cnt_b);
+    k_scan_small<<<1, 1024, 0, st>>>(w.cnt_b, nb_p, n_inst);
     // the instance sort runs ceil(bits/8) passes; emit into the buffer that makes the last
-    // pass land in inst_gid
+    // pass land in the sorted-values output (inst_emit when asked for, else inst_gid)
     const int tbits = bit_length((uint64_t)V * T - 1) > 0 ? bit_length((uint64_t)V * T - 1) : 1;
     const int passes = (tbits + kRadixBits - 1) / kRadixBits;
     uint32_t *ek = w.ik0, *ev = (passes % 2 == 0) ? inst_gid : w.iv1;
     uint32_t *ok = w.ik1, *ov = (passes % 2 == 0) ? w.iv1 : inst_gid;
-    k_inst_emit<<<nb_vn, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, (uint32_t)VN, (uint32_t)n, T,
-                                       (uint32_t)ntx, w.cnt_b, ek, ev, (uint32_t)cap);
-    // 4. stable sort by view-tile
-    s = radix_sort(ek, ev, ok, ov, n_inst, 0, (uint32_t)cap, passes * kRadixBits, w.hist, w.totals, st);
+    uint32_t *inst_emit = em ? em->inst_emit : nullptr;
+    uint32_t *ew = inst_emit ? ((passes % 2 == 0) ? inst_emit : w.iw1) : nullptr;
+    uint32_t *ow = inst_emit ? ((passes % 2 == 0) ? w.iw1 : inst_emit) : nullptr;
+    k_inst_emit<<<nb_p, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, (uint32_t)VN, (uint32_t)n, T,
+                                      (uint32_t)ntx, w.cnt_b, ek, ev, ew, em ? em->pair_gid : nullptr,
+                                      em ? em->pair_first : nullptr, (uint32_t)cap);
+    if (em) k_copy_u32<<<1, 64, 0, st>>>(w.n_vis, em->n_pairs, 1);
+    // 4. stable sort by view-tile (carrying the emission index along when asked for)
+    s = radix_sort(ek, ev, ok, ov, n_inst, 0, (uint32_t)cap, passes * kRadixBits, w.hist, w.totals, st,
+                   inst_emit ? &ew : nullptr, inst_emit ? &ow : nullptr);
     if (s != GSR_OK) return s;
     // 5. per view-tile [start, end)
     k_fill_u32<<<(int)ceil_div(2 * (int64_t)V * T, 256) < 4096 ? (int)ceil_div(2 * (int64_t)V * T, 256) : 4096, 256, 0,

@@ -327,15 +327,16 @@ struct FusedAdam {
     const int32_t *step;
 };
 
-// Chain rule from the screen-space gradients to the parameters and the per-view pose.  With
-// tile_info, a Gaussian that no view rendered costs V 4-byte reads and nothing else.  FUSED:
+// Chain rule from the screen-space gradients (per pair, dsplat) to the parameters and the
+// per-view pose.  A Gaussian that no view rendered costs V 4-byte reads of tile_info and nothing
+// else.  FUSED:
 // instead of accumulating gradients, visible Gaussians of unfrozen segments take their sparse
 // Adam step directly from the register-held gradient (no gradient buffer round trip).  The SH
 // coefficient gradients accumulate across views in LDS ([coefficient][thread], conflict-free).
 template <int DEG, bool FUSED>
 __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_camera *__restrict__ cams, int V,
                                                      int W, int H, const gsr_splat *__restrict__ splats,
-                                                     float *__restrict__ dsplat,
+                                                     const float *__restrict__ dsplat,
                                                      gsr_param_grads out, double *__restrict__ pose_part,
                                                      const uint32_t *__restrict__ tile_info,
                                                      const int32_t *__restrict__ seg, int32_t min_seg,
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
     const bool live = t < cnt;
     const int64_t i = live ? (vlist ? (int64_t)vlist[t] : t) : 0;
     bool anyvis = live;
-    if (live && tile_info) {
+    if (live) {
         anyvis = false;
         for (int vi = 0; vi < V; vi++) anyvis |= tile_info[(int64_t)vi * n + i] > 0;
     }
@@ -382,12 +383,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
         float gs[10];
         bool any = false;
         if (anyvis) {
-            // with tile_info, only the pairs that were rendered can hold gradients: read those and
-            // reset them, leaving dsplat zeroed for the next backward without a separate fill
-            const bool vis = tile_info ? tile_info[(int64_t)vi * n + i] > 0 : true;
+            // only rendered pairs hold gradients (summed per pair beforehand)
+            const bool vis = tile_info[(int64_t)vi * n + i] > 0;
             visible |= vis;
+#pragma unroll
+            for (int e = 0; e < 10; e++) gs[e] = 0.f;
             if (vis) {
-                float2 *s2 = reinterpret_cast<float2 *>(dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS);
+                const float2 *s2 = reinterpret_cast<const float2 *>(dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS);
 #pragma unroll
                 for (int e = 0; e < 5; e++) {
                     const float2 q = s2[e];
@@ -396,10 +398,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
                 }
 #pragma unroll
                 for (int e = 0; e < 10; e++) any |= gs[e] != 0.f;
-                if (tile_info && any) {
-#pragma unroll
-                    for (int e = 0; e < 5; e++) s2[e] = make_float2(0.f, 0.f);
-                }
             }
         }
         Cam k;
@@ -658,13 +656,24 @@ extern "C" gsr_status gsr_project_launch(const gsr_gaussians *g, const gsr_camer
     return last_launch();
 }
 
-extern "C" size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views) {
-    const int64_t nw = 4 * ceil_div(n > 0 ? n : 1, 256);  // per-wave pose partials
-    return (size_t)(nw * (n_views > 0 ? n_views : 1) * 6 * sizeof(double) + 256);
+// Workspace: per-wave pose partials [V][6][waves] (float64), then the per-pair screen-space
+// gradients [V*n][10] (float32) summed from the instance records.
+static size_t pose_part_bytes(int64_t n, int32_t V) {
+    const int64_t nw = 4 * ceil_div(n > 0 ? n : 1, 256);
+    return (size_t)((nw * (V > 0 ? V : 1) * 6 * sizeof(double) + 255) & ~(int64_t)255);
 }
 
+extern "C" size_t gsr_project_bwd_workspace(int64_t n, int32_t n_views) {
+    return pose_part_bytes(n, n_views) +
+           (size_t)((n > 0 ? n : 1) * (int64_t)(n_views > 0 ? n_views : 1) * GSR_SPLAT_GRAD_FLOATS * sizeof(float)) + 256;
+}
+
+extern "C" gsr_status gsr_pair_grads_launch(const float *, const gsr_emission *, const uint32_t *, int64_t, float *,
+                                            bool, hipStream_t);
+
 extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_camera *cams, int V,
-                                             const gsr_raster *r, const gsr_splat *splats, float *dsplat, const gsr_param_grads *out,
+                                             const gsr_raster *r, const gsr_splat *splats, const float *dinst,
+                                             const gsr_emission *em, const gsr_param_grads *out,
                                              double *dpose, const uint32_t *tile_info, const int32_t *seg,
                                              int32_t min_seg, uint8_t *row_mask, const gsr_adam_fused *fa,
                                              const uint32_t *vlist, const uint32_t *vcount, void *ws,
@@ -678,6 +687,9 @@ extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_c
         return last_launch();
     }
     double *part = dpose ? static_cast<double *>(ws) : nullptr;
+    float *dsplat = reinterpret_cast<float *>(static_cast<char *>(ws) + pose_part_bytes(g->n, V));
+    gsr_status s = gsr_pair_grads_launch(dinst, em, tile_info, (int64_t)V * g->n, dsplat, false, st);
+    if (s != GSR_OK) return s;
     FusedAdam A{};
     gsr_param_grads none{};
     if (fa) {
@@ -691,8 +703,8 @@ extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_c
     }
     const gsr_param_grads &O = out ? *out : none;
 #define GSR_PB(D, F)                                                                                          \
-    k_project_bwd<D, F><<<nb, 256, 0, st>>>(*g, cams, V, r->width, r->height, splats, dsplat, O, part, tile_info, seg, \
-                                            min_seg, row_mask, A, vlist, vcount)
+    k_project_bwd<D, F><<<nb, 256, 0, st>>>(*g, cams, V, r->width, r->height, splats, dsplat, O, part, tile_info, \
+                                            seg, min_seg, row_mask, A, vlist, vcount)
 #define GSR_PBD(F)                   \
     switch (g->sh_degree) {          \
         case 0: GSR_PB(0, F); break; \

@@ -170,34 +170,102 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     if (ncon) ncon[(int64_t)v * P + pix] = nc;
 }
 
-// ---- wave64 inclusive scans over lane order (DPP row shifts, then row broadcasts) -------------
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_or(float src, float ident) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(ident), __float_as_int(src), CTRL, ROWS, 0xf,
-                                                      false));
+__global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0.f;
 }
+
+// ---- wave64 inclusive scans over lane order ---------------------------------------------------
+// In place, one DPP-sourced VALU op per step: row shifts by 1, 2, 4, 8 scan each 16-lane row,
+// then the row broadcasts of lanes 15 and 31 carry the row totals forward.  A lane whose source
+// lies outside its row (row_shr without bound_ctrl) or whose row is masked off (row_mask) is not
+// written and keeps its value, which is exactly the identity step of the scan.  Each step is
+// preceded by s_nop 1: two wait states between a VALU write of the register and its DPP read.
+// The whole wave must be active.
 __device__ __forceinline__ float wave_incl_prod(float v) {
-    v *= dpp_or<0x111, 0xf>(v, 1.0f);  // row_shr:1
-    v *= dpp_or<0x112, 0xf>(v, 1.0f);  // row_shr:2
-    v *= dpp_or<0x114, 0xf>(v, 1.0f);  // row_shr:4
-    v *= dpp_or<0x118, 0xf>(v, 1.0f);  // row_shr:8
-    v *= dpp_or<0x142, 0xa>(v, 1.0f);  // row_bcast:15 into rows 1 and 3
-    v *= dpp_or<0x143, 0xc>(v, 1.0f);  // row_bcast:31 into rows 2 and 3
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(v));
     return v;
 }
 __device__ __forceinline__ float wave_incl_sum(float v) {
-    v += dpp_or<0x111, 0xf>(v, 0.0f);
-    v += dpp_or<0x112, 0xf>(v, 0.0f);
-    v += dpp_or<0x114, 0xf>(v, 0.0f);
-    v += dpp_or<0x118, 0xf>(v, 0.0f);
-    v += dpp_or<0x142, 0xa>(v, 0.0f);
-    v += dpp_or<0x143, 0xc>(v, 0.0f);
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(v));
     return v;
+}
+
+// Two independent scans interleaved: each DPP op's source was written two instructions earlier
+// (the other scan's op and an s_nop 0), which covers the same two wait states.
+__device__ __forceinline__ void wave_incl_prod2(float &a, float &b) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void wave_incl_sum2(float &a, float &b) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(a), "+v"(b));
 }
 __device__ __forceinline__ float rdl(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
-__device__ __forceinline__ float wrl(float v, int lane, float old) { return __lane_id() == lane ? v : old; }
 
 // Backward, Gaussian-major.  The tile's instances up to the deepest pixel's last contributor are
 // staged back to front in batches of 256.  Each wave compacts the batch to the Gaussians that
@@ -205,12 +273,18 @@ __device__ __forceinline__ float wrl(float v, int lane, float old) { return __la
 // l-th deepest.  For each of the wave's 64 pixels every lane evaluates its Gaussian; a wave-wide
 // inclusive product scan of (1 - a) recovers the transmittance in front of each Gaussian from the
 // pixel's transmittance behind the chunk, and an inclusive sum scan of w (dL/dC . c + dL/dD z)
-// gives what lies behind it.  Gradients accumulate in registers across pixels, then in LDS across
-// waves (ds_add_f32 per staged slot), and leave with one global atomic per (tile, Gaussian,
-// component).
+// gives what lies behind it.  Pixel state (upstream gradient, transmittance and suffix behind
+// the chunks done so far) sits in LDS and is read by broadcast; the pixel centre by readlane.  Per lane, the mean and
+// conic gradients accumulate as the five moments sum dP (dx, dy, dx^2, dx dy, dy^2) of the
+// exponent gradient dP, mapped through the Cholesky factor once per chunk.  Gradients then
+// accumulate in LDS across waves (ds_add_f32 per staged slot) and leave as one plain 40-byte
+// record per instance, stored at the instance's emission index: the records of one (view,
+// Gaussian) pair are contiguous there, and the projection backward sums them in a fixed order,
+// so no global atomics are needed and the gradients are the same on every run.
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
+                                                    const uint32_t *__restrict__ inst_emit,
                                                     const uint32_t *__restrict__ ranges,
                                                     const uint32_t *__restrict__ order,
                                                     const gsr_camera *__restrict__ cams, int W, int H, int ntx,
@@ -218,11 +292,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                                                     const uint32_t *__restrict__ last,
                                                     const float *__restrict__ dLdrgb,
                                                     const float *__restrict__ dLddepth,
-                                                    float *__restrict__ dsplat) {
+                                                    float *__restrict__ dinst) {
     __shared__ float4 sA[256], sB[256], sC[256];
-    __shared__ uint32_t sG[256];
     __shared__ float sAcc[10][256];
     __shared__ uint8_t sList[4][256];
+    __shared__ float4 sPG[4][64];  // dL/dC (3), dL/dD
+    __shared__ float2 sPS[4][64];  // transmittance and suffix sum behind the chunks done so far
     __shared__ uint32_t s_max;
     const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
     const int v = item / T, tile = item % T;
@@ -233,27 +308,30 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
     const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
     const double ox = (double)bx, oy = (double)by;
-    // per-pixel state, one pixel per lane (read by the wave with readlane)
-    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;
     const int64_t P = (int64_t)W * H;
     const int64_t pix = (int64_t)py * W + px;
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     float wx0, wx1, wy0, wy1;
     wave_box<TW>(tx * TW - bx, ty * TH - by, w, wx0, wx1, wy0, wy1);
-    float Tr = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f;
+    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;  // pixel centre
     uint32_t mylast = 0;
-    if (inside) {
-        Tr = Tfin[(int64_t)v * P + pix];
-        mylast = last[(int64_t)v * P + pix];
-        G0 = dLdrgb[(int64_t)v * 3 * P + pix];
-        G1 = dLdrgb[(int64_t)v * 3 * P + P + pix];
-        G2 = dLdrgb[(int64_t)v * 3 * P + 2 * P + pix];
-        if (dLddepth) GD = dLddepth[(int64_t)v * P + pix];
+    {
+        float Tr = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f;
+        if (inside) {
+            Tr = Tfin[(int64_t)v * P + pix];
+            mylast = last[(int64_t)v * P + pix];
+            G0 = dLdrgb[(int64_t)v * 3 * P + pix];
+            G1 = dLdrgb[(int64_t)v * 3 * P + P + pix];
+            G2 = dLdrgb[(int64_t)v * 3 * P + 2 * P + pix];
+            if (dLddepth) GD = dLddepth[(int64_t)v * P + pix];
+        }
+        const gsr_camera &cam = cams[v];
+        // the suffix starts with the background term T_final (dL/dC . bg)
+        const float S = Tr * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
+        sPG[w][lane] = make_float4(G0, G1, G2, GD);
+        sPS[w][lane] = make_float2(Tr, S);
+        if (threadIdx.x == 0) s_max = 0;
     }
-    const gsr_camera &cam = cams[v];
-    // S = sum over contributors behind of w_j (dL/dC . c_j + dL/dD z_j) plus the background term
-    float S = Tr * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
-    if (threadIdx.x == 0) s_max = 0;
     for (int q = threadIdx.x; q < 2560; q += 256) (&sAcc[0][0])[q] = 0.f;
     __syncthreads();
     if (mylast) atomicMax(&s_max, mylast);
@@ -263,8 +341,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, off));
     __syncthreads();
     const uint32_t nl = min(s_max, end - start);
+    // instances behind every pixel's last contributor receive a zero record
+    for (uint32_t k = start + nl + threadIdx.x; k < end; k += 256) {
+        float2 *rec = reinterpret_cast<float2 *>(dinst + (int64_t)inst_emit[k] * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+        for (int e = 0; e < 5; e++) rec[e] = make_float2(0.f, 0.f);
+    }
     const float kap = (float)GSR_KAPPA;
-    const float ln2 = (float)GSR_LN2;
+    const float nln2 = -(float)GSR_LN2;
     for (int bend = (int)nl; bend > 0; bend -= 256) {
         const int b0 = bend > 256 ? bend - 256 : 0;
         const int cnt = bend - b0;
@@ -276,7 +360,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
             sA[threadIdx.x] = A;
             sB[threadIdx.x] = B;
             sC[threadIdx.x] = C;
-            sG[threadIdx.x] = gid;
         }
         __syncthreads();
         // compact the staged Gaussians that reach this wave's pixels, deepest first
@@ -302,67 +385,97 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
             const float4 B = gvalid ? sB[slot] : make_float4(0.f, -1.f, 0.f, 0.f);
             const float4 C = gvalid ? sC[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
             const uint32_t pos = (uint32_t)(b0 + slot);
+            const uint32_t posv = gvalid ? pos : 0xffffffffu;  // never below a last contributor
             // frontmost position of the chunk: the last valid lane
             const int lastlane = (nw - c0 < 64 ? nw - c0 : 64) - 1;
             const uint32_t cfront = (uint32_t)__builtin_amdgcn_readlane((int)pos, lastlane);
-            float acc[10];
-#pragma unroll
-            for (int e = 0; e < 10; e++) acc[e] = 0.f;
-            for (int p = 0; p < 64; p++) {
-                const uint32_t lastp = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
-                if (cfront >= lastp) continue;
-                const float pfx = rdl(fx, p), pfy = rdl(fy, p);
-                float dx, dy, u1, u2;
-                const float Pw = blend_exponent(A, B.x, pfx, pfy, dx, dy, u1, u2);
-                const bool act = gvalid && pos < lastp && Pw <= B.y;
-                if (__ballot(act) == 0) continue;  // no Gaussian of the chunk reaches this pixel
-                const float e2 = act ? __builtin_amdgcn_exp2f(-Pw) : 0.f;
-                const float ar = B.z * e2;
-                const float a = fminf(ar, GSR_ALPHA_MAX);
-                const float om = 1.0f - a;
-                const float Te = rdl(Tr, p), Se = rdl(S, p);
-                const float g0 = rdl(G0, p), g1 = rdl(G1, p), g2 = rdl(G2, p), gd = rdl(GD, p);
-                const float Pt = wave_incl_prod(om);
-                const float Tb = Te * __builtin_amdgcn_rcpf(Pt);  // transmittance in front of it
-                const float wgt = a * Tb;
-                const float gsum = g0 * C.x + g1 * C.y + g2 * C.z + gd * B.w;
-                const float wg = wgt * gsum;
-                const float incl = wave_incl_sum(wg);
-                const float Sa = Se + (incl - wg);  // everything behind it
-                const float dLda = Tb * gsum - Sa * __builtin_amdgcn_rcpf(om);
-                if (act) {
-                    acc[6] = __builtin_fmaf(g0, wgt, acc[6]);
-                    acc[7] = __builtin_fmaf(g1, wgt, acc[7]);
-                    acc[8] = __builtin_fmaf(g2, wgt, acc[8]);
-                    acc[9] = __builtin_fmaf(gd, wgt, acc[9]);
-                    if (ar <= GSR_ALPHA_MAX) {
-                        // alpha_raw = o 2^-P: d/dP = -ln2 alpha_raw, d/do = 2^-P
-                        const float dP = -ln2 * ar * dLda;
-                        acc[0] -= 2.0f * dP * (A.z * u1);
-                        acc[1] -= 2.0f * dP * (A.w * u1 + B.x * u2);
-                        acc[2] += dP * kap * dx * dx;
-                        acc[3] += dP * 2.0f * kap * dx * dy;
-                        acc[4] += dP * kap * dy * dy;
-                        acc[5] = __builtin_fmaf(dLda, e2, acc[5]);
-                    }
-                }
-                // the pixel's state in front of this chunk (inactive lanes carry a = 0)
-                Tr = wrl(rdl(Tb, 63), p, Tr);
-                S = wrl(Se + rdl(incl, 63), p, S);
+            float cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, go = 0.f;
+            float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f;
+            // two pixels per iteration: their chains are independent, which keeps the SIMD busy
+            // through the scan and transcendental latencies
+            for (int p = 0; p < 64; p += 2) {
+                const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
+                const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p + 1);
+                if (cfront >= l0 && cfront >= l1) continue;
+                const float4 pg0 = sPG[w][p], pg1 = sPG[w][p + 1];  // LDS broadcasts
+                const float4 ps = *reinterpret_cast<const float4 *>(&sPS[w][p]);
+                float dx0, dy0, dx1, dy1, t0, t1;
+                const float P0 = blend_exponent(A, B.x, rdl(fx, p), rdl(fy, p), dx0, dy0, t0, t1);
+                const float P1 = blend_exponent(A, B.x, rdl(fx, p + 1), rdl(fy, p + 1), dx1, dy1, t0, t1);
+                const bool act0 = posv < l0 && P0 <= B.y;
+                const bool act1 = posv < l1 && P1 <= B.y;
+                if (__ballot(act0 || act1) == 0) continue;  // no Gaussian of the chunk reaches them
+                const float e0 = act0 ? __builtin_amdgcn_exp2f(-P0) : 0.f;
+                const float e1 = act1 ? __builtin_amdgcn_exp2f(-P1) : 0.f;
+                const float ar0 = B.z * e0, ar1 = B.z * e1;
+                const float a0 = fminf(ar0, GSR_ALPHA_MAX), a1 = fminf(ar1, GSR_ALPHA_MAX);
+                const float om0 = 1.0f - a0, om1 = 1.0f - a1;
+                float Pt0 = om0, Pt1 = om1;
+                wave_incl_prod2(Pt0, Pt1);
+                // transmittance in front of each Gaussian
+                const float Tb0 = ps.x * __builtin_amdgcn_rcpf(Pt0);
+                const float Tb1 = ps.z * __builtin_amdgcn_rcpf(Pt1);
+                const float w0 = a0 * Tb0, w1 = a1 * Tb1;
+                const float gs0 =
+                    __builtin_fmaf(pg0.x, C.x, __builtin_fmaf(pg0.y, C.y, __builtin_fmaf(pg0.z, C.z, pg0.w * B.w)));
+                const float gs1 =
+                    __builtin_fmaf(pg1.x, C.x, __builtin_fmaf(pg1.y, C.y, __builtin_fmaf(pg1.z, C.z, pg1.w * B.w)));
+                const float wg0 = w0 * gs0, wg1 = w1 * gs1;
+                float in0 = wg0, in1 = wg1;
+                wave_incl_sum2(in0, in1);
+                // everything behind each Gaussian
+                const float Sa0 = ps.y + (in0 - wg0), Sa1 = ps.w + (in1 - wg1);
+                const float d0 = __builtin_fmaf(Tb0, gs0, -Sa0 * __builtin_amdgcn_rcpf(om0));
+                const float d1 = __builtin_fmaf(Tb1, gs1, -Sa1 * __builtin_amdgcn_rcpf(om1));
+                // colour and depth: weight w = a T (zero for lanes that do not blend)
+                cr = __builtin_fmaf(pg0.x, w0, __builtin_fmaf(pg1.x, w1, cr));
+                cg = __builtin_fmaf(pg0.y, w0, __builtin_fmaf(pg1.y, w1, cg));
+                cb = __builtin_fmaf(pg0.z, w0, __builtin_fmaf(pg1.z, w1, cb));
+                cd = __builtin_fmaf(pg0.w, w0, __builtin_fmaf(pg1.w, w1, cd));
+                // unclamped alpha = o 2^-P: dL/dP = -ln2 alpha dL/da, dL/do = 2^-P dL/da
+                const bool lin0 = act0 && ar0 <= GSR_ALPHA_MAX, lin1 = act1 && ar1 <= GSR_ALPHA_MAX;
+                const float dP0 = lin0 ? (nln2 * ar0) * d0 : 0.f;
+                const float dP1 = lin1 ? (nln2 * ar1) * d1 : 0.f;
+                go = __builtin_fmaf(lin0 ? d0 : 0.f, e0, __builtin_fmaf(lin1 ? d1 : 0.f, e1, go));
+                mx = __builtin_fmaf(dP0, dx0, __builtin_fmaf(dP1, dx1, mx));
+                my = __builtin_fmaf(dP0, dy0, __builtin_fmaf(dP1, dy1, my));
+                const float q0 = dP0 * dx0, q1 = dP1 * dx1;
+                mxx = __builtin_fmaf(q0, dx0, __builtin_fmaf(q1, dx1, mxx));
+                mxy = __builtin_fmaf(q0, dy0, __builtin_fmaf(q1, dy1, mxy));
+                myy = __builtin_fmaf(dP0 * dy0, dy0, __builtin_fmaf(dP1 * dy1, dy1, myy));
+                // the pixels' state in front of this chunk (inactive lanes carry a = 0)
+                if (lane == 63)
+                    *reinterpret_cast<float4 *>(&sPS[w][p]) = make_float4(Tb0, ps.y + in0, Tb1, ps.w + in1);
             }
             if (gvalid) {
+                // P = |L^T D|^2 with D = pixel - mean: dP/dmean = -2 L L^T D, dP/dQ = kappa D D^T
+                const float l11 = A.z, l21 = A.w, l22 = B.x;
+                const float m1 = __builtin_fmaf(l11, mx, l21 * my);
+                float acc[10];
+                acc[0] = -2.0f * (l11 * m1);
+                acc[1] = -2.0f * __builtin_fmaf(l21, m1, l22 * l22 * my);
+                acc[2] = kap * mxx;
+                acc[3] = 2.0f * kap * mxy;
+                acc[4] = kap * myy;
+                acc[5] = go;
+                acc[6] = cr;
+                acc[7] = cg;
+                acc[8] = cb;
+                acc[9] = cd;
 #pragma unroll
                 for (int e = 0; e < 10; e++)
                     if (acc[e] != 0.f) atomicAdd(&sAcc[e][slot], acc[e]);
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < 2560; q += 256) {
-            const int e = q >> 8, sl = q & 255;
-            const float sum = sAcc[e][sl];
-            if (sum != 0.f) {
-                atomicAdd(dsplat + (int64_t)sG[sl] * 10 + e, sum);
-                sAcc[e][sl] = 0.f;
+        if ((int)threadIdx.x < cnt) {
+            float2 *rec = reinterpret_cast<float2 *>(
+                dinst + (int64_t)inst_emit[start + b0 + threadIdx.x] * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                rec[e] = make_float2(sAcc[2 * e][threadIdx.x], sAcc[2 * e + 1][threadIdx.x]);
+                sAcc[2 * e][threadIdx.x] = 0.f;
+                sAcc[2 * e + 1][threadIdx.x] = 0.f;
             }
         }
     }
@@ -389,20 +502,60 @@ extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *splats, const uint3
     return last_launch();
 }
 
-extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *splats, const uint32_t *inst, const uint32_t *ranges,
-                                            const uint32_t *order, const gsr_camera *cams, int V,
-                                            const gsr_raster *r, const float *Tfin, const uint32_t *last,
-                                            const float *dLdrgb, const float *dLddepth, float *dsplat,
+extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *splats, const uint32_t *inst, const uint32_t *inst_emit,
+                                            const uint32_t *ranges, const uint32_t *order, const gsr_camera *cams,
+                                            int V, const gsr_raster *r, const float *Tfin, const uint32_t *last,
+                                            const float *dLdrgb, const float *dLddepth, float *dinst,
                                             hipStream_t st) {
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     const int T = ntx * nty;
     const int nb = V * T;
-#define GSR_RB(TW, TH)                                                                                          \
-    k_render_bwd<TW, TH><<<nb, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, r->height, ntx, T, \
-                                             Tfin, last, dLdrgb, dLddepth, dsplat)
+#define GSR_RB(TW, TH)                                                                                              \
+    k_render_bwd<TW, TH><<<nb, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width, r->height, ntx, \
+                                             T, Tfin, last, dLdrgb, dLddepth, dinst)
     if (r->tile_w == 16) GSR_RB(16, 16);
     else if (r->tile_w == 8) GSR_RB(8, 32);
     else GSR_RB(32, 8);
 #undef GSR_RB
+    return last_launch();
+}
+
+// Per-pair screen-space gradient: the fixed-order sum of the pair's instance records.  One
+// thread per visible pair in emission order, so a wave reads one contiguous run of records.
+__global__ void k_pair_grads(const float *__restrict__ dinst, const uint32_t *__restrict__ pair_gid,
+                             const uint32_t *__restrict__ pair_first, const uint32_t *__restrict__ n_pairs,
+                             const uint32_t *__restrict__ ntiles, float *__restrict__ dsplat) {
+    const uint32_t np = *n_pairs;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < np; q += gridDim.x * blockDim.x) {
+        const uint32_t gid = pair_gid[q];
+        const uint32_t cnt = ntiles[gid];
+        const float2 *rec = reinterpret_cast<const float2 *>(dinst + (int64_t)pair_first[q] * GSR_SPLAT_GRAD_FLOATS);
+        float acc[GSR_SPLAT_GRAD_FLOATS];
+#pragma unroll
+        for (int e = 0; e < GSR_SPLAT_GRAD_FLOATS; e++) acc[e] = 0.f;
+        for (uint32_t j = 0; j < cnt; j++)
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                const float2 x = rec[j * 5 + e];
+                acc[2 * e] += x.x;
+                acc[2 * e + 1] += x.y;
+            }
+        float2 *out = reinterpret_cast<float2 *>(dsplat + (int64_t)gid * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+        for (int e = 0; e < 5; e++) out[e] = make_float2(acc[2 * e], acc[2 * e + 1]);
+    }
+}
+
+// all_pairs: zero the pairs that were not rendered first (else they are left untouched).
+extern "C" gsr_status gsr_pair_grads_launch(const float *dinst, const gsr_emission *em, const uint32_t *tile_info,
+                                            int64_t VN, float *dsplat, bool all_pairs, hipStream_t st) {
+    if (VN <= 0) return GSR_OK;
+    if (all_pairs) {
+        const int64_t words = VN * GSR_SPLAT_GRAD_FLOATS;
+        const int nz = (int)(ceil_div(words, 256) < 16384 ? ceil_div(words, 256) : 16384);
+        k_zero_f32<<<nz, 256, 0, st>>>(dsplat, words);
+    }
+    const int nb = (int)(ceil_div(VN, 256) < 16384 ? ceil_div(VN, 256) : 16384);
+    k_pair_grads<<<nb, 256, 0, st>>>(dinst, em->pair_gid, em->pair_first, em->n_pairs, tile_info, dsplat);
     return last_launch();
 }

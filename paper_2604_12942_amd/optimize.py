@@ -89,8 +89,8 @@ class MapOptimizer:
                 self.loss, self.g_rgb, self.g_depth if self.target_depth is not None else None,
                 target_index=self.view_idx32)
         mark("loss")
-        render_bwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.T_final, r.last,
-                   self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dsplat,
+        render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
+                   r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,
                    tile_order=r.tile_order)
         mark("render_bwd")
         self.t += 1
@@ -100,14 +100,13 @@ class MapOptimizer:
             visible_list(r.tile_info, self.n, self.V, self.vis_list, self.vis_count, self.vis_ws)
             self.row_mask.zero_()
             lrs = (lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"], lr["sh_rest"])
-            project_bwd_adam(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dsplat, r.tile_info,
-                             self.m, self.v, lrs, self.step_dev, r.dpose, r.pose_ws, self.segment_id,
+            project_bwd_adam(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em,
+                             r.tile_info, self.m, self.v, lrs, self.step_dev, r.dpose, r.pose_ws, self.segment_id,
                              self.min_segment, self.row_mask, vis_list=self.vis_list, vis_count=self.vis_count)
             mark("project_bwd")
             mark("adam")
         else:
-            project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dsplat, self.grads, r.dpose,
-                        r.pose_ws, r.tile_info, self.segment_id, self.min_segment, self.row_mask)
+            project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em, r.tile_info, self.grads, r.dpose, r.pose_ws, self.segment_id, self.min_segment, self.row_mask)
             mark("project_bwd")
             adam_step(self._groups(), self.n, self.row_mask, step=self.t)
             mark("adam")

@@ -63,22 +63,34 @@ def tile_info(rast):
     return dict(n_tiles=ti[0], zbits=ti[1], tx0=ti[2] & 0xFFFF, ty0=ti[2] >> 16, tx1=ti[3] & 0xFFFF, ty1=ti[3] >> 16)
 
 
-def expected_instances(ti, n, V, raster):
-    """Reference order by numpy.lexsort on (view-tile, depth bits, pair index)."""
-    keys, zb, gids = [], [], []
+def expected_instances(ti, n, V, raster, with_emission=False):
+    """Reference order by numpy.lexsort on (view-tile, depth bits, pair index).  With
+    with_emission, also each sorted instance's emission index (pairs in (depth bits, index)
+    order, a pair's tiles row-major and consecutive) and each visible pair's first index."""
+    keys, zb, gids, local = [], [], [], []
     vis = np.nonzero(ti["n_tiles"] > 0)[0]
     for gid in vis:
         v = gid // n
+        j = 0
         for ty in range(ti["ty0"][gid], ti["ty1"][gid] + 1):
             for tx in range(ti["tx0"][gid], ti["tx1"][gid] + 1):
                 keys.append(v * raster.tiles + ty * raster.ntx + tx)
                 zb.append(ti["zbits"][gid])
                 gids.append(gid)
+                local.append(j)
+                j += 1
     keys = np.asarray(keys, np.int64)
     zb = np.asarray(zb, np.int64)
     gids = np.asarray(gids, np.int64)
+    local = np.asarray(local, np.int64)
     order = np.lexsort((gids, zb, keys))
-    return keys[order], gids[order]
+    if not with_emission:
+        return keys[order], gids[order]
+    porder = vis[np.lexsort((vis, ti["zbits"][vis].astype(np.int64)))]
+    cnt = ti["n_tiles"][porder].astype(np.int64)
+    first = dict(zip(porder.tolist(), (np.cumsum(cnt) - cnt).tolist()))
+    emit = np.array([first[g] for g in gids.tolist()], np.int64) + local
+    return keys[order], gids[order], emit[order], first
 
 
 def random_scene(seed, n, W, H, f, sh_degree=0, z_range=(1.5, 6.0), log_scale_mean=-2.5, xy_half=1.5, logit_shift=0.0):

@@ -98,11 +98,20 @@ def test_binning_order_bit_exact(name, tile):
     out, rast, P, ct = run_forward(g, cams, tile=tile)
     n = g["means"].shape[1]
     ti = tile_info(rast)
-    keys, gids = expected_instances(ti, n, 1, rast.raster)
+    keys, gids, emit, first = expected_instances(ti, n, 1, rast.raster, with_emission=True)
     M = out["M"]
     assert M == len(gids)
     got = rast.inst_gid[:M].cpu().numpy().astype(np.int64)
     assert np.array_equal(got, gids)
+    # emission indices (where the backward stores each instance's record), the emission-ordered
+    # pair list and each pair's first instance
+    assert np.array_equal(rast.inst_emit[:M].cpu().numpy().astype(np.int64), emit)
+    npairs = int(rast.n_pairs.item())
+    assert npairs == len(first)
+    pg = rast.pair_gid[:npairs].cpu().numpy().astype(np.int64)
+    pf = rast.pair_first[:npairs].cpu().numpy().astype(np.int64)
+    assert list(pg) == list(first.keys())  # dict insertion order = emission order
+    assert np.array_equal(pf, np.array([first[x] for x in pg], np.int64))
     rng = rast.tile_ranges.cpu().numpy().reshape(-1, 2).astype(np.int64)
     T = rast.raster.tiles
     exp = np.zeros((T, 2), np.int64)
@@ -178,7 +187,6 @@ def test_render_backward_matches_oracle(name):
     dpose = rast.backward(P, g["sh_degree"], ct, torch.from_numpy(GC[None]).cuda(),
                           torch.from_numpy(GD[None]).cuda(), grads)
     torch.cuda.synchronize()
-    assert torch.count_nonzero(rast.dsplat).item() == 0  # consumed by project bwd
     keep = ~o["knife_g"]
     # screen-space gradients per Gaussian (u, v, Qa, Qb, Qc, o, r, g, b, z)
     n = g["means"].shape[1]
