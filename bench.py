@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
     ap.add_argument("--points", type=int, default=1_500_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (reference for HBM byte counters)")
@@ -193,25 +194,22 @@ def main():
     print("tile autotune (s/step): %s -> %dx%d" % (tune, *tile), file=sys.stderr, flush=True)
 
     opt = make_opt(tile)
-    stages = ["gather", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "adam"]
+    stages = list(MapOptimizer.STAGES)
     stream = torch.cuda.current_stream()
 
-    def staged_steps(o, k, first_step, stage_pair=None):
-        """k steps with HIP events on the launch stream: after every stage, or (stage_pair =
-        (before, stage)) only around one stage.  Returns per-stage ms summed over the steps."""
+    def staged_steps(o, k, first_step):
+        """k eager steps with HIP events on the launch stream after every stage."""
         recs = []
         for s in range(k):
             evs = {}
 
             def mark(name, evs=evs):
-                if stage_pair is None or name in stage_pair:
-                    e = torch.cuda.Event(enable_timing=True)
-                    e.record(stream)
-                    evs[name] = e
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(stream)
+                evs[name] = e
 
             e0 = torch.cuda.Event(enable_timing=True)
-            if stage_pair is None:
-                e0.record(stream)
+            e0.record(stream)
             sv(o, first_step + s)
             o.step(check_capacity=False, timer=mark)
             recs.append((e0, evs))
@@ -240,18 +238,63 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     before = stages[stages.index(dom) - 1]
 
-    # timed region: K steps; HIP events only around the dominant kernel's stage
-    m_seen = torch.zeros(a.steps, dtype=torch.int32, device=dev)
+    # eager step time without events (for reference)
+    k_eager = max(3, min(a.steps, 10))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs = []
+    for s in range(k_eager):
+        sv(opt, s)
+        opt.step(check_capacity=False)
+    torch.cuda.synchronize()
+    eager_ms = 1000.0 * (time.perf_counter() - t0) / k_eager
+
+    # timed region: K steps; HIP events only around the dominant kernel's stage, recorded on the
+    # launch stream between the captured parts (or between eager stages)
+    i_dom = stages.index(dom)
+    use_graph = not a.no_graph
+    if use_graph:
+        split = (dom,) + ((stages[i_dom + 1],) if i_dom + 1 < len(stages) else ())
+        if i_dom == 0:
+            split = split[1:]
+        opt.capture(split=split)
+        dom_part = 0 if i_dom == 0 else 1
+    m_seen = torch.zeros(a.steps, dtype=torch.int32, device=dev)
+    ev_pairs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for s in range(a.steps):
-        recs += staged_steps(opt, 1, a.warmup + s, stage_pair=(before, dom))
+        e_a = torch.cuda.Event(enable_timing=True)
+        e_b = torch.cuda.Event(enable_timing=True)
+        sv(opt, a.warmup + s)
+        if use_graph:
+            if dom_part == 0:
+                e_a.record(stream)
+
+            def between(k, e_a=e_a, e_b=e_b):
+                if k == dom_part:
+                    e_a.record(stream)
+                elif k == dom_part + 1:
+                    e_b.record(stream)
+
+            opt.replay(between=between)
+            if dom_part + 1 == len(opt.graphs):
+                e_b.record(stream)
+        else:
+            def mark(name, e_a=e_a, e_b=e_b):
+                if name == before:
+                    e_a.record(stream)
+                elif name == dom:
+                    e_b.record(stream)
+
+            if i_dom == 0:
+                e_a.record(stream)
+            opt.step(check_capacity=False, timer=mark)
         m_seen[s:s + 1].copy_(opt.rast.n_instances)
+        ev_pairs.append((e_a, e_b))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / a.steps
-    dom_ms = sum(evs[before].elapsed_time(evs[dom]) for _, evs in recs) / a.steps
+    dom_ms = sum(e_a.elapsed_time(e_b) for e_a, e_b in ev_pairs) / a.steps
     m_all = m_seen.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
     if m_all.max() > opt.rast.capacity:
         print("instance capacity exceeded in the timed region", file=sys.stderr)
@@ -322,6 +365,8 @@ def main():
         "visible_pairs_per_step": Nv,
         "updated_rows": Nu,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "graph": use_graph,
+        "eager_ms_per_step": round(eager_ms, 3),
         "step_alg_bytes": B_alg,
         "step_hbm_frac": round(B_alg / step_s / (HBM_PEAK_GBS * 1e9), 4),
         "tile_autotune_s_per_step": {k: round(v, 5) for k, v in tune.items()},

@@ -68,46 +68,96 @@ class MapOptimizer:
             gs.append((P["sh"][3:], G["sh"][3:], M["sh"][3:], Vv["sh"][3:], lr["sh_rest"]))
         return gs
 
-    def step(self, check_capacity=True, timer=None):
-        """One optimisation iteration over the chosen views.  timer(stage) is called between
-        stages (e.g. to record events)."""
-        mark = timer or (lambda s: None)
-        r = self.rast
-        torch.index_select(self.cam_pool, 0, self.view_idx, out=self.cams.view(-1, 96))
-        self.view_idx32.copy_(self.view_idx)
-        mark("gather")
+    def _stage_fns(self, check_capacity):
+        """The step as an ordered list of (name, fn): every fn only enqueues device work (no host
+        synchronisation when check_capacity is False), so any run of stages can be captured."""
         from . import project, render_fwd, render_bwd, project_bwd, project_bwd_adam, visible_list
-        project(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.tile_info)
-        mark("project")
-        r.bin(check_capacity)
-        mark("bin_sort")
-        render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth, r.T_final,
-                   r.last, tile_order=r.tile_order)
-        mark("render_fwd")
-        self.loss.zero_()
-        loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
-                self.loss, self.g_rgb, self.g_depth if self.target_depth is not None else None,
-                target_index=self.view_idx32)
-        mark("loss")
-        render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
-                   r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,
-                   tile_order=r.tile_order)
-        mark("render_bwd")
-        self.t += 1
-        if self.fused:
-            self.step_dev += 1
-            lr = self.lr
-            visible_list(r.tile_info, self.n, self.V, self.vis_list, self.vis_count, self.vis_ws)
-            self.row_mask.zero_()
-            lrs = (lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"], lr["sh_rest"])
-            project_bwd_adam(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em,
-                             r.tile_info, self.m, self.v, lrs, self.step_dev, r.dpose, r.pose_ws, self.segment_id,
-                             self.min_segment, self.row_mask, vis_list=self.vis_list, vis_count=self.vis_count)
-            mark("project_bwd")
-            mark("adam")
-        else:
-            project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em, r.tile_info, self.grads, r.dpose, r.pose_ws, self.segment_id, self.min_segment, self.row_mask)
-            mark("project_bwd")
-            adam_step(self._groups(), self.n, self.row_mask, step=self.t)
-            mark("adam")
+        r = self.rast
+
+        def gather():
+            torch.index_select(self.cam_pool, 0, self.view_idx, out=self.cams.view(-1, 96))
+            self.view_idx32.copy_(self.view_idx)
+
+        def proj():
+            project(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.tile_info)
+
+        def binsort():
+            r.bin(check_capacity)
+
+        def fwd():
+            render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth,
+                       r.T_final, r.last, tile_order=r.tile_order)
+
+        def loss():
+            self.loss.zero_()
+            loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
+                    self.loss, self.g_rgb, self.g_depth if self.target_depth is not None else None,
+                    target_index=self.view_idx32)
+
+        def bwd():
+            render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
+                       r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,
+                       tile_order=r.tile_order)
+
+        def pbwd():
+            if self.fused:
+                self.step_dev += 1
+                lr = self.lr
+                visible_list(r.tile_info, self.n, self.V, self.vis_list, self.vis_count, self.vis_ws)
+                self.row_mask.zero_()
+                lrs = (lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"], lr["sh_rest"])
+                project_bwd_adam(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em,
+                                 r.tile_info, self.m, self.v, lrs, self.step_dev, r.dpose, r.pose_ws,
+                                 self.segment_id, self.min_segment, self.row_mask, vis_list=self.vis_list,
+                                 vis_count=self.vis_count)
+            else:
+                project_bwd(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em,
+                            r.tile_info, self.grads, r.dpose, r.pose_ws, self.segment_id, self.min_segment,
+                            self.row_mask)
+
+        def adam():
+            if not self.fused:
+                self.t += 1
+                adam_step(self._groups(), self.n, self.row_mask, step=self.t)
+
+        return [("gather", gather), ("project", proj), ("bin_sort", binsort), ("render_fwd", fwd), ("loss", loss),
+                ("render_bwd", bwd), ("project_bwd", pbwd), ("adam", adam)]
+
+    STAGES = ("gather", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "adam")
+
+    def step(self, check_capacity=True, timer=None):
+        """One optimisation iteration over the chosen views.  timer(stage) is called after each
+        stage (e.g. to record events)."""
+        for name, fn in self._stage_fns(check_capacity):
+            fn()
+            if timer:
+                timer(name)
+        return self.loss
+
+    def capture(self, split=()):
+        """Capture the fused step into HIP graphs, cut before each stage named in split (so that
+        events can be recorded between the parts).  The instance capacity is fixed from now on;
+        call after at least one eager step.  replay() then runs one step."""
+        if not self.fused:
+            raise ValueError("graph capture needs the fused step (its Adam step counter lives on the device)")
+        fns = self._stage_fns(False)
+        cuts = [0] + [self.STAGES.index(c) for c in split] + [len(fns)]
+        self.graphs = []
+        torch.cuda.synchronize()
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _, fn in fns[a:b]:
+                    fn()
+            self.graphs.append(g)
+        torch.cuda.synchronize()
+        return self.graphs
+
+    def replay(self, between=None):
+        """One step from the captured graphs; between(k) is called after part k (not after the
+        last)."""
+        for k, g in enumerate(self.graphs):
+            if k and between:
+                between(k)
+            g.replay()
         return self.loss
