@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
     ap.add_argument("--points", type=int, default=1_500_000)
+    ap.add_argument("--contrib-compare", action="store_true",
+                    help="instead of the step: stored vs recomputed contributor lists on the 4M-Gaussian 1080p view")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -113,8 +115,76 @@ def cpu_baseline(c, pool_cams, tg, step_views, n_sample=4):
                                                               pool_cams[0]["height"], dt, V))
 
 
+def contrib_compare(a):
+    """Forward + backward of one 1920x1080 view over 4M Gaussians in both contributor modes:
+    time per iteration and peak device memory (one JSON line)."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    t_gen = time.perf_counter()
+    c = synth.config4b()
+    print("workload built in %.1f s" % (time.perf_counter() - t_gen), file=sys.stderr, flush=True)
+    g, cam = c["gaussians"], c["cameras"][0]
+    dev = "cuda"
+    n = g["means"].shape[1]
+    H, W = cam["height"], cam["width"]
+    trgb = torch.from_numpy(c["target_rgb"][0][None]).to(dev)
+    tdep = torch.from_numpy(c["target_depth"][0][None]).to(dev)
+    ct = gsr.camera_tensor([cam], dev)
+    res = {}
+    for mode in ("recompute", "stored"):
+        torch.cuda.empty_cache()
+        P = gsr.gaussians_to_device(g, dev)
+        grads = {k: torch.zeros_like(P[k]) for k in gsr.PARAM_NAMES}
+        g_rgb = torch.empty(1, 3, H, W, device=dev)
+        g_dep = torch.empty(1, H, W, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        rast = gsr.Rasterizer(n, 1, gsr.Raster(W, H, 16, 16), mode=mode, device=dev)
+
+        def it(check):
+            rast.forward(P, g["sh_degree"], ct, check_capacity=check)
+            loss.zero_()
+            gsr.loss_l1(rast.rgb, rast.depth, trgb, tdep, 1, rast.raster, 0.2, loss, g_rgb, g_dep)
+            rast.backward(P, g["sh_degree"], ct, g_rgb, g_dep, grads, want_pose=True)
+
+        it(True)
+        torch.cuda.synchronize()
+        free0, total = torch.cuda.mem_get_info()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        reps = max(3, min(a.steps, 10))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            it(False)
+        e1.record()
+        torch.cuda.synchronize()
+        mode_bytes = 0
+        if mode == "stored":
+            mode_bytes = sum(t.numel() * t.element_size()
+                             for t in (rast.contrib_ids, rast.n_contrib, rast.contrib_offsets, rast.store_ws))
+        res[mode] = dict(ms_per_iter=round(e0.elapsed_time(e1) / reps, 3),
+                         peak_allocated_bytes=int(torch.cuda.max_memory_allocated()),
+                         resident_before_bytes=int(base), device_used_bytes=int(total - free0),
+                         list_bytes=int(mode_bytes),
+                         contributors=rast.contributors() if mode == "stored" else None,
+                         instances=rast.instances(), loss=float(loss.item()))
+        del rast, P, grads
+    out = {"metric": "contributor storage: fwd+bwd ms/iter and peak memory, 4M Gaussians, 1920x1080",
+           "config": {"workload": "loop corridor, %d Gaussians SH3, one 1920x1080 view, L1 rgb + 0.2 L1 depth" % n,
+                      "tile": "16x16"},
+           "data": "synthetic", "dtype": "f32", "modes": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
+    if a.contrib_compare:
+        if a.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        contrib_compare(a)
+        return
     if a.copy_calibration:
         import torch
         x = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -167,6 +167,37 @@ GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_
                           const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb, float *depth,
                           float *T_final, uint32_t *last, uint32_t *n_contrib, gsr_stream stream);
 
+/* ---- stored contributor lists ------------------------------------------------------------------
+ * The alternative to re-walking the tile lists in the backward: the forward keeps, per pixel, the
+ * list of the Gaussians it composited (memory for compute).  gsr_render_fwd_stored writes every
+ * output of gsr_render_fwd (images, last, n_contrib [V][H][W] required) and, by a second pass over
+ * the tiles after an exclusive scan of n_contrib:
+ *   contrib_offsets [V][H][W]  (uint32) exclusive prefix sums of n_contrib in (v, y, x) order
+ *   contrib_ids [contrib_capacity] (uint32) each pixel's composited Gaussians, front to back, as
+ *                              positions in its view-tile's instance list (instance =
+ *                              tile_ranges start + position)
+ *   *n_contrib_total           (device uint32) the REQUIRED list size (must stay below 2^32).
+ * Entries beyond contrib_capacity are not written: the caller compares *n_contrib_total with the
+ * capacity after synchronising and calls again with more room.  ws:
+ * gsr_render_fwd_stored_workspace(V, r) bytes (the scan's block sums).
+ * gsr_render_bwd_stored computes exactly what gsr_render_bwd does (same dinst records), walking
+ * each pixel's own list instead of the tile list; pixels whose list did not fit the capacity get
+ * no gradient, so it must only be called after a forward whose lists fit. */
+GSR_API size_t gsr_render_fwd_stored_workspace(int32_t n_views, const gsr_raster *r);
+GSR_API gsr_status gsr_render_fwd_stored(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *tile_ranges,
+                                         const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views,
+                                         const gsr_raster *r, float *rgb, float *depth, float *T_final,
+                                         uint32_t *last, uint32_t *n_contrib, uint32_t *contrib_offsets,
+                                         uint32_t *contrib_ids, int64_t contrib_capacity, uint32_t *n_contrib_total,
+                                         void *ws, size_t ws_bytes, gsr_stream stream);
+GSR_API gsr_status gsr_render_bwd_stored(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                         const uint32_t *tile_ranges, const uint32_t *tile_order,
+                                         const gsr_camera *cams, int32_t n_views, const gsr_raster *r,
+                                         const float *T_final, const uint32_t *n_contrib,
+                                         const uint32_t *contrib_offsets, const uint32_t *contrib_ids,
+                                         int64_t contrib_capacity, const float *dL_drgb, const float *dL_ddepth,
+                                         float *dinst, gsr_stream stream);
+
 /* ---- render backward -------------------------------------------------------------------------
  * Exact gradient of the forward's outputs (every discrete decision held) given dL/drgb
  * [V][3][H][W] and dL/ddepth [V][H][W] (may be NULL).  Walks each pixel's instances back to

@@ -59,6 +59,7 @@ def lib():
                                      C.c_double, P, P]
         L.orc_render_bwd.restype = C.c_int64
         L.orc_num_threads.restype = C.c_int
+        L.orc_contributors.argtypes = [C.POINTER(_Gauss), C.POINTER(_Cam), P, C.c_int64, C.c_int64, P, P]
         L.orc_adam.argtypes = [P, P, P, P, C.c_int64, C.c_int64, P, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int]
         _lib = L
@@ -150,6 +151,18 @@ def render(g, cam, pixels=None):
     lib().orc_render(C.byref(b.s), C.byref(_cam(cam)), _ptr(pix), m, _ptr(rgb), _ptr(depth), _ptr(T),
                      _ptr(n), _ptr(mg))
     return dict(rgb=rgb, depth=depth, T=T, alpha=1.0 - T, n=n, margin=mg)
+
+
+def contributors(g, cam, pixels, cap=4096):
+    """Composited Gaussian indices of each (x, y) in pixels, front to back: a list of int64 arrays."""
+    b = _Bound(g)
+    pix = np.ascontiguousarray(np.asarray(pixels, np.int32).reshape(-1, 2))
+    ids = np.zeros((pix.shape[0], cap), np.int64)
+    counts = np.zeros(pix.shape[0], np.int32)
+    lib().orc_contributors(C.byref(b.s), C.byref(_cam(cam)), _ptr(pix), pix.shape[0], cap, _ptr(ids), _ptr(counts))
+    if np.any(counts > cap):
+        raise ValueError("more than cap contributors at a pixel")
+    return [ids[k, :counts[k]].copy() for k in range(pix.shape[0])]
 
 
 def render_bwd(g, cam, dL_drgb, dL_ddepth=None, knife_tol=1e-5, want_pose=True):

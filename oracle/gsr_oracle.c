@@ -462,6 +462,29 @@ void orc_render(const orc_gaussians *g, const orc_camera *cam, const int32_t *pi
     free(P);
 }
 
+/* The composited Gaussians of each listed pixel (pix: npix (x, y) pairs), front to back:
+   ids[k * cap + j] for j < min(counts[k], cap); counts[k] is the full number. */
+void orc_contributors(const orc_gaussians *g, const orc_camera *cam, const int32_t *pix, int64_t npix, int64_t cap,
+                      int64_t *ids, int32_t *counts) {
+    orc_pg *P = project_all(g, cam);
+    orc_cells C;
+    build_cells(P, g->n, cam, &C);
+#pragma omp parallel
+    {
+        orc_scratch s = {NULL, 0};
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t k = 0; k < npix; k++) {
+            double c[3], d, t, mg;
+            int64_t n = pixel_composite(P, &C, cam, pix[2 * k], pix[2 * k + 1], &s, c, &d, &t, &mg);
+            counts[k] = (int32_t)n;
+            for (int64_t j = 0; j < n && j < cap; j++) ids[k * cap + j] = s.buf[j].id;
+        }
+        free(s.buf);
+    }
+    free_cells(&C);
+    free(P);
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Backward.                                                                                  */
 /* ------------------------------------------------------------------------------------------ */

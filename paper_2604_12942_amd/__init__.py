@@ -134,6 +134,27 @@ def render_bwd(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, 
                                _ptr(dL_ddepth), _ptr(dinst), _stream()), "gsr_render_bwd")
 
 
+def render_fwd_stored_workspace(n_views, raster):
+    return int(lib().gsr_render_fwd_stored_workspace(n_views, C.byref(raster.c)))
+
+
+def render_fwd_stored(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last, n_contrib,
+                      contrib_offsets, contrib_ids, n_contrib_total, ws, tile_order=None):
+    check(lib().gsr_render_fwd_stored(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
+                                      n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
+                                      _ptr(n_contrib), _ptr(contrib_offsets), _ptr(contrib_ids), contrib_ids.numel(),
+                                      _ptr(n_contrib_total), _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+          "gsr_render_fwd_stored")
+
+
+def render_bwd_stored(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, T_final, n_contrib,
+                      contrib_offsets, contrib_ids, dL_drgb, dL_ddepth, dinst, tile_order=None):
+    check(lib().gsr_render_bwd_stored(_ptr(splats), _ptr(inst_gid), _ptr(inst_emit), _ptr(tile_ranges),
+                                      _ptr(tile_order), _ptr(cams), n_views, C.byref(raster.c), _ptr(T_final),
+                                      _ptr(n_contrib), _ptr(contrib_offsets), _ptr(contrib_ids), contrib_ids.numel(),
+                                      _ptr(dL_drgb), _ptr(dL_ddepth), _ptr(dinst), _stream()), "gsr_render_bwd_stored")
+
+
 def pair_grads(dinst, em, tile_info, n, n_views, dsplat):
     check(lib().gsr_pair_grads(_ptr(dinst), _em(em), _ptr(tile_info), n, n_views, _ptr(dsplat), _stream()),
           "gsr_pair_grads")
@@ -218,8 +239,12 @@ class Rasterizer:
     """Owns the device buffers of one (n Gaussians, V views, raster) configuration and runs the
     forward and backward of the hot path through the C ABI."""
 
-    def __init__(self, n, n_views, raster, capacity=None, device="cuda"):
-        self.n, self.V, self.raster, self.device = int(n), int(n_views), raster, device
+    def __init__(self, n, n_views, raster, capacity=None, device="cuda", mode="recompute"):
+        """mode: "recompute" (the backward re-walks each tile's list) or "stored" (the forward
+        keeps every pixel's list of composited Gaussians for the backward)."""
+        if mode not in ("recompute", "stored"):
+            raise ValueError("mode must be 'recompute' or 'stored'")
+        self.n, self.V, self.raster, self.device, self.mode = int(n), int(n_views), raster, device, mode
         VN = self.V * self.n
         f32, i32 = torch.float32, torch.int32
         self.splats = torch.empty(VN * 12, dtype=f32, device=device)
@@ -240,6 +265,14 @@ class Rasterizer:
         self.dpose = torch.zeros(self.V, 6, dtype=torch.float64, device=device)
         self.keep_dsplat = False  # tests: keep the per-pair screen-space gradients
         self._alloc_instances(capacity if capacity else max(1 << 16, 4 * VN))
+        if mode == "stored":
+            npx = self.V * raster.width * raster.height
+            self.n_contrib = torch.empty(npx, dtype=i32, device=device)
+            self.contrib_offsets = torch.empty(npx, dtype=i32, device=device)
+            self.n_contrib_total = torch.zeros(1, dtype=i32, device=device)
+            self.store_ws = torch.empty((render_fwd_stored_workspace(self.V, raster) + 255) // 256 * 64, dtype=i32,
+                                        device=device)
+            self.contrib_ids = torch.empty(max(1 << 16, 16 * npx), dtype=i32, device=device)
 
     def _alloc_instances(self, cap):
         self.capacity = int(min(cap, (1 << 32) - 2))
@@ -254,9 +287,28 @@ class Rasterizer:
         """project -> bin/sort -> render; returns (rgb, depth, T_final) views of the buffers."""
         project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
         self.bin(check_capacity)
-        render_fwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb, self.depth,
-                   self.T_final, self.last, tile_order=self.tile_order)
+        if self.mode == "stored":
+            self.render_stored(cams, check_capacity)
+        else:
+            render_fwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb, self.depth,
+                       self.T_final, self.last, tile_order=self.tile_order)
         return self.rgb, self.depth, self.T_final
+
+    def render_stored(self, cams, check_capacity=True):
+        def run():
+            render_fwd_stored(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb,
+                              self.depth, self.T_final, self.last, self.n_contrib, self.contrib_offsets,
+                              self.contrib_ids, self.n_contrib_total, self.store_ws, tile_order=self.tile_order)
+        run()
+        if check_capacity:
+            total = int(self.n_contrib_total.item()) & 0xFFFFFFFF
+            if total > self.contrib_ids.numel():
+                self.contrib_ids = torch.empty(int(total * 1.25) + 1024, dtype=torch.int32, device=self.device)
+                run()
+
+    def contributors(self):
+        """Stored mode: number of stored (pixel, Gaussian) entries of the last forward."""
+        return int(self.n_contrib_total.item()) & 0xFFFFFFFF
 
     def bin(self, check_capacity=True):
         def run():
@@ -275,14 +327,23 @@ class Rasterizer:
     def backward(self, P, sh_degree, cams, dL_drgb, dL_ddepth, grads, want_pose=True, segment_id=None,
                  min_segment=0, row_mask=None):
         """render bwd -> project bwd; parameter gradients are accumulated into grads."""
-        render_bwd(self.splats, self.inst_gid, self.inst_emit, self.tile_ranges, cams, self.V, self.raster,
-                   self.T_final, self.last, dL_drgb.contiguous(),
-                   dL_ddepth.contiguous() if dL_ddepth is not None else None, self.dinst, tile_order=self.tile_order)
+        self.render_backward(cams, dL_drgb, dL_ddepth)
         if self.keep_dsplat:
             self.dsplat_copy = self.screen_grads()
         project_bwd(P, sh_degree, cams, self.V, self.raster, self.splats, self.dinst, self.em, self.tile_info, grads, self.dpose if want_pose else None, self.pose_ws, segment_id, min_segment,
                     row_mask)
         return self.dpose
+
+    def render_backward(self, cams, dL_drgb, dL_ddepth):
+        """The compositing backward alone (instance records in self.dinst)."""
+        gd = dL_ddepth.contiguous() if dL_ddepth is not None else None
+        if self.mode == "stored":
+            render_bwd_stored(self.splats, self.inst_gid, self.inst_emit, self.tile_ranges, cams, self.V,
+                              self.raster, self.T_final, self.n_contrib, self.contrib_offsets, self.contrib_ids,
+                              dL_drgb.contiguous(), gd, self.dinst, tile_order=self.tile_order)
+        else:
+            render_bwd(self.splats, self.inst_gid, self.inst_emit, self.tile_ranges, cams, self.V, self.raster,
+                       self.T_final, self.last, dL_drgb.contiguous(), gd, self.dinst, tile_order=self.tile_order)
 
     def screen_grads(self):
         """Per-pair screen-space gradients [V*n*10] of the last backward."""

@@ -62,6 +62,11 @@ _SIGS = {
                       C.c_size_t, P], C.c_int),
     "gsr_render_fwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
     "gsr_render_bwd": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_render_fwd_stored_workspace": ([C.c_int32, C.POINTER(Raster)], C.c_size_t),
+    "gsr_render_fwd_stored": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P, P, C.c_int64, P, P,
+                               C.c_size_t, P], C.c_int),
+    "gsr_render_bwd_stored": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, C.c_int64, P, P, P, P],
+                              C.c_int),
     "gsr_pair_grads": ([P, C.POINTER(Emission), P, C.c_int64, C.c_int32, P, P], C.c_int),
     "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
     "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, C.POINTER(Emission), P,

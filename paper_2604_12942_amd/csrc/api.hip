@@ -24,6 +24,16 @@ extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *,
                                             const uint32_t *, const float *, const float *, float *, hipStream_t);
 extern "C" gsr_status gsr_pair_grads_launch(const float *, const gsr_emission *, const uint32_t *, int64_t, float *,
                                             bool, hipStream_t);
+extern "C" gsr_status gsr_render_store_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
+                                             const gsr_camera *, int, const gsr_raster *, const uint32_t *, uint32_t *,
+                                             uint32_t, hipStream_t);
+extern "C" gsr_status gsr_render_bwd_stored_launch(const gsr_splat *, const uint32_t *, const uint32_t *,
+                                                   const uint32_t *, const uint32_t *, const gsr_camera *, int,
+                                                   const gsr_raster *, const float *, const uint32_t *,
+                                                   const uint32_t *, const uint32_t *, uint32_t, const float *,
+                                                   const float *, float *, hipStream_t);
+extern "C" size_t gsr_scan_ws_bytes(int64_t n);
+extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
 extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const uint8_t *, float, float, float, int,
                                       hipStream_t);
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
@@ -49,6 +59,8 @@ int64_t tiles(const gsr_raster *r) {
 }
 
 hipStream_t S(gsr_stream s) { return static_cast<hipStream_t>(s); }
+
+int64_t pixels(int32_t V, const gsr_raster *r) { return (int64_t)V * r->width * r->height; }
 
 bool emission_ok(const gsr_emission *em) { return em && em->pair_gid && em->pair_first && em->n_pairs; }
 
@@ -134,6 +146,48 @@ extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *in
         return GSR_E_INVALID;
     return gsr_render_bwd_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, T_final, last,
                                  dL_drgb, dL_ddepth, dinst, S(stream));
+}
+
+extern "C" size_t gsr_render_fwd_stored_workspace(int32_t n_views, const gsr_raster *r) {
+    if (!raster_ok(r) || n_views < 1) return 0;
+    return gsr_scan_ws_bytes(pixels(n_views, r));
+}
+
+extern "C" gsr_status gsr_render_fwd_stored(const gsr_splat *splats, const uint32_t *inst_gid,
+                                            const uint32_t *tile_ranges, const uint32_t *tile_order,
+                                            const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb,
+                                            float *depth, float *T_final, uint32_t *last, uint32_t *n_contrib,
+                                            uint32_t *contrib_offsets, uint32_t *contrib_ids,
+                                            int64_t contrib_capacity, uint32_t *n_contrib_total, void *ws,
+                                            size_t ws_bytes, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !rgb || !depth || !T_final || !last || !n_contrib ||
+        !contrib_offsets || !contrib_ids || !n_contrib_total || !ws || !splats || !inst_gid)
+        return GSR_E_INVALID;
+    if (contrib_capacity < 1 || contrib_capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (ws_bytes < gsr_render_fwd_stored_workspace(n_views, r)) return GSR_E_CAPACITY;
+    gsr_status s = gsr_render_fwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, rgb, depth,
+                                         T_final, last, n_contrib, S(stream));
+    if (s != GSR_OK) return s;
+    s = gsr_scan_launch(n_contrib, pixels(n_views, r), contrib_offsets, n_contrib_total, ws, S(stream));
+    if (s != GSR_OK) return s;
+    return gsr_render_store_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, contrib_offsets,
+                                   contrib_ids, (uint32_t)contrib_capacity, S(stream));
+}
+
+extern "C" gsr_status gsr_render_bwd_stored(const gsr_splat *splats, const uint32_t *inst_gid,
+                                            const uint32_t *inst_emit, const uint32_t *tile_ranges,
+                                            const uint32_t *tile_order, const gsr_camera *cams, int32_t n_views,
+                                            const gsr_raster *r, const float *T_final, const uint32_t *n_contrib,
+                                            const uint32_t *contrib_offsets, const uint32_t *contrib_ids,
+                                            int64_t contrib_capacity, const float *dL_drgb, const float *dL_ddepth,
+                                            float *dinst, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !T_final || !n_contrib || !contrib_offsets ||
+        !contrib_ids || !dL_drgb || !dinst || !inst_emit || !inst_gid || !splats)
+        return GSR_E_INVALID;
+    if (contrib_capacity < 1 || contrib_capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    return gsr_render_bwd_stored_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r,
+                                        T_final, n_contrib, contrib_offsets, contrib_ids, (uint32_t)contrib_capacity,
+                                        dL_drgb, dL_ddepth, dinst, S(stream));
 }
 
 extern "C" gsr_status gsr_pair_grads(const float *dinst, const gsr_emission *em, const uint32_t *tile_info, int64_t n,

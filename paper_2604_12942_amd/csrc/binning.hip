@@ -86,6 +86,37 @@ __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *__restrict_
     }
 }
 
+// ---- exclusive scan of a long uint32 array (the stored-contributor offsets) ------------------
+__global__ __launch_bounds__(256) void k_scan_sum(const uint32_t *__restrict__ in, int64_t n,
+                                                  uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) c += base + k < n ? in[base + k] : 0u;
+    uint32_t tot;
+    block_excl_scan256(c, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_write(const uint32_t *__restrict__ in, int64_t n,
+                                                    const uint32_t *__restrict__ boff, uint32_t *__restrict__ out) {
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    uint32_t x[kSortItems], c = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) {
+        x[k] = base + k < n ? in[base + k] : 0u;
+        c += x[k];
+    }
+    uint32_t run = boff[blockIdx.x] + block_excl_scan256(c, s_w, nullptr);
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += x[k];
+    }
+}
+
 // ---- stable LSD radix sort, 8-bit digits -----------------------------------------------------
 // Block b sorts items [b*4096, (b+1)*4096) in round-major order: item r*256 + t is held by
 // thread t in round r, so stability follows (round, thread) order.
@@ -457,3 +488,18 @@ extern "C" gsr_status gsr_tile_order_identity(uint32_t *dst, int64_t n, hipStrea
     k_iota_u32<<<nb, 256, 0, st>>>(dst, n);
     return last_launch();
 }
+
+extern "C" size_t gsr_scan_ws_bytes(int64_t n) { return (size_t)(ceil_div(n > 0 ? n : 1, kSortTile) * 4 + 256); }
+
+// out[i] = sum of in[0..i) (in and out may not alias), *total = sum of all; ws: gsr_scan_ws_bytes.
+extern "C" gsr_status gsr_scan_launch(const uint32_t *in, int64_t n, uint32_t *out, uint32_t *total, void *ws,
+                                      hipStream_t st) {
+    if (n <= 0) return gsr_fill_u32_launch(total, 0u, 1, st);
+    const int nb = (int)ceil_div(n, kSortTile);
+    uint32_t *bsum = static_cast<uint32_t *>(ws);
+    k_scan_sum<<<nb, 256, 0, st>>>(in, n, bsum);
+    k_scan_small<<<1, 1024, 0, st>>>(bsum, nb, total);
+    k_scan_write<<<nb, 256, 0, st>>>(in, n, bsum, out);
+    return last_launch();
+}
+

@@ -75,7 +75,10 @@ __device__ __forceinline__ void wave_box(int tx0, int ty0, int w, float &x0, flo
     y1 = (float)(ty0 + w * rows + rows - 1) + 0.5f;
 }
 
-template <int TW, int TH>
+// STORE: the second pass of the stored-contributor mode; each pixel writes the tile-list positions
+// of its composited Gaussians, front to back, at clist[coff[pixel] ...] (skipped beyond ccap), and
+// no image is written.
+template <int TW, int TH, bool STORE>
 __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
                                                     const uint32_t *__restrict__ ranges,
@@ -83,7 +86,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
                                                     const gsr_camera *__restrict__ cams, int W, int H, int ntx,
                                                     int T, float *__restrict__ rgb, float *__restrict__ depth,
                                                     float *__restrict__ Tfin, uint32_t *__restrict__ last,
-                                                    uint32_t *__restrict__ ncon) {
+                                                    uint32_t *__restrict__ ncon, const uint32_t *__restrict__ coff,
+                                                    uint32_t *__restrict__ clist, uint32_t ccap) {
     static_assert(TW * TH == 256, "one pixel per lane");
     __shared__ float4 sA[256], sB[256], sC[256];
     const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
@@ -104,6 +108,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     float Tr = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dd = 0.f;
     uint32_t lst = 0, nc = 0;
     bool done = !inside;
+    uint32_t cbase = 0;
+    if (STORE && inside) cbase = coff[(int64_t)v * W * H + (int64_t)py * W + px];
     for (uint32_t b = start; b < end; b += 256) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t e = b + threadIdx.x;
@@ -152,12 +158,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
                 dd = __builtin_fmaf(wgt, B.w, dd);
                 Tr = Tr * (1.0f - a);
                 const bool used = a > 0.0f;
+                if (STORE && used && cbase + nc < ccap) clist[cbase + nc] = pos0 - 1 + (uint32_t)j;
                 lst = used ? pos0 + (uint32_t)j : lst;
                 nc += used ? 1u : 0u;
             }
         }
     }
-    if (!inside) return;
+    if (!inside || STORE) return;
     const gsr_camera &cam = cams[v];
     const int64_t P = (int64_t)W * H;
     const int64_t pix = (int64_t)py * W + px;
@@ -481,6 +488,132 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     }
 }
 
+// Backward of the stored-contributor mode, pixel-major: every lane walks its own pixel's list of
+// composited tile positions back to front (no re-evaluation of Gaussians that did not blend),
+// recovering the transmittance in front of each contributor by division.  The tile's instances
+// are staged back to front in batches of 256 as in the recompute backward; per batch each lane
+// handles the entries of its list that fall inside the batch, and the ten gradient components
+// meet in LDS (ds_add_f32 per staged slot) before leaving as one record per instance.
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_render_bwd_stored(const gsr_splat *__restrict__ splats,
+                                                           const uint32_t *__restrict__ inst,
+                                                           const uint32_t *__restrict__ inst_emit,
+                                                           const uint32_t *__restrict__ ranges,
+                                                           const uint32_t *__restrict__ order,
+                                                           const gsr_camera *__restrict__ cams, int W, int H,
+                                                           int ntx, int T, const float *__restrict__ Tfin,
+                                                           const uint32_t *__restrict__ ccount,
+                                                           const uint32_t *__restrict__ coff,
+                                                           const uint32_t *__restrict__ clist, uint32_t ccap,
+                                                           const float *__restrict__ dLdrgb,
+                                                           const float *__restrict__ dLddepth,
+                                                           float *__restrict__ dinst) {
+    __shared__ float4 sA[256], sB[256], sC[256];
+    __shared__ float sAcc[10][256];
+    __shared__ uint32_t s_max;
+    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
+    const int v = item / T, tile = item % T;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    const bool inside = px < W && py < H;
+    const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
+    const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
+    const double ox = (double)bx, oy = (double)by;
+    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;
+    const int64_t P = (int64_t)W * H;
+    const int64_t pix = (int64_t)v * P + (int64_t)py * W + px;
+    float Tr = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f;
+    int cur = -1;  // index into this pixel's list, walked down to 0
+    uint32_t lbase = 0;
+    if (inside) {
+        Tr = Tfin[pix];
+        G0 = dLdrgb[(int64_t)v * 3 * P + (int64_t)py * W + px];
+        G1 = dLdrgb[(int64_t)v * 3 * P + P + (int64_t)py * W + px];
+        G2 = dLdrgb[(int64_t)v * 3 * P + 2 * P + (int64_t)py * W + px];
+        if (dLddepth) GD = dLddepth[pix];
+        lbase = coff[pix];
+        // a list that did not fit the capacity is incomplete: the caller must not pass one
+        cur = lbase + ccount[pix] <= ccap ? (int)ccount[pix] - 1 : -1;
+    }
+    const gsr_camera &cam = cams[v];
+    float S = Tr * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
+    // the deepest composited position over the tile's pixels bounds the batches
+    uint32_t deep = cur >= 0 ? clist[lbase + cur] + 1 : 0u;
+    if (threadIdx.x == 0) s_max = 0;
+    for (int q = threadIdx.x; q < 2560; q += 256) (&sAcc[0][0])[q] = 0.f;
+    __syncthreads();
+    if (deep) atomicMax(&s_max, deep);
+    __syncthreads();
+    const uint32_t nl = min(s_max, end - start);
+    for (uint32_t k = start + nl + threadIdx.x; k < end; k += 256) {
+        float2 *rec = reinterpret_cast<float2 *>(dinst + (int64_t)inst_emit[k] * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+        for (int e = 0; e < 5; e++) rec[e] = make_float2(0.f, 0.f);
+    }
+    const float kap = (float)GSR_KAPPA;
+    const float nln2 = -(float)GSR_LN2;
+    uint32_t nextpos = cur >= 0 ? clist[lbase + cur] : 0u;
+    for (int bend = (int)nl; bend > 0; bend -= 256) {
+        const int b0 = bend > 256 ? bend - 256 : 0;
+        const int cnt = bend - b0;
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            float4 A, B, C;
+            stage_splat(splats, inst[start + b0 + threadIdx.x], ox, oy, A, B, C);
+            sA[threadIdx.x] = A;
+            sB[threadIdx.x] = B;
+            sC[threadIdx.x] = C;
+        }
+        __syncthreads();
+        while (cur >= 0 && nextpos >= (uint32_t)b0) {
+            const int slot = (int)nextpos - b0;
+            const float4 A = sA[slot], B = sB[slot], C = sC[slot];
+            float dx, dy, u1, u2;
+            const float Pw = blend_exponent(A, B.x, fx, fy, dx, dy, u1, u2);
+            const float e2 = __builtin_amdgcn_exp2f(-Pw);
+            const float ar = B.z * e2;
+            const float a = fminf(ar, GSR_ALPHA_MAX);
+            const float om = 1.0f - a;
+            const float rom = __builtin_amdgcn_rcpf(om);
+            const float Tb = Tr * rom;  // transmittance in front of it
+            const float wgt = a * Tb;
+            const float gsum = __builtin_fmaf(G0, C.x, __builtin_fmaf(G1, C.y, __builtin_fmaf(G2, C.z, GD * B.w)));
+            const float dLda = __builtin_fmaf(Tb, gsum, -S * rom);
+            float acc[10];
+            const bool lin = ar <= GSR_ALPHA_MAX;
+            const float dP = lin ? (nln2 * ar) * dLda : 0.f;
+            acc[0] = -2.0f * dP * (A.z * u1);
+            acc[1] = -2.0f * dP * __builtin_fmaf(A.w, u1, B.x * u2);
+            acc[2] = dP * kap * dx * dx;
+            acc[3] = dP * 2.0f * kap * dx * dy;
+            acc[4] = dP * kap * dy * dy;
+            acc[5] = lin ? dLda * e2 : 0.f;
+            acc[6] = G0 * wgt;
+            acc[7] = G1 * wgt;
+            acc[8] = G2 * wgt;
+            acc[9] = GD * wgt;
+#pragma unroll
+            for (int e = 0; e < 10; e++) atomicAdd(&sAcc[e][slot], acc[e]);
+            S = __builtin_fmaf(wgt, gsum, S);
+            Tr = Tb;
+            cur--;
+            nextpos = cur >= 0 ? clist[lbase + cur] : 0u;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            float2 *rec = reinterpret_cast<float2 *>(
+                dinst + (int64_t)inst_emit[start + b0 + threadIdx.x] * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                rec[e] = make_float2(sAcc[2 * e][threadIdx.x], sAcc[2 * e + 1][threadIdx.x]);
+                sAcc[2 * e][threadIdx.x] = 0.f;
+                sAcc[2 * e + 1][threadIdx.x] = 0.f;
+            }
+        }
+    }
+}
+
 }  // namespace gsr
 
 using namespace gsr;
@@ -492,13 +625,31 @@ extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *splats, const uint3
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     const int T = ntx * nty;
     const int nb = V * T;
-#define GSR_RF(TW, TH)                                                                                               \
-    k_render_fwd<TW, TH><<<nb, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, r->height, ntx, T, rgb, \
-                                             depth, Tfin, last, ncon)
+#define GSR_RF(TW, TH)                                                                                          \
+    k_render_fwd<TW, TH, false><<<nb, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, r->height, ntx, T, \
+                                                    rgb, depth, Tfin, last, ncon, nullptr, nullptr, 0u)
     if (r->tile_w == 16) GSR_RF(16, 16);
     else if (r->tile_w == 8) GSR_RF(8, 32);
     else GSR_RF(32, 8);
 #undef GSR_RF
+    return last_launch();
+}
+
+// Second pass of the stored-contributor forward: the per-pixel lists.
+extern "C" gsr_status gsr_render_store_launch(const gsr_splat *splats, const uint32_t *inst, const uint32_t *ranges,
+                                             const uint32_t *order, const gsr_camera *cams, int V,
+                                             const gsr_raster *r, const uint32_t *coff, uint32_t *clist,
+                                             uint32_t ccap, hipStream_t st) {
+    const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
+    const int T = ntx * nty;
+    const int nb = V * T;
+#define GSR_RS(TW, TH)                                                                                        \
+    k_render_fwd<TW, TH, true><<<nb, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, r->height, ntx, T, \
+                                                   nullptr, nullptr, nullptr, nullptr, nullptr, coff, clist, ccap)
+    if (r->tile_w == 16) GSR_RS(16, 16);
+    else if (r->tile_w == 8) GSR_RS(8, 32);
+    else GSR_RS(32, 8);
+#undef GSR_RS
     return last_launch();
 }
 
@@ -559,3 +710,25 @@ extern "C" gsr_status gsr_pair_grads_launch(const float *dinst, const gsr_emissi
     k_pair_grads<<<nb, 256, 0, st>>>(dinst, em->pair_gid, em->pair_first, em->n_pairs, tile_info, dsplat);
     return last_launch();
 }
+
+extern "C" gsr_status gsr_render_bwd_stored_launch(const gsr_splat *splats, const uint32_t *inst,
+                                                   const uint32_t *inst_emit, const uint32_t *ranges,
+                                                   const uint32_t *order, const gsr_camera *cams, int V,
+                                                   const gsr_raster *r, const float *Tfin, const uint32_t *ccount,
+                                                   const uint32_t *coff, const uint32_t *clist, uint32_t ccap,
+                                                   const float *dLdrgb, const float *dLddepth, float *dinst,
+                                                   hipStream_t st) {
+    const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
+    const int T = ntx * nty;
+    const int nb = V * T;
+#define GSR_RBS(TW, TH)                                                                                          \
+    k_render_bwd_stored<TW, TH><<<nb, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width,      \
+                                                    r->height, ntx, T, Tfin, ccount, coff, clist, ccap, dLdrgb,    \
+                                                    dLddepth, dinst)
+    if (r->tile_w == 16) GSR_RBS(16, 16);
+    else if (r->tile_w == 8) GSR_RBS(8, 32);
+    else GSR_RBS(32, 8);
+#undef GSR_RBS
+    return last_launch();
+}
+

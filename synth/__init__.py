@@ -454,3 +454,20 @@ def config3(seed=2, n_points=1_500_000, n_keyframes=100, target_views=None):
             targets[int(k)] = scene.render_gt(cams[int(k)])
     return dict(gaussians=g, cameras=cams, targets=targets, lambda_depth=0.2, scene=scene,
                 points=pc, segment_id=seg, n_segments=20)
+
+
+FHD = dict(fx=960.0, fy=960.0, cx=960.0, cy=540.0, width=1920, height=1080)
+
+
+def config4b(seed=4, n_points=4_000_000, with_target=True):
+    """Loop corridor at 4M Gaussians (SH degree 3) seen by one 1920x1080 keyframe camera
+    (f = 960) at the start of the loop; L1 RGB + 0.2 L1 depth against the ray-traced target."""
+    scene = corridor_scene(seed)
+    rng = np.random.default_rng(seed + 1)
+    scans = np.array([loop_point(s)[0] for s in np.arange(0.0, 200.0, 1.0)])
+    g, pc = lidar_gaussians(scene, rng, scans, n_points)
+    p, yaw = loop_point(0.0)
+    cam = look_camera(np.array([p[0], p[1], 1.8]), yaw, np.deg2rad(-8.0), **FHD)
+    tgt = scene.render_gt(cam) if with_target else (None, None)
+    return dict(gaussians=g, cameras=[cam], target_rgb=[tgt[0]], target_depth=[tgt[1]], lambda_depth=0.2,
+                scene=scene)

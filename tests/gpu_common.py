@@ -34,14 +34,14 @@ def grad_close(g, o, rtol=GRAD_RTOL, mask=None):
     return bad
 
 
-def run_forward(g, cams, tile=(16, 16), capacity=None):
+def run_forward(g, cams, tile=(16, 16), capacity=None, mode="recompute"):
     """HIP forward of all cams (same size).  Returns dict of numpy outputs and the state."""
     W, H = cams[0]["width"], cams[0]["height"]
     raster = gsr.Raster(W, H, *tile)
     P = gsr.gaussians_to_device(g)
     n = P["means"].shape[1]
     ct = gsr.camera_tensor(cams)
-    rast = gsr.Rasterizer(n, len(cams), raster, capacity=capacity)
+    rast = gsr.Rasterizer(n, len(cams), raster, capacity=capacity, mode=mode)
     rgb, depth, Tf = rast.forward(P, g["sh_degree"], ct)
     torch.cuda.synchronize()
     out = dict(rgb=rgb.cpu().numpy().astype(np.float64), depth=depth.cpu().numpy().astype(np.float64),

@@ -260,3 +260,38 @@ def test_order_uses_float32_depth_key_then_index(orc):
     a2 = one_gaussian([0, 0, z + 1e-5], [math.log(0.01)] * 3, logit=logit(0.6), sh=(1.0, 0.0, 0.0))
     r2 = orc.render(stack([a2, b]), c, pixels=[[10, 10]])
     np.testing.assert_allclose(r2["rgb"][0], 0.3 * cb + 0.7 * 0.6 * ca, rtol=1e-13)
+
+
+def test_contributor_lists_by_brute_force(orc):
+    # The composited list of a pixel, rebuilt by brute force from the (separately pinned)
+    # projection: every Gaussian with o exp(-D^T Q D / 2) >= 1/255 at the pixel centre, ordered by
+    # (float32 depth, index), composited front to back until T (1 - min(a, 0.99)) < 1e-4.
+    g = synth.random_gaussians(11, 300, 0, xy_half=1.0, z_range=(2.0, 6.0), log_scale_mean=-2.0)
+    c = cam(40, 30, f=40.0)
+    pr = orc.project(g, c)
+    rng = np.random.default_rng(5)
+    pix = np.stack([rng.integers(0, 40, 60), rng.integers(0, 30, 60)], axis=1)
+    lists = orc.contributors(g, c, pix)
+    ren = orc.render(g, c, pixels=pix)
+    checked = 0
+    for k, (x, y) in enumerate(pix):
+        vis = pr["visible"] > 0
+        dx, dy = x + 0.5 - pr["u"], y + 0.5 - pr["v"]
+        q = pr["Qa"] * dx * dx + 2 * pr["Qb"] * dx * dy + pr["Qc"] * dy * dy
+        a = pr["opacity"] * np.exp(-0.5 * q)
+        cand = np.nonzero(vis & (a >= 1 / 255))[0]
+        if np.any(np.abs(a[vis] * 255 - 1) < 1e-9):
+            continue  # knife edge
+        cand = cand[np.lexsort((cand, pr["z"][cand].astype(np.float32)))]
+        T, exp = 1.0, []
+        for i in cand:
+            ai = min(a[i], 0.99)
+            if T * (1 - ai) < 1e-4:
+                break
+            exp.append(i)
+            T *= 1 - ai
+        assert list(lists[k]) == exp, (x, y)
+        assert ren["n"][k] == len(exp)
+        checked += 1
+    assert checked > 50
+    assert sum(len(x) for x in lists) > 100
