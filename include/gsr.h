@@ -307,6 +307,60 @@ GSR_API gsr_status gsr_loss_l1(const float *rgb, const float *depth, const float
                        const int32_t *target_index, int32_t n_views, const gsr_raster *r, float lambda_depth,
                        double *loss, float *dL_drgb, float *dL_ddepth, gsr_stream stream);
 
+/* ---- voxel-PCA geometric fitting (Sec. III-A, Eq. 1-2) ------------------------------------------
+ * Points [3][n] (float32, world frame) are binned into 0.5 m voxels, key floor(p / 0.5), valid for
+ * x, y in [-512, 512) m and z in [-255.5, 256) m (points outside are counted in *n_outside and
+ * belong to no voxel).  Voxels are numbered in ascending (kx, ky, kz) order.  Inside a voxel the
+ * points are ordered by ascending SplitMix64(seed XOR point index); the first min(count, 32) are
+ * the voxel's fitting points.  Per voxel (arrays sized n, component-major with stride n):
+ * mean and biased covariance of the fitting points, eigenvalues ascending, R_pca (row-major, columns
+ * v_max, v_mid, v_min, each with its largest-magnitude component positive, then v_min flipped so
+ * that det = +1), s_pca = 0.5 log max(lambda, (5 mm)^2) per column, class (planar if
+ * lambda_min < 2.5e-3 m^2, else linear if lambda_max / lambda_min > 4, else unreliable; also
+ * unreliable below 5 points), the trace of the direction block of the descriptor covariance
+ * (Eq. 1-2 with every point covariance (2 cm)^2 I) and reliable = (planar or linear) and
+ * trace < 0.1^2.  ws: gsr_voxel_pca_workspace(n) bytes, 256-byte aligned. */
+typedef struct {
+    uint32_t *n_voxels;    /* [1] */
+    uint32_t *n_outside;   /* [1] */
+    uint32_t *key;         /* [n] packed (kx+1024) << 21 | (ky+1024) << 10 | (kz+511), ascending */
+    uint32_t *start;       /* [n] first entry of the voxel in point_order */
+    uint32_t *count;       /* [n] points in the voxel */
+    uint32_t *point_order; /* [n] point indices grouped by voxel, hash order inside */
+    uint32_t *point_voxel; /* [n] voxel of each point, 0xffffffff outside the key range */
+    float *mu;             /* [3][n] */
+    float *evals;          /* [3][n] ascending */
+    float *R;              /* [9][n] row-major R_pca */
+    float *s_pca;          /* [3][n] */
+    float *trace;          /* [n] (infinity when unreliable by class) */
+    uint8_t *cls;          /* [n] 0 planar, 1 linear, 2 unreliable */
+    uint8_t *reliable;     /* [n] */
+} gsr_voxels;
+GSR_API size_t gsr_voxel_pca_workspace(int64_t n);
+GSR_API gsr_status gsr_voxel_pca(const float *points, int64_t n, uint64_t seed, const gsr_voxels *out, void *ws,
+                                 size_t ws_bytes, gsr_stream stream);
+
+/* ---- cascaded initialisation (Sec. III-B, Eq. 3, 5, 6) ----------------------------------------
+ * One Gaussian per point: mean = point, SH DC = (colour - 0.5) / Y_00, higher SH = 0, and by Eq. 3
+ *   model branch      if the point's voxel has a valid prediction (pred [8][n] per voxel, stride
+ *                     n: log-scales s[3], quaternion q[4], opacity logit; valid = finite, q != 0,
+ *                     s in [log 2 mm, log 0.5 m]): s, q / |q|, logit taken from it;
+ *   PCA branch        else if the voxel is reliable: q from R_pca, s = s_pca + log beta (Eq. 5);
+ *   heuristic branch  else: q = identity, s = log(depth / focal) on every axis (Eq. 6);
+ * non-model branches get opacity 0.1.  beta > 0 is used as given; otherwise per segment
+ * beta = clamp(1 - rho, 0.5, 1), rho = the fraction of the segment's points that are reliable
+ * but lack a valid prediction (segment [n] int32 in [0, n_segments), NULL = one segment).
+ * pred may be NULL (no model).  Outputs: the parameter arrays of out ([c][n]) and branch [n]
+ * (0 model, 1 PCA, 2 heuristic).  ws: gsr_cascade_workspace(n_segments) bytes. */
+typedef struct {
+    float *means, *log_scales, *quats, *opacity_logits, *sh;
+} gsr_params;
+GSR_API size_t gsr_cascade_workspace(int32_t n_segments);
+GSR_API gsr_status gsr_cascade(const float *points, const float *colors, const float *depth, const int32_t *segment,
+                               int32_t n_segments, int64_t n, const gsr_voxels *vox, const float *pred, float focal,
+                               float beta, int32_t sh_degree, const gsr_params *out, uint8_t *branch, void *ws,
+                               size_t ws_bytes, gsr_stream stream);
+
 /* Fill n 32-bit words with a value (graph-capture safe replacement for memset). */
 GSR_API gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream);
 

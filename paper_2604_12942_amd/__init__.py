@@ -232,6 +232,57 @@ def fill_u32(t, value):
 
 
 # ------------------------------------------------------------------------------------------
+# initialisation: voxel PCA and the cascade
+# ------------------------------------------------------------------------------------------
+
+VOXEL_FIELDS = ("n_voxels", "n_outside", "key", "start", "count", "point_order", "point_voxel", "mu", "evals", "R",
+                "s_pca", "trace", "cls", "reliable")
+
+
+def voxel_pca(points, seed, out=None):
+    """Voxel-PCA fitting of points [3, n] (float32 device tensor).  Returns a dict of device
+    tensors named like gsr_voxels (voxel arrays sized n, component-major); out reuses one."""
+    n = points.shape[1]
+    dev = points.device
+    if out is None:
+        i32, f32, u8 = torch.int32, torch.float32, torch.uint8
+        out = dict(n_voxels=torch.zeros(1, dtype=i32, device=dev), n_outside=torch.zeros(1, dtype=i32, device=dev))
+        for k in ("key", "start", "count", "point_order", "point_voxel"):
+            out[k] = torch.empty(max(1, n), dtype=i32, device=dev)
+        for k, c in (("mu", 3), ("evals", 3), ("R", 9), ("s_pca", 3)):
+            out[k] = torch.empty(c, max(1, n), dtype=f32, device=dev)
+        out["trace"] = torch.empty(max(1, n), dtype=f32, device=dev)
+        out["cls"] = torch.empty(max(1, n), dtype=u8, device=dev)
+        out["reliable"] = torch.empty(max(1, n), dtype=u8, device=dev)
+        out["_ws"] = torch.empty((int(lib().gsr_voxel_pca_workspace(n)) + 255) // 256 * 64, dtype=i32, device=dev)
+    V = _abi.Voxels(*[_ptr(out[k]) for k in VOXEL_FIELDS])
+    ws = out["_ws"]
+    check(lib().gsr_voxel_pca(_ptr(points.contiguous()), n, int(seed) & ((1 << 64) - 1), C.byref(V), _ptr(ws),
+                              ws.numel() * 4, _stream()), "gsr_voxel_pca")
+    return out
+
+
+def cascade(points, colors, depth, vox, pred=None, focal=640.0, beta=0.0, segment=None, n_segments=1, sh_degree=0):
+    """Cascaded initialisation (Eq. 3): returns (params dict of [c, n] float32 tensors, branch)."""
+    n = points.shape[1]
+    dev = points.device
+    K = (sh_degree + 1) ** 2
+    f32 = torch.float32
+    P = dict(means=torch.empty(3, n, dtype=f32, device=dev), log_scales=torch.empty(3, n, dtype=f32, device=dev),
+             quats=torch.empty(4, n, dtype=f32, device=dev), opacity_logits=torch.empty(n, dtype=f32, device=dev),
+             sh=torch.empty(3 * K, n, dtype=f32, device=dev))
+    branch = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    ws = torch.empty((int(lib().gsr_cascade_workspace(n_segments if segment is not None else 1)) + 255) // 256 * 64,
+                     dtype=torch.int32, device=dev)
+    V = _abi.Voxels(*[_ptr(vox[k]) for k in VOXEL_FIELDS])
+    O = _abi.Params(*[_ptr(P[k]) for k in PARAM_NAMES])
+    check(lib().gsr_cascade(_ptr(points.contiguous()), _ptr(colors.contiguous()), _ptr(depth.contiguous()),
+                            _ptr(segment), int(n_segments), n, C.byref(V), _ptr(pred), float(focal), float(beta),
+                            sh_degree, C.byref(O), _ptr(branch), _ptr(ws), ws.numel() * 4, _stream()), "gsr_cascade")
+    return P, branch[:n]
+
+
+# ------------------------------------------------------------------------------------------
 # rasterizer state: buffers sized once, grown on demand
 # ------------------------------------------------------------------------------------------
 

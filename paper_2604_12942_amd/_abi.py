@@ -46,6 +46,15 @@ class Emission(C.Structure):
                 ("n_pairs", C.c_void_p)]
 
 
+class Voxels(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("n_voxels", "n_outside", "key", "start", "count", "point_order",
+                                          "point_voxel", "mu", "evals", "R", "s_pca", "trace", "cls", "reliable")]
+
+
+class Params(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
+
+
 assert C.sizeof(Camera) == 96
 assert C.sizeof(Gaussians) == 56
 
@@ -78,6 +87,11 @@ _SIGS = {
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
     "gsr_loss_l1": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
+    "gsr_voxel_pca_workspace": ([C.c_int64], C.c_size_t),
+    "gsr_voxel_pca": ([P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, C.c_size_t, P], C.c_int),
+    "gsr_cascade_workspace": ([C.c_int32], C.c_size_t),
+    "gsr_cascade": ([P, P, P, P, C.c_int32, C.c_int64, C.POINTER(Voxels), P, C.c_float, C.c_float, C.c_int32,
+                     C.POINTER(Params), P, P, C.c_size_t, P], C.c_int),
 }
 
 EXPORTS = tuple(_SIGS)

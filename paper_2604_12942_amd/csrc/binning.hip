@@ -503,3 +503,18 @@ extern "C" gsr_status gsr_scan_launch(const uint32_t *in, int64_t n, uint32_t *o
     return last_launch();
 }
 
+// Stable LSD radix sort of n (key, value) pairs by the low `bits` key bits (host-side count),
+// ping-ponging between (k, v) and (k2, v2): the result is in (k, v) when ceil(bits / 8) is even,
+// else in (k2, v2).  ws: gsr_sort_pairs_ws_bytes(n).
+extern "C" size_t gsr_sort_pairs_ws_bytes(int64_t n) {
+    return (size_t)((int64_t)kRadix * ceil_div(n > 0 ? n : 1, kSortTile) * 4 + kRadix * 4 + 512);
+}
+
+extern "C" gsr_status gsr_sort_pairs_launch(uint32_t *k, uint32_t *v, uint32_t *k2, uint32_t *v2, uint32_t n, int bits,
+                                            void *ws, hipStream_t st) {
+    if (n == 0) return GSR_OK;
+    uint32_t *hist = static_cast<uint32_t *>(ws);
+    uint32_t *totals = hist + (size_t)kRadix * ceil_div(n, kSortTile);
+    return radix_sort(k, v, k2, v2, nullptr, n, n, bits, hist, totals, st);
+}
+
