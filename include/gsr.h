@@ -361,6 +361,32 @@ GSR_API gsr_status gsr_cascade(const float *points, const float *colors, const f
                                float beta, int32_t sh_degree, const gsr_params *out, uint8_t *branch, void *ws,
                                size_t ws_bytes, gsr_stream stream);
 
+/* ---- point network of the model branch (Sec. III-B, Eq. 3) ------------------------------------
+ * Per voxel of gsr_voxel_pca: 32 input rows (the fitting points repeated cyclically, centred on the
+ * voxel mean, divided by 0.5 m) -> shared MLP 3 -> 64 -> 64 -> 64 with ReLU -> max over the rows
+ * -> concat 12 features (log(max(lambda, (5 mm)^2) / 0.25) ascending, then v_min, v_mid, v_max)
+ * -> 76 -> 64 with ReLU -> 64 -> 8 = (log-scales[3], quaternion[4], opacity logit), the prediction
+ * gsr_cascade reads.  BF16 rounding (nearest even) of the weights and of every GEMM input, FP32
+ * bias, ReLU and accumulation; the two 64 x 64 layers run on the matrix cores.  weights: the
+ * float32 flat layout W1[3][64] b1[64] W2[64][64] b2 W3[64][64] b3 W4[76][64] b4 W5[64][8] b5[8]
+ * (gsr_pointnet_weight_count() floats).  y: [8][n] (stride n, like the voxel arrays). */
+GSR_API int gsr_pointnet_weight_count(void);
+GSR_API gsr_status gsr_pointnet_fwd(const float *points, int64_t n, const gsr_voxels *vox, const float *weights,
+                                    float *y, gsr_stream stream);
+/* Gradient of the training loss with respect to the weights, OVERWRITTEN into grad (flat layout):
+ * the sum over voxels with a target (tmask [n] nonzero; NULL = all) of inv_count times
+ * KL(N(0, Sigma_pred) || N(0, Sigma_tgt)) + 0.1 |sigmoid(omega) - o_tgt|, with
+ * Sigma_pred = R(q / |q|) diag(exp(2 s)) R(q / |q|)^T, targets cov_t [6][n] = (xx, xy, xz, yy, yz, zz)
+ * and o_t [n].  The backward GEMMs round their inputs (upstream gradients included) to BF16; the
+ * max-pool routes to the argmax row (lowest row on ties).  The loss value is ADDED to *loss
+ * (device float64).  blocks: persistent workgroups (each keeps partial sums, reduced in a fixed
+ * order); ws: gsr_pointnet_bwd_workspace(blocks) bytes. */
+GSR_API size_t gsr_pointnet_bwd_workspace(int32_t blocks);
+GSR_API gsr_status gsr_pointnet_bwd(const float *points, int64_t n, const gsr_voxels *vox, const float *weights,
+                                    const float *cov_t, const float *o_t, const uint8_t *tmask, float inv_count,
+                                    int32_t blocks, float *grad, double *loss, void *ws, size_t ws_bytes,
+                                    gsr_stream stream);
+
 /* Fill n 32-bit words with a value (graph-capture safe replacement for memset). */
 GSR_API gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream);
 

@@ -282,6 +282,34 @@ def cascade(points, colors, depth, vox, pred=None, focal=640.0, beta=0.0, segmen
     return P, branch[:n]
 
 
+def pointnet_weight_count():
+    return int(lib().gsr_pointnet_weight_count())
+
+
+def pointnet_forward(points, vox, weights, y=None):
+    """Point-network prediction [8, n] for the voxels of voxel_pca(points)."""
+    n = points.shape[1]
+    if y is None:
+        y = torch.zeros(8, max(1, n), dtype=torch.float32, device=points.device)
+    V = _abi.Voxels(*[_ptr(vox[k]) for k in VOXEL_FIELDS])
+    check(lib().gsr_pointnet_fwd(_ptr(points), n, C.byref(V), _ptr(weights), _ptr(y), _stream()), "gsr_pointnet_fwd")
+    return y
+
+
+def pointnet_backward(points, vox, weights, cov_t, o_t, tmask, inv_count, grad, loss, blocks=512, ws=None):
+    """Training-loss gradient of the point network into grad (flat layout); loss (float64 [1]) is
+    accumulated.  Returns the workspace for reuse."""
+    n = points.shape[1]
+    if ws is None:
+        ws = torch.empty((int(lib().gsr_pointnet_bwd_workspace(blocks)) + 3) // 4, dtype=torch.float32,
+                         device=points.device)
+    V = _abi.Voxels(*[_ptr(vox[k]) for k in VOXEL_FIELDS])
+    check(lib().gsr_pointnet_bwd(_ptr(points), n, C.byref(V), _ptr(weights), _ptr(cov_t), _ptr(o_t), _ptr(tmask),
+                                 float(inv_count), int(blocks), _ptr(grad), _ptr(loss), _ptr(ws), ws.numel() * 4,
+                                 _stream()), "gsr_pointnet_bwd")
+    return ws
+
+
 # ------------------------------------------------------------------------------------------
 # rasterizer state: buffers sized once, grown on demand
 # ------------------------------------------------------------------------------------------

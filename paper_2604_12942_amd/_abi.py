@@ -89,6 +89,11 @@ _SIGS = {
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
     "gsr_voxel_pca_workspace": ([C.c_int64], C.c_size_t),
     "gsr_voxel_pca": ([P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, C.c_size_t, P], C.c_int),
+    "gsr_pointnet_weight_count": ([], C.c_int),
+    "gsr_pointnet_fwd": ([P, C.c_int64, C.POINTER(Voxels), P, P, P], C.c_int),
+    "gsr_pointnet_bwd_workspace": ([C.c_int32], C.c_size_t),
+    "gsr_pointnet_bwd": ([P, C.c_int64, C.POINTER(Voxels), P, P, P, P, C.c_float, C.c_int32, P, P, P, C.c_size_t,
+                          P], C.c_int),
     "gsr_cascade_workspace": ([C.c_int32], C.c_size_t),
     "gsr_cascade": ([P, P, P, P, C.c_int32, C.c_int64, C.POINTER(Voxels), P, C.c_float, C.c_float, C.c_int32,
                      C.POINTER(Params), P, P, C.c_size_t, P], C.c_int),

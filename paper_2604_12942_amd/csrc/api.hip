@@ -40,6 +40,13 @@ extern "C" size_t gsr_cascade_ws_bytes(int nseg);
 extern "C" gsr_status gsr_cascade_launch(const float *, const float *, const float *, const int32_t *, int, int64_t,
                                          const gsr_voxels *, const float *, float, float, int, const gsr_params *,
                                          uint8_t *, void *, hipStream_t);
+extern "C" int gsr_pointnet_weight_count(void);
+extern "C" gsr_status gsr_pointnet_fwd_launch(const float *, int64_t, const gsr_voxels *, const float *, float *,
+                                              hipStream_t);
+extern "C" size_t gsr_pointnet_bwd_ws_bytes(int blocks);
+extern "C" gsr_status gsr_pointnet_bwd_launch(const float *, int64_t, const gsr_voxels *, const float *, const float *,
+                                              const float *, const uint8_t *, float, int, float *, double *, void *,
+                                              hipStream_t);
 extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const uint8_t *, float, float, float, int,
                                       hipStream_t);
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
@@ -310,5 +317,31 @@ extern "C" gsr_status gsr_cascade(const float *points, const float *colors, cons
     if (ws_bytes < gsr_cascade_ws_bytes(segment ? n_segments : 1)) return GSR_E_CAPACITY;
     return gsr_cascade_launch(points, colors, depth, segment, segment ? n_segments : 1, n, vox, pred, focal, beta,
                               sh_degree, out, branch, ws, S(stream));
+}
+
+namespace {
+bool voxels_ok(const gsr_voxels *v) {
+    return v && v->n_voxels && v->count && v->start && v->point_order && v->mu && v->evals && v->R;
+}
+}  // namespace
+
+extern "C" gsr_status gsr_pointnet_fwd(const float *points, int64_t n, const gsr_voxels *vox, const float *weights,
+                                       float *y, gsr_stream stream) {
+    if (n < 0 || n >= (int64_t)UINT32_MAX || !voxels_ok(vox)) return GSR_E_INVALID;
+    if (n > 0 && (!points || !weights || !y)) return GSR_E_INVALID;
+    return gsr_pointnet_fwd_launch(points, n, vox, weights, y, S(stream));
+}
+
+extern "C" size_t gsr_pointnet_bwd_workspace(int32_t blocks) { return blocks < 1 ? 0 : gsr_pointnet_bwd_ws_bytes(blocks); }
+
+extern "C" gsr_status gsr_pointnet_bwd(const float *points, int64_t n, const gsr_voxels *vox, const float *weights,
+                                       const float *cov_t, const float *o_t, const uint8_t *tmask, float inv_count,
+                                       int32_t blocks, float *grad, double *loss, void *ws, size_t ws_bytes,
+                                       gsr_stream stream) {
+    if (n < 0 || n >= (int64_t)UINT32_MAX || !voxels_ok(vox) || blocks < 1 || blocks > 65536) return GSR_E_INVALID;
+    if (!points || !weights || !cov_t || !o_t || !grad || !loss || !ws) return GSR_E_INVALID;
+    if (ws_bytes < gsr_pointnet_bwd_ws_bytes(blocks)) return GSR_E_CAPACITY;
+    return gsr_pointnet_bwd_launch(points, n, vox, weights, cov_t, o_t, tmask, inv_count, blocks, grad, loss, ws,
+                                   S(stream));
 }
 
