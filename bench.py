@@ -67,6 +67,12 @@ def parse():
     ap.add_argument("--points", type=int, default=1_500_000)
     ap.add_argument("--contrib-compare", action="store_true",
                     help="instead of the step: stored vs recomputed contributor lists on the 4M-Gaussian 1080p view")
+    ap.add_argument("--init-compare", action="store_true",
+                    help="instead of the step: iterations to a held-out PSNR target, learned vs voxel-PCA init")
+    ap.add_argument("--train-scenes", type=int, default=20)
+    ap.add_argument("--test-scenes", type=int, default=5)
+    ap.add_argument("--init-iters", type=int, default=3000)
+    ap.add_argument("--net-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -177,8 +183,129 @@ def contrib_compare(a):
     print(json.dumps(out), flush=True)
 
 
+def _c5_scene(seed):
+    c = synth.c5_scene(seed)
+    c.pop("scene")
+    return c
+
+
+def init_compare(a):
+    """Iterations to a held-out PSNR target from the learned-cascade init versus the voxel-PCA
+    cascade (beta grid-tuned on the training scenes), identical optimiser settings (one JSON line)."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    from paper_2604_12942_amd import learned_init as li
+    from paper_2604_12942_amd.optimize import MapOptimizer
+
+    dev = "cuda"
+    t0 = time.perf_counter()
+    train_seeds = list(range(100, 100 + a.train_scenes))
+    test_seeds = list(range(200, 200 + a.test_scenes))
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        data = dict(zip(train_seeds + test_seeds, ex.map(_c5_scene, train_seeds + test_seeds)))
+    print("scenes built in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    V = 4
+    every = 25
+
+    def run(c, P, iters, seed, curve=True):
+        cams = c["cameras"]
+        W, H = cams[0]["width"], cams[0]["height"]
+        raster = gsr.Raster(W, H, 16, 16)
+        tv, hv = c["train_views"], c["held_out"]
+        trgb = torch.from_numpy(np.stack([c["targets"][k][0] for k in tv])).to(dev)
+        tdep = torch.from_numpy(np.stack([c["targets"][k][1] for k in tv])).to(dev)
+        hrgb = torch.from_numpy(np.stack([c["targets"][k][0] for k in hv])).to(dev)
+        opt = MapOptimizer(P, 3, gsr.camera_tensor([cams[k] for k in tv], dev), trgb, tdep, raster, V,
+                           lambda_depth=0.2, device=dev)
+        held = gsr.Rasterizer(P["means"].shape[1], len(hv), raster, device=dev)
+        hcams = gsr.camera_tensor([cams[k] for k in hv], dev)
+        rng = np.random.default_rng(seed)
+        sched = torch.from_numpy(np.stack([rng.choice(len(tv), V, replace=False) for _ in range(iters)])).to(dev)
+        out = []
+
+        def psnr():
+            rgb, _, _ = held.forward(P, 3, hcams)
+            mse = torch.mean((rgb.clamp(0, 1) - hrgb) ** 2)
+            return float(10 * torch.log10(1.0 / mse).item())
+
+        if curve:
+            out.append((0, psnr()))
+        for it in range(iters):
+            opt.set_views(sched[it])
+            opt.step(check_capacity=True)
+            if curve and (it + 1) % every == 0:
+                out.append((it + 1, psnr()))
+        return out if curve else psnr()
+
+    def init(c, seed, weights=None, beta=0.0):
+        sc = li.SceneInit(c["points"], c["colors"], c["depth"], c["segment"], c["n_segments"], seed=seed, device=dev)
+        P, br = sc.gaussians(weights=weights, beta=beta)
+        return sc, P, br
+
+    # 1. the voxel-PCA judge: Eq. 5's beta grid-tuned on training scenes (held-out PSNR at 1000 its)
+    grid = [0.25, 0.35, 0.5, 0.7, 1.0]
+    tune = {}
+    for b in grid:
+        vals = []
+        for sd in train_seeds[:5]:
+            sc, P, _ = init(data[sd], sd, beta=b)
+            vals.append(run(data[sd], P, min(1000, a.init_iters), sd, curve=False))
+        tune[b] = float(np.mean(vals))
+    beta = max(grid, key=lambda b: tune[b])
+    print("beta tuning %s -> %.2f" % (tune, beta), file=sys.stderr, flush=True)
+    # 2. training targets: train scenes optimised from the tuned PCA init
+    scenes, targets = [], []
+    for sd in train_seeds:
+        sc, P, _ = init(data[sd], sd, beta=beta)
+        run(data[sd], P, a.init_iters, sd, curve=False)
+        scenes.append(sc)
+        targets.append(sc.targets(P))
+    print("train maps optimised (%.1f s)" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    # 3. the point network
+    weights = li.init_weights(0, dev)
+    net_loss = li.train_pointnet(scenes, targets, weights, a.net_steps,
+                                 log=lambda it, l: print("net step %d loss %.4f" % (it, l), file=sys.stderr,
+                                                         flush=True))
+    # 4. test scenes: identical optimiser, views and iterations from both inits
+    res = []
+    for sd in test_seeds:
+        c = data[sd]
+        _, PA, bA = init(c, sd, beta=beta)
+        curveA = run(c, PA, a.init_iters, 1000 + sd)
+        _, PB, bB = init(c, sd, weights=weights)
+        curveB = run(c, PB, a.init_iters, 1000 + sd)
+        target = curveA[-1][1] - 0.25
+        first = lambda cur: next((it for it, p in cur if p >= target), None)
+        at = lambda cur, it: next((p for i, p in cur if i == it), None)
+        bc = np.bincount(bB.cpu().numpy(), minlength=3)
+        res.append(dict(seed=sd, psnr_target=round(target, 3), iters_pca=first(curveA), iters_learned=first(curveB),
+                        psnr_pca={k: round(at(curveA, k), 3) for k in (0, 100, 300, 1000, a.init_iters)
+                                  if at(curveA, k) is not None},
+                        psnr_learned={k: round(at(curveB, k), 3) for k in (0, 100, 300, 1000, a.init_iters)
+                                      if at(curveB, k) is not None},
+                        branch_counts_learned=dict(model=int(bc[0]), pca=int(bc[1]), heuristic=int(bc[2]))))
+        print("test %d: %s" % (sd, res[-1]), file=sys.stderr, flush=True)
+    wins = sum(1 for r in res if r["iters_learned"] is not None and
+               (r["iters_pca"] is None or r["iters_learned"] < r["iters_pca"]))
+    ratios = [r["iters_learned"] / r["iters_pca"] for r in res if r["iters_learned"] and r["iters_pca"]]
+    out = {"metric": "iterations to held-out PSNR target, learned vs voxel-PCA init",
+           "config": {"workload": "room scenes, 100k LiDAR points, 24 keyframes 640x360 (every 10th held out), "
+                                  "4 views per iteration, SH3", "train_scenes": len(train_seeds),
+                      "test_scenes": len(test_seeds), "iterations": a.init_iters, "net_steps": a.net_steps},
+           "data": "synthetic", "beta_tuned": beta, "beta_grid_psnr_1000": {str(k): round(v, 3) for k, v in tune.items()},
+           "net_final_loss": round(net_loss, 5), "tests": res, "learned_wins": wins,
+           "mean_iter_ratio": round(float(np.mean(ratios)), 4) if ratios else None,
+           "gate": bool(wins >= max(1, (4 * len(res) + 4) // 5) and ratios and float(np.mean(ratios)) < 1.0),
+           "seconds": round(time.perf_counter() - t0, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
+    if a.init_compare:
+        init_compare(a)
+        return
     if a.contrib_compare:
         if a.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)

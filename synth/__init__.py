@@ -471,3 +471,30 @@ def config4b(seed=4, n_points=4_000_000, with_target=True):
     tgt = scene.render_gt(cam) if with_target else (None, None)
     return dict(gaussians=g, cameras=[cam], target_rgb=[tgt[0]], target_depth=[tgt[1]], lambda_depth=0.2,
                 scene=scene)
+
+
+QHD = dict(fx=320.0, fy=320.0, cx=320.0, cy=180.0, width=640, height=360)
+
+
+def c5_scene(seed, n_points=100_000, n_scans=8, n_keyframes=24, targets=True):
+    """Scene of the initialisation experiment: a room (boxes drawn from the seed) scanned by the
+    ring LiDAR from n_scans positions (the scan index is the point's segment), and n_keyframes
+    640x360 keyframe cameras at the scan positions with random headings; every 10th keyframe is
+    held out from optimisation.  Targets are ray-traced."""
+    scene = room_scene(seed)
+    rng = np.random.default_rng(seed + 1)
+    scans = rng.uniform(-15.0, 15.0, (n_scans, 2))
+    pts, surf, nrm, rngs, scan = scene.lidar(rng, scans, int(n_points * 2.5))
+    keep = np.sort(rng.choice(pts.shape[0], n_points, replace=False))
+    pts, surf, rngs, scan = pts[keep], surf[keep], rngs[keep], scan[keep]
+    col = scene.albedo(pts, surf)
+    cams = []
+    for k in range(n_keyframes):
+        p = scans[k % n_scans] + rng.uniform(-1.0, 1.0, 2)
+        cams.append(look_camera(np.array([p[0], p[1], 1.8]), rng.uniform(0, 2 * np.pi), np.deg2rad(-8.0), **QHD))
+    held = [k for k in range(n_keyframes) if k % 10 == 0]
+    train = [k for k in range(n_keyframes) if k % 10 != 0]
+    tg = [scene.render_gt(c) for c in cams] if targets else None
+    return dict(points=pts.astype(np.float32), colors=col.astype(np.float32), depth=rngs.astype(np.float32),
+                segment=scan.astype(np.int32), n_segments=n_scans, cameras=cams, targets=tg, held_out=held,
+                train_views=train, scene=scene)
