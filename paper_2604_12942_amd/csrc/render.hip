@@ -133,34 +133,45 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
             rel[g] = __ballot(r);
         }
         const uint32_t pos0 = b - start + 1;
+        // one Gaussian's blend into this lane's pixel (branch-free: a non-contributing lane
+        // blends with weight exactly 0)
+        auto blend = [&](int j, const float4 &A, const float4 &B, const float4 &C) {
+            float dx, dy, u1, u2;
+            const float P = blend_exponent(A, B.x, fx, fy, dx, dy, u1, u2);
+            const bool cont = (P <= B.y) && !done;
+            const float ar = B.z * __builtin_amdgcn_exp2f(-P);
+            const float a0 = cont ? fminf(ar, GSR_ALPHA_MAX) : 0.0f;
+            const bool term = (Tr * (1.0f - a0)) < GSR_T_MIN;
+            done = done || term;
+            const float a = term ? 0.0f : a0;
+            const float wgt = a * Tr;
+            c0 = __builtin_fmaf(wgt, C.x, c0);
+            c1 = __builtin_fmaf(wgt, C.y, c1);
+            c2 = __builtin_fmaf(wgt, C.z, c2);
+            dd = __builtin_fmaf(wgt, B.w, dd);
+            Tr = Tr * (1.0f - a);
+            const bool used = a > 0.0f;
+            if (STORE && used && cbase + nc < ccap) clist[cbase + nc] = pos0 - 1 + (uint32_t)j;
+            lst = used ? pos0 + (uint32_t)j : lst;
+            nc += used ? 1u : 0u;
+        };
 #pragma unroll
         for (int g = 0; g < 4; g++) {
             uint64_t m = rel[g];
+            // two Gaussians per step: the second one's LDS reads are in flight during the first blend
             while (m) {
-                const int j = g * 64 + __builtin_ctzll(m);
+                const int j1 = g * 64 + __builtin_ctzll(m);
                 m &= m - 1;
-                const float4 A = sA[j];
-                const float4 B = sB[j];
-                float dx, dy, u1, u2;
-                const float P = blend_exponent(A, B.x, fx, fy, dx, dy, u1, u2);
-                // branch-free: non-contributing lanes blend with weight exactly 0
-                const bool cont = (P <= B.y) && !done;
-                const float ar = B.z * __builtin_amdgcn_exp2f(-P);
-                const float a0 = cont ? fminf(ar, GSR_ALPHA_MAX) : 0.0f;
-                const bool term = (Tr * (1.0f - a0)) < GSR_T_MIN;
-                done = done || term;
-                const float a = term ? 0.0f : a0;
-                const float wgt = a * Tr;
-                const float4 C = sC[j];
-                c0 = __builtin_fmaf(wgt, C.x, c0);
-                c1 = __builtin_fmaf(wgt, C.y, c1);
-                c2 = __builtin_fmaf(wgt, C.z, c2);
-                dd = __builtin_fmaf(wgt, B.w, dd);
-                Tr = Tr * (1.0f - a);
-                const bool used = a > 0.0f;
-                if (STORE && used && cbase + nc < ccap) clist[cbase + nc] = pos0 - 1 + (uint32_t)j;
-                lst = used ? pos0 + (uint32_t)j : lst;
-                nc += used ? 1u : 0u;
+                const float4 A1 = sA[j1], B1 = sB[j1], C1 = sC[j1];
+                if (m) {
+                    const int j2 = g * 64 + __builtin_ctzll(m);
+                    m &= m - 1;
+                    const float4 A2 = sA[j2], B2 = sB[j2], C2 = sC[j2];
+                    blend(j1, A1, B1, C1);
+                    blend(j2, A2, B2, C2);
+                } else {
+                    blend(j1, A1, B1, C1);
+                }
             }
         }
     }
