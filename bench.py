@@ -27,6 +27,8 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+# without packed FP32 (not generated in this build): 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_NONPACKED_TFLOPS = 78.6
 # algorithmic float operations per composited (pixel, Gaussian) pair
 FLOP_PER_BLEND_FWD = 23
 FLOP_PER_BLEND_BWD = 48
@@ -529,6 +531,7 @@ def main():
         ach = fl / (dom_ms / 1000.0) / 1e12
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
+                    frac_of_nonpacked_peak=round(ach / FP32_PEAK_NONPACKED_TFLOPS, 4),
                     kernel=kname, launch_ms=round(dom_ms, 4), units_per_launch=blends, unit_kind="blend",
                     flop_per_unit=FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
     else:

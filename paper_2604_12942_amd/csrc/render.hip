@@ -231,8 +231,10 @@ __device__ __forceinline__ float wave_incl_sum(float v) {
 }
 
 // Two independent scans interleaved: each DPP op's source was written two instructions earlier
-// (the other scan's op and an s_nop 0), which covers the same two wait states.
-__device__ __forceinline__ void wave_incl_prod2(float &a, float &b) {
+// (the other scan's op and an s_nop 0), which covers the same two wait states.  ka and kb are
+// values the caller derived from the inputs and needs afterwards: naming them as operands makes
+// them ready before the scan, so the scanned registers need no saved copies.
+__device__ __forceinline__ void wave_incl_prod2(float &a, float &b, float ka, float kb) {
     asm volatile(
         "s_nop 1\n\t"
         "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
@@ -252,9 +254,10 @@ __device__ __forceinline__ void wave_incl_prod2(float &a, float &b) {
         "s_nop 0\n\t"
         "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
         "v_mul_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
-        : "+v"(a), "+v"(b));
+        : "+v"(a), "+v"(b)
+        : "v"(ka), "v"(kb));
 }
-__device__ __forceinline__ void wave_incl_sum2(float &a, float &b) {
+__device__ __forceinline__ void wave_incl_sum2(float &a, float &b, float ka, float kb) {
     asm volatile(
         "s_nop 1\n\t"
         "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
@@ -274,7 +277,8 @@ __device__ __forceinline__ void wave_incl_sum2(float &a, float &b) {
         "s_nop 0\n\t"
         "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
         "v_add_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
-        : "+v"(a), "+v"(b));
+        : "+v"(a), "+v"(b)
+        : "v"(ka), "v"(kb));
 }
 __device__ __forceinline__ float rdl(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -423,8 +427,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                 const float ar0 = B.z * e0, ar1 = B.z * e1;
                 const float a0 = fminf(ar0, GSR_ALPHA_MAX), a1 = fminf(ar1, GSR_ALPHA_MAX);
                 const float om0 = 1.0f - a0, om1 = 1.0f - a1;
+                // the scans overwrite their operands in place, so what is needed of (1 - a) and
+                // of w g afterwards is taken before them
+                const float rom0 = __builtin_amdgcn_rcpf(om0), rom1 = __builtin_amdgcn_rcpf(om1);
                 float Pt0 = om0, Pt1 = om1;
-                wave_incl_prod2(Pt0, Pt1);
+                wave_incl_prod2(Pt0, Pt1, rom0, rom1);
                 // transmittance in front of each Gaussian
                 const float Tb0 = ps.x * __builtin_amdgcn_rcpf(Pt0);
                 const float Tb1 = ps.z * __builtin_amdgcn_rcpf(Pt1);
@@ -433,13 +440,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                     __builtin_fmaf(pg0.x, C.x, __builtin_fmaf(pg0.y, C.y, __builtin_fmaf(pg0.z, C.z, pg0.w * B.w)));
                 const float gs1 =
                     __builtin_fmaf(pg1.x, C.x, __builtin_fmaf(pg1.y, C.y, __builtin_fmaf(pg1.z, C.z, pg1.w * B.w)));
-                const float wg0 = w0 * gs0, wg1 = w1 * gs1;
-                float in0 = wg0, in1 = wg1;
-                wave_incl_sum2(in0, in1);
+                float in0 = w0 * gs0, in1 = w1 * gs1;
+                const float sb0 = ps.y - in0, sb1 = ps.w - in1;
+                wave_incl_sum2(in0, in1, sb0, sb1);
                 // everything behind each Gaussian
-                const float Sa0 = ps.y + (in0 - wg0), Sa1 = ps.w + (in1 - wg1);
-                const float d0 = __builtin_fmaf(Tb0, gs0, -Sa0 * __builtin_amdgcn_rcpf(om0));
-                const float d1 = __builtin_fmaf(Tb1, gs1, -Sa1 * __builtin_amdgcn_rcpf(om1));
+                const float Sa0 = sb0 + in0, Sa1 = sb1 + in1;
+                const float d0 = __builtin_fmaf(Tb0, gs0, -Sa0 * rom0);
+                const float d1 = __builtin_fmaf(Tb1, gs1, -Sa1 * rom1);
                 // colour and depth: weight w = a T (zero for lanes that do not blend)
                 cr = __builtin_fmaf(pg0.x, w0, __builtin_fmaf(pg1.x, w1, cr));
                 cg = __builtin_fmaf(pg0.y, w0, __builtin_fmaf(pg1.y, w1, cg));
