@@ -10,8 +10,8 @@ loops over window offsets (no separable filtering, no tiling):
 * interior mask      M_int = Erode(M_geo, r) with the disk {dx^2 + dy^2 <= r^2}; pixels outside
   the image count as unsupported, so the erosion also trims an r-pixel frame (Eq. 7);
 * Eq. 10 and 12      masked means of the channel-summed |C - C~| and of |D - D~| over M_int;
-* Eq. 11             1 - SSIM of the images restricted to M_int: both images are multiplied by
-  the mask (zero outside it), the usual SSIM map (11x11 Gaussian window, sigma 1.5, zero padding
+* Eq. 11             1 - SSIM of the images restricted to M_int: both images are set to zero
+  outside the mask, the usual SSIM map (11x11 Gaussian window, sigma 1.5, zero padding
   at the image border, C1 = 0.01^2, C2 = 0.03^2 for unit dynamic range) is formed per channel,
   and SSIM is its mean over the pixels of M_int and the three channels;
 * Eq. 9              lambda_rgb L_rgb + lambda_ssim L_ssim + lambda_depth L_depth per view; an
@@ -111,7 +111,7 @@ def ssim_loss(rgb, target, mask, want_grad=True):
     w = gaussian_window()
     total = 0.0
     for c in range(3):
-        X, Y = rgb[c] * Mf, target[c] * Mf
+        X, Y = np.where(M, rgb[c], 0.0), np.where(M, target[c], 0.0)
         t = ssim_terms(X, Y, w)
         total += t["S"][M].sum()
         if not want_grad:
@@ -126,7 +126,7 @@ def ssim_loss(rgb, target, mask, want_grad=True):
         scale = -Mf / (3.0 * cnt)  # dL/dS_c(x)
         gX = (window_mean_adjoint(scale * a, w) + 2.0 * X * window_mean_adjoint(scale * b, w)
               + Y * window_mean_adjoint(scale * e, w))
-        grad[c] = gX * Mf
+        grad[c] = np.where(M, gX, 0.0)
     return 1.0 - total / (3.0 * cnt), grad
 
 
@@ -142,14 +142,13 @@ def masked_loss(rgb, depth, target_rgb, target_depth, mask, lambda_rgb=1.0, lamb
     gD = np.zeros((H, W))
     if cnt == 0:
         return 0.0, gC, gD
-    Mf = M.astype(np.float64)
     dC = rgb - t
-    loss = lambda_rgb * (np.abs(dC) * Mf).sum() / cnt
-    gC += lambda_rgb * np.sign(dC) * Mf / cnt
+    loss = lambda_rgb * np.abs(dC[:, M]).sum() / cnt
+    gC += np.where(M, lambda_rgb * np.sign(dC) / cnt, 0.0)
     if target_depth is not None and lambda_depth != 0.0:
         dD = np.asarray(depth, np.float64) - np.asarray(target_depth, np.float64)
-        loss += lambda_depth * (np.abs(dD) * Mf).sum() / cnt
-        gD = lambda_depth * np.sign(dD) * Mf / cnt
+        loss += lambda_depth * np.abs(dD[M]).sum() / cnt
+        gD = np.where(M, lambda_depth * np.sign(dD) / cnt, 0.0)
     if lambda_ssim != 0.0:
         ls, gs = ssim_loss(rgb, t, M)
         loss += lambda_ssim * ls

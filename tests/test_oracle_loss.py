@@ -114,6 +114,13 @@ def test_pixels_outside_the_mask_do_not_matter():
     np.testing.assert_array_equal(gC, gC2)
     np.testing.assert_array_equal(gD, gD2)
     assert np.all(gC[:, ~M] == 0) and np.all(gD[~M] == 0)
+    # restriction, not multiplication: non-finite values off the mask do not leak in
+    rgb2[:, ~M] = np.nan
+    depth2[~M] = np.inf
+    L3, gC3, gD3 = lo.masked_loss(rgb2, depth2, tgt, tdepth, M, 0.8, 0.2, 0.2)
+    assert L3 == L
+    np.testing.assert_array_equal(gC3, gC)
+    np.testing.assert_array_equal(gD3, gD)
 
 
 def test_all_ones_mask_reduces_to_plain_l1_and_empty_mask_to_zero():
