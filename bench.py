@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
+    ap.add_argument("--no-full-loss", action="store_true",
+                    help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
     ap.add_argument("--contrib-compare", action="store_true",
                     help="instead of the step: stored vs recomputed contributor lists on the 4M-Gaussian 1080p view")
@@ -304,6 +306,63 @@ def init_compare(a):
     print(json.dumps(out), flush=True)
 
 
+FULL_LOSS = dict(lambda_rgb=0.8, lambda_ssim=0.2, support=(0.5, 2))
+# algorithmic HBM bytes per pixel of the full loss stage: support mask (T 4, mask 1), masked L1
+# (rgb 12, targets 16, depth 4, mask 1, gradients 16), SSIM forward (images 24, mask 1, three
+# derivative maps per channel 36), SSIM backward (maps 36, images 24, mask 1, gradient RMW 24)
+FULL_LOSS_BYTES_PER_PX = 5 + 49 + 61 + 85
+
+
+def full_loss_leg(make_opt, sv, a, tile, stages, stream, pixels):
+    """The same step with the supervision mask (Eq. 7) and the SSIM term (Eq. 11) in the loss:
+    captured-step throughput, per-stage times and the loss stage's HBM roofline."""
+    import torch
+    o = make_opt(tile, **FULL_LOSS)
+    for s in range(a.warmup):
+        sv(o, s)
+        o.step(check_capacity=True)
+    k = max(3, min(a.steps, 10))
+    stage_ms = {st: 0.0 for st in stages}
+    for s in range(k):
+        evs = {}
+
+        def mark(name, evs=evs):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            evs[name] = e
+
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sv(o, s)
+        o.step(check_capacity=False, timer=mark)
+        torch.cuda.synchronize()
+        prev = e0
+        for st in stages:
+            stage_ms[st] += prev.elapsed_time(evs[st]) / k
+            prev = evs[st]
+    o.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        sv(o, a.warmup + s)
+        o.replay()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / a.steps
+    ach = FULL_LOSS_BYTES_PER_PX * pixels / (stage_ms["loss"] / 1000.0) / 1e9
+    res = dict(lambda_rgb=FULL_LOSS["lambda_rgb"], lambda_ssim=FULL_LOSS["lambda_ssim"], lambda_depth=0.2,
+               tau_geo=FULL_LOSS["support"][0], r_erode=FULL_LOSS["support"][1], iters_per_s=round(1000.0 / ms, 3),
+               ms_per_step=round(ms, 3), stage_ms={st: round(v, 4) for st, v in stage_ms.items()},
+               mask_pixels=int(o.sup_count.sum().item()), loss_last=float(o.loss.item()),
+               loss_roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                  frac=round(ach / HBM_PEAK_GBS, 4),
+                                  kernels="k_support_mask, k_loss_masked, k_ssim_fwd, k_ssim_bwd",
+                                  alg_bytes_per_launch=FULL_LOSS_BYTES_PER_PX * pixels))
+    print("full loss: %s" % res, file=sys.stderr, flush=True)
+    del o
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.init_compare:
@@ -349,11 +408,11 @@ def main():
     seg = torch.from_numpy(c["segment_id"]).to(dev)
     min_seg = int(c["n_segments"]) - 5
 
-    def make_opt(tile):
+    def make_opt(tile, **kw):
         P = gsr.gaussians_to_device(g, dev)
         raster = gsr.Raster(W, H, *tile)
         return MapOptimizer(P, g["sh_degree"], cam_pool, trgb, tdep, raster, V, lambda_depth=0.2, segment_id=seg,
-                            min_segment=min_seg, device=dev)
+                            min_segment=min_seg, device=dev, **kw)
 
     # the view schedule of every step, resident on the device (no host round-trip per step)
     n_main = max(a.warmup + a.steps, 10)
@@ -540,6 +599,13 @@ def main():
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
                     kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
 
+    loss_last = float(opt.loss.item())
+    full = None
+    if not a.no_full_loss:
+        del opt
+        torch.cuda.empty_cache()
+        full = full_loss_leg(make_opt, sv, a, tile, stages, stream, V * P)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(c, pool_cams, tg, views_for_step(a.warmup + a.steps - 1))
@@ -573,7 +639,8 @@ def main():
         "tile_autotune_s_per_step": {k: round(v, 5) for k, v in tune.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "loss_last": float(opt.loss.item()),
+        "loss_last": loss_last,
+        "full_loss": full,
     }
     print(json.dumps(out), flush=True)
 

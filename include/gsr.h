@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 2
+#define GSR_ABI_VERSION 3
 #define GSR_API __attribute__((visibility("default")))
 
 typedef enum {
@@ -306,6 +306,38 @@ GSR_API gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, co
 GSR_API gsr_status gsr_loss_l1(const float *rgb, const float *depth, const float *target_rgb, const float *target_depth,
                        const int32_t *target_index, int32_t n_views, const gsr_raster *r, float lambda_depth,
                        double *loss, float *dL_drgb, float *dL_ddepth, gsr_stream stream);
+
+/* ---- supervision masks (Sec. III-C, Eq. 7) -------------------------------------------------
+ * Geometric support M_geo(x) = [T_final(x) <= 1 - tau_geo] (accumulated opacity at least tau_geo,
+ * the comparison taken in float32 against the float32 value 1 - tau_geo), and the interior mask
+ * M_int = binary erosion of M_geo by the disk dx^2 + dy^2 <= r_erode^2, pixels outside the image
+ * counting as unsupported.  T_final [V][H][W] as written by the forward render.  Writes
+ * mask [V][H][W] (uint8, 1 = in M_int) and count [V] (uint32, |M_int| per view, OVERWRITTEN).
+ * tau_geo in [0, 1], r_erode in [0, 8], else GSR_E_INVALID. */
+GSR_API gsr_status gsr_support_mask(const float *T_final, int32_t n_views, const gsr_raster *r, float tau_geo,
+                                    int32_t r_erode, uint8_t *mask, uint32_t *count, gsr_stream stream);
+
+/* ---- full training loss (Sec. III-C, Eq. 9-12) ------------------------------------------------
+ * Per view v with mask M (mask NULL = all pixels, count then unused; else count[v] = |M| as from
+ * gsr_support_mask):
+ *   L_v = lambda_rgb (1/|M|) sum_{x in M} sum_ch |C - C~|            (Eq. 10)
+ *       + lambda_ssim (1 - SSIM(M C, M C~))                          (Eq. 11)
+ *       + lambda_depth (1/|M|) sum_{x in M} |D - D~|                 (Eq. 12)
+ * where SSIM is the mean over the pixels of M and the three channels of the SSIM map of the
+ * mask-restricted images (both multiplied by M): 11 x 11 Gaussian window of sigma 1.5, zero
+ * padding outside the image, C1 = 0.01^2, C2 = 0.03^2.  A view with an empty mask adds nothing.
+ * The loss is summed over views into *loss (device float64, ACCUMULATED); dL_drgb [V][3][H][W]
+ * and dL_ddepth [V][H][W] (may be NULL) are OVERWRITTEN (sign(0) = 0; zero off the mask).
+ * Targets are read from slot target_index[v] (NULL = slot v) of target_rgb [S][3][H][W] and
+ * target_depth [S][H][W] (may be NULL: no depth term).  ws: gsr_loss_workspace(V, r) bytes,
+ * 256-byte aligned (the per-pixel SSIM derivative maps and per-block partial sums, which are
+ * added in a fixed order, so the loss value is reproducible). */
+GSR_API size_t gsr_loss_workspace(int32_t n_views, const gsr_raster *r);
+GSR_API gsr_status gsr_loss(const float *rgb, const float *depth, const float *target_rgb, const float *target_depth,
+                            const int32_t *target_index, int32_t n_views, const gsr_raster *r, const uint8_t *mask,
+                            const uint32_t *count, float lambda_rgb, float lambda_ssim, float lambda_depth,
+                            double *loss, float *dL_drgb, float *dL_ddepth, void *ws, size_t ws_bytes,
+                            gsr_stream stream);
 
 /* ---- voxel-PCA geometric fitting (Sec. III-A, Eq. 1-2) ------------------------------------------
  * Points [3][n] (float32, world frame) are binned into 0.5 m voxels, key floor(p / 0.5), valid for

@@ -226,6 +226,38 @@ def loss_l1(rgb, depth, target_rgb, target_depth, n_views, raster, lambda_depth,
                             _stream()), "gsr_loss_l1")
 
 
+def support_mask(T_final, n_views, raster, tau_geo, r_erode, mask=None, count=None):
+    """Eq. 7: interior supervision mask [V, H, W] (uint8) and its pixel count per view (int32
+    tensor holding uint32) from the final transmittance [V, H, W]."""
+    dev = T_final.device
+    H, W = raster.c.height, raster.c.width
+    if mask is None:
+        mask = torch.empty((n_views, H, W), dtype=torch.uint8, device=dev)
+    if count is None:
+        count = torch.empty(n_views, dtype=torch.int32, device=dev)
+    check(lib().gsr_support_mask(_ptr(T_final), n_views, C.byref(raster.c), tau_geo, r_erode, _ptr(mask), _ptr(count),
+                                 _stream()), "gsr_support_mask")
+    return mask, count
+
+
+def loss_workspace(n_views, raster):
+    return lib().gsr_loss_workspace(n_views, C.byref(raster.c))
+
+
+def loss(rgb, depth, target_rgb, target_depth, n_views, raster, loss_acc, dL_drgb, dL_ddepth, mask=None, count=None,
+         lambda_rgb=1.0, lambda_ssim=0.0, lambda_depth=0.0, target_index=None, ws=None):
+    """Eq. 9-12 (masked L1 colour, SSIM, masked L1 depth).  Accumulates into loss_acc (float64
+    [1]); overwrites dL_drgb and dL_ddepth.  Returns the workspace (reuse it across calls)."""
+    nb = loss_workspace(n_views, raster)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=rgb.device)
+    check(lib().gsr_loss(_ptr(rgb), _ptr(depth), _ptr(target_rgb), _ptr(target_depth), _ptr(target_index), n_views,
+                         C.byref(raster.c), _ptr(mask), _ptr(count), lambda_rgb, lambda_ssim, lambda_depth,
+                         _ptr(loss_acc), _ptr(dL_drgb), _ptr(dL_ddepth), _ptr(ws), ws.numel(), _stream()),
+          "gsr_loss")
+    return ws
+
+
 def fill_u32(t, value):
     check(lib().gsr_fill_u32(_ptr(t), value & 0xFFFFFFFF, t.numel() * t.element_size() // 4, _stream()),
           "gsr_fill_u32")

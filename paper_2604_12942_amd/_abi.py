@@ -87,6 +87,10 @@ _SIGS = {
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
     "gsr_loss_l1": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
+    "gsr_support_mask": ([P, C.c_int32, C.POINTER(Raster), C.c_float, C.c_int32, P, P, P], C.c_int),
+    "gsr_loss_workspace": ([C.c_int32, C.POINTER(Raster)], C.c_size_t),
+    "gsr_loss": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, C.c_float, C.c_float, C.c_float, P, P, P, P,
+                  C.c_size_t, P], C.c_int),
     "gsr_voxel_pca_workspace": ([C.c_int64], C.c_size_t),
     "gsr_voxel_pca": ([P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, C.c_size_t, P], C.c_int),
     "gsr_pointnet_weight_count": ([], C.c_int),

@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, then launches on the caller's stream.
 #include "gsr_internal.h"
+#include <cmath>
 
 using namespace gsr;
 
@@ -52,6 +53,12 @@ extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const ui
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
                                          int, const gsr_raster *, float, double *, float *, float *, hipStream_t);
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+extern "C" size_t gsr_loss_ws_bytes(int, const gsr_raster *);
+extern "C" gsr_status gsr_support_mask_launch(const float *, int, const gsr_raster *, float, int, uint8_t *, uint32_t *,
+                                              hipStream_t);
+extern "C" gsr_status gsr_loss_launch(const float *, const float *, const float *, const float *, const int32_t *, int,
+                                      const gsr_raster *, const uint8_t *, const uint32_t *, float, float, float,
+                                      double *, float *, float *, void *, hipStream_t);
 extern "C" gsr_status gsr_tile_order_identity(uint32_t *, int64_t, hipStream_t);
 
 namespace {
@@ -281,6 +288,32 @@ extern "C" gsr_status gsr_loss_l1(const float *rgb, const float *depth, const fl
     if (target_depth && !depth) return GSR_E_INVALID;
     return gsr_loss_l1_launch(rgb, depth, target_rgb, target_depth, target_index, n_views, r, lambda_depth, loss,
                               dL_drgb, dL_ddepth, S(stream));
+}
+
+extern "C" gsr_status gsr_support_mask(const float *T_final, int32_t n_views, const gsr_raster *r, float tau_geo,
+                                       int32_t r_erode, uint8_t *mask, uint32_t *count, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !T_final || !mask || !count) return GSR_E_INVALID;
+    if (!(tau_geo >= 0.0f && tau_geo <= 1.0f) || r_erode < 0 || r_erode > 8) return GSR_E_INVALID;
+    return gsr_support_mask_launch(T_final, n_views, r, tau_geo, r_erode, mask, count, S(stream));
+}
+
+extern "C" size_t gsr_loss_workspace(int32_t n_views, const gsr_raster *r) {
+    if (!raster_ok(r) || n_views < 1) return 0;
+    return gsr_loss_ws_bytes(n_views, r);
+}
+
+extern "C" gsr_status gsr_loss(const float *rgb, const float *depth, const float *target_rgb, const float *target_depth,
+                               const int32_t *target_index, int32_t n_views, const gsr_raster *r, const uint8_t *mask,
+                               const uint32_t *count, float lambda_rgb, float lambda_ssim, float lambda_depth,
+                               double *loss, float *dL_drgb, float *dL_ddepth, void *ws, size_t ws_bytes,
+                               gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !rgb || !target_rgb || !loss || !dL_drgb) return GSR_E_INVALID;
+    if (target_depth && !depth) return GSR_E_INVALID;
+    if (mask && !count) return GSR_E_INVALID;
+    if (!std::isfinite(lambda_rgb) || !std::isfinite(lambda_ssim) || !std::isfinite(lambda_depth)) return GSR_E_INVALID;
+    if (!ws || ws_bytes < gsr_loss_ws_bytes(n_views, r)) return GSR_E_INVALID;
+    return gsr_loss_launch(rgb, depth, target_rgb, target_depth, target_index, n_views, r, mask, count, lambda_rgb,
+                           lambda_ssim, lambda_depth, loss, dL_drgb, dL_ddepth, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream) {

@@ -1,8 +1,9 @@
 """Global Gaussian-map optimisation step (paper Sec. III-C), batched over keyframe views.
 
 One step: the views chosen for this iteration are projected and binned together, rendered
-(colour + depth, Eq. 8), supervised with the L1 colour + lambda_depth L1 depth loss (Eq. 9, 10,
-12 with the all-ones mask), differentiated back to every parameter (and the per-view pose), and
+(colour + depth, Eq. 8), supervised with Eq. 9 (by default the L1 colour + lambda_depth L1 depth
+loss over all pixels; optionally inside the interior support mask of Eq. 7 and with the SSIM
+term of Eq. 11), differentiated back to every parameter (and the per-view pose), and
 the visible Gaussians of the unfrozen segments take a sparse Adam step.  Every stage is a
 libgsr kernel on torch's current stream; this class only owns buffers.
 """
@@ -10,7 +11,7 @@ from __future__ import annotations
 
 import torch
 
-from . import PARAM_NAMES, Rasterizer, adam_step, loss_l1
+from . import PARAM_NAMES, Rasterizer, adam_step, loss, loss_l1, support_mask
 
 # learning rates per parameter group: means (m), log-scales, quaternions, opacity logits,
 # SH DC, SH rest
@@ -19,9 +20,12 @@ DEFAULT_LR = dict(means=5e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, 
 
 class MapOptimizer:
     def __init__(self, params, sh_degree, cam_pool, target_rgb, target_depth, raster, n_views, lambda_depth=0.2,
-                 lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda", fused=True):
+                 lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda", fused=True,
+                 lambda_rgb=1.0, lambda_ssim=0.0, support=None):
         """params: dict of float32 [c, n] device tensors (optimised in place); cam_pool: device
-        uint8 [S*96] gsr_camera records; target_rgb [S,3,H,W], target_depth [S,H,W] (or None)."""
+        uint8 [S*96] gsr_camera records; target_rgb [S,3,H,W], target_depth [S,H,W] (or None).
+        support = (tau_geo, r_erode) supervises only inside the interior mask of Eq. 7 computed
+        from this step's own render; None uses every pixel."""
         self.P = params
         self.sh_degree = int(sh_degree)
         self.n = params["means"].shape[1]
@@ -30,6 +34,8 @@ class MapOptimizer:
         self.cam_pool = cam_pool.view(-1, 96)
         self.target_rgb, self.target_depth = target_rgb, target_depth
         self.lambda_depth = float(lambda_depth)
+        self.lambda_rgb, self.lambda_ssim = float(lambda_rgb), float(lambda_ssim)
+        self.support = support
         self.lr = dict(DEFAULT_LR, **(lr or {}))
         self.segment_id, self.min_segment = segment_id, int(min_segment)
         self.rast = Rasterizer(self.n, self.V, raster, capacity=capacity, device=device)
@@ -40,6 +46,12 @@ class MapOptimizer:
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         self.g_rgb = torch.empty(self.V, 3, H, W, device=device)
         self.g_depth = torch.empty(self.V, H, W, device=device)
+        self.full_loss = support is not None or self.lambda_ssim != 0.0 or self.lambda_rgb != 1.0
+        self.sup_mask = torch.ones(self.V, H, W, dtype=torch.uint8, device=device)
+        self.sup_count = torch.zeros(self.V, dtype=torch.int32, device=device)
+        from . import loss_workspace
+        self.loss_ws = torch.empty(loss_workspace(self.V, raster) if self.full_loss else 1, dtype=torch.uint8,
+                                   device=device)
         self.row_mask = torch.zeros(self.n, dtype=torch.uint8, device=device)
         self.view_idx = torch.zeros(self.V, dtype=torch.int64, device=device)
         self.view_idx32 = torch.zeros(self.V, dtype=torch.int32, device=device)
@@ -88,11 +100,20 @@ class MapOptimizer:
             render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth,
                        r.T_final, r.last, tile_order=r.tile_order)
 
-        def loss():
+        def loss_stage():
             self.loss.zero_()
-            loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
-                    self.loss, self.g_rgb, self.g_depth if self.target_depth is not None else None,
-                    target_index=self.view_idx32)
+            gd = self.g_depth if self.target_depth is not None else None
+            if not self.full_loss:
+                loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
+                        self.loss, self.g_rgb, gd, target_index=self.view_idx32)
+                return
+            mask = count = None
+            if self.support is not None:
+                tau, rad = self.support
+                mask, count = support_mask(r.T_final, self.V, self.raster, tau, rad, self.sup_mask, self.sup_count)
+            loss(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.loss, self.g_rgb, gd,
+                 mask=mask, count=count, lambda_rgb=self.lambda_rgb, lambda_ssim=self.lambda_ssim,
+                 lambda_depth=self.lambda_depth, target_index=self.view_idx32, ws=self.loss_ws)
 
         def bwd():
             render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
@@ -120,7 +141,7 @@ class MapOptimizer:
                 self.t += 1
                 adam_step(self._groups(), self.n, self.row_mask, step=self.t)
 
-        return [("gather", gather), ("project", proj), ("bin_sort", binsort), ("render_fwd", fwd), ("loss", loss),
+        return [("gather", gather), ("project", proj), ("bin_sort", binsort), ("render_fwd", fwd), ("loss", loss_stage),
                 ("render_bwd", bwd), ("project_bwd", pbwd), ("adam", adam)]
 
     STAGES = ("gather", "project", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd", "adam")

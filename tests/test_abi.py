@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared():
         assert hasattr(lib, name), name
     assert set(declared()) == set(_abi.EXPORTS)
-    assert lib.gsr_abi_version() == 2
+    assert lib.gsr_abi_version() == 3
 
 
 def test_invalid_arguments_are_rejected_before_launch():

@@ -10,14 +10,14 @@ import synth
 pytestmark = pytest.mark.gpu
 
 
-def _opt(fused, g, cams, tgt_rgb, tgt_dep, seg, min_seg):
+def _opt(fused, g, cams, tgt_rgb, tgt_dep, seg, min_seg, **kw):
     import paper_2604_12942_amd as gsr
     from paper_2604_12942_amd.optimize import MapOptimizer
     P = gsr.gaussians_to_device(g)
     raster = gsr.Raster(cams[0]["width"], cams[0]["height"])
     pool = gsr.camera_tensor(cams)
     return MapOptimizer(P, g["sh_degree"], pool, tgt_rgb, tgt_dep, raster, len(cams), segment_id=seg,
-                        min_segment=min_seg, fused=fused)
+                        min_segment=min_seg, fused=fused, **kw)
 
 
 def test_fused_step_equals_separate_step():
@@ -56,9 +56,14 @@ def test_fused_step_equals_separate_step():
         assert np.any(moved[segs >= 2]), k
 
 
-def test_graph_replay_matches_eager_step():
+FULL_LOSS = dict(lambda_rgb=0.8, lambda_ssim=0.2, support=(0.5, 2))
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_graph_replay_matches_eager_step(full):
     """The fused step captured into HIP graphs (cut before the render backward) and replayed,
-    with eager work and synchronisations between replays, follows the eager step."""
+    with eager work and synchronisations between replays, follows the eager step; also with the
+    support mask and the SSIM term in the loss."""
     c = synth.config4a()
     g = c["gaussians"]
     rng = np.random.default_rng(2)
@@ -69,8 +74,9 @@ def test_graph_replay_matches_eager_step():
     H, W = 120, 160
     trgb = torch.from_numpy(rng.uniform(0, 1, (3, 3, H, W)).astype(np.float32)).cuda()
     tdep = torch.from_numpy(rng.uniform(2, 10, (3, H, W)).astype(np.float32)).cuda()
-    a = _opt(True, g, cams, trgb, tdep, None, 0)
-    b = _opt(True, g, cams, trgb, tdep, None, 0)
+    kw = FULL_LOSS if full else {}
+    a = _opt(True, g, cams, trgb, tdep, None, 0, **kw)
+    b = _opt(True, g, cams, trgb, tdep, None, 0, **kw)
     views = [[0, 1, 2], [2, 0, 1], [1, 2, 0], [0, 2, 1], [2, 1, 0]]
     for o in (a, b):
         o.set_views(views[0])
