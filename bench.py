@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
+    ap.add_argument("--no-maintenance", action="store_true", help="skip the pruning / insertion timing")
     ap.add_argument("--no-full-loss", action="store_true",
                     help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
@@ -363,6 +364,70 @@ def full_loss_leg(make_opt, sv, a, tile, stages, stream, pixels):
     return res
 
 
+# map maintenance readings: at most 5 % of the rows pruned per call; insertion filter radius 5 cm.
+# The timed pruning call uses opacity threshold 0.2, above the initial opacity of every row, so
+# that all rows of the unfrozen segments are candidates and the budget binds (the selection's
+# worst case: the full candidate sort); the reading for training is 0.005.
+PRUNE_MIN_OPACITY, PRUNE_MAX_RATIO, INSERT_D_MIN = 0.2, 0.05, 0.05
+
+
+def maintenance_leg(g, seg, min_seg, dev, reps=5):
+    """Pruning (selection + compaction of parameters, Adam moments and segment ids) and the
+    proximity-filtered insertion of a re-scanned segment, on the full map; kernel times from HIP
+    events on the launch stream, median over reps."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    from paper_2604_12942_amd.maintain import _gather_all
+    P = gsr.gaussians_to_device(g, dev)
+    n = P["means"].shape[1]
+    rows = {k: P[k] for k in gsr.PARAM_NAMES}
+    rows.update({"m_" + k: torch.zeros_like(P[k]) for k in gsr.PARAM_NAMES})
+    rows.update({"v_" + k: torch.zeros_like(P[k]) for k in gsr.PARAM_NAMES})
+    rows["segment_id"] = seg
+    floats_per_row = sum(t.numel() // n for t in rows.values())
+    # new segment: 40k means re-observing mapped surface (2 cm jitter) and 20k off the map
+    rng = np.random.default_rng(11)
+    src = torch.from_numpy(rng.integers(0, n, 60_000)).to(dev)
+    jit = torch.from_numpy(np.concatenate([rng.normal(0, 0.02, (3, 40_000)), rng.normal(0, 0.5, (3, 20_000))],
+                                          axis=1).astype(np.float32)).to(dev)
+    new_means = (P["means"][:, src] + jit).contiguous()
+    stream = torch.cuda.current_stream()
+    import math
+    max_logit = math.log(PRUNE_MIN_OPACITY / (1 - PRUNE_MIN_OPACITY))
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), out
+
+    t_sel, (keep, n_keep) = timed(lambda: gsr.prune_select(P["opacity_logits"], max_logit, PRUNE_MAX_RATIO, seg,
+                                                           min_seg))
+    k = int(n_keep.item())
+    dst = {name: torch.empty(tuple(t.shape[:-1]) + (k,), dtype=t.dtype, device=dev) for name, t in rows.items()}
+    t_cmp, _ = timed(lambda: _gather_all([(rows[nm], dst[nm]) for nm in rows], n, keep, k, k, 0))
+    t_prox, (keep_new, idx, n_new) = timed(lambda: gsr.proximity_filter(P["means"], new_means, INSERT_D_MIN))
+    kn = int(n_new.item())
+    b_cmp = 2 * 4 * floats_per_row * k + 4 * k
+    res = dict(rows=n, floats_per_row=floats_per_row, min_opacity=PRUNE_MIN_OPACITY, max_ratio=PRUNE_MAX_RATIO,
+               removed=n - k, prune_select_ms=round(t_sel, 4), compaction_ms=round(t_cmp, 4),
+               compaction_roofline=dict(bound="hbm", achieved=round(b_cmp / (t_cmp / 1e3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                                        unit="GB/s", frac=round(b_cmp / (t_cmp / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                        alg_bytes_per_launch=b_cmp),
+               insert_candidates=int(new_means.shape[1]), insert_d_min=INSERT_D_MIN, inserted=kn,
+               proximity_ms=round(t_prox, 4))
+    print("maintenance: %s" % res, file=sys.stderr, flush=True)
+    del P, rows, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.init_compare:
@@ -600,6 +665,9 @@ def main():
                     kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
 
     loss_last = float(opt.loss.item())
+    maint = None
+    if not a.no_maintenance:
+        maint = maintenance_leg(g, seg, min_seg, dev)
     full = None
     if not a.no_full_loss:
         del opt
@@ -641,6 +709,7 @@ def main():
         "cpu_baseline": cpu,
         "loss_last": loss_last,
         "full_loss": full,
+        "maintenance": maint,
     }
     print(json.dumps(out), flush=True)
 

@@ -339,6 +339,48 @@ GSR_API gsr_status gsr_loss(const float *rgb, const float *depth, const float *t
                             double *loss, float *dL_drgb, float *dL_ddepth, void *ws, size_t ws_bytes,
                             gsr_stream stream);
 
+/* ---- map maintenance (Sec. III-C) -------------------------------------------------------------
+ * Low-opacity pruning under a bounded removal ratio.  Candidates are the rows with
+ * opacity_logits[i] < max_logit (opacity below sigmoid(max_logit)) and, when segment_id is not
+ * NULL, segment_id[i] >= min_segment (frozen segments are never pruned).  At most
+ * k = floor((double)max_ratio * n) rows are removed: every candidate when there are at most k,
+ * else the k candidates with the smallest logits, equal logits in ascending row order.
+ * keep_index [n] receives the surviving rows in ascending order and *n_keep (device uint32)
+ * their count; compact the arrays with gsr_gather_rows.  n < 2^32 - 1, max_ratio in [0, 1].
+ * ws: gsr_prune_workspace(n) bytes, 256-byte aligned. */
+GSR_API size_t gsr_prune_workspace(int64_t n);
+GSR_API gsr_status gsr_prune_select(const float *opacity_logits, const int32_t *segment_id, int32_t min_segment,
+                                    int64_t n, float max_logit, float max_ratio, uint32_t *keep_index,
+                                    uint32_t *n_keep, void *ws, size_t ws_bytes, gsr_stream stream);
+
+/* Row gather over groups of component-major arrays of 4-byte elements (float32 / int32):
+ *   dst[g][c * dst_rows + dst_offset + j] = src[g][c * src_rows + r_j],  r_j = index ? index[j] : j
+ * for j < n_rows, c < cols[g].  Compaction: index = keep_index, dst_offset = 0; appending rows:
+ * two calls into one destination with different offsets.  Requires dst_offset + n_rows <=
+ * dst_rows; rows r_j >= src_rows are skipped.  src and dst must not overlap. */
+#define GSR_MAX_ROW_GROUPS 16
+typedef struct {
+    const void *src[GSR_MAX_ROW_GROUPS];
+    void *dst[GSR_MAX_ROW_GROUPS];
+    int32_t cols[GSR_MAX_ROW_GROUPS];
+    int32_t n_groups;
+    int32_t _pad;
+} gsr_row_groups;
+GSR_API gsr_status gsr_gather_rows(const gsr_row_groups *groups, int64_t src_rows, const uint32_t *index,
+                                   int64_t n_rows, int64_t dst_rows, int64_t dst_offset, gsr_stream stream);
+
+/* Proximity filter for newly initialised Gaussians (spatial test in 3-D Euclidean space): new
+ * mean j is redundant when a map mean lies strictly within d_min, the squared distance taken in
+ * float64 from the float32 coordinates as ((dx dx + dy dy) + dz dz) with every operation rounded
+ * separately and compared with (double)d_min squared.  Means are [3][n] (coordinates below 10^6 m
+ * in magnitude).  Writes keep [n_new] (uint8, 1 = insert), keep_index [n_new] (kept rows,
+ * ascending) and *n_keep (device uint32).  d_min > 0; n_map, n_new < 2^32 - 1.
+ * ws: gsr_proximity_workspace(n_map, n_new) bytes, 256-byte aligned. */
+GSR_API size_t gsr_proximity_workspace(int64_t n_map, int64_t n_new);
+GSR_API gsr_status gsr_proximity_filter(const float *map_means, int64_t n_map, const float *new_means, int64_t n_new,
+                                        float d_min, uint8_t *keep, uint32_t *keep_index, uint32_t *n_keep, void *ws,
+                                        size_t ws_bytes, gsr_stream stream);
+
 /* ---- voxel-PCA geometric fitting (Sec. III-A, Eq. 1-2) ------------------------------------------
  * Points [3][n] (float32, world frame) are binned into 0.5 m voxels, key floor(p / 0.5), valid for
  * x, y in [-512, 512) m and z in [-255.5, 256) m (points outside are counted in *n_outside and

@@ -258,6 +258,54 @@ def loss(rgb, depth, target_rgb, target_depth, n_views, raster, loss_acc, dL_drg
     return ws
 
 
+def prune_select(opacity_logits, max_logit, max_ratio, segment_id=None, min_segment=0, keep_index=None,
+                 n_keep=None, ws=None):
+    """Low-opacity pruning selection (Sec. III-C).  Returns (keep_index [n] int32 tensor holding
+    uint32 row indices, n_keep [1] device tensor); the first n_keep entries are the survivors."""
+    n = opacity_logits.numel()
+    dev = opacity_logits.device
+    keep_index = torch.empty(max(1, n), dtype=torch.int32, device=dev) if keep_index is None else keep_index
+    n_keep = torch.zeros(1, dtype=torch.int32, device=dev) if n_keep is None else n_keep
+    nb = lib().gsr_prune_workspace(n)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(1, nb), dtype=torch.uint8, device=dev)
+    check(lib().gsr_prune_select(_ptr(opacity_logits), _ptr(segment_id), min_segment, n, max_logit, max_ratio,
+                                 _ptr(keep_index), _ptr(n_keep), _ptr(ws), ws.numel(), _stream()), "gsr_prune_select")
+    return keep_index, n_keep
+
+
+def gather_rows(pairs, src_rows, index, n_rows, dst_rows, dst_offset=0):
+    """pairs: list of (src, dst) component-major tensors of 4-byte elements ([c, rows] or [rows])."""
+    if len(pairs) > _abi.MAX_ROW_GROUPS:
+        raise GsrError("at most %d row groups" % _abi.MAX_ROW_GROUPS)
+    G = _abi.RowGroups()
+    for k, (src, dst) in enumerate(pairs):
+        if src.element_size() != 4 or dst.element_size() != 4 or not dst.is_contiguous() or not src.is_contiguous():
+            raise GsrError("gather_rows takes contiguous 4-byte tensors")
+        G.src[k], G.dst[k] = src.data_ptr(), dst.data_ptr()
+        G.cols[k] = src.numel() // src_rows if src_rows else (dst.numel() // dst_rows if dst_rows else 0)
+    G.n_groups = len(pairs)
+    check(lib().gsr_gather_rows(C.byref(G), src_rows, _ptr(index), n_rows, dst_rows, dst_offset, _stream()),
+          "gsr_gather_rows")
+
+
+def proximity_filter(map_means, new_means, d_min, ws=None):
+    """Insertion filter: (keep [M] uint8, keep_index [M] int32, n_keep [1]) for new means [3, M]
+    against map means [3, N]."""
+    n_map, n_new = map_means.shape[1], new_means.shape[1]
+    dev = new_means.device
+    keep = torch.empty(max(1, n_new), dtype=torch.uint8, device=dev)
+    keep_index = torch.empty(max(1, n_new), dtype=torch.int32, device=dev)
+    n_keep = torch.zeros(1, dtype=torch.int32, device=dev)
+    nb = lib().gsr_proximity_workspace(n_map, n_new)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(1, nb), dtype=torch.uint8, device=dev)
+    check(lib().gsr_proximity_filter(_ptr(map_means), n_map, _ptr(new_means), n_new, d_min, _ptr(keep),
+                                     _ptr(keep_index), _ptr(n_keep), _ptr(ws), ws.numel(), _stream()),
+          "gsr_proximity_filter")
+    return keep, keep_index, n_keep
+
+
 def fill_u32(t, value):
     check(lib().gsr_fill_u32(_ptr(t), value & 0xFFFFFFFF, t.numel() * t.element_size() // 4, _stream()),
           "gsr_fill_u32")

@@ -51,6 +51,14 @@ class Voxels(C.Structure):
                                           "point_voxel", "mu", "evals", "R", "s_pca", "trace", "cls", "reliable")]
 
 
+MAX_ROW_GROUPS = 16
+
+
+class RowGroups(C.Structure):
+    _fields_ = [("src", P * MAX_ROW_GROUPS), ("dst", P * MAX_ROW_GROUPS), ("cols", C.c_int32 * MAX_ROW_GROUPS),
+                ("n_groups", C.c_int32), ("_pad", C.c_int32)]
+
+
 class Params(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
 
@@ -89,6 +97,11 @@ _SIGS = {
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
     "gsr_support_mask": ([P, C.c_int32, C.POINTER(Raster), C.c_float, C.c_int32, P, P, P], C.c_int),
     "gsr_loss_workspace": ([C.c_int32, C.POINTER(Raster)], C.c_size_t),
+    "gsr_prune_workspace": ([C.c_int64], C.c_size_t),
+    "gsr_prune_select": ([P, P, C.c_int32, C.c_int64, C.c_float, C.c_float, P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_gather_rows": ([C.POINTER(RowGroups), C.c_int64, P, C.c_int64, C.c_int64, C.c_int64, P], C.c_int),
+    "gsr_proximity_workspace": ([C.c_int64, C.c_int64], C.c_size_t),
+    "gsr_proximity_filter": ([P, C.c_int64, P, C.c_int64, C.c_float, P, P, P, P, C.c_size_t, P], C.c_int),
     "gsr_loss": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, C.c_float, C.c_float, C.c_float, P, P, P, P,
                   C.c_size_t, P], C.c_int),
     "gsr_voxel_pca_workspace": ([C.c_int64], C.c_size_t),

@@ -53,6 +53,14 @@ extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const ui
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
                                          int, const gsr_raster *, float, double *, float *, float *, hipStream_t);
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+extern "C" size_t gsr_prune_ws_bytes(int64_t);
+extern "C" gsr_status gsr_prune_launch(const float *, const int32_t *, int32_t, int64_t, float, uint64_t, uint32_t *,
+                                       uint32_t *, void *, hipStream_t);
+extern "C" gsr_status gsr_gather_launch(const gsr_row_groups *, int64_t, const uint32_t *, int64_t, int64_t, int64_t,
+                                        hipStream_t);
+extern "C" size_t gsr_proximity_ws_bytes(int64_t, int64_t);
+extern "C" gsr_status gsr_proximity_launch(const float *, int64_t, const float *, int64_t, float, uint8_t *, uint32_t *,
+                                           uint32_t *, void *, hipStream_t);
 extern "C" size_t gsr_loss_ws_bytes(int, const gsr_raster *);
 extern "C" gsr_status gsr_support_mask_launch(const float *, int, const gsr_raster *, float, int, uint8_t *, uint32_t *,
                                               hipStream_t);
@@ -314,6 +322,47 @@ extern "C" gsr_status gsr_loss(const float *rgb, const float *depth, const float
     if (!ws || ws_bytes < gsr_loss_ws_bytes(n_views, r)) return GSR_E_INVALID;
     return gsr_loss_launch(rgb, depth, target_rgb, target_depth, target_index, n_views, r, mask, count, lambda_rgb,
                            lambda_ssim, lambda_depth, loss, dL_drgb, dL_ddepth, ws, S(stream));
+}
+
+extern "C" size_t gsr_prune_workspace(int64_t n) { return n < 0 ? 0 : gsr_prune_ws_bytes(n); }
+
+extern "C" gsr_status gsr_prune_select(const float *opacity_logits, const int32_t *segment_id, int32_t min_segment,
+                                       int64_t n, float max_logit, float max_ratio, uint32_t *keep_index,
+                                       uint32_t *n_keep, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (n < 0 || n >= (int64_t)UINT32_MAX || !n_keep) return GSR_E_INVALID;
+    if (!(max_ratio >= 0.0f && max_ratio <= 1.0f) || std::isnan(max_logit)) return GSR_E_INVALID;
+    if (n > 0 && (!opacity_logits || !keep_index || !ws || ws_bytes < gsr_prune_ws_bytes(n))) return GSR_E_INVALID;
+    const uint64_t budget = (uint64_t)floor((double)max_ratio * (double)n);
+    return gsr_prune_launch(opacity_logits, segment_id, min_segment, n, max_logit, budget, keep_index, n_keep, ws,
+                            S(stream));
+}
+
+extern "C" gsr_status gsr_gather_rows(const gsr_row_groups *groups, int64_t src_rows, const uint32_t *index,
+                                      int64_t n_rows, int64_t dst_rows, int64_t dst_offset, gsr_stream stream) {
+    if (!groups || groups->n_groups < 0 || groups->n_groups > GSR_MAX_ROW_GROUPS) return GSR_E_INVALID;
+    if (src_rows < 0 || n_rows < 0 || dst_offset < 0 || dst_offset + n_rows > dst_rows) return GSR_E_INVALID;
+    if (!index && n_rows > src_rows) return GSR_E_INVALID;
+    for (int k = 0; k < groups->n_groups; k++)
+        if (groups->cols[k] < 0 || (groups->cols[k] > 0 && n_rows > 0 && (!groups->src[k] || !groups->dst[k])))
+            return GSR_E_INVALID;
+    if (n_rows > 0 && index == nullptr && src_rows == 0) return GSR_E_INVALID;
+    return gsr_gather_launch(groups, src_rows, index, n_rows, dst_rows, dst_offset, S(stream));
+}
+
+extern "C" size_t gsr_proximity_workspace(int64_t n_map, int64_t n_new) {
+    return (n_map < 0 || n_new < 0) ? 0 : gsr_proximity_ws_bytes(n_map, n_new);
+}
+
+extern "C" gsr_status gsr_proximity_filter(const float *map_means, int64_t n_map, const float *new_means,
+                                           int64_t n_new, float d_min, uint8_t *keep, uint32_t *keep_index,
+                                           uint32_t *n_keep, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (n_map < 0 || n_new < 0 || n_map >= (int64_t)UINT32_MAX || n_new >= (int64_t)UINT32_MAX || !n_keep)
+        return GSR_E_INVALID;
+    if (!(d_min > 0.0f) || !std::isfinite(d_min)) return GSR_E_INVALID;
+    if (n_map > 0 && !map_means) return GSR_E_INVALID;
+    if (n_new > 0 && (!new_means || !keep || !keep_index || !ws || ws_bytes < gsr_proximity_ws_bytes(n_map, n_new)))
+        return GSR_E_INVALID;
+    return gsr_proximity_launch(map_means, n_map, new_means, n_new, d_min, keep, keep_index, n_keep, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream) {

@@ -510,6 +510,16 @@ extern "C" size_t gsr_sort_pairs_ws_bytes(int64_t n) {
     return (size_t)((int64_t)kRadix * ceil_div(n > 0 ? n : 1, kSortTile) * 4 + kRadix * 4 + 512);
 }
 
+// As gsr_sort_pairs_launch with the count read on the device (*n_dev, at most cap).
+extern "C" gsr_status gsr_sort_pairs_dev_launch(uint32_t *k, uint32_t *v, uint32_t *k2, uint32_t *v2,
+                                                const uint32_t *n_dev, uint32_t cap, int bits, void *ws,
+                                                hipStream_t st) {
+    if (cap == 0) return GSR_OK;
+    uint32_t *hist = static_cast<uint32_t *>(ws);
+    uint32_t *totals = hist + (size_t)kRadix * ceil_div(cap, kSortTile);
+    return radix_sort(k, v, k2, v2, n_dev, cap, cap, bits, hist, totals, st);
+}
+
 extern "C" gsr_status gsr_sort_pairs_launch(uint32_t *k, uint32_t *v, uint32_t *k2, uint32_t *v2, uint32_t n, int bits,
                                             void *ws, hipStream_t st) {
     if (n == 0) return GSR_OK;

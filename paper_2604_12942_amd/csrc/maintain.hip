@@ -1,0 +1,308 @@
+// Map maintenance around the optimisation (Sec. III-C): low-opacity pruning under a bounded
+// removal ratio, the proximity filter that drops newly initialised Gaussians lying on top of the
+// existing map, and the row gather that compacts or appends component-major arrays (parameters
+// and their Adam moments travel together).
+//
+// Pruning is a selection: candidates are compacted in row order, stably radix-sorted on an
+// order-preserving encoding of the logit (so equal logits stay in row order), the first
+// min(count, budget) are marked, and the survivors are compacted.  Everything stays on the device.
+//
+// The proximity filter hashes map means into cells of edge slightly above d_min, sorts the 32-bit
+// cell hashes, and lets every new mean probe the 27 cells around its own: a hash collision only
+// adds candidates, and the exact distance test decides.
+#include "gsr_internal.h"
+
+extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
+extern "C" size_t gsr_scan_ws_bytes(int64_t);
+extern "C" size_t gsr_sort_pairs_ws_bytes(int64_t);
+extern "C" gsr_status gsr_sort_pairs_launch(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, int, void *,
+                                            hipStream_t);
+extern "C" gsr_status gsr_sort_pairs_dev_launch(uint32_t *, uint32_t *, uint32_t *, uint32_t *, const uint32_t *,
+                                                uint32_t, int, void *, hipStream_t);
+extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+
+namespace gsr {
+
+constexpr int kBucketBits = 16;
+constexpr int kBuckets = 1 << kBucketBits;
+
+// Order-preserving map of a float to uint32 (ascending floats give ascending keys).
+__device__ __forceinline__ uint32_t float_key(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void k_prune_flags(const float *__restrict__ logit, const int32_t *__restrict__ seg, int32_t min_seg,
+                              int64_t n, float thr, uint32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (logit[i] < thr && (!seg || seg[i] >= min_seg)) ? 1u : 0u;
+}
+
+__global__ void k_prune_scatter(const float *__restrict__ logit, const uint32_t *__restrict__ flag,
+                                const uint32_t *__restrict__ off, int64_t n, uint32_t *__restrict__ key,
+                                uint32_t *__restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    key[off[i]] = float_key(logit[i]);
+    val[off[i]] = (uint32_t)i;
+}
+
+// keep[i] = 0 for the first min(count, budget) sorted candidates (keep was filled with 1)
+__global__ void k_prune_mark(const uint32_t *__restrict__ sorted_val, const uint32_t *__restrict__ count,
+                             uint64_t budget, uint32_t *__restrict__ keep) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t c = *count;
+    if (j < c && j < budget) keep[sorted_val[j]] = 0u;
+}
+
+// out[off[i]] = i for every flagged i (ordered compaction of row indices)
+__global__ void k_compact_index(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ off, int64_t n,
+                                uint32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) out[off[i]] = (uint32_t)i;
+}
+
+struct RowGroupsDev {
+    const uint32_t *src[GSR_MAX_ROW_GROUPS];
+    uint32_t *dst[GSR_MAX_ROW_GROUPS];
+    int32_t col_end[GSR_MAX_ROW_GROUPS];  // exclusive running column count
+    int32_t n_groups;
+};
+
+constexpr int kGatherCols = 8;  // columns per block: the row index is read once for all of them
+
+// dst[c][dst_offset + j] = src[c][index ? index[j] : j]; blockIdx.y walks chunks of kGatherCols
+// consecutive columns of the groups' concatenated column list
+__global__ __launch_bounds__(256) void k_gather_rows(RowGroupsDev G, int total_cols, int64_t src_rows,
+                                                     const uint32_t *__restrict__ index, int64_t n_rows,
+                                                     int64_t dst_rows, int64_t dst_offset) {
+    const int col0 = blockIdx.y * kGatherCols;
+    const uint32_t *s[kGatherCols];
+    uint32_t *d[kGatherCols];
+    int g = 0;
+#pragma unroll
+    for (int q = 0; q < kGatherCols; q++) {
+        const int col = col0 + q < total_cols ? col0 + q : total_cols - 1;
+        while (g + 1 < G.n_groups && col >= G.col_end[g]) g++;
+        const int c = col - (g ? G.col_end[g - 1] : 0);
+        s[q] = G.src[g] + (int64_t)c * src_rows;
+        d[q] = G.dst[g] + (int64_t)c * dst_rows + dst_offset;
+    }
+    const int nq = total_cols - col0 < kGatherCols ? total_cols - col0 : kGatherCols;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_rows; j += (int64_t)gridDim.x * 256) {
+        const int64_t r = index ? (int64_t)index[j] : j;
+        if (r >= src_rows) continue;
+        uint32_t x[kGatherCols];
+#pragma unroll
+        for (int q = 0; q < kGatherCols; q++) x[q] = q < nq ? s[q][r] : 0u;
+#pragma unroll
+        for (int q = 0; q < kGatherCols; q++)
+            if (q < nq) d[q][j] = x[q];
+    }
+}
+
+// ---- proximity filter -------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cell_hash(int64_t cx, int64_t cy, int64_t cz) {
+    uint64_t z = ((uint64_t)cx & 0x1FFFFFull) | (((uint64_t)cy & 0x1FFFFFull) << 21) |
+                 (((uint64_t)cz & 0x1FFFFFull) << 42);
+    // SplitMix64 finaliser
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (uint32_t)z;
+}
+
+__device__ __forceinline__ int64_t cell_of(float x, double inv_cell) { return (int64_t)floor((double)x * inv_cell); }
+
+__global__ void k_map_cells(const float *__restrict__ means, int64_t n, double inv_cell, uint32_t *__restrict__ key,
+                            uint32_t *__restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = cell_hash(cell_of(means[i], inv_cell), cell_of(means[n + i], inv_cell), cell_of(means[2 * n + i], inv_cell));
+    val[i] = (uint32_t)i;
+}
+
+// bucket[b] = first sorted position whose hash has top bits >= b; bucket[kBuckets] = n
+__global__ void k_bucket_bounds(const uint32_t *__restrict__ key, int64_t n, uint32_t *__restrict__ bucket) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > kBuckets) return;
+    if (b == kBuckets) {
+        bucket[b] = (uint32_t)n;
+        return;
+    }
+    const uint32_t target = (uint32_t)b << (32 - kBucketBits);
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    bucket[b] = (uint32_t)lo;
+}
+
+__global__ __launch_bounds__(256) void k_proximity(const float *__restrict__ map, int64_t n_map,
+                                                   const float *__restrict__ nw, int64_t n_new, double inv_cell,
+                                                   double dd, const uint32_t *__restrict__ key,
+                                                   const uint32_t *__restrict__ val, const uint32_t *__restrict__ bucket,
+                                                   uint8_t *__restrict__ keep, uint32_t *__restrict__ flag) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_new) return;
+    const float px = nw[j], py = nw[n_new + j], pz = nw[2 * n_new + j];
+    const int64_t cx = cell_of(px, inv_cell), cy = cell_of(py, inv_cell), cz = cell_of(pz, inv_cell);
+    bool found = false;
+    for (int d = 0; d < 27 && !found; d++) {
+        const uint32_t h = cell_hash(cx + d % 3 - 1, cy + (d / 3) % 3 - 1, cz + d / 9 - 1);
+        const uint32_t b = h >> (32 - kBucketBits);
+        uint32_t lo = bucket[b], hi = bucket[b + 1];
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (key[mid] < h) lo = mid + 1;
+            else hi = mid;
+        }
+        for (uint32_t e = lo; e < (uint32_t)n_map && key[e] == h && !found; e++) {
+            const uint32_t i = val[e];
+            // float64, no contraction: ((dx dx + dy dy) + dz dz) < d_min^2
+            const double dx = __dsub_rn((double)px, (double)map[i]);
+            const double dy = __dsub_rn((double)py, (double)map[n_map + i]);
+            const double dz = __dsub_rn((double)pz, (double)map[2 * n_map + i]);
+            const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            found = d2 < dd;
+        }
+    }
+    keep[j] = found ? 0 : 1;
+    flag[j] = found ? 0u : 1u;
+}
+
+size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct PruneWs {
+    uint32_t *flag, *off, *k, *v, *k2, *v2, *count;
+    void *scan, *sort;
+    size_t bytes;
+};
+
+PruneWs prune_layout(void *base, int64_t n) {
+    PruneWs w;
+    const size_t words = a256((size_t)(n > 0 ? n : 1) * 4);
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        void *r = p ? p + off : nullptr;
+        off += a256(b);
+        return r;
+    };
+    w.flag = (uint32_t *)take(words);
+    w.off = (uint32_t *)take(words);
+    w.k = (uint32_t *)take(words);
+    w.v = (uint32_t *)take(words);
+    w.k2 = (uint32_t *)take(words);
+    w.v2 = (uint32_t *)take(words);
+    w.count = (uint32_t *)take(256);
+    w.scan = take(gsr_scan_ws_bytes(n));
+    w.sort = take(gsr_sort_pairs_ws_bytes(n));
+    w.bytes = off;
+    return w;
+}
+
+struct ProxWs {
+    uint32_t *k, *v, *k2, *v2, *bucket, *flag, *off;
+    void *scan, *sort;
+    size_t bytes;
+};
+
+ProxWs prox_layout(void *base, int64_t n_map, int64_t n_new) {
+    ProxWs w;
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        void *r = p ? p + off : nullptr;
+        off += a256(b);
+        return r;
+    };
+    const size_t wm = (size_t)(n_map > 0 ? n_map : 1) * 4, wn = (size_t)(n_new > 0 ? n_new : 1) * 4;
+    w.k = (uint32_t *)take(wm);
+    w.v = (uint32_t *)take(wm);
+    w.k2 = (uint32_t *)take(wm);
+    w.v2 = (uint32_t *)take(wm);
+    w.bucket = (uint32_t *)take((size_t)(kBuckets + 1) * 4);
+    w.flag = (uint32_t *)take(wn);
+    w.off = (uint32_t *)take(wn);
+    w.scan = take(gsr_scan_ws_bytes(n_new));
+    w.sort = take(gsr_sort_pairs_ws_bytes(n_map));
+    w.bytes = off;
+    return w;
+}
+
+int nblk(int64_t n) { return (int)ceil_div(n > 0 ? n : 1, 256); }
+
+}  // namespace gsr
+
+using namespace gsr;
+
+extern "C" size_t gsr_prune_ws_bytes(int64_t n) { return prune_layout(nullptr, n).bytes; }
+
+extern "C" gsr_status gsr_prune_launch(const float *logit, const int32_t *seg, int32_t min_seg, int64_t n, float thr,
+                                       uint64_t budget, uint32_t *keep_index, uint32_t *n_keep, void *ws,
+                                       hipStream_t st) {
+    if (n == 0) return gsr_fill_u32_launch(n_keep, 0u, 1, st);
+    PruneWs w = prune_layout(ws, n);
+    k_prune_flags<<<nblk(n), 256, 0, st>>>(logit, seg, min_seg, n, thr, w.flag);
+    gsr_status s = gsr_scan_launch(w.flag, n, w.off, w.count, w.scan, st);
+    if (s != GSR_OK) return s;
+    k_prune_scatter<<<nblk(n), 256, 0, st>>>(logit, w.flag, w.off, n, w.k, w.v);
+    // four 8-bit passes: the sorted pairs end in (k, v)
+    s = gsr_sort_pairs_dev_launch(w.k, w.v, w.k2, w.v2, w.count, (uint32_t)n, 32, w.sort, st);
+    if (s != GSR_OK) return s;
+    s = gsr_fill_u32_launch(w.flag, 1u, n, st);  // flag becomes the keep flag
+    if (s != GSR_OK) return s;
+    if (budget > 0) k_prune_mark<<<nblk(n), 256, 0, st>>>(w.v, w.count, budget, w.flag);
+    s = gsr_scan_launch(w.flag, n, w.off, n_keep, w.scan, st);
+    if (s != GSR_OK) return s;
+    k_compact_index<<<nblk(n), 256, 0, st>>>(w.flag, w.off, n, keep_index);
+    return last_launch();
+}
+
+extern "C" gsr_status gsr_gather_launch(const gsr_row_groups *g, int64_t src_rows, const uint32_t *index,
+                                        int64_t n_rows, int64_t dst_rows, int64_t dst_offset, hipStream_t st) {
+    RowGroupsDev G;
+    int cols = 0;
+    for (int k = 0; k < g->n_groups; k++) {
+        G.src[k] = static_cast<const uint32_t *>(g->src[k]);
+        G.dst[k] = static_cast<uint32_t *>(g->dst[k]);
+        cols += g->cols[k];
+        G.col_end[k] = cols;
+    }
+    G.n_groups = g->n_groups;
+    if (n_rows == 0 || cols == 0) return GSR_OK;
+    const int nbx = (int)(ceil_div(n_rows, 256) < 512 ? ceil_div(n_rows, 256) : 512);
+    k_gather_rows<<<dim3(nbx, (unsigned)ceil_div(cols, kGatherCols)), 256, 0, st>>>(G, cols, src_rows, index, n_rows,
+                                                                                    dst_rows, dst_offset);
+    return last_launch();
+}
+
+extern "C" size_t gsr_proximity_ws_bytes(int64_t n_map, int64_t n_new) { return prox_layout(nullptr, n_map, n_new).bytes; }
+
+extern "C" gsr_status gsr_proximity_launch(const float *map, int64_t n_map, const float *nw, int64_t n_new, float d_min,
+                                           uint8_t *keep, uint32_t *keep_index, uint32_t *n_keep, void *ws,
+                                           hipStream_t st) {
+    if (n_new == 0) return gsr_fill_u32_launch(n_keep, 0u, 1, st);
+    ProxWs w = prox_layout(ws, n_map, n_new);
+    // cells a little wider than d_min: two means closer than d_min always fall in neighbouring
+    // cells even after the float64 rounding of x / cell
+    const double cell = (double)d_min * (1.0 + 1.0 / (1 << 20));
+    const double inv_cell = 1.0 / cell;
+    const double dd = (double)d_min * (double)d_min;
+    if (n_map > 0) {
+        k_map_cells<<<nblk(n_map), 256, 0, st>>>(map, n_map, inv_cell, w.k, w.v);
+        gsr_status s = gsr_sort_pairs_launch(w.k, w.v, w.k2, w.v2, (uint32_t)n_map, 32, w.sort, st);
+        if (s != GSR_OK) return s;
+    }
+    k_bucket_bounds<<<nblk(kBuckets + 1), 256, 0, st>>>(w.k, n_map, w.bucket);
+    k_proximity<<<nblk(n_new), 256, 0, st>>>(map, n_map, nw, n_new, inv_cell, dd, w.k, w.v, w.bucket, keep, w.flag);
+    gsr_status s = gsr_scan_launch(w.flag, n_new, w.off, n_keep, w.scan, st);
+    if (s != GSR_OK) return s;
+    k_compact_index<<<nblk(n_new), 256, 0, st>>>(w.flag, w.off, n_new, keep_index);
+    return last_launch();
+}

@@ -64,6 +64,58 @@ class MapOptimizer:
         self.vis_ws = torch.empty((visible_list_workspace(self.n) + 3) // 4, dtype=torch.int32, device=device)
         self.t = 0
 
+    def _set_rows(self, P, m, v, segment_id):
+        """Adopt new row arrays (after pruning or insertion) and re-size every per-row buffer.
+        Captured graphs refer to the old buffers: capture again afterwards."""
+        from . import visible_list_workspace
+        dev = P["means"].device
+        self.P, self.m, self.v, self.segment_id = P, m, v, segment_id
+        self.n = P["means"].shape[1]
+        self.rast = Rasterizer(self.n, self.V, self.raster, device=dev)
+        self.grads = {k: torch.zeros_like(P[k]) for k in PARAM_NAMES}
+        self.row_mask = torch.zeros(self.n, dtype=torch.uint8, device=dev)
+        self.vis_list = torch.empty(max(1, self.n), dtype=torch.int32, device=dev)
+        self.vis_ws = torch.empty((visible_list_workspace(self.n) + 3) // 4, dtype=torch.int32, device=dev)
+        self.graphs = []
+
+    def _row_arrays(self):
+        rows = {k: self.P[k] for k in PARAM_NAMES}
+        rows.update({"m_" + k: self.m[k] for k in PARAM_NAMES})
+        rows.update({"v_" + k: self.v[k] for k in PARAM_NAMES})
+        if self.segment_id is not None:
+            rows["segment_id"] = self.segment_id
+        return rows
+
+    def _adopt(self, rows):
+        P = dict(self.P)
+        P.update({k: rows[k] for k in PARAM_NAMES})
+        self._set_rows(P, {k: rows["m_" + k] for k in PARAM_NAMES}, {k: rows["v_" + k] for k in PARAM_NAMES},
+                       rows.get("segment_id"))
+
+    def prune(self, min_opacity=0.005, max_ratio=0.05):
+        """Low-opacity pruning (Sec. III-C) of the unfrozen segments; Adam moments and segment ids
+        follow their rows.  Returns the number of removed Gaussians."""
+        from .maintain import prune
+        rows, removed = prune(self._row_arrays(), self.P["opacity_logits"], min_opacity, max_ratio,
+                              self.segment_id, self.min_segment)
+        self._adopt(rows)
+        return removed
+
+    def insert(self, new_params, new_segment_id=None, d_min=0.05):
+        """Insert new Gaussians (dict of [c, m] tensors) except those within d_min of the map,
+        with zero Adam moments.  Returns the number inserted."""
+        from .maintain import insert
+        new = {k: new_params[k] for k in PARAM_NAMES}
+        new.update({"m_" + k: torch.zeros_like(new_params[k]) for k in PARAM_NAMES})
+        new.update({"v_" + k: torch.zeros_like(new_params[k]) for k in PARAM_NAMES})
+        if self.segment_id is not None:
+            if new_segment_id is None:
+                raise ValueError("the map has segment ids: give the new rows theirs")
+            new["segment_id"] = new_segment_id
+        rows, added = insert(self._row_arrays(), new, d_min)
+        self._adopt(rows)
+        return added
+
     def set_views(self, idx):
         """Choose this iteration's keyframes (slots of the camera / target pool).  A device
         tensor is copied on the stream without a host round-trip."""
