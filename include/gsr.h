@@ -381,6 +381,43 @@ GSR_API gsr_status gsr_proximity_filter(const float *map_means, int64_t n_map, c
                                         float d_min, uint8_t *keep, uint32_t *keep_index, uint32_t *n_keep, void *ws,
                                         size_t ws_bytes, gsr_stream stream);
 
+/* ---- Gaussian-based loop registration (Sec. III-D, Eq. 13-16) -------------------------------------
+ * Geometric decisions are taken in float64 from the float32 inputs with every operation rounded
+ * separately, in this order: camera k sees mean mu when, with p = R mu + t computed per coordinate
+ * as ((R_r0 x + R_r1 y) + R_r2 z) + t_r, z > z_near and u = fx (x / z) + cx in [0, W),
+ * v = fy (y / z) + cy in [0, H); its centre is c = -R^T t (each coordinate
+ * -((R_0i t_0 + R_1i t_1) + R_2i t_2)); squared distances are ((dx dx + dy dy) + dz dz).
+ *
+ * gsr_gicp_prepare: the source set (rows with segment_id == src_segment) into src_index and the
+ * target set of Eq. 13 (rows outside the source set that some camera of cams [n_cams] (device)
+ * sees, with the camera centre closer than d_max) into tgt_index, both in ascending row order,
+ * counts (device uint32 [2]) = (n_src, n_tgt).  Every listed Gaussian's covariance R_q S^2 R_q^T
+ * has its eigenvalues replaced by (1, 1, 1e-3), the 1e-3 on the smallest-scale axis (the first
+ * on ties), and the target means are gridded for d_corr; all of it is kept in ws.  stats (device
+ * double [40]) is cleared.  g supplies means, log_scales and quats; src_index, tgt_index [n].
+ *
+ * gsr_gicp_iterate: n_iter Gauss-Newton iterations of Eq. 16 from pose (device double [12]: R
+ * row-major, then t; the transform applied to the source means), updated in place.  Each
+ * iteration pairs source mean m, moved to q = R mu_m + t, with the nearest target mean strictly
+ * within d_corr (lowest target position on ties), forms r = mu_n - q, C = S_n + R S_m R^T,
+ * W = C^-1, J = dr/dxi = [-I, [q]x] for the left perturbation xi = (rho, phi), sums
+ * H = J^T W J, g = J^T W r, cost = r^T W r, |r|^2 and the count, solves H xi = -g and sets
+ * (R, t) <- (Exp(phi) R, Exp(phi) t + rho).  stats: [0, 21) H upper triangle row-major, [21, 27) g,
+ * 27 cost, 28 sum |r|^2, 29 count (of the last linearisation), [30, 36) the last xi, 36 converged
+ * (last step |rho| < 2.5e-3 m and |phi| < 2.5e-4 rad), 37 iterations done, 38 failed (fewer than 6 correspondences
+ * or H not positive definite).  Once converged or failed, further iterations do nothing.  corr
+ * (device int32 [n], may be NULL) receives, per source position, the target position of the last
+ * linearisation or -1.  Call with the same g, index arrays, d_corr and ws as gsr_gicp_prepare.
+ * ws: gsr_gicp_workspace(n) bytes, 256-byte aligned.  d_max, d_corr > 0. */
+GSR_API size_t gsr_gicp_workspace(int64_t n);
+GSR_API gsr_status gsr_gicp_prepare(const gsr_gaussians *g, const int32_t *segment_id, int32_t src_segment,
+                                    const gsr_camera *cams, int32_t n_cams, float d_max, float d_corr,
+                                    uint32_t *src_index, uint32_t *tgt_index, uint32_t *counts, double *stats,
+                                    void *ws, size_t ws_bytes, gsr_stream stream);
+GSR_API gsr_status gsr_gicp_iterate(const gsr_gaussians *g, const uint32_t *src_index, const uint32_t *tgt_index,
+                                    const uint32_t *counts, float d_corr, double *pose, double *stats, int32_t *corr,
+                                    int32_t n_iter, void *ws, size_t ws_bytes, gsr_stream stream);
+
 /* ---- voxel-PCA geometric fitting (Sec. III-A, Eq. 1-2) ------------------------------------------
  * Points [3][n] (float32, world frame) are binned into 0.5 m voxels, key floor(p / 0.5), valid for
  * x, y in [-512, 512) m and z in [-255.5, 256) m (points outside are counted in *n_outside and

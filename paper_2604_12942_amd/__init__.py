@@ -306,6 +306,35 @@ def proximity_filter(map_means, new_means, d_min, ws=None):
     return keep, keep_index, n_keep
 
 
+def gicp_prepare(P, sh_degree, segment_id, src_segment, cams, n_cams, d_max, d_corr, state=None):
+    """Loop-registration set-up (Sec. III-D, Eq. 13): returns a state dict (source / target row
+    lists, counts, stats and the workspace) for gicp_iterate."""
+    G = _gauss_struct(P, sh_degree)
+    n = G.n
+    dev = P["means"].device
+    if state is None or state["n"] != n:
+        state = dict(n=n, src_index=torch.empty(max(1, n), dtype=torch.int32, device=dev),
+                     tgt_index=torch.empty(max(1, n), dtype=torch.int32, device=dev),
+                     counts=torch.zeros(2, dtype=torch.int32, device=dev),
+                     stats=torch.zeros(40, dtype=torch.float64, device=dev),
+                     ws=torch.empty(max(1, lib().gsr_gicp_workspace(n)), dtype=torch.uint8, device=dev))
+    state["d_corr"] = float(d_corr)
+    check(lib().gsr_gicp_prepare(C.byref(G), _ptr(segment_id), src_segment, _ptr(cams), n_cams, d_max, d_corr,
+                                 _ptr(state["src_index"]), _ptr(state["tgt_index"]), _ptr(state["counts"]),
+                                 _ptr(state["stats"]), _ptr(state["ws"]), state["ws"].numel(), _stream()),
+          "gsr_gicp_prepare")
+    return state
+
+
+def gicp_iterate(P, sh_degree, state, pose, n_iter, corr=None):
+    """n_iter Gauss-Newton iterations of Eq. 16 on pose (device float64 [12]: R row-major, t),
+    in place; statistics in state["stats"]."""
+    G = _gauss_struct(P, sh_degree)
+    check(lib().gsr_gicp_iterate(C.byref(G), _ptr(state["src_index"]), _ptr(state["tgt_index"]),
+                                 _ptr(state["counts"]), state["d_corr"], _ptr(pose), _ptr(state["stats"]), _ptr(corr),
+                                 n_iter, _ptr(state["ws"]), state["ws"].numel(), _stream()), "gsr_gicp_iterate")
+
+
 def fill_u32(t, value):
     check(lib().gsr_fill_u32(_ptr(t), value & 0xFFFFFFFF, t.numel() * t.element_size() // 4, _stream()),
           "gsr_fill_u32")

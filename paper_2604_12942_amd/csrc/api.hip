@@ -53,6 +53,13 @@ extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const ui
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
                                          int, const gsr_raster *, float, double *, float *, float *, hipStream_t);
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+extern "C" size_t gsr_gicp_ws_bytes(int64_t);
+extern "C" gsr_status gsr_gicp_prepare_launch(const gsr_gaussians *, const int32_t *, int32_t, const gsr_camera *, int,
+                                              float, float, uint32_t *, uint32_t *, uint32_t *, double *, void *,
+                                              hipStream_t);
+extern "C" gsr_status gsr_gicp_iterate_launch(const gsr_gaussians *, const uint32_t *, const uint32_t *,
+                                              const uint32_t *, float, double *, double *, int32_t *, int, void *,
+                                              hipStream_t);
 extern "C" size_t gsr_prune_ws_bytes(int64_t);
 extern "C" gsr_status gsr_prune_launch(const float *, const int32_t *, int32_t, int64_t, float, uint64_t, uint32_t *,
                                        uint32_t *, void *, hipStream_t);
@@ -363,6 +370,35 @@ extern "C" gsr_status gsr_proximity_filter(const float *map_means, int64_t n_map
     if (n_new > 0 && (!new_means || !keep || !keep_index || !ws || ws_bytes < gsr_proximity_ws_bytes(n_map, n_new)))
         return GSR_E_INVALID;
     return gsr_proximity_launch(map_means, n_map, new_means, n_new, d_min, keep, keep_index, n_keep, ws, S(stream));
+}
+
+extern "C" size_t gsr_gicp_workspace(int64_t n) { return n < 0 ? 0 : gsr_gicp_ws_bytes(n); }
+
+namespace {
+bool gicp_gauss_ok(const gsr_gaussians *g) {
+    return g && g->n >= 0 && g->n < (int64_t)UINT32_MAX && (g->n == 0 || (g->means && g->quats && g->log_scales));
+}
+}  // namespace
+
+extern "C" gsr_status gsr_gicp_prepare(const gsr_gaussians *g, const int32_t *segment_id, int32_t src_segment,
+                                       const gsr_camera *cams, int32_t n_cams, float d_max, float d_corr,
+                                       uint32_t *src_index, uint32_t *tgt_index, uint32_t *counts, double *stats,
+                                       void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (!gicp_gauss_ok(g) || !counts || !stats || n_cams < 0 || (n_cams > 0 && !cams)) return GSR_E_INVALID;
+    if (!(d_max > 0.0f) || !(d_corr > 0.0f) || !std::isfinite(d_max) || !std::isfinite(d_corr)) return GSR_E_INVALID;
+    if (g->n > 0 && (!segment_id || !src_index || !tgt_index || !ws || ws_bytes < gsr_gicp_ws_bytes(g->n)))
+        return GSR_E_INVALID;
+    return gsr_gicp_prepare_launch(g, segment_id, src_segment, cams, n_cams, d_max, d_corr, src_index, tgt_index,
+                                   counts, stats, ws, S(stream));
+}
+
+extern "C" gsr_status gsr_gicp_iterate(const gsr_gaussians *g, const uint32_t *src_index, const uint32_t *tgt_index,
+                                       const uint32_t *counts, float d_corr, double *pose, double *stats,
+                                       int32_t *corr, int32_t n_iter, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (!gicp_gauss_ok(g) || !counts || !pose || !stats || n_iter < 0) return GSR_E_INVALID;
+    if (!(d_corr > 0.0f) || !std::isfinite(d_corr)) return GSR_E_INVALID;
+    if (g->n > 0 && (!src_index || !tgt_index || !ws || ws_bytes < gsr_gicp_ws_bytes(g->n))) return GSR_E_INVALID;
+    return gsr_gicp_iterate_launch(g, src_index, tgt_index, counts, d_corr, pose, stats, corr, n_iter, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream) {

@@ -10,7 +10,7 @@
 // The proximity filter hashes map means into cells of edge slightly above d_min, sorts the 32-bit
 // cell hashes, and lets every new mean probe the 27 cells around its own: a hash collision only
 // adds candidates, and the exact distance test decides.
-#include "gsr_internal.h"
+#include "grid.h"
 
 extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
 extern "C" size_t gsr_scan_ws_bytes(int64_t);
@@ -22,9 +22,6 @@ extern "C" gsr_status gsr_sort_pairs_dev_launch(uint32_t *, uint32_t *, uint32_t
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
 
 namespace gsr {
-
-constexpr int kBucketBits = 16;
-constexpr int kBuckets = 1 << kBucketBits;
 
 // Order-preserving map of a float to uint32 (ascending floats give ascending keys).
 __device__ __forceinline__ uint32_t float_key(float x) {
@@ -102,32 +99,26 @@ __global__ __launch_bounds__(256) void k_gather_rows(RowGroupsDev G, int total_c
     }
 }
 
-// ---- proximity filter -------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t cell_hash(int64_t cx, int64_t cy, int64_t cz) {
-    uint64_t z = ((uint64_t)cx & 0x1FFFFFull) | (((uint64_t)cy & 0x1FFFFFull) << 21) |
-                 (((uint64_t)cz & 0x1FFFFFull) << 42);
-    // SplitMix64 finaliser
-    z += 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    return (uint32_t)z;
+// ---- grid over points (the insertion filter's map, the registration's target set) -------------
+__global__ void k_grid_cells(const float *__restrict__ means, int64_t stride, const uint32_t *__restrict__ index,
+                             const uint32_t *__restrict__ count_dev, int64_t cap, double inv_cell,
+                             uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = count_dev ? (int64_t)*count_dev : cap;
+    if (j >= n || j >= cap) return;
+    const int64_t i = index ? (int64_t)index[j] : j;
+    key[j] = cell_hash(cell_of(means[i], inv_cell), cell_of(means[stride + i], inv_cell),
+                       cell_of(means[2 * stride + i], inv_cell));
+    val[j] = (uint32_t)j;
 }
 
-__device__ __forceinline__ int64_t cell_of(float x, double inv_cell) { return (int64_t)floor((double)x * inv_cell); }
-
-__global__ void k_map_cells(const float *__restrict__ means, int64_t n, double inv_cell, uint32_t *__restrict__ key,
-                            uint32_t *__restrict__ val) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    key[i] = cell_hash(cell_of(means[i], inv_cell), cell_of(means[n + i], inv_cell), cell_of(means[2 * n + i], inv_cell));
-    val[i] = (uint32_t)i;
-}
-
-// bucket[b] = first sorted position whose hash has top bits >= b; bucket[kBuckets] = n
-__global__ void k_bucket_bounds(const uint32_t *__restrict__ key, int64_t n, uint32_t *__restrict__ bucket) {
+// bucket[b] = first sorted position whose hash has top bits >= b; bucket[kBuckets] = count
+__global__ void k_bucket_bounds(const uint32_t *__restrict__ key, const uint32_t *__restrict__ count_dev, int64_t cap,
+                                uint32_t *__restrict__ bucket) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > kBuckets) return;
+    int64_t n = count_dev ? (int64_t)*count_dev : cap;
+    n = n < cap ? n : cap;
     if (b == kBuckets) {
         bucket[b] = (uint32_t)n;
         return;
@@ -149,26 +140,15 @@ __global__ __launch_bounds__(256) void k_proximity(const float *__restrict__ map
                                                    uint8_t *__restrict__ keep, uint32_t *__restrict__ flag) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_new) return;
-    const float px = nw[j], py = nw[n_new + j], pz = nw[2 * n_new + j];
+    const double px = nw[j], py = nw[n_new + j], pz = nw[2 * n_new + j];
     const int64_t cx = cell_of(px, inv_cell), cy = cell_of(py, inv_cell), cz = cell_of(pz, inv_cell);
     bool found = false;
     for (int d = 0; d < 27 && !found; d++) {
         const uint32_t h = cell_hash(cx + d % 3 - 1, cy + (d / 3) % 3 - 1, cz + d / 9 - 1);
-        const uint32_t b = h >> (32 - kBucketBits);
-        uint32_t lo = bucket[b], hi = bucket[b + 1];
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (key[mid] < h) lo = mid + 1;
-            else hi = mid;
-        }
-        for (uint32_t e = lo; e < (uint32_t)n_map && key[e] == h && !found; e++) {
+        for (uint32_t e = grid_lower_bound(key, bucket, h); e < (uint32_t)n_map && key[e] == h && !found; e++) {
             const uint32_t i = val[e];
-            // float64, no contraction: ((dx dx + dy dy) + dz dz) < d_min^2
-            const double dx = __dsub_rn((double)px, (double)map[i]);
-            const double dy = __dsub_rn((double)py, (double)map[n_map + i]);
-            const double dz = __dsub_rn((double)pz, (double)map[2 * n_map + i]);
-            const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-            found = d2 < dd;
+            // ((dx dx + dy dy) + dz dz) < d_min^2 in float64
+            found = sqdist_rn(px, py, pz, map[i], map[n_map + i], map[2 * n_map + i]) < dd;
         }
     }
     keep[j] = found ? 0 : 1;
@@ -241,6 +221,21 @@ int nblk(int64_t n) { return (int)ceil_div(n > 0 ? n : 1, 256); }
 
 using namespace gsr;
 
+extern "C" gsr_status gsr_grid_build_launch(const float *means, int64_t stride, const uint32_t *index,
+                                            const uint32_t *count_dev, int64_t cap, double cell, uint32_t *keys,
+                                            uint32_t *vals, uint32_t *k2, uint32_t *v2, uint32_t *bucket,
+                                            void *sort_ws, hipStream_t st) {
+    if (cap > 0) {
+        k_grid_cells<<<nblk(cap), 256, 0, st>>>(means, stride, index, count_dev, cap, 1.0 / cell, keys, vals);
+        gsr_status s = count_dev
+                           ? gsr_sort_pairs_dev_launch(keys, vals, k2, v2, count_dev, (uint32_t)cap, 32, sort_ws, st)
+                           : gsr_sort_pairs_launch(keys, vals, k2, v2, (uint32_t)cap, 32, sort_ws, st);
+        if (s != GSR_OK) return s;
+    }
+    k_bucket_bounds<<<nblk(kBuckets + 1), 256, 0, st>>>(keys, count_dev, cap, bucket);
+    return last_launch();
+}
+
 extern "C" size_t gsr_prune_ws_bytes(int64_t n) { return prune_layout(nullptr, n).bytes; }
 
 extern "C" gsr_status gsr_prune_launch(const float *logit, const int32_t *seg, int32_t min_seg, int64_t n, float thr,
@@ -294,14 +289,11 @@ extern "C" gsr_status gsr_proximity_launch(const float *map, int64_t n_map, cons
     const double cell = (double)d_min * (1.0 + 1.0 / (1 << 20));
     const double inv_cell = 1.0 / cell;
     const double dd = (double)d_min * (double)d_min;
-    if (n_map > 0) {
-        k_map_cells<<<nblk(n_map), 256, 0, st>>>(map, n_map, inv_cell, w.k, w.v);
-        gsr_status s = gsr_sort_pairs_launch(w.k, w.v, w.k2, w.v2, (uint32_t)n_map, 32, w.sort, st);
-        if (s != GSR_OK) return s;
-    }
-    k_bucket_bounds<<<nblk(kBuckets + 1), 256, 0, st>>>(w.k, n_map, w.bucket);
+    gsr_status s = gsr_grid_build_launch(map, n_map, nullptr, nullptr, n_map, cell, w.k, w.v, w.k2, w.v2, w.bucket,
+                                         w.sort, st);
+    if (s != GSR_OK) return s;
     k_proximity<<<nblk(n_new), 256, 0, st>>>(map, n_map, nw, n_new, inv_cell, dd, w.k, w.v, w.bucket, keep, w.flag);
-    gsr_status s = gsr_scan_launch(w.flag, n_new, w.off, n_keep, w.scan, st);
+    s = gsr_scan_launch(w.flag, n_new, w.off, n_keep, w.scan, st);
     if (s != GSR_OK) return s;
     k_compact_index<<<nblk(n_new), 256, 0, st>>>(w.flag, w.off, n_new, keep_index);
     return last_launch();
