@@ -174,3 +174,77 @@ def register(R0, t0, src_means, src_cov, tgt_means, tgt_cov, d_corr, max_iter=30
             break
     accepted = bool(conv and ne["count"] >= MIN_CORR and ne["cost"] / ne["count"] < ACCEPT_COST)
     return dict(R=R, t=t, converged=conv, iterations=it, stats=ne, accepted=accepted)
+
+
+# ---- propagation of a corrected pose to a segment (Sec. III-D, last paragraph) ---------------------
+#
+# The segment's Gaussians move rigidly with the world-frame transform (R, t): means R mu + t,
+# orientations R R_q (quaternion q_R (x) q), and the view-dependent colour rotates with them:
+# colour'(R d) = colour(d), i.e. the new SH coefficients of each degree are the least-squares fit
+# of the old colour function sampled at R^T d.  The segment's cameras (world -> camera R_c, t_c)
+# move with it: R_c R^T, t_c - R_c R^T t.
+
+def rot_to_quat(R):
+    """Unit quaternion (w, x, y, z) of a rotation matrix (scipy's conversion), sign chosen w >= 0."""
+    from scipy.spatial.transform import Rotation
+    x, y, z, w = Rotation.from_matrix(np.asarray(R, np.float64)).as_quat()
+    q = np.array([w, x, y, z])
+    return -q if w < 0 else q
+
+
+def quat_mul(a, b):
+    """Hamilton product a (x) b for (w, x, y, z) quaternions; b may be [4, n]."""
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw])
+
+
+def sh_rotation_fit(R, degree, n_dirs=400, seed=0):
+    """Per degree l >= 1, the matrix D_l with c' = D_l c such that sum_a c'_a Y_a(d) =
+    sum_b c_b Y_b(R^T d) for every direction d: the least-squares solution of Y D = Y_rot over
+    random directions (exact, since each degree's span is closed under rotation)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n_dirs, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y, _ = oracle.sh_basis(degree, d)                 # [n_dirs, K]
+    Yr, _ = oracle.sh_basis(degree, d @ np.asarray(R))  # rows R^T d
+    out = {}
+    for l in range(1, degree + 1):
+        s = slice(l * l, (l + 1) * (l + 1))
+        # Y[:, s] D = Yr[:, s]  =>  new coefficients c' = D c
+        D, *_ = np.linalg.lstsq(Y[:, s], Yr[:, s], rcond=None)
+        out[l] = D
+    return out
+
+
+def transform_segment(g, segment_id, segment, R, t):
+    """New means [3, n], quats [4, n] and sh [3K, n] (float64) with the segment moved by (R, t)."""
+    R, t = np.asarray(R, np.float64), np.asarray(t, np.float64)
+    sel = np.asarray(segment_id) == segment
+    means = _f64(g["means"]).copy()
+    quats = _f64(g["quats"]).copy()
+    sh = _f64(g["sh"]).copy()
+    means[:, sel] = R @ means[:, sel] + t[:, None]
+    quats[:, sel] = quat_mul(rot_to_quat(R), quats[:, sel])
+    deg = int(g["sh_degree"])
+    D = sh_rotation_fit(R, deg) if deg > 0 else {}
+    K = (deg + 1) ** 2
+    old = sh.reshape(K, 3, -1)
+    new = old.copy()
+    for l, Dl in D.items():
+        s = slice(l * l, (l + 1) * (l + 1))
+        blk = new[s]
+        blk[:, :, sel] = np.einsum("ab,bcn->acn", Dl, old[s][:, :, sel])
+        new[s] = blk
+    return means, quats, new.reshape(3 * K, -1)
+
+
+def transform_camera(cam, R, t):
+    Rc = _f64(np.asarray(cam["R"]).reshape(3, 3))
+    tc = _f64(cam["t"])
+    R, t = np.asarray(R, np.float64), np.asarray(t, np.float64)
+    return Rc @ R.T, tc - Rc @ R.T @ t

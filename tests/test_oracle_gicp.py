@@ -137,3 +137,45 @@ def test_register_recovers_a_known_transform():
     # the float32 rounding of the moved source means bounds the recovery
     assert np.abs(out["R"] - Rt).max() < 1e-5 and np.abs(out["t"] - tt).max() < 1e-5
     assert out["stats"]["cost"] / out["stats"]["count"] < 1e-6
+
+
+def test_segment_transform_moves_geometry_and_colour():
+    import oracle
+    rng = np.random.default_rng(4)
+    g = synth.random_gaussians(5, 300, 3)
+    seg = rng.integers(0, 3, 300)
+    R = Rotation.from_rotvec([0.3, -0.2, 0.5]).as_matrix()
+    t = np.array([1.0, -2.0, 0.5])
+    means, quats, sh = go.transform_segment(g, seg, 1, R, t)
+    sel = seg == 1
+    m0 = g["means"].astype(np.float64)
+    np.testing.assert_allclose(means[:, sel], R @ m0[:, sel] + t[:, None], atol=1e-12)
+    np.testing.assert_array_equal(means[:, ~sel], m0[:, ~sel])
+    # orientation: R_q' = R R_q, magnitude of the raw quaternion kept
+    Rq0 = go.quat_to_rot(g["quats"].astype(np.float64).T)
+    Rq1 = go.quat_to_rot(quats.T)
+    np.testing.assert_allclose(Rq1[sel], np.einsum("ij,njk->nik", R, Rq0[sel]), atol=1e-12)
+    np.testing.assert_allclose(np.linalg.norm(quats, axis=0), np.linalg.norm(g["quats"].astype(np.float64), axis=0),
+                               rtol=1e-12)
+    # colour seen along R d after the move equals the colour seen along d before it
+    d = rng.standard_normal((50, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y0, _ = oracle.sh_basis(3, d)
+    Y1, _ = oracle.sh_basis(3, d @ R.T)
+    old = g["sh"].astype(np.float64).reshape(16, 3, -1)
+    new = sh.reshape(16, 3, -1)
+    for i in np.nonzero(sel)[0][:20]:
+        np.testing.assert_allclose(Y1 @ new[:, :, i], Y0 @ old[:, :, i], atol=1e-10)
+    # each degree's matrix is orthogonal and the map is a representation: D(R1 R2) = D(R1) D(R2)
+    R2 = Rotation.from_rotvec([-0.1, 0.4, 0.2]).as_matrix()
+    D1, D2, D12 = go.sh_rotation_fit(R, 3), go.sh_rotation_fit(R2, 3), go.sh_rotation_fit(R @ R2, 3)
+    for l in (1, 2, 3):
+        np.testing.assert_allclose(D1[l] @ D1[l].T, np.eye(2 * l + 1), atol=1e-10)
+        np.testing.assert_allclose(D12[l], D1[l] @ D2[l], atol=1e-10)
+    # the segment's camera moves with it: a moved point projects where the old one did
+    cam = synth.make_camera(Rotation.from_rotvec([0.1, 0.2, -0.3]).as_matrix(), [0.3, 0.1, 2.0], 100, 100, 50, 40,
+                            100, 80)
+    Rc, tc = go.transform_camera(cam, R, t)
+    p = rng.standard_normal(3)
+    np.testing.assert_allclose(Rc @ (R @ p + t) + tc, cam["R"].astype(np.float64) @ p + cam["t"].astype(np.float64),
+                               atol=1e-6)
