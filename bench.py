@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
-    ap.add_argument("--no-maintenance", action="store_true", help="skip the pruning / insertion timing")
+    ap.add_argument("--no-maintenance", action="store_true",
+                    help="skip the pruning / insertion and loop-registration timing")
     ap.add_argument("--no-full-loss", action="store_true",
                     help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
@@ -428,6 +429,74 @@ def maintenance_leg(g, seg, min_seg, dev, reps=5):
     return res
 
 
+def loop_leg(c, seg, dev, reps=3):
+    """Loop registration on the full map: the last segment (closing the loop) against what the first
+    four keyframes see within 30 m, from a drifted initial pose (1 deg of yaw about the target
+    set's centre, 0.2 m across the corridor, 0.1 m up); then the corrected pose is propagated to the segment's Gaussians.  The map itself is
+    consistent, so the ideal correction is the identity; the displacement it leaves is measured over
+    the source means paired in the last linearisation.  Kernel times from HIP events."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    from paper_2604_12942_amd import loop
+    g = c["gaussians"]
+    P = gsr.gaussians_to_device(g, dev)
+    src_seg = int(c["segment_id"].max())
+    cams = gsr.camera_tensor(c["cameras"][:4], dev)
+    yaw = np.deg2rad(1.0)
+    R0 = np.array([[np.cos(yaw), -np.sin(yaw), 0.0], [np.sin(yaw), np.cos(yaw), 0.0], [0.0, 0.0, 1.0]])
+    stream = torch.cuda.current_stream()
+    state = gsr.gicp_prepare(P, g["sh_degree"], seg, src_seg, cams, 4, loop.D_MAX, loop.D_CORR)
+    nt = int(state["counts"][1].item())
+    centre = g["means"][:, state["tgt_index"][:nt].cpu().numpy()].astype(np.float64).mean(axis=1)
+    # drift: 1 deg of yaw about the centre of the target set, 0.2 m across and 0.1 m up
+    t0 = centre - R0 @ centre + np.array([0.0, 0.2, 0.1])
+    rec = []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        state = gsr.gicp_prepare(P, g["sh_degree"], seg, src_seg, cams, 4, loop.D_MAX, loop.D_CORR, state)
+        e[1].record(stream)
+        pose = torch.tensor(np.concatenate([R0.ravel(), t0]), dtype=torch.float64, device=dev)
+        corr = torch.empty(P["means"].shape[1], dtype=torch.int32, device=dev)
+        gsr.gicp_iterate(P, g["sh_degree"], state, pose, 30, corr=corr)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        rec.append((e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])))
+    st = state["stats"].cpu().numpy()
+    its = int(st[37])
+    prep = float(np.median([r[0] for r in rec]))
+    itm = float(np.median([r[1] for r in rec]))
+    pz = pose.cpu().numpy()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    gsr.transform_segment(P, g["sh_degree"], seg, src_seg, pose)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    count = int(st[29])
+    # RMS motion under the estimated pose of the source means paired in the last linearisation
+    # (the overlap with the target set)
+    ns = int(state["counts"][0].item())
+    sm = g["means"][:, c["segment_id"] == src_seg].astype(np.float64)
+    paired = corr[:ns].cpu().numpy() >= 0
+    sm = sm[:, paired]
+    disp = float(np.sqrt(np.mean(np.sum((pz[:9].reshape(3, 3) @ sm + pz[9:, None] - sm) ** 2, axis=0))))
+    disp0 = float(np.sqrt(np.mean(np.sum((R0 @ sm + t0[:, None] - sm) ** 2, axis=0))))
+    ang = float(np.degrees(np.arccos(np.clip((np.trace(pz[:9].reshape(3, 3)) - 1) / 2, -1, 1))))
+    res = dict(rows=int(P["means"].shape[1]), n_src=int(state["counts"][0].item()),
+               n_tgt=int(state["counts"][1].item()), d_max=loop.D_MAX, d_corr=loop.D_CORR, iterations=its,
+               converged=bool(st[36]), correspondences=count, mean_cost=round(float(st[27]) / max(count, 1), 5),
+               accepted=bool(st[36] and count >= loop.MIN_CORR and st[27] / max(count, 1) < loop.ACCEPT_COST),
+               prepare_ms=round(prep, 4), iterations_ms=round(itm, 4), ms_per_iteration=round(itm / max(its, 1), 4),
+               initial_displacement_rms_m=round(disp0, 4), final_displacement_rms_m=round(disp, 5),
+               final_rotation_deg=round(ang, 5),
+               propagate_ms=round(e0.elapsed_time(e1), 4))
+    print("loop registration: %s" % res, file=sys.stderr, flush=True)
+    del P, state
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.init_compare:
@@ -665,9 +734,10 @@ def main():
                     kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
 
     loss_last = float(opt.loss.item())
-    maint = None
+    maint = loopr = None
     if not a.no_maintenance:
         maint = maintenance_leg(g, seg, min_seg, dev)
+        loopr = loop_leg(c, seg, dev)
     full = None
     if not a.no_full_loss:
         del opt
@@ -710,6 +780,7 @@ def main():
         "loss_last": loss_last,
         "full_loss": full,
         "maintenance": maint,
+        "loop_registration": loopr,
     }
     print(json.dumps(out), flush=True)
 

@@ -498,6 +498,21 @@ GSR_API gsr_status gsr_pointnet_bwd(const float *points, int64_t n, const gsr_vo
                                     int32_t blocks, float *grad, double *loss, void *ws, size_t ws_bytes,
                                     gsr_stream stream);
 
+/* ---- propagation of a corrected pose to a segment (Sec. III-D) ----------------------------------
+ * The Gaussians with segment_id == segment move rigidly by pose (device double [12]: R row-major,
+ * then t; world -> world): means R mu + t, quaternions q_R (x) q with q_R the unit quaternion of R
+ * (w >= 0; the raw quaternion's norm is kept), and every SH degree l >= 1 of every colour channel
+ * c' = D_l c with D_ab = the integral over the sphere of Y_a(d) Y_b(R^T d), so that the colour seen
+ * along R d afterwards equals the colour seen along d before.  Arithmetic in float64, stored as
+ * float32; p->means, p->quats and p->sh are updated in place (log-scales and opacities unchanged).
+ * ws: device double [96], scratch for D_1..D_3 and q_R.  gsr_transform_cameras moves the cameras
+ * flagged in mask [n_cams] (device uint8; NULL = all) of a device array with the same transform:
+ * world -> camera (R_c, t_c) becomes (R_c R^T, t_c - R_c R^T t). */
+GSR_API gsr_status gsr_transform_segment(const gsr_params *p, int64_t n, int32_t sh_degree, const int32_t *segment_id,
+                                         int32_t segment, const double *pose, double *ws, gsr_stream stream);
+GSR_API gsr_status gsr_transform_cameras(gsr_camera *cams, int32_t n_cams, const uint8_t *mask, const double *pose,
+                                         gsr_stream stream);
+
 /* Fill n 32-bit words with a value (graph-capture safe replacement for memset). */
 GSR_API gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream);
 

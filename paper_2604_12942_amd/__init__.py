@@ -335,6 +335,20 @@ def gicp_iterate(P, sh_degree, state, pose, n_iter, corr=None):
                                  n_iter, _ptr(state["ws"]), state["ws"].numel(), _stream()), "gsr_gicp_iterate")
 
 
+def transform_segment(P, sh_degree, segment_id, segment, pose, ws=None):
+    """Moves the Gaussians of one segment by pose (device float64 [12]) in place (Sec. III-D)."""
+    n = P["means"].shape[1]
+    prm = _abi.Params(*[P[k].data_ptr() for k in PARAM_NAMES])
+    ws = torch.empty(96, dtype=torch.float64, device=P["means"].device) if ws is None else ws
+    check(lib().gsr_transform_segment(C.byref(prm), n, int(sh_degree), _ptr(segment_id), segment, _ptr(pose), _ptr(ws),
+                                      _stream()), "gsr_transform_segment")
+
+
+def transform_cameras(cams, n_cams, pose, mask=None):
+    """Moves the flagged cameras (device gsr_camera records) by pose, in place."""
+    check(lib().gsr_transform_cameras(_ptr(cams), n_cams, _ptr(mask), _ptr(pose), _stream()), "gsr_transform_cameras")
+
+
 def fill_u32(t, value):
     check(lib().gsr_fill_u32(_ptr(t), value & 0xFFFFFFFF, t.numel() * t.element_size() // 4, _stream()),
           "gsr_fill_u32")

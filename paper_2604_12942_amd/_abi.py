@@ -97,6 +97,8 @@ _SIGS = {
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
     "gsr_support_mask": ([P, C.c_int32, C.POINTER(Raster), C.c_float, C.c_int32, P, P, P], C.c_int),
     "gsr_loss_workspace": ([C.c_int32, C.POINTER(Raster)], C.c_size_t),
+    "gsr_transform_segment": ([C.POINTER(Params), C.c_int64, C.c_int32, P, C.c_int32, P, P, P], C.c_int),
+    "gsr_transform_cameras": ([P, C.c_int32, P, P, P], C.c_int),
     "gsr_gicp_workspace": ([C.c_int64], C.c_size_t),
     "gsr_gicp_prepare": ([C.POINTER(Gaussians), P, C.c_int32, P, C.c_int32, C.c_float, C.c_float, P, P, P, P, P,
                           C.c_size_t, P], C.c_int),

@@ -53,6 +53,9 @@ extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *, int64_t, const ui
 extern "C" gsr_status gsr_loss_l1_launch(const float *, const float *, const float *, const float *, const int32_t *,
                                          int, const gsr_raster *, float, double *, float *, float *, hipStream_t);
 extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
+extern "C" gsr_status gsr_transform_segment_launch(const gsr_params *, int64_t, int, const int32_t *, int32_t,
+                                                   const double *, double *, hipStream_t);
+extern "C" gsr_status gsr_transform_cameras_launch(gsr_camera *, int, const uint8_t *, const double *, hipStream_t);
 extern "C" size_t gsr_gicp_ws_bytes(int64_t);
 extern "C" gsr_status gsr_gicp_prepare_launch(const gsr_gaussians *, const int32_t *, int32_t, const gsr_camera *, int,
                                               float, float, uint32_t *, uint32_t *, uint32_t *, double *, void *,
@@ -399,6 +402,20 @@ extern "C" gsr_status gsr_gicp_iterate(const gsr_gaussians *g, const uint32_t *s
     if (!(d_corr > 0.0f) || !std::isfinite(d_corr)) return GSR_E_INVALID;
     if (g->n > 0 && (!src_index || !tgt_index || !ws || ws_bytes < gsr_gicp_ws_bytes(g->n))) return GSR_E_INVALID;
     return gsr_gicp_iterate_launch(g, src_index, tgt_index, counts, d_corr, pose, stats, corr, n_iter, ws, S(stream));
+}
+
+extern "C" gsr_status gsr_transform_segment(const gsr_params *p, int64_t n, int32_t sh_degree,
+                                            const int32_t *segment_id, int32_t segment, const double *pose, double *ws,
+                                            gsr_stream stream) {
+    if (!p || n < 0 || sh_degree < 0 || sh_degree > 3 || !pose || !ws) return GSR_E_INVALID;
+    if (n > 0 && (!p->means || !p->quats || !segment_id || (sh_degree > 0 && !p->sh))) return GSR_E_INVALID;
+    return gsr_transform_segment_launch(p, n, sh_degree, segment_id, segment, pose, ws, S(stream));
+}
+
+extern "C" gsr_status gsr_transform_cameras(gsr_camera *cams, int32_t n_cams, const uint8_t *mask, const double *pose,
+                                           gsr_stream stream) {
+    if (n_cams < 0 || (n_cams > 0 && !cams) || !pose) return GSR_E_INVALID;
+    return gsr_transform_cameras_launch(cams, n_cams, mask, pose, S(stream));
 }
 
 extern "C" gsr_status gsr_fill_u32(void *dst, uint32_t value, int64_t n_words, gsr_stream stream) {

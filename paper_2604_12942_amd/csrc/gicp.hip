@@ -96,6 +96,18 @@ __global__ void k_gicp_cov(const uint32_t *__restrict__ list, const uint32_t *__
     cov[5 * cap + j] = 1.0 - k * az * az;
 }
 
+// Target means in grid order (x, y, z as float, list position as bits), so that a probe scans a
+// cell's candidates contiguously instead of gathering them through two index arrays.
+__global__ void k_gicp_grid_points(const float *__restrict__ means, int64_t n, const uint32_t *__restrict__ tgt_list,
+                                   const uint32_t *__restrict__ counts, const uint32_t *__restrict__ val,
+                                   float4 *__restrict__ gp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)counts[1]) return;
+    const uint32_t p = val[e];
+    const int64_t i = tgt_list[p];
+    gp[e] = make_float4(means[i], means[n + i], means[2 * n + i], __uint_as_float(p));
+}
+
 __device__ __forceinline__ int tri(int i, int j) { return i * 6 - i * (i - 1) / 2 + (j - i); }  // i <= j
 
 __device__ __forceinline__ bool gicp_stopped(const double *stats) {
@@ -107,8 +119,9 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(
     const float *__restrict__ means, int64_t n, const uint32_t *__restrict__ src_list,
     const uint32_t *__restrict__ tgt_list, const uint32_t *__restrict__ counts, const double *__restrict__ src_cov,
     const double *__restrict__ tgt_cov, int64_t cap, const uint32_t *__restrict__ key, const uint32_t *__restrict__ val,
-    const uint32_t *__restrict__ bucket, double inv_cell, double dd_corr, const double *__restrict__ pose,
-    const double *__restrict__ stats, double *__restrict__ partial, int32_t *__restrict__ corr) {
+    const uint32_t *__restrict__ bucket, const float4 *__restrict__ gp, double inv_cell, double dd_corr,
+    const double *__restrict__ pose, const double *__restrict__ stats, double *__restrict__ partial,
+    int32_t *__restrict__ corr) {
     __shared__ double s_acc[4][kGicpAcc];
     if (gicp_stopped(stats)) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,9 +145,9 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(
         for (int d = 0; d < 27; d++) {
             const uint32_t h = cell_hash(cx + d % 3 - 1, cy + (d / 3) % 3 - 1, cz + d / 9 - 1);
             for (uint32_t e = grid_lower_bound(key, bucket, h); e < n_tgt && key[e] == h; e++) {
-                const uint32_t p = val[e];
-                const int64_t it = tgt_list[p];
-                const double d2 = sqdist_rn(means[it], means[n + it], means[2 * n + it], q[0], q[1], q[2]);
+                const float4 c = gp[e];
+                const uint32_t p = __float_as_uint(c.w);
+                const double d2 = sqdist_rn(c.x, c.y, c.z, q[0], q[1], q[2]);
                 if (d2 < best || (d2 == best && p < bi && bi != 0xFFFFFFFFu)) {
                     best = d2;
                     bi = p;
@@ -293,6 +306,7 @@ size_t a256g(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct GicpWs {
     double *src_cov, *tgt_cov, *partial;
+    float4 *gp;
     uint32_t *f_src, *f_tgt, *off, *key, *val, *k2, *v2, *bucket;
     void *scan, *sort;
     size_t bytes;
@@ -313,6 +327,7 @@ GicpWs gicp_layout(void *base, int64_t n) {
     w.src_cov = (double *)take(6 * nn * 8);
     w.tgt_cov = (double *)take(6 * nn * 8);
     w.partial = (double *)take((size_t)nblk256(n) * kGicpAcc * 8);
+    w.gp = (float4 *)take(nn * 16);
     w.f_src = (uint32_t *)take(nn * 4);
     w.f_tgt = (uint32_t *)take(nn * 4);
     w.off = (uint32_t *)take(nn * 4);
@@ -354,8 +369,11 @@ extern "C" gsr_status gsr_gicp_prepare_launch(const gsr_gaussians *g, const int3
     k_gicp_compact<<<nblk256(n), 256, 0, st>>>(w.f_tgt, w.off, n, tgt_index);
     k_gicp_cov<<<nblk256(n), 256, 0, st>>>(src_index, counts, n, g->quats, g->log_scales, n, w.src_cov);
     k_gicp_cov<<<nblk256(n), 256, 0, st>>>(tgt_index, counts + 1, n, g->quats, g->log_scales, n, w.tgt_cov);
-    return gsr_grid_build_launch(g->means, n, tgt_index, counts + 1, n, grid_cell(d_corr), w.key, w.val, w.k2, w.v2,
-                                 w.bucket, w.sort, st);
+    s = gsr_grid_build_launch(g->means, n, tgt_index, counts + 1, n, grid_cell(d_corr), w.key, w.val, w.k2, w.v2,
+                              w.bucket, w.sort, st);
+    if (s != GSR_OK) return s;
+    k_gicp_grid_points<<<nblk256(n), 256, 0, st>>>(g->means, n, tgt_index, counts, w.val, w.gp);
+    return last_launch();
 }
 
 extern "C" gsr_status gsr_gicp_iterate_launch(const gsr_gaussians *g, const uint32_t *src_index,
@@ -370,8 +388,163 @@ extern "C" gsr_status gsr_gicp_iterate_launch(const gsr_gaussians *g, const uint
     const int nb = nblk256(n);
     for (int it = 0; it < n_iter; it++) {
         k_gicp_linearise<<<nb, 256, 0, st>>>(g->means, n, src_index, tgt_index, counts, w.src_cov, w.tgt_cov, n, w.key,
-                                             w.val, w.bucket, inv_cell, dd, pose, stats, w.partial, corr);
+                                             w.val, w.bucket, w.gp, inv_cell, dd, pose, stats, w.partial, corr);
         k_gicp_solve<<<1, 256, 0, st>>>(w.partial, nb, pose, stats);
     }
+    return last_launch();
+}
+
+// ---- propagation of a corrected pose to a segment ------------------------------------------------
+// The segment moves rigidly by (R, t): means R mu + t, orientations q_R (x) q (so R_q' = R R_q),
+// and each SH degree l >= 1 turns with D_l, D_ab = integral of Y_a(d) Y_b(R^T d) over the sphere, so
+// that the colour seen along R d afterwards is the colour seen along d before.  The integrand is
+// a spherical polynomial of degree <= 6; the product rule of the 4-point Gauss-Legendre rule in
+// z = cos(theta) with 8 equally spaced azimuths integrates it exactly.
+namespace gsr {
+
+constexpr int kShRotEntries = 9 + 25 + 49;  // D_1, D_2, D_3 row-major, then q_R (w, x, y, z)
+
+// Real orthonormal SH without Condon-Shortley phase, degree <= 3, in float64 (index k = l^2 + l + m)
+__device__ double sh_basis_d(int k, double x, double y, double z) {
+    const double pi = 3.141592653589793;
+    switch (k) {
+        case 1: return sqrt(3.0 / (4.0 * pi)) * y;
+        case 2: return sqrt(3.0 / (4.0 * pi)) * z;
+        case 3: return sqrt(3.0 / (4.0 * pi)) * x;
+        case 4: return sqrt(15.0 / (4.0 * pi)) * x * y;
+        case 5: return sqrt(15.0 / (4.0 * pi)) * y * z;
+        case 6: return sqrt(5.0 / (16.0 * pi)) * (3.0 * z * z - 1.0);
+        case 7: return sqrt(15.0 / (4.0 * pi)) * x * z;
+        case 8: return sqrt(15.0 / (16.0 * pi)) * (x * x - y * y);
+        case 9: return sqrt(35.0 / (32.0 * pi)) * y * (3.0 * x * x - y * y);
+        case 10: return sqrt(105.0 / (4.0 * pi)) * x * y * z;
+        case 11: return sqrt(21.0 / (32.0 * pi)) * y * (5.0 * z * z - 1.0);
+        case 12: return sqrt(7.0 / (16.0 * pi)) * z * (5.0 * z * z - 3.0);
+        case 13: return sqrt(21.0 / (32.0 * pi)) * x * (5.0 * z * z - 1.0);
+        case 14: return sqrt(105.0 / (16.0 * pi)) * z * (x * x - y * y);
+        case 15: return sqrt(35.0 / (32.0 * pi)) * x * (x * x - 3.0 * y * y);
+        default: return 0.28209479177387814;
+    }
+}
+
+__global__ void k_sh_rotation(const double *__restrict__ pose, double *__restrict__ out) {
+    const int e = threadIdx.x;
+    double R[9];
+    for (int i = 0; i < 9; i++) R[i] = pose[i];
+    if (e < kShRotEntries) {
+        int l, a, b;
+        if (e < 9) l = 1, a = e / 3, b = e % 3;
+        else if (e < 34) l = 2, a = (e - 9) / 5, b = (e - 9) % 5;
+        else l = 3, a = (e - 34) / 7, b = (e - 34) % 7;
+        const int ka = l * l + a, kb = l * l + b;
+        // 4-point Gauss-Legendre nodes: roots of 35 z^4 - 30 z^2 + 3, weights 2 / ((1 - z^2) P4'(z)^2)
+        const double r30 = sqrt(30.0);
+        const double zs[2] = {sqrt((15.0 - 2.0 * r30) / 35.0), sqrt((15.0 + 2.0 * r30) / 35.0)};
+        const double pi = 3.141592653589793;
+        double acc = 0.0;
+        for (int zi = 0; zi < 4; zi++) {
+            const double z = zi < 2 ? zs[zi] : -zs[zi - 2];
+            const double dp = (140.0 * z * z * z - 60.0 * z) / 8.0;  // P4'(z)
+            const double wz = 2.0 / ((1.0 - z * z) * dp * dp);
+            const double rho = sqrt(1.0 - z * z);
+            for (int j = 0; j < 8; j++) {
+                const double ph = 2.0 * pi * j / 8.0;
+                const double x = rho * cos(ph), y = rho * sin(ph);
+                // R^T d
+                const double rx = R[0] * x + R[3] * y + R[6] * z;
+                const double ry = R[1] * x + R[4] * y + R[7] * z;
+                const double rz = R[2] * x + R[5] * y + R[8] * z;
+                acc += wz * (2.0 * pi / 8.0) * sh_basis_d(ka, x, y, z) * sh_basis_d(kb, rx, ry, rz);
+            }
+        }
+        out[e] = acc;
+    } else if (e == kShRotEntries) {
+        // q_R by Shepperd's method, sign with w >= 0
+        double w, x, y, z;
+        const double tr = R[0] + R[4] + R[8];
+        if (tr > 0.0) {
+            const double s = 2.0 * sqrt(tr + 1.0);
+            w = 0.25 * s, x = (R[7] - R[5]) / s, y = (R[2] - R[6]) / s, z = (R[3] - R[1]) / s;
+        } else if (R[0] > R[4] && R[0] > R[8]) {
+            const double s = 2.0 * sqrt(1.0 + R[0] - R[4] - R[8]);
+            w = (R[7] - R[5]) / s, x = 0.25 * s, y = (R[1] + R[3]) / s, z = (R[2] + R[6]) / s;
+        } else if (R[4] > R[8]) {
+            const double s = 2.0 * sqrt(1.0 + R[4] - R[0] - R[8]);
+            w = (R[2] - R[6]) / s, x = (R[1] + R[3]) / s, y = 0.25 * s, z = (R[5] + R[7]) / s;
+        } else {
+            const double s = 2.0 * sqrt(1.0 + R[8] - R[0] - R[4]);
+            w = (R[3] - R[1]) / s, x = (R[2] + R[6]) / s, y = (R[5] + R[7]) / s, z = 0.25 * s;
+        }
+        const double sg = w < 0.0 ? -1.0 : 1.0;
+        out[kShRotEntries] = sg * w, out[kShRotEntries + 1] = sg * x;
+        out[kShRotEntries + 2] = sg * y, out[kShRotEntries + 3] = sg * z;
+    }
+}
+
+__global__ void k_transform_rows(float *__restrict__ means, float *__restrict__ quats, float *__restrict__ sh,
+                                 int64_t n, int deg, const int32_t *__restrict__ seg, int32_t segment,
+                                 const double *__restrict__ pose, const double *__restrict__ rot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || seg[i] != segment) return;
+    double R[9], t[3];
+    for (int e = 0; e < 9; e++) R[e] = pose[e];
+    for (int e = 0; e < 3; e++) t[e] = pose[9 + e];
+    const double mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    means[i] = (float)(R[0] * mx + R[1] * my + R[2] * mz + t[0]);
+    means[n + i] = (float)(R[3] * mx + R[4] * my + R[5] * mz + t[1]);
+    means[2 * n + i] = (float)(R[6] * mx + R[7] * my + R[8] * mz + t[2]);
+    const double aw = rot[kShRotEntries], ax = rot[kShRotEntries + 1], ay = rot[kShRotEntries + 2],
+                 az = rot[kShRotEntries + 3];
+    const double bw = quats[i], bx = quats[n + i], by = quats[2 * n + i], bz = quats[3 * n + i];
+    quats[i] = (float)(aw * bw - ax * bx - ay * by - az * bz);
+    quats[n + i] = (float)(aw * bx + ax * bw + ay * bz - az * by);
+    quats[2 * n + i] = (float)(aw * by - ax * bz + ay * bw + az * bx);
+    quats[3 * n + i] = (float)(aw * bz + ax * by - ay * bx + az * bw);
+    int off = 0;
+    for (int l = 1; l <= deg; l++) {
+        const int w = 2 * l + 1;
+        const double *D = rot + off;
+        for (int ch = 0; ch < 3; ch++) {
+            double c[7], o[7];
+            for (int b = 0; b < w; b++) c[b] = sh[(int64_t)((l * l + b) * 3 + ch) * n + i];
+            for (int a = 0; a < w; a++) {
+                double v = 0.0;
+                for (int b = 0; b < w; b++) v += D[a * w + b] * c[b];
+                o[a] = v;
+            }
+            for (int a = 0; a < w; a++) sh[(int64_t)((l * l + a) * 3 + ch) * n + i] = (float)o[a];
+        }
+        off += w * w;
+    }
+}
+
+// world -> camera of a moved segment: R_c R^T, t_c - R_c R^T t
+__global__ void k_transform_cams(gsr_camera *__restrict__ cams, int n_cams, const uint8_t *__restrict__ mask,
+                                 const double *__restrict__ pose) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_cams || (mask && !mask[k])) return;
+    double R[9], t[3], Rc[9], tc[3], M[9];
+    for (int e = 0; e < 9; e++) R[e] = pose[e], Rc[e] = cams[k].R[e];
+    for (int e = 0; e < 3; e++) t[e] = pose[9 + e], tc[e] = cams[k].t[e];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) M[3 * a + b] = Rc[3 * a] * R[3 * b] + Rc[3 * a + 1] * R[3 * b + 1] + Rc[3 * a + 2] * R[3 * b + 2];
+    for (int e = 0; e < 9; e++) cams[k].R[e] = (float)M[e];
+    for (int a = 0; a < 3; a++) cams[k].t[a] = (float)(tc[a] - (M[3 * a] * t[0] + M[3 * a + 1] * t[1] + M[3 * a + 2] * t[2]));
+}
+
+}  // namespace gsr
+
+extern "C" gsr_status gsr_transform_segment_launch(const gsr_params *p, int64_t n, int deg, const int32_t *seg,
+                                                   int32_t segment, const double *pose, double *ws, hipStream_t st) {
+    k_sh_rotation<<<1, 128, 0, st>>>(pose, ws);
+    if (n > 0)
+        k_transform_rows<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(p->means, p->quats, p->sh, n, deg, seg, segment,
+                                                                     pose, ws);
+    return last_launch();
+}
+
+extern "C" gsr_status gsr_transform_cameras_launch(gsr_camera *cams, int n_cams, const uint8_t *mask,
+                                                   const double *pose, hipStream_t st) {
+    if (n_cams > 0) k_transform_cams<<<(unsigned)ceil_div(n_cams, 64), 64, 0, st>>>(cams, n_cams, mask, pose);
     return last_launch();
 }

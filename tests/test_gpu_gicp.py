@@ -105,3 +105,31 @@ def test_too_few_correspondences_fail(scene):
     stats = st["stats"].cpu().numpy()
     assert stats[38] == 1.0 and stats[36] == 0.0 and stats[37] == 1.0
     assert np.array_equal(far.cpu().numpy()[9:], [500.0, 0.0, 0.0])
+
+
+def test_transform_segment_and_cameras_match_oracle():
+    import paper_2604_12942_amd as gsr
+    rng = np.random.default_rng(9)
+    n = 20_000
+    g = synth.random_gaussians(6, n, 3)
+    seg = rng.integers(0, 4, n).astype(np.int32)
+    R, t = _pose([0.3, -0.2, 0.5], [1.0, -2.0, 0.5])
+    P = gsr.gaussians_to_device(g)
+    pose = torch.tensor(np.concatenate([R.ravel(), t]), dtype=torch.float64, device="cuda")
+    gsr.transform_segment(P, 3, torch.from_numpy(seg).cuda(), 2, pose)
+    cams = [synth.make_camera(_pose(rng.normal(0, 0.3, 3), [0, 0, 0])[0], rng.normal(0, 1, 3), 100, 100, 50, 40, 100, 80)
+            for _ in range(3)]
+    ct = gsr.camera_tensor(cams)
+    gsr.transform_cameras(ct, 3, pose, mask=torch.tensor([1, 0, 1], dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    means, quats, sh = go.transform_segment(g, seg, 2, R, t)
+    for name, exp in (("means", means), ("quats", quats), ("sh", sh)):
+        got = P[name].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - exp) <= 2e-7 * np.abs(exp) + 1e-6 * np.abs(exp).max()), name
+    for name in ("log_scales", "opacity_logits"):
+        assert np.array_equal(P[name].cpu().numpy(), g[name].astype(np.float32)), name
+    raw = ct.cpu().numpy().view(np.float32).reshape(3, 24)
+    for k, cam in enumerate(cams):
+        Rc, tc = go.transform_camera(cam, R, t) if k != 1 else (cam["R"].astype(np.float64), cam["t"].astype(np.float64))
+        np.testing.assert_allclose(raw[k, :9], Rc.ravel(), atol=1e-6)
+        np.testing.assert_allclose(raw[k, 9:12], tc, atol=1e-5)
