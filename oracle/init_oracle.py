@@ -238,3 +238,39 @@ def cascade(points, colors, depth, segment, vox, pred=None, f=640.0, beta=None, 
     sh[0:3] = ((np.asarray(colors, np.float64) - 0.5) / Y00).T
     return dict(means=P.T.copy(), log_scales=ls, quats=qs, opacity_logits=lo, sh=sh, sh_degree=sh_degree,
                 branch=branch, beta=b)
+
+
+def descriptor_covariance(points, vox, point_cov):
+    """Eq. 1-2 with per-point world covariances.  point_cov [n, 6] = (xx, xy, xz, yy, yz, zz).
+    For each planar / linear voxel: J_i = [V F_i; I/N] with V = [v_min v_mid v_max] (the
+    canonical frame's columns) and F_i's rows f^(m) = (p_i - mu)^T (v_m v_k^T + v_k v_m^T) /
+    (N (lambda_k - lambda_m)) for m != k (zero for m = k), k the descriptor direction (v_min for
+    planar, v_max for linear); Sigma_g = sum_i J_i Sigma_i J_i^T over the voxel's fitting points.
+    Returns Sigma_g [V, 6, 6] (zero for unreliable-class voxels), the direction-block trace
+    (infinity for them) and reliable = class planar / linear and trace < 0.1^2."""
+    P = np.asarray(points, np.float64)
+    c6 = np.asarray(point_cov, np.float32).astype(np.float64)
+    S = np.stack([np.stack([c6[:, 0], c6[:, 1], c6[:, 2]], -1), np.stack([c6[:, 1], c6[:, 3], c6[:, 4]], -1),
+                  np.stack([c6[:, 2], c6[:, 4], c6[:, 5]], -1)], -2)
+    nv = len(vox["n"])
+    Sg = np.zeros((nv, 6, 6))
+    tr = np.full(nv, np.inf)
+    for v in range(nv):
+        if vox["cls"][v] == UNRELIABLE:
+            continue
+        Vm = vox["R"][v][:, ::-1]               # columns v_min, v_mid, v_max
+        lam = vox["evals"][v]
+        k = 0 if vox["cls"][v] == PLANAR else 2
+        ids = vox["ids"][v]
+        N = len(ids)
+        for i in ids:
+            d = P[i] - vox["mu"][v]
+            F = np.zeros((3, 3))
+            for m in range(3):
+                if m != k:
+                    F[m] = d @ (np.outer(Vm[:, m], Vm[:, k]) + np.outer(Vm[:, k], Vm[:, m])) / (N * (lam[k] - lam[m]))
+            J = np.concatenate([Vm @ F, np.eye(3) / N])
+            Sg[v] += J @ S[i] @ J.T
+        tr[v] = np.trace(Sg[v][:3, :3])
+    reliable = (vox["cls"] != UNRELIABLE) & (tr < REL_TRACE)
+    return Sg, tr, reliable

@@ -289,6 +289,19 @@ class Scene:
                 np.concatenate(scan))
 
 
+def lidar_point_cov(points, origins, sigma_range=0.02, sigma_angle=np.deg2rad(0.1), sigma_pose=0.01):
+    """World-frame covariance of LiDAR points, [n, 6] = (xx, xy, xz, yy, yz, zz): range noise along
+    the beam, angular noise (times the range) across it, and an isotropic pose term."""
+    d = np.asarray(points, np.float64) - np.asarray(origins, np.float64)
+    r = np.linalg.norm(d, axis=1)
+    b = d / r[:, None]
+    along = sigma_range ** 2
+    across = (r * sigma_angle) ** 2
+    C = (along - across)[:, None, None] * b[:, :, None] * b[:, None, :] + \
+        (across + sigma_pose ** 2)[:, None, None] * np.eye(3)[None]
+    return np.stack([C[:, 0, 0], C[:, 0, 1], C[:, 0, 2], C[:, 1, 1], C[:, 1, 2], C[:, 2, 2]], 1).astype(np.float32)
+
+
 def _boxes_uniform(rng, n, lo, hi, start_id):
     c = rng.uniform(lo, hi, (n, 2))
     size = rng.uniform(0.3, 2.0, (n, 3))

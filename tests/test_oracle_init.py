@@ -5,6 +5,7 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 from oracle import init_oracle as io
+import synth
 
 
 def test_splitmix64_published_sequence():
@@ -147,3 +148,65 @@ def test_cascade_branches():
     np.testing.assert_allclose(g2["log_scales"][:, 41], np.log(6.4 / 640.0))
     np.testing.assert_allclose(g2["quats"][:, 41], [1, 0, 0, 0])
     np.testing.assert_allclose(g2["sh"][0:3, 5], (col[5] - 0.5) / io.Y00)
+
+
+def _cloud(seed):
+    """Two planar patches and a thin bar inside a few voxels, with anisotropic LiDAR covariances."""
+    rng = np.random.default_rng(seed)
+    a = np.c_[rng.uniform(0.02, 0.48, (300, 2)), 0.25 + rng.normal(0, 0.01, 300)]
+    b = np.c_[0.75 + rng.normal(0, 0.01, 300), rng.uniform(0.52, 0.98, (300, 2))]
+    c = np.c_[rng.uniform(0.52, 0.98, 200), 0.25 + rng.normal(0, 0.05, 200), 0.25 + rng.normal(0, 0.05, 200)]
+    pts = np.concatenate([a, b, c])
+    org = np.tile([[3.0, -2.0, 1.8]], (pts.shape[0], 1))
+    return pts, synth.lidar_point_cov(pts, org)
+
+
+def test_descriptor_covariance_isotropic_reduces_to_the_trace():
+    pts, _ = _cloud(5)
+    vox = io.voxel_pca(pts, 3)
+    iso = np.tile(np.array([io.SIGMA_PT ** 2, 0, 0, io.SIGMA_PT ** 2, 0, io.SIGMA_PT ** 2], np.float32), (len(pts), 1))
+    Sg, tr, rel = io.descriptor_covariance(pts, vox, iso)
+    ok = vox["cls"] != io.UNRELIABLE
+    assert ok.sum() >= 2
+    # point covariances are float32 inputs: sigma^2 = 4e-4 carries a 2.5e-8 relative rounding
+    np.testing.assert_allclose(tr[ok], vox["trace"][ok], rtol=1e-7)
+    assert np.array_equal(rel, vox["reliable"])
+    for v in np.nonzero(ok)[0]:
+        N = vox["n"][v]
+        np.testing.assert_allclose(Sg[v][3:, 3:], io.SIGMA_PT ** 2 / N * np.eye(3), rtol=1e-6, atol=1e-15)
+        np.testing.assert_allclose(Sg[v], Sg[v].T, atol=1e-18)
+        assert np.linalg.eigvalsh(Sg[v]).min() > -1e-15
+
+
+def test_descriptor_jacobian_matches_finite_differences():
+    """J_i of Eq. 1 against central differences of (v_k, mu) through numpy's eigh, per point."""
+    import synth as _s  # noqa: F401
+    pts, cov = _cloud(6)
+    vox = io.voxel_pca(pts, 4)
+    Sg, tr, _ = io.descriptor_covariance(pts, vox, cov)
+    c6 = cov.astype(np.float64)
+    for v in np.nonzero(vox["cls"] != io.UNRELIABLE)[0][:3]:
+        ids = vox["ids"][v]
+        k = 0 if vox["cls"][v] == io.PLANAR else 2
+        vref = vox["R"][v][:, ::-1][:, k]
+
+        def desc(P):
+            mu = P.mean(axis=0)
+            C = (P - mu).T @ (P - mu) / len(P)
+            lam, V = np.linalg.eigh(C)
+            e = V[:, k] * np.sign(V[:, k] @ vref)
+            return np.concatenate([e, mu])
+        P0 = pts[ids].astype(np.float64)
+        h = 1e-6
+        ref = np.zeros((6, 6))
+        for j in range(len(ids)):
+            J = np.zeros((6, 3))
+            for c in range(3):
+                Pp, Pm = P0.copy(), P0.copy()
+                Pp[j, c] += h
+                Pm[j, c] -= h
+                J[:, c] = (desc(Pp) - desc(Pm)) / (2 * h)
+            Si = np.array([[c6[ids[j], 0], c6[ids[j], 1], c6[ids[j], 2]], [c6[ids[j], 1], c6[ids[j], 3], c6[ids[j], 4]],
+                           [c6[ids[j], 2], c6[ids[j], 4], c6[ids[j], 5]]])
+            ref += J @ Si @ J.T
+        np.testing.assert_allclose(Sg[v], ref, rtol=1e-4, atol=1e-6 * np.abs(ref).max())
