@@ -450,6 +450,16 @@ typedef struct {
 GSR_API size_t gsr_voxel_pca_workspace(int64_t n);
 GSR_API gsr_status gsr_voxel_pca(const float *points, int64_t n, uint64_t seed, const gsr_voxels *out, void *ws,
                                  size_t ws_bytes, gsr_stream stream);
+/* As gsr_voxel_pca with each point's world-frame covariance Sigma_i^W (point_cov [6][n] =
+ * xx, xy, xz, yy, yz, zz; measurement and pose noise) in Eq. 2: for a planar or linear voxel,
+ * Sigma_g = sum_i J_i Sigma_i J_i^T over its fitting points with J_i = [V F_i; I/N] of Eq. 1
+ * (V = [v_min v_mid v_max], the R_pca columns in reverse; f_i^(m) = (p_i - mu)^T (v_m v_k^T +
+ * v_k v_m^T) / (N (lambda_k - lambda_m)) for m != k, k = min for planar and max for linear).
+ * trace and reliable come from its direction block; sigma_g [21][n] (may be NULL) receives the
+ * upper triangle of Sigma_g row-major per voxel (zero for unreliable-class voxels). */
+GSR_API gsr_status gsr_voxel_pca_cov(const float *points, const float *point_cov, int64_t n, uint64_t seed,
+                                     const gsr_voxels *out, float *sigma_g, void *ws, size_t ws_bytes,
+                                     gsr_stream stream);
 
 /* ---- cascaded initialisation (Sec. III-B, Eq. 3, 5, 6) ----------------------------------------
  * One Gaussian per point: mean = point, SH DC = (colour - 0.5) / Y_00, higher SH = 0, and by Eq. 3
@@ -471,6 +481,14 @@ GSR_API gsr_status gsr_cascade(const float *points, const float *colors, const f
                                int32_t n_segments, int64_t n, const gsr_voxels *vox, const float *pred, float focal,
                                float beta, int32_t sh_degree, const gsr_params *out, uint8_t *branch, void *ws,
                                size_t ws_bytes, gsr_stream stream);
+/* As gsr_cascade with the model branch of Eq. 4: the prediction's log-scales are read as an axis
+ * ratio only, a = exp(s - max(s)), and anchored at the point's depth, s_out = log((d / focal) a),
+ * so an isotropic prediction gives the heuristic branch's size (the validity test is unchanged). */
+GSR_API gsr_status gsr_cascade_anchored(const float *points, const float *colors, const float *depth,
+                                        const int32_t *segment, int32_t n_segments, int64_t n, const gsr_voxels *vox,
+                                        const float *pred, float focal, float beta, int32_t sh_degree,
+                                        const gsr_params *out, uint8_t *branch, void *ws, size_t ws_bytes,
+                                        gsr_stream stream);
 
 /* ---- point network of the model branch (Sec. III-B, Eq. 3) ------------------------------------
  * Per voxel of gsr_voxel_pca: 32 input rows (the fitting points repeated cyclically, centred on the

@@ -194,12 +194,14 @@ def prediction_valid(pred):
     return fin & np.all((s >= LOG_S_MIN) & (s <= LOG_S_MAX), axis=1)
 
 
-def cascade(points, colors, depth, segment, vox, pred=None, f=640.0, beta=None, sh_degree=0):
+def cascade(points, colors, depth, segment, vox, pred=None, f=640.0, beta=None, sh_degree=0, anchored=False):
     """Cascaded initialisation (Eq. 3): per point, the model branch if its voxel's prediction is
     valid, else the PCA branch if the voxel is geometrically reliable (R from the eigenvectors,
     s = s_pca + log beta, Eq. 5), else the heuristic branch (R = I, s = log(d / f), Eq. 6).
     beta: None = per segment, clamp(1 - rho, 0.5, 1) with rho the fraction of the segment's points
     that are reliable but lack a valid prediction; or one fixed value.
+    anchored: the model branch keeps only the predicted axis ratio a = exp(s - max s) and anchors it
+    at the point's depth, s = log((d / f) a) (Eq. 4).
     Returns Gaussian parameters (component-major [c][N] float64) and the branch per point
     (0 model, 1 PCA, 2 heuristic)."""
     P = np.asarray(points, np.float64)
@@ -225,6 +227,8 @@ def cascade(points, colors, depth, segment, vox, pred=None, f=640.0, beta=None, 
         if branch[i] == 0:
             p = pred[v[i]]
             ls[:, i] = p[:3]
+            if anchored:
+                ls[:, i] = np.log(depth[i] / f) + (p[:3] - np.max(p[:3]))
             qs[:, i] = p[3:7] / np.linalg.norm(p[3:7])
             lo[i] = p[7]
         elif branch[i] == 1:

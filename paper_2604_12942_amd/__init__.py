@@ -362,9 +362,11 @@ VOXEL_FIELDS = ("n_voxels", "n_outside", "key", "start", "count", "point_order",
                 "s_pca", "trace", "cls", "reliable")
 
 
-def voxel_pca(points, seed, out=None):
+def voxel_pca(points, seed, out=None, point_cov=None, sigma_g=False):
     """Voxel-PCA fitting of points [3, n] (float32 device tensor).  Returns a dict of device
-    tensors named like gsr_voxels (voxel arrays sized n, component-major); out reuses one."""
+    tensors named like gsr_voxels (voxel arrays sized n, component-major); out reuses one.
+    point_cov [6, n] (world covariances) puts them into Eq. 2; with sigma_g the full descriptor
+    covariance [21, n] is returned as out["sigma_g"]."""
     n = points.shape[1]
     dev = points.device
     if out is None:
@@ -380,13 +382,24 @@ def voxel_pca(points, seed, out=None):
         out["_ws"] = torch.empty((int(lib().gsr_voxel_pca_workspace(n)) + 255) // 256 * 64, dtype=i32, device=dev)
     V = _abi.Voxels(*[_ptr(out[k]) for k in VOXEL_FIELDS])
     ws = out["_ws"]
-    check(lib().gsr_voxel_pca(_ptr(points.contiguous()), n, int(seed) & ((1 << 64) - 1), C.byref(V), _ptr(ws),
-                              ws.numel() * 4, _stream()), "gsr_voxel_pca")
+    sd = int(seed) & ((1 << 64) - 1)
+    if point_cov is None:
+        check(lib().gsr_voxel_pca(_ptr(points.contiguous()), n, sd, C.byref(V), _ptr(ws), ws.numel() * 4, _stream()),
+              "gsr_voxel_pca")
+        return out
+    if sigma_g and out.get("sigma_g") is None:
+        out["sigma_g"] = torch.empty(21, max(1, n), dtype=torch.float32, device=points.device)
+    check(lib().gsr_voxel_pca_cov(_ptr(points.contiguous()), _ptr(point_cov.contiguous()), n, sd, C.byref(V),
+                                  _ptr(out.get("sigma_g") if sigma_g else None), _ptr(ws), ws.numel() * 4, _stream()),
+          "gsr_voxel_pca_cov")
     return out
 
 
-def cascade(points, colors, depth, vox, pred=None, focal=640.0, beta=0.0, segment=None, n_segments=1, sh_degree=0):
-    """Cascaded initialisation (Eq. 3): returns (params dict of [c, n] float32 tensors, branch)."""
+def cascade(points, colors, depth, vox, pred=None, focal=640.0, beta=0.0, segment=None, n_segments=1, sh_degree=0,
+            anchored=False):
+    """Cascaded initialisation (Eq. 3): returns (params dict of [c, n] float32 tensors, branch).
+    anchored: the model branch takes only the predicted axis ratios and anchors them at d / f
+    (Eq. 4)."""
     n = points.shape[1]
     dev = points.device
     K = (sh_degree + 1) ** 2
@@ -399,9 +412,10 @@ def cascade(points, colors, depth, vox, pred=None, focal=640.0, beta=0.0, segmen
                      dtype=torch.int32, device=dev)
     V = _abi.Voxels(*[_ptr(vox[k]) for k in VOXEL_FIELDS])
     O = _abi.Params(*[_ptr(P[k]) for k in PARAM_NAMES])
-    check(lib().gsr_cascade(_ptr(points.contiguous()), _ptr(colors.contiguous()), _ptr(depth.contiguous()),
-                            _ptr(segment), int(n_segments), n, C.byref(V), _ptr(pred), float(focal), float(beta),
-                            sh_degree, C.byref(O), _ptr(branch), _ptr(ws), ws.numel() * 4, _stream()), "gsr_cascade")
+    fn = lib().gsr_cascade_anchored if anchored else lib().gsr_cascade
+    check(fn(_ptr(points.contiguous()), _ptr(colors.contiguous()), _ptr(depth.contiguous()), _ptr(segment),
+             int(n_segments), n, C.byref(V), _ptr(pred), float(focal), float(beta), sh_degree, C.byref(O), _ptr(branch),
+             _ptr(ws), ws.numel() * 4, _stream()), "gsr_cascade")
     return P, branch[:n]
 
 

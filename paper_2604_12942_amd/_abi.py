@@ -112,6 +112,7 @@ _SIGS = {
                   C.c_size_t, P], C.c_int),
     "gsr_voxel_pca_workspace": ([C.c_int64], C.c_size_t),
     "gsr_voxel_pca": ([P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, C.c_size_t, P], C.c_int),
+    "gsr_voxel_pca_cov": ([P, P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, P, C.c_size_t, P], C.c_int),
     "gsr_pointnet_weight_count": ([], C.c_int),
     "gsr_pointnet_fwd": ([P, C.c_int64, C.POINTER(Voxels), P, P, P], C.c_int),
     "gsr_pointnet_bwd_workspace": ([C.c_int32], C.c_size_t),
@@ -120,6 +121,8 @@ _SIGS = {
     "gsr_cascade_workspace": ([C.c_int32], C.c_size_t),
     "gsr_cascade": ([P, P, P, P, C.c_int32, C.c_int64, C.POINTER(Voxels), P, C.c_float, C.c_float, C.c_int32,
                      C.POINTER(Params), P, P, C.c_size_t, P], C.c_int),
+    "gsr_cascade_anchored": ([P, P, P, P, C.c_int32, C.c_int64, C.POINTER(Voxels), P, C.c_float, C.c_float,
+                              C.c_int32, C.POINTER(Params), P, P, C.c_size_t, P], C.c_int),
 }
 
 EXPORTS = tuple(_SIGS)

@@ -37,10 +37,12 @@ extern "C" size_t gsr_scan_ws_bytes(int64_t n);
 extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
 extern "C" size_t gsr_voxel_pca_ws_bytes(int64_t n);
 extern "C" gsr_status gsr_voxel_pca_launch(const float *, int64_t, uint64_t, const gsr_voxels *, void *, hipStream_t);
+extern "C" gsr_status gsr_voxel_pca_cov_launch(const float *, const float *, int64_t, uint64_t, const gsr_voxels *,
+                                               float *, void *, hipStream_t);
 extern "C" size_t gsr_cascade_ws_bytes(int nseg);
 extern "C" gsr_status gsr_cascade_launch(const float *, const float *, const float *, const int32_t *, int, int64_t,
                                          const gsr_voxels *, const float *, float, float, int, const gsr_params *,
-                                         uint8_t *, void *, hipStream_t);
+                                         uint8_t *, void *, hipStream_t, int);
 extern "C" int gsr_pointnet_weight_count(void);
 extern "C" gsr_status gsr_pointnet_fwd_launch(const float *, int64_t, const gsr_voxels *, const float *, float *,
                                               hipStream_t);
@@ -437,6 +439,20 @@ extern "C" gsr_status gsr_voxel_pca(const float *points, int64_t n, uint64_t see
     return gsr_voxel_pca_launch(points, n, seed, out, ws, S(stream));
 }
 
+extern "C" gsr_status gsr_voxel_pca_cov(const float *points, const float *point_cov, int64_t n, uint64_t seed,
+                                        const gsr_voxels *out, float *sigma_g, void *ws, size_t ws_bytes,
+                                        gsr_stream stream) {
+    if (n > 0 && !point_cov) return GSR_E_INVALID;
+    if (n < 0 || n >= (int64_t)UINT32_MAX || !out || !out->n_voxels || !out->n_outside) return GSR_E_INVALID;
+    if (n > 0 && (!points || !out->key || !out->start || !out->count || !out->point_order || !out->point_voxel ||
+                  !out->mu || !out->evals || !out->R || !out->s_pca || !out->trace || !out->cls || !out->reliable ||
+                  !ws))
+        return GSR_E_INVALID;
+    if (n > 0 && (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
+    if (n > 0 && ws_bytes < gsr_voxel_pca_ws_bytes(n)) return GSR_E_CAPACITY;
+    return gsr_voxel_pca_cov_launch(points, point_cov, n, seed, out, sigma_g, ws, S(stream));
+}
+
 extern "C" size_t gsr_cascade_workspace(int32_t n_segments) { return gsr_cascade_ws_bytes(n_segments); }
 
 extern "C" gsr_status gsr_cascade(const float *points, const float *colors, const float *depth, const int32_t *segment,
@@ -451,7 +467,23 @@ extern "C" gsr_status gsr_cascade(const float *points, const float *colors, cons
     if (!(focal > 0.f)) return GSR_E_INVALID;
     if (ws_bytes < gsr_cascade_ws_bytes(segment ? n_segments : 1)) return GSR_E_CAPACITY;
     return gsr_cascade_launch(points, colors, depth, segment, segment ? n_segments : 1, n, vox, pred, focal, beta,
-                              sh_degree, out, branch, ws, S(stream));
+                              sh_degree, out, branch, ws, S(stream), 0);
+}
+
+extern "C" gsr_status gsr_cascade_anchored(const float *points, const float *colors, const float *depth,
+                                           const int32_t *segment, int32_t n_segments, int64_t n,
+                                           const gsr_voxels *vox, const float *pred, float focal, float beta,
+                                           int32_t sh_degree, const gsr_params *out, uint8_t *branch, void *ws,
+                                           size_t ws_bytes, gsr_stream stream) {
+    if (n < 0 || n >= (int64_t)UINT32_MAX || sh_degree < 0 || sh_degree > 3 || !vox || !out) return GSR_E_INVALID;
+    if (segment && n_segments < 1) return GSR_E_INVALID;
+    if (n > 0 && (!points || !colors || !depth || !vox->point_voxel || !vox->reliable || !vox->s_pca || !vox->R ||
+                  !out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh || !branch || !ws))
+        return GSR_E_INVALID;
+    if (!(focal > 0.f)) return GSR_E_INVALID;
+    if (ws_bytes < gsr_cascade_ws_bytes(segment ? n_segments : 1)) return GSR_E_CAPACITY;
+    return gsr_cascade_launch(points, colors, depth, segment, segment ? n_segments : 1, n, vox, pred, focal, beta,
+                              sh_degree, out, branch, ws, S(stream), 1);
 }
 
 namespace {

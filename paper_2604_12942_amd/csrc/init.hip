@@ -8,7 +8,9 @@
 // points in double precision: mean, biased covariance, cyclic Jacobi eigensystem, canonical
 // frame, planar / linear / unreliable class, and the trace of the descriptor's direction
 // covariance, which Eq. 1-2 with isotropic point covariance sigma^2 I reduce to
-// sigma^2 / N * sum_{m != k} (l_m + l_k) / (l_k - l_m)^2.
+// sigma^2 / N * sum_{m != k} (l_m + l_k) / (l_k - l_m)^2.  Given per-point world covariances,
+// the same thread sums Eq. 2 itself, J_i Sigma_i J_i^T over the fitting points, for the full 6x6
+// descriptor covariance and its trace.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -114,7 +116,12 @@ __device__ void jacobi3(double a[9], double w[9]) {
     }
 }
 
-__global__ void k_vox_pca(const float *__restrict__ pts, int64_t n, gsr_voxels V) {
+// COV: Eq. 1-2 with the per-point world covariances pcov [6][n] (xx, xy, xz, yy, yz, zz) instead
+// of sigma^2 I; the full descriptor covariance goes to sg [21][n] (upper triangle, row-major)
+// when sg is not null.
+template <bool COV>
+__global__ __launch_bounds__(256) void k_vox_pca(const float *__restrict__ pts, int64_t n, gsr_voxels V, const float *__restrict__ pcov,
+                          float *__restrict__ sg) {
     const uint32_t nv = *V.n_voxels;
     const uint32_t nvalid = (uint32_t)n - *V.n_outside;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
@@ -171,12 +178,70 @@ __global__ void k_vox_pca(const float *__restrict__ pts, int64_t n, gsr_voxels V
         else if (l[2] / l[0] > kTauL) cls = 1;
         if (m < kMinPts) cls = 2;
         double tr = INFINITY;
-        if (cls != 2) {
+        if (cls != 2 && !COV) {
             const int k = cls == 0 ? 0 : 2;
             double t = 0.0;
             for (int q = 0; q < 3; q++)
                 if (q != k) t += (l[q] + l[k]) / ((l[k] - l[q]) * (l[k] - l[q]));
             tr = kSigma * kSigma / m * t;
+        }
+        if (COV) {
+            double G[21];
+#pragma unroll
+            for (int e = 0; e < 21; e++) G[e] = 0.0;
+            if (cls != 2) {
+                // eigenvectors ascending (v_min, v_mid, v_max) = R_pca columns 2, 1, 0
+                const int k = cls == 0 ? 0 : 2;
+                double ev[3][3];
+#pragma unroll
+                for (int q = 0; q < 3; q++)
+#pragma unroll
+                    for (int r = 0; r < 3; r++) ev[q][r] = R[r * 3 + (2 - q)];
+                double vk[3], lk = k == 0 ? l[0] : l[2];
+#pragma unroll
+                for (int r = 0; r < 3; r++) vk[r] = k == 0 ? ev[0][r] : ev[2][r];
+                for (int j = 0; j < m; j++) {
+                    const uint32_t p = V.point_order[s0 + j];
+                    const double d[3] = {pts[p] - mu[0], pts[n + p] - mu[1], pts[2 * n + p] - mu[2]};
+                    const double dk = d[0] * vk[0] + d[1] * vk[1] + d[2] * vk[2];
+                    // T = V F = sum_{q != k} v_q f_q^T, f_q = ((d.v_q) v_k + (d.v_k) v_q) / (m (l_k - l_q))
+                    double T[9];
+#pragma unroll
+                    for (int e = 0; e < 9; e++) T[e] = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 3; q++) {
+                        if (q == k) continue;
+                        const double dq = d[0] * ev[q][0] + d[1] * ev[q][1] + d[2] * ev[q][2];
+                        const double inv = 1.0 / (m * (lk - l[q]));
+#pragma unroll
+                        for (int r = 0; r < 3; r++)
+#pragma unroll
+                            for (int c = 0; c < 3; c++) T[r * 3 + c] += ev[q][r] * ((dq * vk[c] + dk * ev[q][c]) * inv);
+                    }
+                    const double S[9] = {pcov[p],         pcov[n + p],     pcov[2 * n + p],
+                                         pcov[n + p],     pcov[3 * n + p], pcov[4 * n + p],
+                                         pcov[2 * n + p], pcov[4 * n + p], pcov[5 * n + p]};
+                    // J = [T; I/m] (6 x 3), G += J S J^T
+                    double J[6][3], JS[6][3];
+#pragma unroll
+                    for (int r = 0; r < 3; r++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) J[r][c] = T[r * 3 + c], J[3 + r][c] = r == c ? 1.0 / m : 0.0;
+#pragma unroll
+                    for (int r = 0; r < 6; r++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) JS[r][c] = J[r][0] * S[c] + J[r][1] * S[3 + c] + J[r][2] * S[6 + c];
+#pragma unroll
+                    for (int r = 0; r < 6; r++)
+#pragma unroll
+                        for (int c = r; c < 6; c++)
+                            G[r * 6 - r * (r - 1) / 2 + (c - r)] += JS[r][0] * J[c][0] + JS[r][1] * J[c][1] + JS[r][2] * J[c][2];
+                }
+                tr = G[0] + G[6] + G[11];  // (0,0), (1,1), (2,2) of the upper triangle
+            }
+            if (sg)
+#pragma unroll
+                for (int e = 0; e < 21; e++) sg[(int64_t)e * n + v] = (float)G[e];
         }
         const int64_t N = n;
         for (int c = 0; c < 3; c++) {
@@ -237,8 +302,8 @@ int grid(int64_t n) { return (int)(ceil_div(n > 0 ? n : 1, 256) < 16384 ? ceil_d
 
 extern "C" size_t gsr_voxel_pca_ws_bytes(int64_t n) { return vox_layout(nullptr, n).bytes; }
 
-extern "C" gsr_status gsr_voxel_pca_launch(const float *pts, int64_t n, uint64_t seed, const gsr_voxels *out,
-                                           void *ws, hipStream_t st) {
+static gsr_status voxel_pca_run(const float *pts, int64_t n, uint64_t seed, const gsr_voxels *out, void *ws,
+                                hipStream_t st, const float *pcov, float *sg) {
     gsr_status s = gsr_fill_u32_launch(out->n_outside, 0u, 1, st);
     if (s != GSR_OK) return s;
     if (n == 0) return gsr_fill_u32_launch(out->n_voxels, 0u, 1, st);
@@ -259,8 +324,19 @@ extern "C" gsr_status gsr_voxel_pca_launch(const float *pts, int64_t n, uint64_t
     s = gsr_scan_launch(w.head, n, w.hscan, out->n_voxels, w.scan_ws, st);
     if (s != GSR_OK) return s;
     k_vox_assign<<<g, 256, 0, st>>>(w.k0, w.v0, w.head, w.hscan, n, *out);
-    k_vox_pca<<<g, 256, 0, st>>>(pts, n, *out);
+    if (pcov) k_vox_pca<true><<<g, 256, 0, st>>>(pts, n, *out, pcov, sg);
+    else k_vox_pca<false><<<g, 256, 0, st>>>(pts, n, *out, nullptr, nullptr);
     return last_launch();
+}
+
+extern "C" gsr_status gsr_voxel_pca_launch(const float *pts, int64_t n, uint64_t seed, const gsr_voxels *out,
+                                           void *ws, hipStream_t st) {
+    return voxel_pca_run(pts, n, seed, out, ws, st, nullptr, nullptr);
+}
+
+extern "C" gsr_status gsr_voxel_pca_cov_launch(const float *pts, const float *pcov, int64_t n, uint64_t seed,
+                                               const gsr_voxels *out, float *sg, void *ws, hipStream_t st) {
+    return voxel_pca_run(pts, n, seed, out, ws, st, pcov, sg);
 }
 
 // ---- cascaded initialisation (Eq. 3, 5, 6) ------------------------------------------------------
@@ -324,7 +400,7 @@ __global__ void k_cascade(const float *__restrict__ pts, const float *__restrict
                           const int32_t *__restrict__ seg, int nseg, int64_t n, gsr_voxels V,
                           const float *__restrict__ pred, float focal, float beta_fixed,
                           const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ fb, int K, gsr_params out,
-                          uint8_t *__restrict__ branch) {
+                          uint8_t *__restrict__ branch, int anchored) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t v = V.point_voxel[i];
         for (int c = 0; c < 3; c++) {
@@ -343,6 +419,12 @@ __global__ void k_cascade(const float *__restrict__ pts, const float *__restrict
             for (int k = 0; k < 4; k++) nq += pred[(3 + k) * n + v] * pred[(3 + k) * n + v];
             nq = sqrtf(nq);
             for (int k = 0; k < 3; k++) ls[k] = pred[k * n + v];
+            if (anchored) {
+                // Eq. 4: keep the axis ratios a = exp(s - max s) and anchor the size at d / f
+                const float mx = fmaxf(ls[0], fmaxf(ls[1], ls[2]));
+                const float a0 = logf(depth[i] / focal);
+                for (int k = 0; k < 3; k++) ls[k] = a0 + (ls[k] - mx);
+            }
             for (int k = 0; k < 4; k++) q[k] = pred[(3 + k) * n + v] / nq;
             lo = pred[7 * n + v];
         } else if (br == 1) {
@@ -377,7 +459,7 @@ extern "C" size_t gsr_cascade_ws_bytes(int nseg) { return (size_t)(2 * (nseg > 0
 extern "C" gsr_status gsr_cascade_launch(const float *pts, const float *col, const float *depth, const int32_t *seg,
                                          int nseg, int64_t n, const gsr_voxels *vox, const float *pred, float focal,
                                          float beta, int sh_degree, const gsr_params *out, uint8_t *branch, void *ws,
-                                         hipStream_t st) {
+                                         hipStream_t st, int anchored) {
     if (n == 0) return GSR_OK;
     uint32_t *cnt = static_cast<uint32_t *>(ws);
     uint32_t *fb = cnt + (nseg > 0 ? nseg : 1);
@@ -386,6 +468,6 @@ extern "C" gsr_status gsr_cascade_launch(const float *pts, const float *col, con
     const int g = grid(n);
     k_seg_counts<<<g, 256, 0, st>>>(vox->point_voxel, vox->reliable, pred, n, seg, nseg, cnt, fb);
     k_cascade<<<g, 256, 0, st>>>(pts, col, depth, seg, nseg, n, *vox, pred, focal, beta, cnt, fb,
-                                 (sh_degree + 1) * (sh_degree + 1), *out, branch);
+                                 (sh_degree + 1) * (sh_degree + 1), *out, branch, anchored);
     return last_launch();
 }

@@ -112,8 +112,8 @@ def test_voxel_pca_outside_points_and_tiny_inputs():
     assert int(out1["n_voxels"].item()) == 1 and out1["cls"][0].item() == io.UNRELIABLE
 
 
-@pytest.mark.parametrize("with_model", [False, True])
-def test_cascade_matches_oracle(with_model):
+@pytest.mark.parametrize("with_model,anchored", [(False, False), (True, False), (True, True)])
+def test_cascade_matches_oracle(with_model, anchored):
     import paper_2604_12942_amd as gsr
     n = 20000
     pts, col, rng_, seg = _room_points(n, seed=2)
@@ -133,9 +133,10 @@ def test_cascade_matches_oracle(with_model):
     c_t = torch.from_numpy(np.ascontiguousarray(col.T)).cuda()
     d_t = torch.from_numpy(rng_).cuda()
     s_t = torch.from_numpy(seg).cuda()
-    P, br = gsr.cascade(t, c_t, d_t, vox, pred=pred_t, focal=640.0, beta=0.0, segment=s_t, n_segments=3, sh_degree=1)
+    P, br = gsr.cascade(t, c_t, d_t, vox, pred=pred_t, focal=640.0, beta=0.0, segment=s_t, n_segments=3, sh_degree=1,
+                        anchored=anchored)
     torch.cuda.synchronize()
-    g = io.cascade(pts, col, rng_, seg, o, pred=pred, f=640.0, sh_degree=1)
+    g = io.cascade(pts, col, rng_, seg, o, pred=pred, f=640.0, sh_degree=1, anchored=anchored)
     ok = _margins_ok(o)[o["voxel"]]
     if with_model:
         # a prediction near the validity bounds is a knife edge in float32
@@ -153,3 +154,45 @@ def test_cascade_matches_oracle(with_model):
     q = P["quats"].cpu().numpy().astype(np.float64)
     qok = ok & ((g["branch"] != 1) | _frame_ok(o)[o["voxel"]])
     assert np.all(np.abs(q[:, qok] - g["quats"][:, qok]) <= 1e-3)
+
+
+def test_voxel_pca_with_point_covariances_matches_oracle():
+    """Eq. 1-2 with anisotropic LiDAR point covariances: the full descriptor covariance, its
+    direction trace and the reliability flags against the oracle's per-point sum."""
+    import paper_2604_12942_amd as gsr
+    n, seed = 40000, 11
+    scene = synth.room_scene(1)
+    rng = np.random.default_rng(2)
+    scans = rng.uniform(-15.0, 15.0, (4, 2))
+    pts, surf, nrm, rngs, scan = scene.lidar(rng, scans, int(n * 2.5))
+    keep = np.sort(rng.choice(pts.shape[0], n, replace=False))
+    pts = pts[keep].astype(np.float32)
+    org = np.c_[scans[scan[keep]], np.full(n, 1.8)]
+    cov = synth.lidar_point_cov(pts, org)
+    t = torch.from_numpy(np.ascontiguousarray(pts.T)).cuda()
+    out = gsr.voxel_pca(t, seed, point_cov=torch.from_numpy(np.ascontiguousarray(cov.T)).cuda(), sigma_g=True)
+    torch.cuda.synchronize()
+    o = io.voxel_pca(pts, seed)
+    Sg, tr_o, rel_o = io.descriptor_covariance(pts, o, cov)
+    nv = len(o["n"])
+    assert int(out["n_voxels"].item()) == nv
+    o2 = dict(o, trace=tr_o)
+    ok = _margins_ok(o2)
+    assert ok.mean() > 0.98
+    rel = out["reliable"][:nv].cpu().numpy().astype(bool)
+    assert np.array_equal(rel[ok], rel_o[ok])
+    assert rel_o.sum() > 50 and (~rel_o & (o["cls"] != io.UNRELIABLE)).sum() > 0
+    tr = out["trace"][:nv].cpu().numpy().astype(np.float64)
+    fin = np.isfinite(tr_o) & ok
+    np.testing.assert_allclose(tr[fin], tr_o[fin], rtol=1e-4)
+    # full covariance on voxels with a unique frame (the cross block follows v_k's sign)
+    sel = fin & _frame_ok(o)
+    assert sel.sum() > 50
+    g = out["sigma_g"][:, :nv].cpu().numpy().T.astype(np.float64)
+    iu = np.triu_indices(6)
+    exp = Sg[:, iu[0], iu[1]]
+    diag = Sg[:, np.arange(6), np.arange(6)]
+    scale = np.sqrt(diag[:, iu[0]] * diag[:, iu[1]])
+    bad = np.abs(g[sel] - exp[sel]) > 1e-4 * scale[sel] + 1e-12
+    assert bad.sum() == 0, np.argwhere(bad)[:5]
+    assert not g[o["cls"] == io.UNRELIABLE].any()

@@ -210,3 +210,27 @@ def test_descriptor_jacobian_matches_finite_differences():
                            [c6[ids[j], 2], c6[ids[j], 4], c6[ids[j], 5]]])
             ref += J @ Si @ J.T
         np.testing.assert_allclose(Sg[v], ref, rtol=1e-4, atol=1e-6 * np.abs(ref).max())
+
+
+def test_anchored_model_scale_keeps_ratios_and_reduces_to_the_heuristic():
+    """Eq. 4: the anchored model branch keeps the predicted axis ratios, puts the largest axis at
+    d / f, and an isotropic prediction reproduces Eq. 6's size."""
+    pts, _ = _cloud(7)
+    vox = io.voxel_pca(pts, 5)
+    nv = len(vox["n"])
+    rng = np.random.default_rng(1)
+    pred = np.concatenate([rng.uniform(-6, -1, (nv, 3)), rng.standard_normal((nv, 4)), rng.standard_normal((nv, 1))],
+                          axis=1)
+    pred[0, :3] = -3.0  # isotropic
+    depth = rng.uniform(2, 20, len(pts))
+    seg = np.zeros(len(pts), np.int64)
+    a = io.cascade(pts, np.full((len(pts), 3), 0.5), depth, seg, vox, pred=pred, f=500.0, anchored=True)
+    p = io.cascade(pts, np.full((len(pts), 3), 0.5), depth, seg, vox, pred=pred, f=500.0)
+    m = a["branch"] == 0
+    assert m.sum() > 100
+    s, s0 = a["log_scales"][:, m], p["log_scales"][:, m]
+    np.testing.assert_allclose(np.max(s, axis=0), np.log(depth[m] / 500.0), rtol=1e-12)
+    np.testing.assert_allclose(s - s.max(axis=0), s0 - s0.max(axis=0), atol=1e-12)
+    iso = m & (vox["voxel"] == 0)
+    if iso.any():
+        np.testing.assert_allclose(a["log_scales"][:, iso], np.tile(np.log(depth[iso] / 500.0), (3, 1)), rtol=1e-12)
