@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
     ap.add_argument("--no-maintenance", action="store_true",
-                    help="skip the pruning / insertion and loop-registration timing")
+                    help="skip the pruning / insertion, loop-registration and init-path timing")
     ap.add_argument("--no-full-loss", action="store_true",
                     help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
@@ -497,6 +497,60 @@ def loop_leg(c, seg, dev, reps=3):
     return res
 
 
+# point network forward: per voxel 32 rows x (3x64 + 64x64 + 64x64) and the 76x64 + 64x8 head
+PN_FLOP_PER_VOXEL = 2 * 32 * (192 + 4096 + 4096) + 2 * (4864 + 512)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def init_leg(dev, reps=5):
+    """The initialisation path on a batch of 200k occupied voxels with 32 LiDAR-like points each
+    (6.4M points): voxel PCA (isotropic, and with per-point LiDAR covariances in Eq. 2), the point
+    network forward and the cascade, timed with HIP events (median of reps)."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    from paper_2604_12942_amd import learned_init as li
+    pts, cols, org, rngs = synth.voxel_batch(0)
+    n = pts.shape[0]
+    cov = torch.from_numpy(np.ascontiguousarray(synth.lidar_point_cov(pts, org).T)).to(dev)
+    t = torch.from_numpy(np.ascontiguousarray(pts.T)).to(dev)
+    col = torch.from_numpy(np.ascontiguousarray(cols.T)).to(dev)
+    depth = torch.from_numpy(rngs).to(dev)
+    w = li.init_weights(0, dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        ts = []
+        out = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), out
+
+    vox = gsr.voxel_pca(t, 1)
+    t_pca, _ = timed(lambda: gsr.voxel_pca(t, 1, out=vox))
+    nv = int(vox["n_voxels"].item())
+    rel_iso = int(vox["reliable"][:nv].sum().item())
+    t_cov, _ = timed(lambda: gsr.voxel_pca(t, 1, out=vox, point_cov=cov, sigma_g=True))
+    rel_cov = int(vox["reliable"][:nv].sum().item())
+    t_pn, pred = timed(lambda: gsr.pointnet_forward(t, vox, w))
+    t_cas, _ = timed(lambda: gsr.cascade(t, col, depth, vox, pred=pred, focal=640.0, beta=0.0, sh_degree=3))
+    ach = PN_FLOP_PER_VOXEL * nv / (t_pn / 1e3) / 1e12
+    res = dict(points=n, voxels=nv, reliable_isotropic=rel_iso, reliable_point_cov=rel_cov,
+               voxel_pca_ms=round(t_pca, 4), voxel_pca_point_cov_ms=round(t_cov, 4), pointnet_fwd_ms=round(t_pn, 4),
+               cascade_ms=round(t_cas, 4),
+               pointnet_roofline=dict(bound="mfma", achieved=round(ach, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                                      frac=round(ach / BF16_PEAK_TFLOPS, 5), flop_per_voxel=PN_FLOP_PER_VOXEL))
+    print("init path: %s" % res, file=sys.stderr, flush=True)
+    del vox, t, cov
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.init_compare:
@@ -734,10 +788,11 @@ def main():
                     kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
 
     loss_last = float(opt.loss.item())
-    maint = loopr = None
+    maint = loopr = initr = None
     if not a.no_maintenance:
         maint = maintenance_leg(g, seg, min_seg, dev)
         loopr = loop_leg(c, seg, dev)
+        initr = init_leg(dev)
     full = None
     if not a.no_full_loss:
         del opt
@@ -781,6 +836,7 @@ def main():
         "full_loss": full,
         "maintenance": maint,
         "loop_registration": loopr,
+        "init_path": initr,
     }
     print(json.dumps(out), flush=True)
 

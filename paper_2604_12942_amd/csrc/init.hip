@@ -363,16 +363,39 @@ __device__ __forceinline__ bool pred_valid(const float *pred, int64_t stride, ui
     return true;
 }
 
-__global__ void k_seg_counts(const uint32_t *__restrict__ pvox, const uint8_t *__restrict__ reliable,
-                             const float *__restrict__ pred, int64_t n, const int32_t *__restrict__ seg, int nseg,
-                             uint32_t *__restrict__ cnt, uint32_t *__restrict__ fb) {
+// Per-segment point counts for beta.  Points of one segment arrive together, so per-point global
+// atomics would all hit one address; each workgroup counts in LDS (up to kSegLds segments) and
+// adds its totals once.
+constexpr int kSegLds = 1024;
+
+__global__ __launch_bounds__(256) void k_seg_counts(const uint32_t *__restrict__ pvox,
+                                                    const uint8_t *__restrict__ reliable, const float *__restrict__ pred,
+                                                    int64_t n, const int32_t *__restrict__ seg, int nseg,
+                                                    uint32_t *__restrict__ cnt, uint32_t *__restrict__ fb) {
+    __shared__ uint32_t s_cnt[kSegLds], s_fb[kSegLds];
+    const bool lds = nseg <= kSegLds;
+    if (lds)
+        for (int e = threadIdx.x; e < nseg; e += 256) s_cnt[e] = s_fb[e] = 0u;
+    __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t v = pvox[i];
         const int s = seg ? seg[i] : 0;
         if (v == kOutside || s < 0 || s >= nseg) continue;
-        atomicAdd(&cnt[s], 1u);
-        if (reliable[v] && !pred_valid(pred, n, v)) atomicAdd(&fb[s], 1u);
+        const bool f = reliable[v] && !pred_valid(pred, n, v);
+        if (lds) {
+            atomicAdd(&s_cnt[s], 1u);
+            if (f) atomicAdd(&s_fb[s], 1u);
+        } else {
+            atomicAdd(&cnt[s], 1u);
+            if (f) atomicAdd(&fb[s], 1u);
+        }
     }
+    __syncthreads();
+    if (lds)
+        for (int e = threadIdx.x; e < nseg; e += 256) {
+            if (s_cnt[e]) atomicAdd(&cnt[e], s_cnt[e]);
+            if (s_fb[e]) atomicAdd(&fb[e], s_fb[e]);
+        }
 }
 
 // rotation matrix (row-major) -> unit quaternion (w, x, y, z), w >= 0, largest-pivot method
@@ -466,7 +489,7 @@ extern "C" gsr_status gsr_cascade_launch(const float *pts, const float *col, con
     gsr_status s = gsr_fill_u32_launch(cnt, 0u, 2 * (int64_t)(nseg > 0 ? nseg : 1), st);
     if (s != GSR_OK) return s;
     const int g = grid(n);
-    k_seg_counts<<<g, 256, 0, st>>>(vox->point_voxel, vox->reliable, pred, n, seg, nseg, cnt, fb);
+    k_seg_counts<<<g < 1024 ? g : 1024, 256, 0, st>>>(vox->point_voxel, vox->reliable, pred, n, seg, nseg, cnt, fb);
     k_cascade<<<g, 256, 0, st>>>(pts, col, depth, seg, nseg, n, *vox, pred, focal, beta, cnt, fb,
                                  (sh_degree + 1) * (sh_degree + 1), *out, branch, anchored);
     return last_launch();

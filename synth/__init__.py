@@ -302,6 +302,41 @@ def lidar_point_cov(points, origins, sigma_range=0.02, sigma_angle=np.deg2rad(0.
     return np.stack([C[:, 0, 0], C[:, 0, 1], C[:, 0, 2], C[:, 1, 1], C[:, 1, 2], C[:, 2, 2]], 1).astype(np.float32)
 
 
+def voxel_batch(seed, n_voxels=200_000, pts_per_voxel=32, voxel=0.5):
+    """A batch of occupied 0.5 m voxels with pts_per_voxel LiDAR-like points each, for the
+    initialisation path at scale: voxels on a lattice (x, y across 50 m, 20 layers in z), 60 % of
+    them a noisy plane patch (2 cm noise), 20 % a noisy bar, 20 % scattered.  Points keep 2 cm from
+    the voxel faces.  Returns points [n, 3], colours [n, 3], sensor origins [n, 3] (one per 10 m
+    tile, 1.8 m up) and ranges [n]."""
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(np.sqrt(n_voxels / 20)))
+    idx = np.arange(n_voxels)
+    kx, ky, kz = idx % side - side // 2, (idx // side) % side - side // 2, idx // (side * side) - 10
+    base = np.stack([kx, ky, kz], 1).astype(np.float64) * voxel
+    m = pts_per_voxel
+    kind = rng.random(n_voxels)
+    u = rng.uniform(0.04, voxel - 0.04, (n_voxels, m, 3))
+    # plane: a random tilt of the local xy plane through the voxel centre
+    nrm = rng.standard_normal((n_voxels, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    c = voxel / 2
+    d = u - c
+    plane = u - (np.einsum("vmk,vk->vm", d, nrm) - rng.normal(0, 0.02, (n_voxels, m)))[..., None] * nrm[:, None, :]
+    axis = rng.standard_normal((n_voxels, 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    tt = rng.uniform(-0.2, 0.2, (n_voxels, m, 1))
+    bar = c + tt * axis[:, None, :] + rng.normal(0, 0.02, (n_voxels, m, 3))
+    loc = np.where((kind < 0.6)[:, None, None], plane, np.where((kind < 0.8)[:, None, None], bar, u))
+    loc = np.clip(loc, 0.02, voxel - 0.02)
+    pts = (base[:, None, :] + loc).reshape(-1, 3)
+    tile = np.floor(pts[:, :2] / 10.0) * 10.0 + 5.0
+    org = np.c_[tile, np.full(len(pts), 1.8)]
+    rngs = np.linalg.norm(pts - org, axis=1)
+    col = rng.uniform(0.1, 0.9, (n_voxels, 3)).repeat(m, axis=0)
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    return f32(pts), f32(col), f32(org), f32(rngs)
+
+
 def _boxes_uniform(rng, n, lo, hi, start_id):
     c = rng.uniform(lo, hi, (n, 2))
     size = rng.uniform(0.3, 2.0, (n, 3))
