@@ -211,19 +211,140 @@ __device__ void forward_tile(const float *pts, int64_t n, const gsr_voxels &V, u
     head(V, n, v0, nv, S);
 }
 
+// ---- forward (inference) ------------------------------------------------------------------------
+// Persistent: each workgroup converts the weights once and loops over tiles of 8 voxels.  Each
+// wave owns two voxels (64 rows) end to end, so the layers need no workgroup barrier:
+//   layer 1 on the matrix cores with K padded from 3 to 16 (A built in registers from the
+//   gathered points, B = W1 from registers);
+//   layers 2 and 3 with B from the transposed weights in LDS; between layers the wave turns its
+//   accumulators (D layout) into the next A operand through its own 64-row LDS block, in place;
+//   max-pool in registers, then the 76 -> 64 -> 8 head on the VALU from the wave's LDS.
+struct PnFwdShared {
+    __attribute__((aligned(16))) __bf16 h[4][2 * kRows][kLd];  // per wave: its 64 rows
+    __attribute__((aligned(16))) __bf16 w2t[kWidth][kLd];       // W2, W3 transposed: [out][in]
+    __attribute__((aligned(16))) __bf16 w3t[kWidth][kLd];
+    __bf16 w4[kWidth + kFeat][kWidth];
+    __bf16 w5[kWidth][kOut];
+    float b[kWidth * 4 + kOut];
+    __bf16 z[4][2][kWidth + kFeat];
+    __bf16 h4[4][2][kWidth];
+};
+
 __global__ __launch_bounds__(256) void k_pn_fwd(const float *__restrict__ pts, int64_t n, gsr_voxels V,
                                                 const float *__restrict__ W, float *__restrict__ y) {
-    __shared__ PnShared S;
+    __shared__ PnFwdShared S;
     const uint32_t nv = *V.n_voxels;
-    const uint32_t v0 = blockIdx.x * kVox;
-    if (v0 >= nv) return;
-    load_weights(W, S);
+    const int t = threadIdx.x, lane = __lane_id(), w = t >> 6, half = lane >> 5, l32 = lane & 31;
+    const uint32_t ntiles = (nv + kVox - 1) / kVox;
+    if (blockIdx.x >= ntiles) return;
+    for (int q = t; q < (kWidth + kFeat) * kWidth; q += 256) S.w4[q / kWidth][q % kWidth] = tobf(W[oW4 + q]);
+    for (int q = t; q < kWidth * kOut; q += 256) S.w5[q / kOut][q % kOut] = tobf(W[oW5 + q]);
+    S.b[t] = t < 64 ? W[oB1 + t] : (t < 128 ? W[oB2 + t - 64] : (t < 192 ? W[oB3 + t - 128] : W[oB4 + t - 192]));
+    if (t < kOut) S.b[256 + t] = W[oB5 + t];
+    for (int q = t; q < kWidth * kWidth; q += 256) {
+        const int k = q / kWidth, o = q % kWidth;
+        S.w2t[o][k] = tobf(W[oW2 + q]);
+        S.w3t[o][k] = tobf(W[oW3 + q]);
+    }
+    // layer 1's B fragment: W1 padded to K = 16 (only k < 3 non-zero, in the first half-wave)
+    bf16x8 b1[2];
+    for (int ct = 0; ct < 2; ct++)
+        for (int j = 0; j < 8; j++) b1[ct][j] = tobf(half == 0 && j < 3 ? W[oW1 + j * kWidth + 32 * ct + l32] : 0.f);
     __syncthreads();
-    forward_tile(pts, n, V, v0, nv, S);
-    const int t = threadIdx.x;
-    if (t < kVox * kOut) {
-        const uint32_t v = v0 + t / kOut;
-        if (v < nv) y[(int64_t)(t % kOut) * n + v] = S.y[t / kOut][t % kOut];
+    __bf16(*H)[kLd] = S.h[w];
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t vb = tile * kVox + 2 * w;  // this wave's first voxel
+        // layer 1: A rows = the voxel's fitting points, repeated cyclically, centred and scaled
+        bf16x8 a1[2];
+        for (int rt = 0; rt < 2; rt++) {
+            const uint32_t v = vb + rt;
+            float x[3] = {0.f, 0.f, 0.f};
+            if (half == 0 && v < nv) {
+                const uint32_t cnt = V.count[v];
+                const uint32_t m = cnt < (uint32_t)kRows ? cnt : (uint32_t)kRows;
+                const uint32_t p = V.point_order[V.start[v] + (uint32_t)l32 % m];
+                for (int c = 0; c < 3; c++) x[c] = (pts[c * n + p] - V.mu[c * n + v]) / 0.5f;
+            }
+            for (int j = 0; j < 8; j++) a1[rt][j] = tobf(j < 3 ? x[j] : 0.f);
+        }
+        f32x16 acc[4];
+        for (int rt = 0; rt < 2; rt++)
+            for (int ct = 0; ct < 2; ct++)
+                acc[2 * rt + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[rt], b1[ct], f32x16{}, 0, 0, 0);
+        // layers 2 and 3: bias + ReLU of the previous layer into the wave's LDS rows, then GEMM
+        for (int layer = 0; layer < 2; layer++) {
+            for (int rt = 0; rt < 2; rt++)
+                for (int ct = 0; ct < 2; ct++) {
+                    const int col = 32 * ct + l32;
+                    const float bb = S.b[64 * layer + col];
+                    for (int r = 0; r < 16; r++)
+                        H[32 * rt + 8 * (r >> 2) + 4 * half + (r & 3)][col] =
+                            tobf(fmaxf(acc[2 * rt + ct][r] + bb, 0.f));
+                }
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+            for (int q = 0; q < 4; q++) acc[q] = f32x16{};
+            const __bf16(*Bt)[kLd] = layer == 0 ? S.w2t : S.w3t;
+            for (int kb = 0; kb < 4; kb++) {
+                const int k0 = 16 * kb + 8 * half;
+                bf16x8 a[2], b[2];
+                for (int rt = 0; rt < 2; rt++) a[rt] = *reinterpret_cast<const bf16x8 *>(&H[32 * rt + l32][k0]);
+                for (int ct = 0; ct < 2; ct++) b[ct] = *reinterpret_cast<const bf16x8 *>(&Bt[32 * ct + l32][k0]);
+                for (int rt = 0; rt < 2; rt++)
+                    for (int ct = 0; ct < 2; ct++)
+                        acc[2 * rt + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b[ct], acc[2 * rt + ct], 0, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // layer-3 bias + ReLU and the max-pool over each voxel's 32 rows
+        for (int rt = 0; rt < 2; rt++)
+            for (int ct = 0; ct < 2; ct++) {
+                const int col = 32 * ct + l32;
+                const float bb = S.b[128 + col];
+                float best = 0.f;
+                for (int r = 0; r < 16; r++) best = fmaxf(best, fmaxf(acc[2 * rt + ct][r] + bb, 0.f));
+                best = fmaxf(best, __shfl_xor(best, 32));
+                if (half == 0) S.z[w][rt][col] = tobf(best);
+            }
+        // the 12 voxel features: log(max(lambda, floor) / 0.25) ascending, then v_min, v_mid, v_max
+        if (lane < 24) {
+            const int rt = lane / 12, f = lane % 12;
+            const uint32_t v = vb + rt;
+            float val = 0.f;
+            if (v < nv) {
+                if (f < 3) {
+                    val = logf(fmaxf(V.evals[f * n + v], 0.005f * 0.005f) / 0.25f);
+                } else {
+                    const int col = 2 - (f - 3) / 3, row = (f - 3) % 3;
+                    val = V.R[(row * 3 + col) * n + v];
+                }
+            }
+            S.z[w][rt][kWidth + f] = tobf(val);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        // layer 4 (76 -> 64): lane = output column, both voxels
+        {
+            float a0 = S.b[192 + lane], a1v = a0;
+            for (int k = 0; k < kWidth + kFeat; k++) {
+                const float wk = fbf(S.w4[k][lane]);
+                a0 = __builtin_fmaf(fbf(S.z[w][0][k]), wk, a0);
+                a1v = __builtin_fmaf(fbf(S.z[w][1][k]), wk, a1v);
+            }
+            S.h4[w][0][lane] = tobf(fmaxf(a0, 0.f));
+            S.h4[w][1][lane] = tobf(fmaxf(a1v, 0.f));
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        // layer 5 (64 -> 8): lanes 0..15 = (voxel, output)
+        if (lane < 2 * kOut) {
+            const int rt = lane / kOut, j = lane % kOut;
+            float a = S.b[256 + j];
+            for (int k = 0; k < kWidth; k++) a = __builtin_fmaf(fbf(S.h4[w][rt][k]), fbf(S.w5[k][j]), a);
+            const uint32_t v = vb + rt;
+            if (v < nv) y[(int64_t)j * n + v] = a;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -472,7 +593,11 @@ extern "C" int gsr_pointnet_weight_count(void) { return kNW; }
 extern "C" gsr_status gsr_pointnet_fwd_launch(const float *pts, int64_t n, const gsr_voxels *vox, const float *W,
                                               float *y, hipStream_t st) {
     if (n == 0) return GSR_OK;
-    const int nb = (int)ceil_div(n, kVox);
+    // persistent: two workgroups per compute unit (the LDS allows two), each loops over tiles
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t tiles = ceil_div(n, kVox);
+    const int nb = (int)(tiles < 2 * cus ? tiles : 2 * cus);
     k_pn_fwd<<<nb, 256, 0, st>>>(pts, n, *vox, W, y);
     return last_launch();
 }
