@@ -39,3 +39,31 @@ def test_invalid_arguments_are_rejected_before_launch():
     assert L.gsr_project(ctypes.byref(g), None, 1, ctypes.byref(r), None, None, None) == 1
     assert L.gsr_bin_sort_workspace(-1, 1, 10, ctypes.byref(r)) == 0
     assert L.gsr_status_str(1) == b"invalid argument"
+
+
+def test_new_entry_points_reject_invalid_arguments():
+    # masks and loss, maintenance, registration, segment moves, voxel covariances: host checks only
+    from paper_2604_12942_amd import _abi
+    L = _abi.load()
+    c = ctypes
+    r = _abi.Raster(128, 96, 16, 16)
+    P = c.c_void_p(1)  # never dereferenced: every call below fails validation first
+    assert L.gsr_support_mask(P, 1, c.byref(r), 1.5, 2, P, P, None) == 1      # tau outside [0, 1]
+    assert L.gsr_support_mask(P, 1, c.byref(r), 0.5, 9, P, P, None) == 1      # radius above 8
+    assert L.gsr_loss(P, P, P, P, None, 1, c.byref(r), P, None, 1.0, 0.2, 0.2, P, P, P, P, 0, None) == 1  # mask w/o count
+    assert L.gsr_loss(P, P, P, P, None, 1, c.byref(r), None, None, 1.0, 0.2, 0.2, P, P, P, P, 1, None) == 1  # ws too small
+    assert L.gsr_prune_select(P, None, 0, 10, -1.0, 1.5, P, P, P, 1 << 30, None) == 1  # ratio above 1
+    assert L.gsr_prune_select(P, None, 0, -1, -1.0, 0.5, P, P, P, 1 << 30, None) == 1
+    g = _abi.RowGroups()
+    g.n_groups = 1
+    g.cols[0] = 1
+    assert L.gsr_gather_rows(c.byref(g), 10, None, 5, 4, 0, None) == 1        # rows past the destination
+    assert L.gsr_proximity_filter(P, 10, P, 10, 0.0, P, P, P, P, 1 << 30, None) == 1  # d_min = 0
+    gs = _abi.Gaussians(None, None, None, None, None, 10, 0, 0)
+    assert L.gsr_gicp_prepare(c.byref(gs), P, 0, P, 1, 30.0, 0.5, P, P, P, P, P, 1 << 30, None) == 1  # NULL means
+    assert L.gsr_gicp_iterate(c.byref(gs), P, P, P, 0.5, P, P, None, -1, P, 1 << 30, None) == 1
+    prm = _abi.Params(None, None, None, None, None)
+    assert L.gsr_transform_segment(c.byref(prm), 10, 3, P, 0, P, P, None) == 1  # NULL parameter arrays
+    assert L.gsr_transform_cameras(None, 2, None, P, None) == 1
+    assert L.gsr_voxel_pca_cov(P, None, 10, 0, None, None, P, 1 << 30, None) == 1  # no point covariances
+    assert L.gsr_loss_workspace(0, c.byref(r)) == 0
