@@ -266,10 +266,8 @@ GSR_API gsr_status gsr_project_bwd_adam(const gsr_gaussians *g, const gsr_camera
                                         double *dpose, uint8_t *row_mask, void *ws, size_t ws_bytes,
                                         gsr_stream stream);
 
-/* List of the Gaussians visible in at least one view (tile_info row 0 > 0 for some view),
- * grouped by the set of views that see them (ascending bitmask, bit v % 32 for view v; rows
- * ascending inside a group), so that neighbouring lanes of the projection backward visit the same
- * views: list [n] receives their indices and *count (device) their number.
+/* Ordered list of the Gaussians visible in at least one view (tile_info row 0 > 0 for some
+ * view): list [n] receives their indices in ascending order and *count (device) their number.
  * Passing it to gsr_project_bwd_adam (visible_list, visible_count; both or neither) makes the
  * backward launch dense work over the visible Gaussians only; row_mask is then written for the
  * listed rows only.  ws: gsr_visible_list_workspace(n) bytes. */

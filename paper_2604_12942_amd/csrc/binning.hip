@@ -53,14 +53,18 @@ __global__ __launch_bounds__(1024) void k_scan_small(uint32_t *__restrict__ v, i
 }
 
 // ---- ordered compaction of visible pairs ---------------------------------------------------------
-// block b covers pairs [b*4096, (b+1)*4096); thread t owns the 16 consecutive pairs t*16..t*16+15
+// Block b covers pairs [b*4096, (b+1)*4096) in round-major order: pair b*4096 + r*256 + t is read by
+// thread t in round r, so every load is coalesced; (round, wave, lane) order is pair order.
 __global__ __launch_bounds__(256) void k_vis_count(const uint32_t *__restrict__ ntiles, uint32_t VN,
                                                    uint32_t *__restrict__ bsum) {
     __shared__ uint32_t s_w[4];
-    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    const uint32_t base = blockIdx.x * kSortTile;
     uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < kSortItems; k++) c += (base + k < VN && ntiles[base + k] > 0) ? 1u : 0u;
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t e = base + r * kSortThreads + threadIdx.x;
+        c += (e < VN && ntiles[e] > 0) ? 1u : 0u;
+    }
     uint32_t tot;
     block_excl_scan256(c, s_w, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -69,19 +73,32 @@ __global__ __launch_bounds__(256) void k_vis_count(const uint32_t *__restrict__ 
 __global__ __launch_bounds__(256) void k_vis_compact(const uint32_t *__restrict__ info, uint32_t VN,
                                                      const uint32_t *__restrict__ boff, uint32_t *__restrict__ keys,
                                                      uint32_t *__restrict__ vals) {
-    __shared__ uint32_t s_w[4];
-    const uint32_t base = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
-    uint32_t c = 0;
+    __shared__ uint32_t s_cnt[kSortItems * 4];
+    const uint32_t base = blockIdx.x * kSortTile;
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    uint64_t m[kSortItems];
 #pragma unroll
-    for (int k = 0; k < kSortItems; k++) c += (base + k < VN && info[base + k] > 0) ? 1u : 0u;
-    uint32_t pos = boff[blockIdx.x] + block_excl_scan256(c, s_w, nullptr);
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t e = base + r * kSortThreads + threadIdx.x;
+        m[r] = __ballot(e < VN && info[e] > 0);
+        if (lane == 0) s_cnt[r * 4 + w] = (uint32_t)__popcll(m[r]);
+    }
+    __syncthreads();
+    // exclusive prefix of the 64 (round, wave) counts, in that order
+    if (threadIdx.x < kSortItems * 4) {
+        const uint32_t c = s_cnt[threadIdx.x];
+        s_cnt[threadIdx.x] = wave_incl_scan(c) - c;
+    }
+    __syncthreads();
+    const uint32_t b0 = boff[blockIdx.x];
+    const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int k = 0; k < kSortItems; k++) {
-        const uint32_t gid = base + k;
-        if (gid < VN && info[gid] > 0) {
-            keys[pos] = info[VN + gid];
-            vals[pos] = gid;
-            pos++;
+    for (int r = 0; r < kSortItems; r++) {
+        if ((m[r] >> lane) & 1ull) {
+            const uint32_t e = base + r * kSortThreads + threadIdx.x;
+            const uint32_t pos = b0 + s_cnt[r * 4 + w] + (uint32_t)__popcll(m[r] & lt);
+            keys[pos] = info[VN + e];
+            vals[pos] = e;
         }
     }
 }
@@ -145,23 +162,23 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
 // total goes to totals[d].
 __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ hist, int nblocks,
                                                          uint32_t *__restrict__ totals) {
+    // one digit's row per workgroup; each thread owns a contiguous run of the row: sum it, one
+    // workgroup scan of the run sums, then rewrite the run as exclusive prefixes
     __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_carry;
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int base = 0; base < nblocks; base += 256) {
-        const int idx = base + threadIdx.x;
-        const uint32_t x = idx < nblocks ? row[idx] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan256(x, s_w, &tot);
-        const uint32_t carry = s_carry;
-        if (idx < nblocks) row[idx] = carry + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry = carry + tot;
-        __syncthreads();
+    const int per = (nblocks + 255) / 256;
+    const int b0 = threadIdx.x * per;
+    const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    uint32_t sum = 0;
+    for (int idx = b0; idx < b1; idx++) sum += row[idx];
+    uint32_t tot;
+    uint32_t run = block_excl_scan256(sum, s_w, &tot);
+    for (int idx = b0; idx < b1; idx++) {
+        const uint32_t x = row[idx];
+        row[idx] = run;
+        run += x;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = s_carry;
+    if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,

@@ -723,37 +723,7 @@ extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_c
     return last_launch();
 }
 
-extern "C" size_t gsr_sort_pairs_ws_bytes(int64_t);
-extern "C" gsr_status gsr_sort_pairs_dev_launch(uint32_t *, uint32_t *, uint32_t *, uint32_t *, const uint32_t *,
-                                                uint32_t, int, void *, hipStream_t);
-
-namespace gsr {
-// key of a listed Gaussian: the set of views that see it (bit v % 32 for view v)
-__global__ void k_vis_mask_keys(const uint32_t *__restrict__ info, int64_t n, int V, const uint32_t *__restrict__ list,
-                                const uint32_t *__restrict__ count, uint32_t *__restrict__ key,
-                                uint32_t *__restrict__ val) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)*count) return;
-    const uint32_t i = list[j];
-    uint32_t m = 0;
-    for (int v = 0; v < V; v++) m |= (info[(int64_t)v * n + i] > 0 ? 1u : 0u) << (v & 31);
-    key[j] = m;
-    val[j] = i;
-}
-
-__global__ void k_vis_copy(const uint32_t *__restrict__ src, const uint32_t *__restrict__ count,
-                           uint32_t *__restrict__ dst) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < (int64_t)*count) dst[j] = src[j];
-}
-
-size_t vis_words(int64_t n) { return (size_t)(ceil_div(n > 0 ? n : 1, 64) * 64); }
-}  // namespace gsr
-
-// [block sums][keys][vals][keys'][sort workspace]
-extern "C" size_t gsr_visible_list_ws_bytes(int64_t n) {
-    return (size_t)(ceil_div(n > 0 ? n : 1, 256) * 4 + 256) + 3 * vis_words(n) * 4 + gsr_sort_pairs_ws_bytes(n);
-}
+extern "C" size_t gsr_visible_list_ws_bytes(int64_t n) { return (size_t)(ceil_div(n > 0 ? n : 1, 256) * 4 + 256); }
 
 extern "C" gsr_status gsr_visible_list_launch(const uint32_t *info, int64_t n, int V, uint32_t *list, uint32_t *count,
                                               void *ws, hipStream_t st) {
@@ -762,16 +732,5 @@ extern "C" gsr_status gsr_visible_list_launch(const uint32_t *info, int64_t n, i
     k_vis_any_count<<<nb, 256, 0, st>>>(info, n, V, bsum);
     k_scan_blocks<<<1, 1024, 0, st>>>(bsum, nb, count);
     k_vis_any_write<<<nb, 256, 0, st>>>(info, n, V, bsum, list);
-    if (n == 0) return last_launch();
-    // group the list by view set (stable, so rows stay ascending inside a group): lanes of a wave
-    // then walk the same views in the projection backward
-    uint32_t *key = bsum + (ceil_div(n, 256) * 4 + 256) / 4;
-    uint32_t *val = key + vis_words(n), *key2 = val + vis_words(n);
-    void *sws = key2 + vis_words(n);
-    k_vis_mask_keys<<<nb, 256, 0, st>>>(info, n, V, list, count, key, val);
-    const int bits = V >= 32 ? 32 : ((V + 7) / 8) * 8;
-    gsr_status s = gsr_sort_pairs_dev_launch(key, val, key2, list, count, (uint32_t)n, bits, sws, st);
-    if (s != GSR_OK) return s;
-    if ((bits / 8) % 2 == 0) k_vis_copy<<<nb, 256, 0, st>>>(val, count, list);
     return last_launch();
 }
