@@ -310,14 +310,31 @@ __device__ __forceinline__ float wave_total_f(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// In-place Adam on one element (the same float expression as the standalone optimiser kernel).
-__device__ __forceinline__ void adam_elem(float *p, float *m, float *v, int64_t e, float g, float lr, float b1,
-                                          float b2, float eps, float bc1, float bc2) {
-    const float mm = b1 * m[e] + (1.0f - b1) * g;
-    const float vv = b2 * v[e] + (1.0f - b2) * g * g;
-    m[e] = mm;
-    v[e] = vv;
-    p[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+// In-place Adam on the first cnt (at most N) elements of one Gaussian's row of a parameter group,
+// element k at base + k * stride, with the same float expression as the standalone optimiser
+// kernel. The three arrays never overlap: every load is issued before any store, so the elements
+// do not each wait out a separate memory round trip.
+template <int N>
+__device__ __forceinline__ void adam_batch(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                                           int64_t base, int64_t stride, int cnt, const float *g, const float *lr,
+                                           float b1, float b2, float eps, float bc1, float bc2) {
+    float pm[N], mv[N], vv[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        if (k >= cnt) break;
+        pm[k] = p[base + k * stride];
+        mv[k] = m[base + k * stride];
+        vv[k] = v[base + k * stride];
+    }
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        if (k >= cnt) break;
+        const float mm = b1 * mv[k] + (1.0f - b1) * g[k];
+        const float v2 = b2 * vv[k] + (1.0f - b2) * g[k] * g[k];
+        m[base + k * stride] = mm;
+        v[base + k * stride] = v2;
+        p[base + k * stride] = pm[k] - lr[k] * (mm / bc1) / (sqrtf(v2 / bc2) + eps);
+    }
 }
 
 struct FusedAdam {
@@ -555,16 +572,27 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
         float *P2 = const_cast<float *>(g.quats), *P3 = const_cast<float *>(g.opacity_logits);
         float *P4 = const_cast<float *>(g.sh);
         const float b1 = adam.b1, b2 = adam.b2, eps = adam.eps;
-        for (int a = 0; a < 3; a++)
-            adam_elem(P0, adam.m.means, adam.v.means, a * n + i, (float)gmu[a], adam.lr[0], b1, b2, eps, bc1, bc2);
-        for (int c = 0; c < 3; c++)
-            adam_elem(P1, adam.m.log_scales, adam.v.log_scales, c * n + i, gls[c], adam.lr[1], b1, b2, eps, bc1, bc2);
-        for (int a = 0; a < 4; a++)
-            adam_elem(P2, adam.m.quats, adam.v.quats, a * n + i, gqf[a], adam.lr[2], b1, b2, eps, bc1, bc2);
-        adam_elem(P3, adam.m.opacity_logits, adam.v.opacity_logits, i, gomf, adam.lr[3], b1, b2, eps, bc1, bc2);
-        for (int e = 0; e < 3 * K; e++)
-            adam_elem(P4, adam.m.sh, adam.v.sh, e * n + i, gh[e * 256], e < 3 ? adam.lr[4] : adam.lr[5], b1, b2, eps,
-                      bc1, bc2);
+        float gg[16], lr[16];
+        for (int a = 0; a < 3; a++) gg[a] = (float)gmu[a], lr[a] = adam.lr[0];
+        adam_batch<3>(P0, adam.m.means, adam.v.means, i, n, 3, gg, lr, b1, b2, eps, bc1, bc2);
+        for (int c = 0; c < 3; c++) gg[c] = gls[c], lr[c] = adam.lr[1];
+        adam_batch<3>(P1, adam.m.log_scales, adam.v.log_scales, i, n, 3, gg, lr, b1, b2, eps, bc1, bc2);
+        for (int a = 0; a < 4; a++) gg[a] = gqf[a], lr[a] = adam.lr[2];
+        adam_batch<4>(P2, adam.m.quats, adam.v.quats, i, n, 4, gg, lr, b1, b2, eps, bc1, bc2);
+        gg[0] = gomf, lr[0] = adam.lr[3];
+        adam_batch<1>(P3, adam.m.opacity_logits, adam.v.opacity_logits, i, n, 1, gg, lr, b1, b2, eps, bc1, bc2);
+        // SH in batches of up to 16 coefficients (rows e = 0..2 are the DC terms)
+#pragma unroll
+        for (int e0 = 0; e0 < 3 * K; e0 += 16) {
+            const int cnt = 3 * K - e0 < 16 ? 3 * K - e0 : 16;
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (k >= cnt) break;
+                gg[k] = gh[(e0 + k) * 256];
+                lr[k] = e0 + k < 3 ? adam.lr[4] : adam.lr[5];
+            }
+            adam_batch<16>(P4, adam.m.sh, adam.v.sh, (int64_t)e0 * n + i, n, cnt, gg, lr, b1, b2, eps, bc1, bc2);
+        }
     }
 }
 
