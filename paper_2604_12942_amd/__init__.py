@@ -121,10 +121,24 @@ def bin_sort(tile_info, n, n_views, raster, inst_gid, capacity, tile_ranges, n_i
 
 
 def render_fwd(splats, inst_gid, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last, n_contrib=None,
-               tile_order=None):
-    check(lib().gsr_render_fwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
-                               n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
-                               _ptr(n_contrib), _stream()), "gsr_render_fwd")
+               tile_order=None, ws=None, capacity=None):
+    """Whole tiles (gsr_render_fwd) without ws; with ws (render_fwd_sliced_workspace bytes) and
+    the lists' instance capacity, long tiles are composited in depth slices (gsr_render_fwd_sliced)."""
+    if ws is None:
+        check(lib().gsr_render_fwd(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
+                                   n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
+                                   _ptr(n_contrib), _stream()), "gsr_render_fwd")
+        return
+    if n_contrib is not None or capacity is None:
+        raise ValueError("the sliced forward takes the instance capacity and counts no contributors")
+    check(lib().gsr_render_fwd_sliced(_ptr(splats), _ptr(inst_gid), _ptr(tile_ranges), _ptr(tile_order), _ptr(cams),
+                                      n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth), _ptr(T_final), _ptr(last),
+                                      capacity, _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+          "gsr_render_fwd_sliced")
+
+
+def render_fwd_sliced_workspace(n_views, raster, capacity):
+    return int(lib().gsr_render_fwd_sliced_workspace(n_views, C.byref(raster.c), capacity))
 
 
 def render_bwd(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth,
@@ -498,16 +512,21 @@ class Rasterizer:
         self.em = emission(self.inst_emit, self.pair_gid, self.pair_first, self.n_pairs)
         wsb = bin_sort_workspace(self.n, self.V, self.capacity, self.raster)
         self.bin_ws = torch.empty((wsb + 255) // 256 * 64, dtype=torch.int32, device=self.device)
+        wsf = render_fwd_sliced_workspace(self.V, self.raster, self.capacity)
+        self.fwd_ws = torch.empty((wsf + 255) // 256 * 64, dtype=torch.int32, device=self.device)
 
-    def forward(self, P, sh_degree, cams, check_capacity=True):
-        """project -> bin/sort -> render; returns (rgb, depth, T_final) views of the buffers."""
+    def forward(self, P, sh_degree, cams, check_capacity=True, sliced=True):
+        """project -> bin/sort -> render; returns (rgb, depth, T_final) views of the buffers.
+        sliced=False composites every tile whole (gsr_render_fwd) instead of cutting long tiles
+        into depth slices (gsr_render_fwd_sliced)."""
         project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
         self.bin(check_capacity)
         if self.mode == "stored":
             self.render_stored(cams, check_capacity)
         else:
+            ws = self.fwd_ws if sliced else None
             render_fwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb, self.depth,
-                       self.T_final, self.last, tile_order=self.tile_order)
+                       self.T_final, self.last, tile_order=self.tile_order, ws=ws, capacity=self.capacity)
         return self.rgb, self.depth, self.T_final
 
     def render_stored(self, cams, check_capacity=True):

@@ -17,9 +17,10 @@ extern "C" gsr_status gsr_visible_list_launch(const uint32_t *, int64_t, int, ui
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT);
 extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, const gsr_emission *,
                                           int64_t, uint32_t *, uint32_t *, uint32_t *, void *, hipStream_t);
+extern "C" size_t gsr_render_fwd_ws_bytes(int, const gsr_raster *, int64_t);
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
-                                            uint32_t *, uint32_t *, hipStream_t);
+                                            uint32_t *, uint32_t *, int64_t, void *, hipStream_t);
 extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const uint32_t *, const gsr_camera *, int, const gsr_raster *, const float *,
                                             const uint32_t *, const float *, const float *, float *, hipStream_t);
@@ -174,7 +175,25 @@ extern "C" gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *in
     if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !rgb || !depth || !T_final || !last)
         return GSR_E_INVALID;
     return gsr_render_fwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, rgb, depth, T_final,
-                                 last, n_contrib, S(stream));
+                                 last, n_contrib, 0, nullptr, S(stream));
+}
+
+extern "C" size_t gsr_render_fwd_sliced_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity) {
+    if (!raster_ok(r) || n_views < 1 || capacity < 0) return 0;
+    return gsr_render_fwd_ws_bytes(n_views, r, capacity);
+}
+
+extern "C" gsr_status gsr_render_fwd_sliced(const gsr_splat *splats, const uint32_t *inst_gid,
+                                            const uint32_t *tile_ranges, const uint32_t *tile_order,
+                                            const gsr_camera *cams, int32_t n_views, const gsr_raster *r, float *rgb,
+                                            float *depth, float *T_final, uint32_t *last, int64_t capacity, void *ws,
+                                            size_t ws_bytes, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !rgb || !depth || !T_final || !last || !ws ||
+        capacity < 0 || capacity >= (int64_t)UINT32_MAX)
+        return GSR_E_INVALID;
+    if (ws_bytes < gsr_render_fwd_ws_bytes(n_views, r, capacity)) return GSR_E_CAPACITY;
+    return gsr_render_fwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, rgb, depth, T_final,
+                                 last, nullptr, capacity, ws, S(stream));
 }
 
 extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
@@ -206,7 +225,7 @@ extern "C" gsr_status gsr_render_fwd_stored(const gsr_splat *splats, const uint3
     if (contrib_capacity < 1 || contrib_capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
     if (ws_bytes < gsr_render_fwd_stored_workspace(n_views, r)) return GSR_E_CAPACITY;
     gsr_status s = gsr_render_fwd_launch(splats, inst_gid, tile_ranges, tile_order, cams, n_views, r, rgb, depth,
-                                         T_final, last, n_contrib, S(stream));
+                                         T_final, last, n_contrib, 0, nullptr, S(stream));
     if (s != GSR_OK) return s;
     s = gsr_scan_launch(n_contrib, pixels(n_views, r), contrib_offsets, n_contrib_total, ws, S(stream));
     if (s != GSR_OK) return s;

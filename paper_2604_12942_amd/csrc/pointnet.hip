@@ -595,7 +595,9 @@ extern "C" gsr_status gsr_pointnet_fwd_launch(const float *pts, int64_t n, const
     if (n == 0) return GSR_OK;
     // persistent: two workgroups per compute unit (the LDS allows two), each loops over tiles
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
     const int64_t tiles = ceil_div(n, kVox);
     const int nb = (int)(tiles < 2 * cus ? tiles : 2 * cus);
     k_pn_fwd<<<nb, 256, 0, st>>>(pts, n, *vox, W, y);

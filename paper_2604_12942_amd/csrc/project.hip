@@ -647,10 +647,10 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ v, 
     if (threadIdx.x == 0) *total = s_carry;
 }
 
-// dpose[v][e] = sum over waves of the partial sums (fixed order: deterministic)
+// dpose[v][e] = sum over waves of the partial sums
 // One workgroup per (view, component): the sum of the per-wave partials of the waves that ran
 // (all nw waves, or those covering the first *vcount entries of the visible list), in a fixed
-// order, so the pose gradient is reproducible.
+// order, so this reduction adds no run-dependent rounding of its own.
 __global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ part, int64_t nw,
                                                      const uint32_t *__restrict__ vcount,
                                                      double *__restrict__ dpose) {

@@ -75,9 +75,257 @@ __device__ __forceinline__ void wave_box(int tx0, int ty0, int w, float &x0, flo
     y1 = (float)(ty0 + w * rows + rows - 1) + 0.5f;
 }
 
+// ---- front-to-back walk -----------------------------------------------------------------------
+constexpr int kNullSlot = 256;    // LDS slot of the null Gaussian (cut-off below every exponent)
+constexpr float kGone = 1.0e30f;  // centre of a finished pixel: out of reach of every ellipse
+
+// The calling lane's pixel in one (view, tile) work item.
+struct TileGeom {
+    int v, px, py;
+    bool inside;
+    double ox, oy;             // origin of the 32x32-aligned block holding the tile
+    float fx, fy;              // pixel centre in block coordinates
+    float wx0, wx1, wy0, wy1;  // the wave's box of pixel centres
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileGeom tile_geom(uint32_t item, int T, int ntx, int W, int H) {
+    TileGeom t;
+    t.v = item / T;
+    const int tile = item % T;
+    const int tx = tile % ntx, ty = tile / ntx;
+    t.px = tx * TW + (int)threadIdx.x % TW;
+    t.py = ty * TH + (int)threadIdx.x / TW;
+    t.inside = t.px < W && t.py < H;
+    // means are re-centred on the 32x32-aligned block holding the tile: the same origin for
+    // every tile shape, so whole-tile images are bit-identical across 16x16, 8x32 and 32x8 tiles
+    const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
+    t.ox = (double)bx;
+    t.oy = (double)by;
+    t.fx = (float)(t.px - bx) + 0.5f;
+    t.fy = (float)(t.py - by) + 0.5f;
+    wave_box<TW>(tx * TW - bx, ty * TH - by, (int)threadIdx.x >> 6, t.wx0, t.wx1, t.wy0, t.wy1);
+    return t;
+}
+
+// Per-pixel state of the walk.  A finished pixel (terminated, or outside the image) moves its
+// centre to kGone: the exponent then overflows to +inf, the pixel blends with weight 0, and the
+// loop needs no separate flag.
+struct PixelWalk {
+    float Tr, c0, c1, c2, dd;
+    uint32_t lst, nc;
+    float fxl;
+};
+
+__device__ __forceinline__ PixelWalk walk_start(const TileGeom &t, float T0) {
+    PixelWalk w;
+    w.Tr = T0;
+    w.c0 = w.c1 = w.c2 = w.dd = 0.f;
+    w.lst = w.nc = 0;
+    w.fxl = (t.inside && T0 >= GSR_T_MIN) ? t.fx : kGone;
+    return w;
+}
+
+// Composites the instances [lo, hi) of a tile list that begins at `start` (positions count from
+// it) into the walk.  The instances are staged through LDS in batches of 256; each wave tests
+// every staged ellipse against its pixel box and walks only the Gaussians that reach it, two per
+// step (the second one's LDS reads are in flight during the first blend; an odd last one is
+// paired with the null slot).  A wave stops at the first step after which all its pixels have
+// finished, the workgroup at the first batch none of its pixels needs.  Block-uniform arguments;
+// the null slot must have been written before the call.
 // STORE: the second pass of the stored-contributor mode; each pixel writes the tile-list positions
-// of its composited Gaussians, front to back, at clist[coff[pixel] ...] (skipped beyond ccap), and
-// no image is written.
+// of its composited Gaussians, front to back, at clist[cbase ...] (skipped beyond ccap).
+template <bool STORE>
+__device__ __forceinline__ void composite(const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst,
+                                          uint32_t start, uint32_t lo, uint32_t hi, const TileGeom &t,
+                                          float4 *sA, float4 *sB, float4 *sC, PixelWalk &pw,
+                                          uint32_t *__restrict__ clist, uint32_t cbase, uint32_t ccap) {
+    for (uint32_t b = lo; b < hi; b += 256) {
+        if (__syncthreads_count(pw.fxl != kGone) == 0) break;
+        const uint32_t e = b + threadIdx.x;
+        const int cnt = (int)min(256u, hi - b);
+        if (e < hi) {
+            float4 A, B, C;
+            stage_splat(splats, inst[e], t.ox, t.oy, A, B, C);
+            sA[threadIdx.x] = A;
+            sB[threadIdx.x] = B;
+            sC[threadIdx.x] = C;
+        }
+        __syncthreads();
+        const uint32_t pos0 = b - start + 1;
+        // one Gaussian's blend into this lane's pixel (branch-free: a non-contributing lane
+        // blends with weight exactly 0)
+        auto blend = [&](int j, const float4 &A, const float4 &B, const float4 &C) {
+            float dx, dy, u1, u2;
+            const float P = blend_exponent(A, B.x, pw.fxl, t.fy, dx, dy, u1, u2);
+            const bool cont = P <= B.y;
+            const float ar = B.z * __builtin_amdgcn_exp2f(-P);
+            const float a0 = cont ? fminf(ar, GSR_ALPHA_MAX) : 0.0f;
+            const float Tn = pw.Tr * (1.0f - a0);
+            const bool term = Tn < GSR_T_MIN;
+            pw.fxl = term ? kGone : pw.fxl;
+            const float a = term ? 0.0f : a0;
+            const float wgt = a * pw.Tr;
+            pw.c0 = __builtin_fmaf(wgt, C.x, pw.c0);
+            pw.c1 = __builtin_fmaf(wgt, C.y, pw.c1);
+            pw.c2 = __builtin_fmaf(wgt, C.z, pw.c2);
+            pw.dd = __builtin_fmaf(wgt, B.w, pw.dd);
+            pw.Tr = term ? pw.Tr : Tn;
+            const bool used = a > 0.0f;
+            if (STORE && used && cbase + pw.nc < ccap) clist[cbase + pw.nc] = pos0 - 1 + (uint32_t)j;
+            pw.lst = used ? pos0 + (uint32_t)j : pw.lst;
+            pw.nc += used ? 1u : 0u;
+        };
+        for (int g = 0; g < 4 && g * 64 < cnt; g++) {
+            if (__ballot(pw.fxl != kGone) == 0) break;
+            const int slot = g * 64 + __lane_id();
+            const bool r = slot < cnt && ellipse_meets_box(sA[slot], sB[slot], t.wx0, t.wx1, t.wy0, t.wy1);
+            uint64_t m = __ballot(r);
+            while (m) {
+                const int j1 = g * 64 + __builtin_ctzll(m);
+                m &= m - 1;
+                const int j2 = m ? g * 64 + __builtin_ctzll(m) : kNullSlot;
+                m &= m - 1;
+                const float4 A1 = sA[j1], B1 = sB[j1], C1 = sC[j1];
+                const float4 A2 = sA[j2], B2 = sB[j2], C2 = sC[j2];
+                blend(j1, A1, B1, C1);
+                blend(j2, A2, B2, C2);
+                if (__ballot(pw.fxl != kGone) == 0) break;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void write_null_slot(float4 *sA, float4 *sB, float4 *sC) {
+    if (threadIdx.x == 0) {
+        sA[kNullSlot] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sB[kNullSlot] = make_float4(0.f, -1.f, 0.f, 0.f);
+        sC[kNullSlot] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// ---- depth slices of long tiles ------------------------------------------------------------------
+// A tile whose list holds more than kSliceLen instances would keep one workgroup busy long after
+// the rest of the launch has drained (a view down a corridor piles tens of thousands of distant
+// Gaussians into the tile at the vanishing point).  Such a tile is cut into slices of kSliceLen
+// consecutive instances.  Compositing is associative in the transmittance: the walk through
+// slice k starts from T_in(k), the product over the earlier slices of their own (1 - a)
+// products, and the pixel has terminated before slice k exactly when T_in(k) < 1e-4 (T never
+// increases).  So one pass computes every slice's product (a pixel whose product falls below
+// 1e-4 stops and records 0), a second composites all slices at once from their T_in, and a merge
+// sums each pixel's slice results in order, stopping after the slice in which it terminated.
+// The results are those of the whole-tile walk up to the float rounding of the transmittance
+// products (which are associated per slice).
+constexpr uint32_t kSliceLen = 2048;
+constexpr uint32_t kNoSlice = 0xffffffffu;  // list entry of a slice that did not fit
+
+struct SliceArgs {
+    const uint32_t *tile_slices;  // [V*T] number of slices of each view-tile (0: whole tile)
+    const uint2 *info;            // [cap] (view-tile, slice index within the tile)
+    const uint32_t *count;        // [1] number of slices
+    float *tprod;                 // [cap][256] per-pixel product of (1 - a) over the slice
+    float4 *part;                 // [cap][256] slice colour (3) and depth, already times T_in
+    uint2 *part2;                 // [cap][256] (T after the slice, negated if it terminated there;
+                                  //             last composited position)
+    uint32_t cap, grid;           // slice capacity; workgroups that walk the slice list
+};
+
+__global__ void k_slice_count(const uint32_t *__restrict__ ranges, uint32_t VT, uint32_t *__restrict__ ns) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT; i += gridDim.x * blockDim.x) {
+        const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
+        ns[i] = len > kSliceLen ? (len + kSliceLen - 1) / kSliceLen : 0u;
+    }
+}
+
+// Lists the slices tile by tile.  A tile whose slices would not fit the capacity (impossible
+// while the lists hold at most `cap` * kSliceLen / 2 instances) is left whole.
+__global__ void k_slice_emit(uint32_t *__restrict__ ns, const uint32_t *__restrict__ off, uint32_t VT,
+                             uint32_t cap, uint2 *__restrict__ info) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT; i += gridDim.x * blockDim.x) {
+        const uint32_t k = ns[i];
+        if (!k) continue;
+        if (off[i] + k > cap) {
+            ns[i] = 0;
+            for (uint32_t q = off[i]; q < cap && q < off[i] + k; q++) info[q] = make_uint2(kNoSlice, 0u);
+            continue;
+        }
+        for (uint32_t q = 0; q < k; q++) info[off[i] + q] = make_uint2(i, q);
+    }
+}
+
+__device__ __forceinline__ float slice_T_in(const SliceArgs &sl, uint32_t j, uint32_t k) {
+    float T = 1.0f;
+    for (uint32_t q = 0; q < k; q++) T *= sl.tprod[(size_t)(j - k + q) * 256 + threadIdx.x];
+    return T;
+}
+
+// Pass 1: the (1 - a) product of every slice but each tile's last.
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_slice_prod(const gsr_splat *__restrict__ splats,
+                                                    const uint32_t *__restrict__ inst,
+                                                    const uint32_t *__restrict__ ranges, int W, int H, int ntx,
+                                                    int T, SliceArgs sl) {
+    __shared__ float4 sA[257], sB[257], sC[257];
+    write_null_slot(sA, sB, sC);
+    const uint32_t n = min(*sl.count, sl.cap);
+    for (uint32_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const uint2 si = sl.info[j];
+        if (si.x == kNoSlice || si.y + 1 == sl.tile_slices[si.x]) continue;
+        const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
+        const uint32_t start = ranges[2 * si.x], end = ranges[2 * si.x + 1];
+        const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
+        PixelWalk pw = walk_start(t, 1.0f);
+        composite<false>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
+        sl.tprod[(size_t)j * 256 + threadIdx.x] = (t.inside && pw.fxl == kGone) ? 0.0f : pw.Tr;
+    }
+}
+
+// Pass 3: per pixel, the slices' results in order.
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_slice_merge(const uint32_t *__restrict__ ranges,
+                                                     const gsr_camera *__restrict__ cams, int W, int H, int ntx,
+                                                     int T, SliceArgs sl, float *__restrict__ rgb,
+                                                     float *__restrict__ depth, float *__restrict__ Tfin,
+                                                     uint32_t *__restrict__ last) {
+    const uint32_t n = min(*sl.count, sl.cap);
+    for (uint32_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const uint2 si = sl.info[j];
+        if (si.x == kNoSlice || si.y != 0) continue;
+        const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
+        if (!t.inside) continue;
+        const uint32_t K = sl.tile_slices[si.x];
+        float Tin = 1.0f, Tr = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dd = 0.f;
+        uint32_t lst = 0;
+        for (uint32_t k = 0; k < K; k++) {
+            if (Tin < GSR_T_MIN) break;  // terminated in an earlier slice
+            const size_t q = (size_t)(j + k) * 256 + threadIdx.x;
+            const float4 pc = sl.part[q];
+            const uint2 p2 = sl.part2[q];
+            c0 += pc.x;
+            c1 += pc.y;
+            c2 += pc.z;
+            dd += pc.w;
+            const float To = __uint_as_float(p2.x);
+            Tr = fabsf(To);
+            lst = p2.y ? p2.y : lst;
+            if (To < 0.0f) break;  // terminated in this slice
+            if (k + 1 < K) Tin *= sl.tprod[q];
+        }
+        const gsr_camera &cam = cams[t.v];
+        const int64_t P = (int64_t)W * H;
+        const int64_t pix = (int64_t)t.py * W + t.px;
+        rgb[(int64_t)t.v * 3 * P + pix] = __builtin_fmaf(Tr, cam.bg[0], c0);
+        rgb[(int64_t)t.v * 3 * P + P + pix] = __builtin_fmaf(Tr, cam.bg[1], c1);
+        rgb[(int64_t)t.v * 3 * P + 2 * P + pix] = __builtin_fmaf(Tr, cam.bg[2], c2);
+        depth[(int64_t)t.v * P + pix] = dd;
+        Tfin[(int64_t)t.v * P + pix] = Tr;
+        last[(int64_t)t.v * P + pix] = lst;
+    }
+}
+
+// One 256-lane workgroup per (view, tile) in `order` (longest list first), one pixel per lane.
+// With slices (sl.grid > 0) the first sl.grid workgroups composite the slices of the long tiles
+// (pass 2), and the long tiles' own workgroups return at once.
 template <int TW, int TH, bool STORE>
 __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
@@ -87,105 +335,47 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
                                                     int T, float *__restrict__ rgb, float *__restrict__ depth,
                                                     float *__restrict__ Tfin, uint32_t *__restrict__ last,
                                                     uint32_t *__restrict__ ncon, const uint32_t *__restrict__ coff,
-                                                    uint32_t *__restrict__ clist, uint32_t ccap) {
+                                                    uint32_t *__restrict__ clist, uint32_t ccap, SliceArgs sl) {
     static_assert(TW * TH == 256, "one pixel per lane");
-    __shared__ float4 sA[256], sB[256], sC[256];
-    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
-    const int v = item / T, tile = item % T;
-    const int tx = tile % ntx, ty = tile / ntx;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < W && py < H;
-    const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
-    // means are re-centred on the 32x32-aligned block holding the tile: the same origin for
-    // every tile shape, so images are bit-identical across 16x16, 8x32 and 32x8 tiles
-    const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
-    const double ox = (double)bx, oy = (double)by;
-    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;
-    const int w = threadIdx.x >> 6;
-    float wx0, wx1, wy0, wy1;
-    wave_box<TW>(tx * TW - bx, ty * TH - by, w, wx0, wx1, wy0, wy1);
-    float Tr = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dd = 0.f;
-    uint32_t lst = 0, nc = 0;
-    bool done = !inside;
-    uint32_t cbase = 0;
-    if (STORE && inside) cbase = coff[(int64_t)v * W * H + (int64_t)py * W + px];
-    for (uint32_t b = start; b < end; b += 256) {
-        if (__syncthreads_count(!done) == 0) break;
-        const uint32_t e = b + threadIdx.x;
-        const int cnt = (int)min(256u, end - b);
-        if (e < end) {
-            float4 A, B, C;
-            stage_splat(splats, inst[e], ox, oy, A, B, C);
-            sA[threadIdx.x] = A;
-            sB[threadIdx.x] = B;
-            sC[threadIdx.x] = C;
+    __shared__ float4 sA[257], sB[257], sC[257];
+    write_null_slot(sA, sB, sC);
+    if (blockIdx.x < sl.grid) {
+        const uint32_t n = min(*sl.count, sl.cap);
+        for (uint32_t j = blockIdx.x; j < n; j += sl.grid) {
+            const uint2 si = sl.info[j];
+            if (si.x == kNoSlice) continue;
+            const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
+            const uint32_t start = ranges[2 * si.x], end = ranges[2 * si.x + 1];
+            const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
+            const float Tin = slice_T_in(sl, j, si.y);
+            PixelWalk pw = walk_start(t, Tin);
+            composite<false>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
+            const bool term = t.inside && Tin >= GSR_T_MIN && pw.fxl == kGone;
+            sl.part[(size_t)j * 256 + threadIdx.x] = make_float4(pw.c0, pw.c1, pw.c2, pw.dd);
+            sl.part2[(size_t)j * 256 + threadIdx.x] = make_uint2(__float_as_uint(term ? -pw.Tr : pw.Tr), pw.lst);
         }
-        __syncthreads();
-        if (__ballot(!done) == 0) continue;  // the whole wave has terminated
-        // which staged Gaussians reach this wave's pixels
-        uint64_t rel[4];
-#pragma unroll
-        for (int g = 0; g < 4; g++) {
-            const int slot = g * 64 + __lane_id();
-            bool r = false;
-            if (slot < cnt) r = ellipse_meets_box(sA[slot], sB[slot], wx0, wx1, wy0, wy1);
-            rel[g] = __ballot(r);
-        }
-        const uint32_t pos0 = b - start + 1;
-        // one Gaussian's blend into this lane's pixel (branch-free: a non-contributing lane
-        // blends with weight exactly 0)
-        auto blend = [&](int j, const float4 &A, const float4 &B, const float4 &C) {
-            float dx, dy, u1, u2;
-            const float P = blend_exponent(A, B.x, fx, fy, dx, dy, u1, u2);
-            const bool cont = (P <= B.y) && !done;
-            const float ar = B.z * __builtin_amdgcn_exp2f(-P);
-            const float a0 = cont ? fminf(ar, GSR_ALPHA_MAX) : 0.0f;
-            const bool term = (Tr * (1.0f - a0)) < GSR_T_MIN;
-            done = done || term;
-            const float a = term ? 0.0f : a0;
-            const float wgt = a * Tr;
-            c0 = __builtin_fmaf(wgt, C.x, c0);
-            c1 = __builtin_fmaf(wgt, C.y, c1);
-            c2 = __builtin_fmaf(wgt, C.z, c2);
-            dd = __builtin_fmaf(wgt, B.w, dd);
-            Tr = Tr * (1.0f - a);
-            const bool used = a > 0.0f;
-            if (STORE && used && cbase + nc < ccap) clist[cbase + nc] = pos0 - 1 + (uint32_t)j;
-            lst = used ? pos0 + (uint32_t)j : lst;
-            nc += used ? 1u : 0u;
-        };
-#pragma unroll
-        for (int g = 0; g < 4; g++) {
-            uint64_t m = rel[g];
-            // two Gaussians per step: the second one's LDS reads are in flight during the first blend
-            while (m) {
-                const int j1 = g * 64 + __builtin_ctzll(m);
-                m &= m - 1;
-                const float4 A1 = sA[j1], B1 = sB[j1], C1 = sC[j1];
-                if (m) {
-                    const int j2 = g * 64 + __builtin_ctzll(m);
-                    m &= m - 1;
-                    const float4 A2 = sA[j2], B2 = sB[j2], C2 = sC[j2];
-                    blend(j1, A1, B1, C1);
-                    blend(j2, A2, B2, C2);
-                } else {
-                    blend(j1, A1, B1, C1);
-                }
-            }
-        }
+        return;
     }
-    if (!inside || STORE) return;
-    const gsr_camera &cam = cams[v];
+    const uint32_t b = blockIdx.x - sl.grid, nb = gridDim.x - sl.grid;
+    const uint32_t item = order ? order[b] : xcd_remap(b, nb);
+    if (sl.grid && sl.tile_slices[item]) return;  // composited in slices
+    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
+    const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
+    uint32_t cbase = 0;
+    if (STORE && t.inside) cbase = coff[(int64_t)t.v * W * H + (int64_t)t.py * W + t.px];
+    PixelWalk pw = walk_start(t, 1.0f);
+    composite<STORE>(splats, inst, start, start, end, t, sA, sB, sC, pw, clist, cbase, ccap);
+    if (!t.inside || STORE) return;
+    const gsr_camera &cam = cams[t.v];
     const int64_t P = (int64_t)W * H;
-    const int64_t pix = (int64_t)py * W + px;
-    rgb[(int64_t)v * 3 * P + pix] = __builtin_fmaf(Tr, cam.bg[0], c0);
-    rgb[(int64_t)v * 3 * P + P + pix] = __builtin_fmaf(Tr, cam.bg[1], c1);
-    rgb[(int64_t)v * 3 * P + 2 * P + pix] = __builtin_fmaf(Tr, cam.bg[2], c2);
-    depth[(int64_t)v * P + pix] = dd;
-    Tfin[(int64_t)v * P + pix] = Tr;
-    last[(int64_t)v * P + pix] = lst;
-    if (ncon) ncon[(int64_t)v * P + pix] = nc;
+    const int64_t pix = (int64_t)t.py * W + t.px;
+    rgb[(int64_t)t.v * 3 * P + pix] = __builtin_fmaf(pw.Tr, cam.bg[0], pw.c0);
+    rgb[(int64_t)t.v * 3 * P + P + pix] = __builtin_fmaf(pw.Tr, cam.bg[1], pw.c1);
+    rgb[(int64_t)t.v * 3 * P + 2 * P + pix] = __builtin_fmaf(pw.Tr, cam.bg[2], pw.c2);
+    depth[(int64_t)t.v * P + pix] = pw.dd;
+    Tfin[(int64_t)t.v * P + pix] = pw.Tr;
+    last[(int64_t)t.v * P + pix] = pw.lst;
+    if (ncon) ncon[(int64_t)t.v * P + pix] = pw.nc;
 }
 
 // ---- wave64 inclusive scans over lane order ---------------------------------------------------
@@ -297,7 +487,8 @@ __device__ __forceinline__ float rdl(float v, int lane) {
 // accumulate in LDS across waves (ds_add_f32 per staged slot) and leave as one plain 40-byte
 // record per instance, stored at the instance's emission index: the records of one (view,
 // Gaussian) pair are contiguous there, and the projection backward sums them in a fixed order,
-// so no global atomics are needed and the gradients are the same on every run.
+// so no global atomics are needed.  The four waves' adds to one slot come in a run-dependent
+// order, so gradients repeat from run to run only up to float rounding.
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
@@ -631,16 +822,88 @@ __global__ __launch_bounds__(256) void k_render_bwd_stored(const gsr_splat *__re
 
 using namespace gsr;
 
+extern "C" size_t gsr_scan_ws_bytes(int64_t n);
+extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
+
+namespace {
+
+struct SliceWs {
+    uint32_t *tile_slices, *off, *count;
+    void *scan;
+    uint2 *info;
+    float *tprod;
+    float4 *part;
+    uint2 *part2;
+    uint32_t cap;
+    size_t bytes;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Every sliced tile holds more than kSliceLen instances and ceil(len / kSliceLen) < 2 len /
+// kSliceLen slices, so 2 capacity / kSliceLen + 1 slices always fit.
+SliceWs slice_layout(void *base, int64_t VT, int64_t capacity) {
+    SliceWs w{};
+    const int64_t cap = 2 * (capacity > 0 ? capacity : 1) / kSliceLen + 1;
+    w.cap = (uint32_t)(cap < 0x7fffffff ? cap : 0x7fffffff);
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void *r = p ? p + off : nullptr;
+        off += al256(bytes);
+        return r;
+    };
+    w.tile_slices = static_cast<uint32_t *>(take((size_t)VT * 4));
+    w.off = static_cast<uint32_t *>(take((size_t)VT * 4));
+    w.count = static_cast<uint32_t *>(take(4));
+    w.scan = take(gsr_scan_ws_bytes(VT));
+    w.info = static_cast<uint2 *>(take((size_t)w.cap * sizeof(uint2)));
+    w.tprod = static_cast<float *>(take((size_t)w.cap * 256 * sizeof(float)));
+    w.part = static_cast<float4 *>(take((size_t)w.cap * 256 * sizeof(float4)));
+    w.part2 = static_cast<uint2 *>(take((size_t)w.cap * 256 * sizeof(uint2)));
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+
+extern "C" size_t gsr_render_fwd_ws_bytes(int V, const gsr_raster *r, int64_t capacity) {
+    const int64_t T = ceil_div(r->width, r->tile_w) * ceil_div(r->height, r->tile_h);
+    return slice_layout(nullptr, (int64_t)V * T, capacity).bytes;
+}
+
+// ws == NULL: every tile is composited whole (and n_contrib may be asked for); otherwise the
+// tiles longer than kSliceLen are composited in depth slices (ncon must then be NULL).
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *splats, const uint32_t *inst, const uint32_t *ranges,
                                             const uint32_t *order, const gsr_camera *cams, int V,
                                             const gsr_raster *r, float *rgb, float *depth, float *Tfin,
-                                            uint32_t *last, uint32_t *ncon, hipStream_t st) {
+                                            uint32_t *last, uint32_t *ncon, int64_t capacity, void *ws,
+                                            hipStream_t st) {
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     const int T = ntx * nty;
     const int nb = V * T;
-#define GSR_RF(TW, TH)                                                                                          \
-    k_render_fwd<TW, TH, false><<<nb, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, r->height, ntx, T, \
-                                                    rgb, depth, Tfin, last, ncon, nullptr, nullptr, 0u)
+    SliceArgs sl{};
+    if (ws) {
+        const SliceWs w = slice_layout(ws, nb, capacity);
+        const int g = (int)(ceil_div(nb, 256) < 1024 ? ceil_div(nb, 256) : 1024);
+        k_slice_count<<<g, 256, 0, st>>>(ranges, (uint32_t)nb, w.tile_slices);
+        gsr_status s = gsr_scan_launch(w.tile_slices, nb, w.off, w.count, w.scan, st);
+        if (s != GSR_OK) return s;
+        k_slice_emit<<<g, 256, 0, st>>>(w.tile_slices, w.off, (uint32_t)nb, w.cap, w.info);
+        sl = SliceArgs{w.tile_slices, w.info, w.count, w.tprod, w.part, w.part2, w.cap,
+                       w.cap < 2048u ? w.cap : 2048u};
+    }
+#define GSR_RF(TW, TH)                                                                                            \
+    do {                                                                                                          \
+        if (sl.grid)                                                                                              \
+            k_slice_prod<TW, TH><<<sl.grid, 256, 0, st>>>(splats, inst, ranges, r->width, r->height, ntx, T, sl); \
+        k_render_fwd<TW, TH, false><<<nb + sl.grid, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width,     \
+                                                                  r->height, ntx, T, rgb, depth, Tfin, last, ncon, \
+                                                                  nullptr, nullptr, 0u, sl);                       \
+        if (sl.grid)                                                                                              \
+            k_slice_merge<TW, TH><<<sl.grid, 256, 0, st>>>(ranges, cams, r->width, r->height, ntx, T, sl, rgb,    \
+                                                           depth, Tfin, last);                                    \
+    } while (0)
     if (r->tile_w == 16) GSR_RF(16, 16);
     else if (r->tile_w == 8) GSR_RF(8, 32);
     else GSR_RF(32, 8);
@@ -658,7 +921,8 @@ extern "C" gsr_status gsr_render_store_launch(const gsr_splat *splats, const uin
     const int nb = V * T;
 #define GSR_RS(TW, TH)                                                                                        \
     k_render_fwd<TW, TH, true><<<nb, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, r->height, ntx, T, \
-                                                   nullptr, nullptr, nullptr, nullptr, nullptr, coff, clist, ccap)
+                                                   nullptr, nullptr, nullptr, nullptr, nullptr, coff, clist, ccap, \
+                                                   SliceArgs{})
     if (r->tile_w == 16) GSR_RS(16, 16);
     else if (r->tile_w == 8) GSR_RS(8, 32);
     else GSR_RS(32, 8);

@@ -150,7 +150,7 @@ class MapOptimizer:
 
         def fwd():
             render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth,
-                       r.T_final, r.last, tile_order=r.tile_order)
+                       r.T_final, r.last, tile_order=r.tile_order, ws=r.fwd_ws, capacity=r.capacity)
 
         def loss_stage():
             self.loss.zero_()

@@ -34,15 +34,16 @@ def grad_close(g, o, rtol=GRAD_RTOL, mask=None):
     return bad
 
 
-def run_forward(g, cams, tile=(16, 16), capacity=None, mode="recompute"):
-    """HIP forward of all cams (same size).  Returns dict of numpy outputs and the state."""
+def run_forward(g, cams, tile=(16, 16), capacity=None, mode="recompute", sliced=True):
+    """HIP forward of all cams (same size).  Returns dict of numpy outputs and the state.
+    sliced=False: every tile composited whole."""
     W, H = cams[0]["width"], cams[0]["height"]
     raster = gsr.Raster(W, H, *tile)
     P = gsr.gaussians_to_device(g)
     n = P["means"].shape[1]
     ct = gsr.camera_tensor(cams)
     rast = gsr.Rasterizer(n, len(cams), raster, capacity=capacity, mode=mode)
-    rgb, depth, Tf = rast.forward(P, g["sh_degree"], ct)
+    rgb, depth, Tf = rast.forward(P, g["sh_degree"], ct, sliced=sliced)
     torch.cuda.synchronize()
     out = dict(rgb=rgb.cpu().numpy().astype(np.float64), depth=depth.cpu().numpy().astype(np.float64),
                T=Tf.cpu().numpy().astype(np.float64), last=rast.last.cpu().numpy(), M=rast.instances())
@@ -91,6 +92,24 @@ def expected_instances(ti, n, V, raster, with_emission=False):
     first = dict(zip(porder.tolist(), (np.cumsum(cnt) - cnt).tolist()))
     emit = np.array([first[g] for g in gids.tolist()], np.int64) + local
     return keys[order], gids[order], emit[order], first
+
+
+def long_tile_scene(seed=11, W=64, H=64, f=60.0):
+    """A vanishing-point pile-up on a 64x64 image: 20,000 small, faint Gaussians at depths 2-8 m
+    crowd the four central 16x16 tiles (lists of about 4,800 instances, so the forward cuts them
+    into depth slices of 2048), and 600 nearly opaque ones at 4.5-5.5 m, about the 2048th list
+    position, on which a few hundred central pixels terminate."""
+    import synth
+    faint = synth.random_gaussians(seed, 20_000, 1, xy_half=1.0, z_range=(2.0, 8.0), log_scale_mean=-2.3,
+                                   log_scale_std=0.4)
+    faint["opacity_logits"] = (faint["opacity_logits"] - 5.0).astype(np.float32)
+    solid = synth.random_gaussians(seed + 1, 600, 1, xy_half=0.6, z_range=(4.5, 5.5), log_scale_mean=-2.8,
+                                   log_scale_std=0.3)
+    solid["opacity_logits"] = (solid["opacity_logits"] + 3.0).astype(np.float32)
+    g = {k: np.concatenate([faint[k], solid[k]], axis=-1) if isinstance(faint[k], np.ndarray) else faint[k]
+         for k in faint}
+    cam = synth.make_camera(np.eye(3), np.zeros(3), f, f, W / 2.0, H / 2.0, W, H)
+    return g, cam
 
 
 def random_scene(seed, n, W, H, f, sh_degree=0, z_range=(1.5, 6.0), log_scale_mean=-2.5, xy_half=1.5, logit_shift=0.0):

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared():
         assert hasattr(lib, name), name
     assert set(declared()) == set(_abi.EXPORTS)
-    assert lib.gsr_abi_version() == 3
+    assert lib.gsr_abi_version() == 4
 
 
 def test_invalid_arguments_are_rejected_before_launch():
@@ -67,3 +67,9 @@ def test_new_entry_points_reject_invalid_arguments():
     assert L.gsr_transform_cameras(None, 2, None, P, None) == 1
     assert L.gsr_voxel_pca_cov(P, None, 10, 0, None, None, P, 1 << 30, None) == 1  # no point covariances
     assert L.gsr_loss_workspace(0, c.byref(r)) == 0
+    # depth-sliced forward: workspace grows with the instance capacity; missing ws or a short one fails
+    small, big = L.gsr_render_fwd_sliced_workspace(1, c.byref(r), 1 << 16), L.gsr_render_fwd_sliced_workspace(
+        1, c.byref(r), 1 << 24)
+    assert 0 < small < big and L.gsr_render_fwd_sliced_workspace(1, c.byref(r), -1) == 0
+    assert L.gsr_render_fwd_sliced(P, P, P, None, P, 1, c.byref(r), P, P, P, P, 1 << 16, None, small, None) == 1
+    assert L.gsr_render_fwd_sliced(P, P, P, None, P, 1, c.byref(r), P, P, P, P, 1 << 16, P, small - 1, None) == 2

@@ -161,9 +161,10 @@ def test_render_forward_matches_oracle(name):
 @pytest.mark.parametrize("name", list(SCENES))
 def test_render_tile_shape_invariance(name):
     g, cams = SCENES[name]
-    a, *_ = run_forward(g, cams, tile=(16, 16))
+    # whole tiles (the depth slices of long tiles are tile-shape dependent)
+    a, *_ = run_forward(g, cams, tile=(16, 16), sliced=False)
     for tile in ((8, 32), (32, 8)):
-        b, *_ = run_forward(g, cams, tile=tile)
+        b, *_ = run_forward(g, cams, tile=tile, sliced=False)
         assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["depth"], b["depth"])
         assert np.array_equal(a["T"], b["T"])
 

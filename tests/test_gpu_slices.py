@@ -1,0 +1,85 @@
+"""Depth slices of long tiles (gsr_render_fwd_sliced): the front-to-back recurrence of Eq. 8
+regrouped by the associativity of the transmittance product, checked against the FP64 oracle
+and against the whole-tile forward on a vanishing-point pile-up whose central tiles hold about
+4,800 instances (three slices of 2048), with terminations on both sides of the first slice
+boundary.  Tolerances and knife-edge exclusion as in the other parity tests."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+from gpu_common import GRAD_RTOL, KNIFE, grad_close, img_close, long_tile_scene, run_forward
+
+pytestmark = pytest.mark.gpu
+
+SLICE = 2048
+G, CAM = long_tile_scene()
+_CACHE = {}
+
+
+def _oracle():
+    if "o" not in _CACHE:
+        _CACHE["o"] = oracle.render(G, CAM)
+    return _CACHE["o"]
+
+
+def _lengths(rast):
+    rg = rast.tile_ranges.cpu().numpy().view(np.uint32).astype(np.int64).reshape(-1, 2)
+    return rg[:, 1] - rg[:, 0]
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 32)])
+def test_sliced_forward_matches_oracle(tile):
+    out, rast, P, ct = run_forward(G, [CAM], tile=tile)
+    ln = _lengths(rast)
+    assert ln.max() > 2 * SLICE and (ln > SLICE).sum() >= 2  # the path under test is taken
+    o = _oracle()
+    ok = o["margin"] >= KNIFE
+    assert (~ok).sum() <= 0.01 * ok.size
+    m3 = np.broadcast_to(ok, o["rgb"].shape)
+    assert img_close(out["rgb"][0], o["rgb"], mask=m3).sum() == 0
+    assert img_close(out["depth"][0], o["depth"], mask=ok).sum() == 0
+    assert img_close(1 - out["T"][0], o["alpha"], mask=ok).sum() == 0
+    # walks that end in a later slice, terminated or not
+    assert (out["last"][0] > SLICE).sum() > 100
+    assert ((out["last"][0] > SLICE) & (out["T"][0] < 1e-3)).sum() > 10
+
+
+def test_sliced_forward_matches_whole_tiles():
+    a, ra, *_ = run_forward(G, [CAM], sliced=False)
+    b, rb, *_ = run_forward(G, [CAM], sliced=True)
+    ok = _oracle()["margin"] >= KNIFE
+    assert img_close(b["rgb"][0], a["rgb"][0], mask=np.broadcast_to(ok, a["rgb"][0].shape)).sum() == 0
+    assert img_close(b["depth"][0], a["depth"][0], mask=ok).sum() == 0
+    assert img_close(b["T"][0], a["T"][0], mask=ok).sum() == 0
+    assert np.array_equal(b["last"][0][ok], a["last"][0][ok])
+    # tiles of at most 2048 instances are composited by the same code from the same start
+    ln = _lengths(rb)
+    short = np.zeros(ok.shape, bool)
+    T = rb.raster.tiles
+    for t in np.nonzero(ln[:T] <= SLICE)[0]:
+        ty, tx = divmod(int(t), rb.raster.ntx)
+        short[ty * rb.raster.tile_h:(ty + 1) * rb.raster.tile_h, tx * rb.raster.tile_w:(tx + 1) * rb.raster.tile_w] = True
+    assert short.any() and (~short).any()
+    assert np.array_equal(b["rgb"][0][:, short], a["rgb"][0][:, short])
+    assert np.array_equal(b["T"][0][short], a["T"][0][short])
+
+
+def test_backward_after_sliced_forward_matches_oracle():
+    import paper_2604_12942_amd as gsr
+    out, rast, P, ct = run_forward(G, [CAM])
+    rng = np.random.default_rng(5)
+    H, W = CAM["height"], CAM["width"]
+    GC = rng.standard_normal((3, H, W)).astype(np.float32)
+    GD = rng.standard_normal((H, W)).astype(np.float32)
+    o = oracle.render_bwd(G, CAM, GC.astype(np.float64), GD.astype(np.float64), want_pose=False)
+    grads = {k: torch.zeros_like(P[k]) for k in gsr.PARAM_NAMES}
+    rast.backward(P, G["sh_degree"], ct, torch.from_numpy(GC[None]).cuda(), torch.from_numpy(GD[None]).cuda(), grads)
+    torch.cuda.synchronize()
+    keep = ~o["knife_g"]
+    assert keep.mean() > 0.85  # faint Gaussians near the 1/255 cut-off make many knife-edge candidates
+    for k in gsr.PARAM_NAMES:
+        gk = grads[k].cpu().numpy().astype(np.float64)
+        bad = grad_close(gk, o[k], mask=keep)
+        assert bad.sum() == 0, (k, bad.sum())

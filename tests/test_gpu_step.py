@@ -41,11 +41,12 @@ def test_fused_step_equals_separate_step():
             o.set_views([0, 1, 2] if step % 2 == 0 else [2, 0, 1])
             o.step()
     torch.cuda.synchronize()
-    # the two paths compute the same gradients; the update is compared to rounding, the moments
-    # relative to their rms
+    # the two paths compute the same gradients (each from its own render backward, whose LDS
+    # adds come in run-dependent order); the update is compared to rounding raised by Adam's
+    # normalisation, the moments relative to their rms
     for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         pa, pb = a.P[k].cpu().numpy(), b.P[k].cpu().numpy()
-        assert np.allclose(pa, pb, rtol=2e-6, atol=1e-7), k
+        assert np.allclose(pa, pb, rtol=2e-6, atol=1e-6), k
         ma, mb = a.m[k].cpu().numpy().astype(np.float64), b.m[k].cpu().numpy().astype(np.float64)
         rms = np.sqrt(np.mean(mb ** 2))
         assert np.all(np.abs(ma - mb) <= 1e-4 * (np.abs(mb) + rms)), k
@@ -92,7 +93,10 @@ def test_graph_replay_matches_eager_step(full):
         junk = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
         assert np.isfinite(junk)
         assert abs(la - lb) <= 1e-6 * abs(la), (k, la, lb)
+        # the render backward's four waves add to a Gaussian's LDS accumulators in run-dependent
+        # order, so two runs of the same step agree to float rounding, which Adam's
+        # normalisation raises to a few 1e-7 on parameters whose gradient nearly cancels
         for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
             pa, pb = a.P[name].cpu().numpy(), b.P[name].cpu().numpy()
-            assert np.allclose(pa, pb, rtol=2e-6, atol=1e-7), (k, name)
+            assert np.allclose(pa, pb, rtol=2e-6, atol=1e-6), (k, name)
     assert int(b.step_dev.item()) == len(views)
