@@ -205,10 +205,10 @@ __device__ __forceinline__ void write_null_slot(float4 *sA, float4 *sB, float4 *
 }
 
 // ---- depth slices of long tiles ------------------------------------------------------------------
-// A tile whose list holds more than kSliceLen instances would keep one workgroup busy long after
-// the rest of the launch has drained (a view down a corridor piles tens of thousands of distant
-// Gaussians into the tile at the vanishing point).  Such a tile is cut into slices of kSliceLen
-// consecutive instances.  Compositing is associative in the transmittance: the walk through
+// A tile whose list holds tens of thousands of instances would keep one workgroup busy long after
+// the rest of the launch has drained (a view down a corridor piles them into the tile at the
+// vanishing point).  A tile longer than kSplitMin is cut into slices of kSliceLen consecutive
+// instances.  Compositing is associative in the transmittance: the walk through
 // slice k starts from T_in(k), the product over the earlier slices of their own (1 - a)
 // products, and the pixel has terminated before slice k exactly when T_in(k) < 1e-4 (T never
 // increases).  So one pass computes every slice's product (a pixel whose product falls below
@@ -217,6 +217,7 @@ __device__ __forceinline__ void write_null_slot(float4 *sA, float4 *sB, float4 *
 // The results are those of the whole-tile walk up to the float rounding of the transmittance
 // products (which are associated per slice).
 constexpr uint32_t kSliceLen = 2048;
+constexpr uint32_t kSplitMin = 4 * kSliceLen;  // shorter tiles finish within the launch anyway
 constexpr uint32_t kNoSlice = 0xffffffffu;  // list entry of a slice that did not fit
 
 struct SliceArgs {
@@ -233,12 +234,12 @@ struct SliceArgs {
 __global__ void k_slice_count(const uint32_t *__restrict__ ranges, uint32_t VT, uint32_t *__restrict__ ns) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT; i += gridDim.x * blockDim.x) {
         const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
-        ns[i] = len > kSliceLen ? (len + kSliceLen - 1) / kSliceLen : 0u;
+        ns[i] = len > kSplitMin ? (len + kSliceLen - 1) / kSliceLen : 0u;
     }
 }
 
 // Lists the slices tile by tile.  A tile whose slices would not fit the capacity (impossible
-// while the lists hold at most `cap` * kSliceLen / 2 instances) is left whole.
+// while the lists hold at most the capacity the slice list was sized for) is left whole.
 __global__ void k_slice_emit(uint32_t *__restrict__ ns, const uint32_t *__restrict__ off, uint32_t VT,
                              uint32_t cap, uint2 *__restrict__ info) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT; i += gridDim.x * blockDim.x) {
@@ -840,11 +841,11 @@ struct SliceWs {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Every sliced tile holds more than kSliceLen instances and ceil(len / kSliceLen) < 2 len /
-// kSliceLen slices, so 2 capacity / kSliceLen + 1 slices always fit.
+// Every sliced tile holds len > kSplitMin = 4 kSliceLen instances, so its ceil(len / kSliceLen)
+// slices number less than 1.25 len / kSliceLen: 1.25 capacity / kSliceLen + 1 always fit.
 SliceWs slice_layout(void *base, int64_t VT, int64_t capacity) {
     SliceWs w{};
-    const int64_t cap = 2 * (capacity > 0 ? capacity : 1) / kSliceLen + 1;
+    const int64_t cap = 5 * (capacity > 0 ? capacity : 1) / (4 * (int64_t)kSliceLen) + 1;
     w.cap = (uint32_t)(cap < 0x7fffffff ? cap : 0x7fffffff);
     char *p = static_cast<char *>(base);
     size_t off = 0;

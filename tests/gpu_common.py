@@ -95,12 +95,12 @@ def expected_instances(ti, n, V, raster, with_emission=False):
 
 
 def long_tile_scene(seed=11, W=64, H=64, f=60.0):
-    """A vanishing-point pile-up on a 64x64 image: 20,000 small, faint Gaussians at depths 2-8 m
-    crowd the four central 16x16 tiles (lists of about 4,800 instances, so the forward cuts them
-    into depth slices of 2048), and 600 nearly opaque ones at 4.5-5.5 m, about the 2048th list
+    """A vanishing-point pile-up on a 64x64 image: 48,000 small, faint Gaussians at depths 2-8 m
+    crowd the four central 16x16 tiles (lists of about 11,000 instances, so the forward cuts them
+    into depth slices of 2048), and 600 nearly opaque ones at 4.5-5.5 m, past the 4,000th list
     position, on which a few hundred central pixels terminate."""
     import synth
-    faint = synth.random_gaussians(seed, 20_000, 1, xy_half=1.0, z_range=(2.0, 8.0), log_scale_mean=-2.3,
+    faint = synth.random_gaussians(seed, 48_000, 1, xy_half=1.0, z_range=(2.0, 8.0), log_scale_mean=-2.3,
                                    log_scale_std=0.4)
     faint["opacity_logits"] = (faint["opacity_logits"] - 5.0).astype(np.float32)
     solid = synth.random_gaussians(seed + 1, 600, 1, xy_half=0.6, z_range=(4.5, 5.5), log_scale_mean=-2.8,
