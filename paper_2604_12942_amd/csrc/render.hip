@@ -9,6 +9,8 @@
 // sub-rectangle (exact minimum of the quadratic form over the rectangle) and walks only the
 // Gaussians that reach it.  The blend exponent is the whitened form |L^T D|^2 (L the Cholesky
 // factor of (log2(e)/2) Q): no cancellation for thin ellipses; exp2 is the hardware v_exp_f32.
+#include <type_traits>
+
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -471,6 +473,94 @@ __device__ __forceinline__ void wave_incl_sum2(float &a, float &b, float ka, flo
         : "+v"(a), "+v"(b)
         : "v"(ka), "v"(kb));
 }
+// The same two scans over independent groups of 32 lanes (rows 0-1 and rows 2-3: the lane-15
+// broadcast is the last step) or of 16 lanes (each row on its own: the row shifts alone).
+__device__ __forceinline__ void half_incl_prod2(float &a, float &b, float ka, float kb) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf"
+        : "+v"(a), "+v"(b)
+        : "v"(ka), "v"(kb));
+}
+__device__ __forceinline__ void half_incl_sum2(float &a, float &b, float ka, float kb) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf"
+        : "+v"(a), "+v"(b)
+        : "v"(ka), "v"(kb));
+}
+__device__ __forceinline__ void row_incl_prod2(float &a, float &b, float ka, float kb) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mul_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf"
+        : "+v"(a), "+v"(b)
+        : "v"(ka), "v"(kb));
+}
+__device__ __forceinline__ void row_incl_sum2(float &a, float &b, float ka, float kb) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf"
+        : "+v"(a), "+v"(b)
+        : "v"(ka), "v"(kb));
+}
+template <int GL>
+__device__ __forceinline__ void group_incl_prod2(float &a, float &b, float ka, float kb) {
+    if constexpr (GL == 64) wave_incl_prod2(a, b, ka, kb);
+    else if constexpr (GL == 32) half_incl_prod2(a, b, ka, kb);
+    else row_incl_prod2(a, b, ka, kb);
+}
+template <int GL>
+__device__ __forceinline__ void group_incl_sum2(float &a, float &b, float ka, float kb) {
+    if constexpr (GL == 64) wave_incl_sum2(a, b, ka, kb);
+    else if constexpr (GL == 32) half_incl_sum2(a, b, ka, kb);
+    else row_incl_sum2(a, b, ka, kb);
+}
 __device__ __forceinline__ float rdl(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -479,11 +569,11 @@ __device__ __forceinline__ float rdl(float v, int lane) {
 // staged back to front in batches of 256.  Each wave compacts the batch to the Gaussians that
 // reach its pixel sub-rectangle and cuts them, deepest first, into chunks of 64: lane l holds the
 // l-th deepest.  For each of the wave's 64 pixels every lane evaluates its Gaussian; a wave-wide
-// inclusive product scan of (1 - a) recovers the transmittance in front of each Gaussian from the
-// pixel's transmittance behind the chunk, and an inclusive sum scan of w (dL/dC . c + dL/dD z)
+// inclusive product scan of 1 / (1 - a) recovers the transmittance in front of each Gaussian from
+// the pixel's transmittance behind the chunk, and an inclusive sum scan of w (dL/dC . c + dL/dD z)
 // gives what lies behind it.  Pixel state (upstream gradient, transmittance and suffix behind
-// the chunks done so far) sits in LDS and is read by broadcast; the pixel centre by readlane.  Per lane, the mean and
-// conic gradients accumulate as the five moments sum dP (dx, dy, dx^2, dx dy, dy^2) of the
+// the chunks done so far) sits in LDS and is read by broadcast; the pixel centre by readlane.
+// Per lane, the mean and conic gradients accumulate as the five moments sum dP (dx, dy, dx^2, dx dy, dy^2) of the
 // exponent gradient dP, mapped through the Cholesky factor once per chunk.  Gradients then
 // accumulate in LDS across waves (ds_add_f32 per staged slot) and leave as one plain 40-byte
 // record per instance, stored at the instance's emission index: the records of one (view,
@@ -491,7 +581,7 @@ __device__ __forceinline__ float rdl(float v, int lane) {
 // so no global atomics are needed.  The four waves' adds to one slot come in a run-dependent
 // order, so gradients repeat from run to run only up to float rounding.
 template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict__ splats,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
                                                     const uint32_t *__restrict__ inst_emit,
                                                     const uint32_t *__restrict__ ranges,
@@ -507,6 +597,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     __shared__ uint8_t sList[4][256];
     __shared__ float4 sPG[4][64];  // dL/dC (3), dL/dD
     __shared__ float2 sPS[4][64];  // transmittance and suffix sum behind the chunks done so far
+    __shared__ uint32_t sPL[4][64];  // last composited position of each pixel
     __shared__ uint32_t s_max;
     const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
     const int v = item / T, tile = item % T;
@@ -523,6 +614,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
     float wx0, wx1, wy0, wy1;
     wave_box<TW>(tx * TW - bx, ty * TH - by, w, wx0, wx1, wy0, wy1);
     const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;  // pixel centre
+    // centre of the wave's first pixel (the wave's 64 pixels are TW-wide rows)
+    static_assert(TW % 8 == 0, "packed chunks assume 8 | TW");
+    const float fxw = (float)(tx * TW - bx) + 0.5f, fyw = (float)(ty * TH - by + w * (64 / TW)) + 0.5f;
     uint32_t mylast = 0;
     {
         float Tr = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f;
@@ -539,6 +633,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
         const float S = Tr * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
         sPG[w][lane] = make_float4(G0, G1, G2, GD);
         sPS[w][lane] = make_float2(Tr, S);
+        sPL[w][lane] = mylast;
         if (threadIdx.x == 0) s_max = 0;
     }
     for (int q = threadIdx.x; q < 2560; q += 256) (&sAcc[0][0])[q] = 0.f;
@@ -586,31 +681,63 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
             nw += __popcll(m);
         }
         __builtin_amdgcn_wave_barrier();  // the wave reads back what its lanes just wrote
-        for (int c0 = 0; c0 < nw; c0 += 64) {
-            const int idx = c0 + lane;
-            const bool gvalid = idx < nw;
-            const int slot = gvalid ? sList[w][idx] : 0;
+        // One chunk of the compacted list, c0 onwards: lane l holds the chunk's (l % GL)-th
+        // deepest Gaussian for pixel group l / GL.  A full chunk runs as one group (GL = 64);
+        // when at most 32 or 16 Gaussians remain, 2 or 4 groups of lanes work on different
+        // pixels of the same Gaussians at once, and their sums meet before the LDS adds.
+        auto chunk = [&](auto glc, int c0) {
+            constexpr int GL = decltype(glc)::value;
+            constexpr int NG = 64 / GL;
+            const int gl = lane % GL, grp = lane / GL;
+            const int rem = nw - c0;
+            const bool gvalid = gl < rem;
+            const int slot = gvalid ? sList[w][c0 + gl] : 0;
             const float4 A = gvalid ? sA[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
             const float4 B = gvalid ? sB[slot] : make_float4(0.f, -1.f, 0.f, 0.f);
             const float4 C = gvalid ? sC[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
             const uint32_t pos = (uint32_t)(b0 + slot);
             const uint32_t posv = gvalid ? pos : 0xffffffffu;  // never below a last contributor
-            // frontmost position of the chunk: the last valid lane
-            const int lastlane = (nw - c0 < 64 ? nw - c0 : 64) - 1;
+            // frontmost position of the chunk: the last valid lane of the first group
+            const int lastlane = (rem < GL ? rem : GL) - 1;
             const uint32_t cfront = (uint32_t)__builtin_amdgcn_readlane((int)pos, lastlane);
             float cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, go = 0.f;
             float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f;
-            // two pixels per iteration: their chains are independent, which keeps the SIMD busy
-            // through the scan and transcendental latencies
-            for (int p = 0; p < 64; p += 2) {
-                const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
-                const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p + 1);
-                if (cfront >= l0 && cfront >= l1) continue;
-                const float4 pg0 = sPG[w][p], pg1 = sPG[w][p + 1];  // LDS broadcasts
-                const float4 ps = *reinterpret_cast<const float4 *>(&sPS[w][p]);
+            // two pixels per group and iteration: their chains are independent, which keeps the
+            // SIMD busy through the scan and transcendental latencies
+            for (int p = 0; p < 64; p += 2 * NG) {
+                int q0 = p, q1 = p + 1;
+                uint32_t l0, l1;
+                float4 pg0, pg1;
+                float T0, S0, T1, S1, fx0, fy0, fx1, fy1;
+                if constexpr (NG == 1) {
+                    l0 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
+                    l1 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p + 1);
+                    if (cfront >= l0 && cfront >= l1) continue;
+                    pg0 = sPG[w][p];  // LDS broadcasts
+                    pg1 = sPG[w][p + 1];
+                    const float4 ps = *reinterpret_cast<const float4 *>(&sPS[w][p]);
+                    T0 = ps.x, S0 = ps.y, T1 = ps.z, S1 = ps.w;
+                    fx0 = rdl(fx, p), fy0 = rdl(fy, p), fx1 = rdl(fx, p + 1), fy1 = rdl(fy, p + 1);
+                } else {
+                    q0 = p + grp;
+                    q1 = p + NG + grp;
+                    l0 = sPL[w][q0];
+                    l1 = sPL[w][q1];
+                    if (__ballot(cfront < l0 || cfront < l1) == 0) continue;
+                    pg0 = sPG[w][q0];
+                    pg1 = sPG[w][q1];
+                    const float2 s0 = sPS[w][q0], s1 = sPS[w][q1];
+                    T0 = s0.x, S0 = s0.y, T1 = s1.x, S1 = s1.y;
+                    // the wave's pixels lie row-major in a TW-wide box and 2 NG divides TW, so
+                    // q0 and q1 sit in the row of p, at columns p % TW + grp and + NG
+                    const float fxp = fxw + (float)(p % TW);
+                    fx0 = fxp + (float)grp;
+                    fx1 = fxp + (float)(NG + grp);
+                    fy0 = fy1 = fyw + (float)(p / TW);
+                }
                 float dx0, dy0, dx1, dy1, t0, t1;
-                const float P0 = blend_exponent(A, B.x, rdl(fx, p), rdl(fy, p), dx0, dy0, t0, t1);
-                const float P1 = blend_exponent(A, B.x, rdl(fx, p + 1), rdl(fy, p + 1), dx1, dy1, t0, t1);
+                const float P0 = blend_exponent(A, B.x, fx0, fy0, dx0, dy0, t0, t1);
+                const float P1 = blend_exponent(A, B.x, fx1, fy1, dx1, dy1, t0, t1);
                 const bool act0 = posv < l0 && P0 <= B.y;
                 const bool act1 = posv < l1 && P1 <= B.y;
                 if (__ballot(act0 || act1) == 0) continue;  // no Gaussian of the chunk reaches them
@@ -619,22 +746,24 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                 const float ar0 = B.z * e0, ar1 = B.z * e1;
                 const float a0 = fminf(ar0, GSR_ALPHA_MAX), a1 = fminf(ar1, GSR_ALPHA_MAX);
                 const float om0 = 1.0f - a0, om1 = 1.0f - a1;
-                // the scans overwrite their operands in place, so what is needed of (1 - a) and
-                // of w g afterwards is taken before them
+                // the scans overwrite their operands in place, so they run on copies of what is
+                // needed afterwards: here the product of 1 / (1 - a) over the chunk's Gaussians
+                // up to each one (deepest first), which spares dividing by the product of (1 - a)
                 const float rom0 = __builtin_amdgcn_rcpf(om0), rom1 = __builtin_amdgcn_rcpf(om1);
-                float Pt0 = om0, Pt1 = om1;
-                wave_incl_prod2(Pt0, Pt1, rom0, rom1);
-                // transmittance in front of each Gaussian
-                const float Tb0 = ps.x * __builtin_amdgcn_rcpf(Pt0);
-                const float Tb1 = ps.z * __builtin_amdgcn_rcpf(Pt1);
+                float R0 = rom0, R1 = rom1;
+                group_incl_prod2<GL>(R0, R1, rom0, rom1);
+                // transmittance in front of each Gaussian: T behind the chunk times that product
+                // (at most 1e4, since T behind is at least T_final >= 1e-4)
+                const float Tb0 = T0 * R0;
+                const float Tb1 = T1 * R1;
                 const float w0 = a0 * Tb0, w1 = a1 * Tb1;
                 const float gs0 =
                     __builtin_fmaf(pg0.x, C.x, __builtin_fmaf(pg0.y, C.y, __builtin_fmaf(pg0.z, C.z, pg0.w * B.w)));
                 const float gs1 =
                     __builtin_fmaf(pg1.x, C.x, __builtin_fmaf(pg1.y, C.y, __builtin_fmaf(pg1.z, C.z, pg1.w * B.w)));
                 float in0 = w0 * gs0, in1 = w1 * gs1;
-                const float sb0 = ps.y - in0, sb1 = ps.w - in1;
-                wave_incl_sum2(in0, in1, sb0, sb1);
+                const float sb0 = S0 - in0, sb1 = S1 - in1;
+                group_incl_sum2<GL>(in0, in1, sb0, sb1);
                 // everything behind each Gaussian
                 const float Sa0 = sb0 + in0, Sa1 = sb1 + in1;
                 const float d0 = __builtin_fmaf(Tb0, gs0, -Sa0 * rom0);
@@ -651,15 +780,33 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                 go = __builtin_fmaf(lin0 ? d0 : 0.f, e0, __builtin_fmaf(lin1 ? d1 : 0.f, e1, go));
                 mx = __builtin_fmaf(dP0, dx0, __builtin_fmaf(dP1, dx1, mx));
                 my = __builtin_fmaf(dP0, dy0, __builtin_fmaf(dP1, dy1, my));
-                const float q0 = dP0 * dx0, q1 = dP1 * dx1;
-                mxx = __builtin_fmaf(q0, dx0, __builtin_fmaf(q1, dx1, mxx));
-                mxy = __builtin_fmaf(q0, dy0, __builtin_fmaf(q1, dy1, mxy));
+                const float qq0 = dP0 * dx0, qq1 = dP1 * dx1;
+                mxx = __builtin_fmaf(qq0, dx0, __builtin_fmaf(qq1, dx1, mxx));
+                mxy = __builtin_fmaf(qq0, dy0, __builtin_fmaf(qq1, dy1, mxy));
                 myy = __builtin_fmaf(dP0 * dy0, dy0, __builtin_fmaf(dP1 * dy1, dy1, myy));
-                // the pixels' state in front of this chunk (inactive lanes carry a = 0)
-                if (lane == 63)
-                    *reinterpret_cast<float4 *>(&sPS[w][p]) = make_float4(Tb0, ps.y + in0, Tb1, ps.w + in1);
+                // the pixels' state in front of this chunk, kept by each group's frontmost lane
+                // (inactive lanes carry a = 0)
+                if (gl == GL - 1) {
+                    if constexpr (NG == 1) {
+                        *reinterpret_cast<float4 *>(&sPS[w][p]) = make_float4(Tb0, S0 + in0, Tb1, S1 + in1);
+                    } else {
+                        sPS[w][q0] = make_float2(Tb0, S0 + in0);
+                        sPS[w][q1] = make_float2(Tb1, S1 + in1);
+                    }
+                }
             }
-            if (gvalid) {
+            if constexpr (NG > 1) {
+                // the groups' sums for one Gaussian meet in the first group
+                float *const sums[10] = {&cr, &cg, &cb, &cd, &go, &mx, &my, &mxx, &mxy, &myy};
+#pragma unroll
+                for (int e = 0; e < 10; e++) {
+                    float x = *sums[e];
+#pragma unroll
+                    for (int off = GL; off < 64; off <<= 1) x += __shfl_xor(x, off);
+                    *sums[e] = x;
+                }
+            }
+            if (gvalid && grp == 0) {
                 // P = |L^T D|^2 with D = pixel - mean: dP/dmean = -2 L L^T D, dP/dQ = kappa D D^T
                 const float l11 = A.z, l21 = A.w, l22 = B.x;
                 const float m1 = __builtin_fmaf(l11, mx, l21 * my);
@@ -678,6 +825,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(const gsr_splat *__restrict_
                 for (int e = 0; e < 10; e++)
                     if (acc[e] != 0.f) atomicAdd(&sAcc[e][slot], acc[e]);
             }
+        };
+        for (int c0 = 0; c0 < nw; c0 += 64) {
+            const int rem = nw - c0;
+            if (rem > 32) chunk(std::integral_constant<int, 64>{}, c0);
+            else if (rem > 16) chunk(std::integral_constant<int, 32>{}, c0);
+            else chunk(std::integral_constant<int, 16>{}, c0);
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
