@@ -415,6 +415,10 @@ def maintenance_leg(g, seg, min_seg, dev, reps=5):
     t_cmp, _ = timed(lambda: _gather_all([(rows[nm], dst[nm]) for nm in rows], n, keep, k, k, 0))
     t_prox, (keep_new, idx, n_new) = timed(lambda: gsr.proximity_filter(P["means"], new_means, INSERT_D_MIN))
     kn = int(n_new.item())
+    # storage order (segment-major, Morton inside a segment) and the move of every row into it
+    t_ord, order = timed(lambda: gsr.row_order(P["means"], seg))
+    dst2 = {name: torch.empty_like(t) for name, t in rows.items()}
+    t_mv, _ = timed(lambda: _gather_all([(rows[nm], dst2[nm]) for nm in rows], n, order, n, n, 0))
     b_cmp = 2 * 4 * floats_per_row * k + 4 * k
     res = dict(rows=n, floats_per_row=floats_per_row, min_opacity=PRUNE_MIN_OPACITY, max_ratio=PRUNE_MAX_RATIO,
                removed=n - k, prune_select_ms=round(t_sel, 4), compaction_ms=round(t_cmp, 4),
@@ -422,9 +426,9 @@ def maintenance_leg(g, seg, min_seg, dev, reps=5):
                                         unit="GB/s", frac=round(b_cmp / (t_cmp / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                         alg_bytes_per_launch=b_cmp),
                insert_candidates=int(new_means.shape[1]), insert_d_min=INSERT_D_MIN, inserted=kn,
-               proximity_ms=round(t_prox, 4))
+               proximity_ms=round(t_prox, 4), row_order_ms=round(t_ord, 4), row_move_ms=round(t_mv, 4))
     print("maintenance: %s" % res, file=sys.stderr, flush=True)
-    del P, rows, dst
+    del P, rows, dst, dst2
     torch.cuda.empty_cache()
     return res
 
@@ -599,8 +603,10 @@ def main():
     def make_opt(tile, **kw):
         P = gsr.gaussians_to_device(g, dev)
         raster = gsr.Raster(W, H, *tile)
-        return MapOptimizer(P, g["sh_degree"], cam_pool, trgb, tdep, raster, V, lambda_depth=0.2, segment_id=seg,
-                            min_segment=min_seg, device=dev, **kw)
+        o = MapOptimizer(P, g["sh_degree"], cam_pool, trgb, tdep, raster, V, lambda_depth=0.2, segment_id=seg,
+                         min_segment=min_seg, device=dev, **kw)
+        o.reorder()  # the map's rows in storage order: by segment, Morton order inside a segment
+        return o
 
     # the view schedule of every step, resident on the device (no host round-trip per step)
     n_main = max(a.warmup + a.steps, 10)

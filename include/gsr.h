@@ -375,6 +375,23 @@ GSR_API gsr_status gsr_prune_select(const float *opacity_logits, const int32_t *
                                     int64_t n, float max_logit, float max_ratio, uint32_t *keep_index,
                                     uint32_t *n_keep, void *ws, size_t ws_bytes, gsr_stream stream);
 
+/* ---- row order for memory locality -------------------------------------------------------------
+ * Not a step of the paper's method: the order in which the map's rows are stored.  The paper's
+ * segments grow by appending, and the optimisation updates only the K latest segments (Sec.
+ * III-C); keeping rows grouped by segment, and spatially ordered inside a segment, makes the rows
+ * one step touches (visible, and in the latest segments) dense in memory.
+ * order[j] (uint32 [n], written) = the row that moves to position j: rows sorted by segment_id
+ * (int32 [n], ascending; NULL = one segment), then by the Morton code of the mean (means
+ * float32 [3][n]) on a 1024^3 grid over the means' bounding box, then by row index.  A
+ * coordinate's cell is floor((x - lo) * (1024 / (hi - lo))) evaluated in float32 in that order
+ * (0 when hi = lo), clamped to [0, 1023]; the code interleaves the ten bits of the x, y and z
+ * cells with x lowest.  Move the rows with gsr_gather_rows(groups, n, order, n, n, 0) into new
+ * arrays.  ws: gsr_row_order_workspace(n) bytes, 256-byte aligned.  Errors: GSR_E_INVALID (bad
+ * pointers, n >= 2^32), GSR_E_CAPACITY (ws_bytes too small). */
+GSR_API size_t gsr_row_order_workspace(int64_t n);
+GSR_API gsr_status gsr_row_order(const float *means, const int32_t *segment_id, int64_t n, uint32_t *order,
+                                 void *ws, size_t ws_bytes, gsr_stream stream);
+
 /* Row gather over groups of component-major arrays of 4-byte elements (float32 / int32):
  *   dst[g][c * dst_rows + dst_offset + j] = src[g][c * src_rows + r_j],  r_j = index ? index[j] : j
  * for j < n_rows, c < cols[g].  Compaction: index = keep_index, dst_offset = 0; appending rows:

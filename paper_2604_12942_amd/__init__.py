@@ -272,6 +272,20 @@ def loss(rgb, depth, target_rgb, target_depth, n_views, raster, loss_acc, dL_drg
     return ws
 
 
+def row_order(means, segment_id=None, order=None, ws=None):
+    """Storage order of the map's rows: by segment, then by the Morton code of the mean (see
+    gsr_row_order).  Returns order [n] (int32 tensor holding uint32 row indices)."""
+    n = means.shape[1]
+    dev = means.device
+    order = torch.empty(max(1, n), dtype=torch.int32, device=dev) if order is None else order
+    nb = lib().gsr_row_order_workspace(n)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(1, nb), dtype=torch.uint8, device=dev)
+    check(lib().gsr_row_order(_ptr(means), _ptr(segment_id), n, _ptr(order), _ptr(ws), ws.numel(), _stream()),
+          "gsr_row_order")
+    return order
+
+
 def prune_select(opacity_logits, max_logit, max_ratio, segment_id=None, min_segment=0, keep_index=None,
                  n_keep=None, ws=None):
     """Low-opacity pruning selection (Sec. III-C).  Returns (keep_index [n] int32 tensor holding

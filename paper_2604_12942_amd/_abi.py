@@ -107,6 +107,8 @@ _SIGS = {
                           C.c_size_t, P], C.c_int),
     "gsr_gicp_iterate": ([C.POINTER(Gaussians), P, P, P, C.c_float, P, P, P, C.c_int32, P, C.c_size_t, P], C.c_int),
     "gsr_prune_workspace": ([C.c_int64], C.c_size_t),
+    "gsr_row_order_workspace": ([C.c_int64], C.c_size_t),
+    "gsr_row_order": ([P, P, C.c_int64, P, P, C.c_size_t, P], C.c_int),
     "gsr_prune_select": ([P, P, C.c_int32, C.c_int64, C.c_float, C.c_float, P, P, P, C.c_size_t, P], C.c_int),
     "gsr_gather_rows": ([C.POINTER(RowGroups), C.c_int64, P, C.c_int64, C.c_int64, C.c_int64, P], C.c_int),
     "gsr_proximity_workspace": ([C.c_int64, C.c_int64], C.c_size_t),

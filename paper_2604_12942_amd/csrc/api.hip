@@ -35,6 +35,8 @@ extern "C" gsr_status gsr_render_bwd_stored_launch(const gsr_splat *, const uint
                                                    const uint32_t *, const uint32_t *, uint32_t, const float *,
                                                    const float *, float *, hipStream_t);
 extern "C" size_t gsr_scan_ws_bytes(int64_t n);
+extern "C" size_t gsr_row_order_ws_bytes(int64_t n);
+extern "C" gsr_status gsr_row_order_launch(const float *, const int32_t *, int64_t, uint32_t *, void *, hipStream_t);
 extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
 extern "C" size_t gsr_voxel_pca_ws_bytes(int64_t n);
 extern "C" gsr_status gsr_voxel_pca_launch(const float *, int64_t, uint64_t, const gsr_voxels *, void *, hipStream_t);
@@ -353,6 +355,16 @@ extern "C" gsr_status gsr_loss(const float *rgb, const float *depth, const float
     if (!ws || ws_bytes < gsr_loss_ws_bytes(n_views, r)) return GSR_E_INVALID;
     return gsr_loss_launch(rgb, depth, target_rgb, target_depth, target_index, n_views, r, mask, count, lambda_rgb,
                            lambda_ssim, lambda_depth, loss, dL_drgb, dL_ddepth, ws, S(stream));
+}
+
+extern "C" size_t gsr_row_order_workspace(int64_t n) { return n < 0 ? 0 : gsr_row_order_ws_bytes(n); }
+
+extern "C" gsr_status gsr_row_order(const float *means, const int32_t *segment_id, int64_t n, uint32_t *order,
+                                    void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (n < 0 || n >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (n > 0 && (!means || !order || !ws)) return GSR_E_INVALID;
+    if (ws_bytes < gsr_row_order_ws_bytes(n)) return GSR_E_CAPACITY;
+    return gsr_row_order_launch(means, segment_id, n, order, ws, S(stream));
 }
 
 extern "C" size_t gsr_prune_workspace(int64_t n) { return n < 0 ? 0 : gsr_prune_ws_bytes(n); }

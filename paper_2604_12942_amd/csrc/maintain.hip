@@ -215,6 +215,109 @@ ProxWs prox_layout(void *base, int64_t n_map, int64_t n_new) {
     return w;
 }
 
+// ---- row order: segment-major, Morton order of the means within a segment --------------------
+constexpr int kBoxBlocks = 256;
+
+// Per-block minimum and maximum of each coordinate: part[b][0..2] = min, part[b][3..5] = max.
+__global__ __launch_bounds__(256) void k_box_part(const float *__restrict__ means, int64_t n,
+                                                  float *__restrict__ part) {
+    float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int a = 0; a < 3; a++) {
+            const float x = means[a * n + i];
+            lo[a] = fminf(lo[a], x);
+            hi[a] = fmaxf(hi[a], x);
+        }
+    __shared__ float s[6][256];
+    for (int a = 0; a < 3; a++) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int a = 0; a < 3; a++) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + h]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + h]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// Spread the low 10 bits of x to every third bit.
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// box[0..2] = minimum, box[3..5] = maximum over the per-block partials.
+__global__ void k_box_final(const float *__restrict__ part, int nparts, float *__restrict__ box) {
+    if (threadIdx.x >= 6) return;
+    const int a = threadIdx.x;
+    float r = a < 3 ? 3.0e38f : -3.0e38f;
+    for (int b = 0; b < nparts; b++) r = a < 3 ? fminf(r, part[b * 6 + a]) : fmaxf(r, part[b * 6 + a]);
+    box[a] = r;
+}
+
+// key[i] = Morton code of the mean's cell on a 1024^3 grid over the box (x bits lowest), val[i] = i.
+// The cell is floor((x - lo) * (1024 / (hi - lo))) in float32, clamped to [0, 1023].
+__global__ void k_morton_keys(const float *__restrict__ means, int64_t n, const float *__restrict__ box,
+                              uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    float lo[3], sc[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = box[a];
+        sc[a] = box[3 + a] > box[a] ? 1024.0f / (box[3 + a] - box[a]) : 0.0f;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t k = 0;
+        for (int a = 0; a < 3; a++) {
+            const float c = floorf((means[a * n + i] - lo[a]) * sc[a]);
+            const uint32_t q = c >= 1023.0f ? 1023u : (c > 0.0f ? (uint32_t)c : 0u);
+            k |= spread3(q) << a;
+        }
+        key[i] = k;
+        val[i] = (uint32_t)i;
+    }
+}
+
+// key[j] = segment of row order[j], sign bit flipped so that the unsigned order is the signed one.
+__global__ void k_segment_keys(const int32_t *__restrict__ seg, const uint32_t *__restrict__ order, int64_t n,
+                               uint32_t *__restrict__ key) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        key[j] = (uint32_t)seg[order[j]] ^ 0x80000000u;
+}
+
+struct OrderWs {
+    float *part;
+    uint32_t *key, *k2, *v2;
+    void *sort;
+    size_t bytes;
+};
+
+OrderWs order_layout(void *base, int64_t n) {
+    OrderWs w{};
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        void *r = p ? p + off : nullptr;
+        off += a256(b);
+        return r;
+    };
+    const size_t wn = (size_t)(n > 0 ? n : 1) * 4;
+    w.part = (float *)take((size_t)(kBoxBlocks + 1) * 6 * 4);  // partials, then the box
+    w.key = (uint32_t *)take(wn);
+    w.k2 = (uint32_t *)take(wn);
+    w.v2 = (uint32_t *)take(wn);
+    w.sort = take(gsr_sort_pairs_ws_bytes(n));
+    w.bytes = off;
+    return w;
+}
+
 int nblk(int64_t n) { return (int)ceil_div(n > 0 ? n : 1, 256); }
 
 }  // namespace gsr
@@ -297,4 +400,25 @@ extern "C" gsr_status gsr_proximity_launch(const float *map, int64_t n_map, cons
     if (s != GSR_OK) return s;
     k_compact_index<<<nblk(n_new), 256, 0, st>>>(w.flag, w.off, n_new, keep_index);
     return last_launch();
+}
+
+extern "C" size_t gsr_row_order_ws_bytes(int64_t n) { return order_layout(nullptr, n).bytes; }
+
+// order[j] = the row that moves to position j: rows by segment id (when given), then by the Morton
+// code of the mean, ties by row index (both sorts are stable).
+extern "C" gsr_status gsr_row_order_launch(const float *means, const int32_t *seg, int64_t n, uint32_t *order,
+                                           void *ws, hipStream_t st) {
+    if (n == 0) return GSR_OK;
+    OrderWs w = order_layout(ws, n);
+    const int nb = (int)(ceil_div(n, 256) < kBoxBlocks ? ceil_div(n, 256) : kBoxBlocks);
+    k_box_part<<<nb, 256, 0, st>>>(means, n, w.part);
+    const int ng = (int)(ceil_div(n, 256) < 4096 ? ceil_div(n, 256) : 4096);
+    float *box = w.part + kBoxBlocks * 6;
+    k_box_final<<<1, 64, 0, st>>>(w.part, nb, box);
+    k_morton_keys<<<ng, 256, 0, st>>>(means, n, box, w.key, order);
+    // four 8-bit passes each: the sorted pairs end in (key, order)
+    gsr_status s = gsr_sort_pairs_launch(w.key, order, w.k2, w.v2, (uint32_t)n, 32, w.sort, st);
+    if (s != GSR_OK || !seg) return s;
+    k_segment_keys<<<ng, 256, 0, st>>>(seg, order, n, w.key);
+    return gsr_sort_pairs_launch(w.key, order, w.k2, w.v2, (uint32_t)n, 32, w.sort, st);
 }

@@ -10,7 +10,7 @@ import math
 
 import torch
 
-from . import _abi, gather_rows, prune_select, proximity_filter
+from . import _abi, gather_rows, prune_select, proximity_filter, row_order
 
 
 def _columns(t, rows):
@@ -52,3 +52,13 @@ def insert(arrays, new_arrays, d_min):
     _gather_all([(arrays[name], out[name]) for name in arrays], n, None, n, n + k, 0)
     _gather_all([(new_arrays[name], out[name]) for name in arrays], n_new, index, k, n + k, n)
     return out, k
+
+
+def reorder(arrays, segment_id=None):
+    """Rows of arrays (same keys as for prune) moved into storage order: by segment, then by the
+    Morton code of the mean (gsr_row_order).  Returns (dict of new tensors, the order)."""
+    n = arrays["means"].shape[1]
+    order = row_order(arrays["means"], segment_id)
+    out = {k: _new_like(a, n) for k, a in arrays.items()}
+    _gather_all([(arrays[k], out[k]) for k in arrays], n, order, n, n, 0)
+    return out, order

@@ -116,6 +116,16 @@ class MapOptimizer:
         self._adopt(rows)
         return added
 
+    def reorder(self):
+        """Store the rows segment by segment, in Morton order of the means inside a segment, so
+        that the rows a step touches lie close together in memory (the rendered images and the
+        updates do not depend on the order, up to depth ties).  Returns the order: position j
+        holds the former row order[j]."""
+        from .maintain import reorder
+        rows, order = reorder(self._row_arrays(), self.segment_id)
+        self._adopt(rows)
+        return order
+
     def set_views(self, idx):
         """Choose this iteration's keyframes (slots of the camera / target pool).  A device
         tensor is copied on the stream without a host round-trip."""

@@ -63,3 +63,46 @@ def test_redundant_matches_kdtree_and_hand_cases():
     assert not mo.redundant(a, b, 0.25)[0]
     assert mo.redundant(a, b, np.nextafter(np.float32(0.25), np.float32(1)))[0]
     assert not mo.redundant(np.zeros((3, 0), np.float32), b, 1.0).any()
+
+
+def _interleave_by_string(x, y, z):
+    # bit string of the Morton code, most significant first: z9 y9 x9 z8 y8 x8 ... z0 y0 x0
+    bits = "".join(f"{c:010b}"[9 - b] for b in range(9, -1, -1) for c in (z, y, x))
+    return int(bits, 2)
+
+
+def test_morton_code_matches_bitstring_interleave():
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, 1024, (3, 500))
+    q[:, 0] = 0
+    q[:, 1] = 1023
+    codes = mo.morton_code(q)
+    for k in range(q.shape[1]):
+        assert codes[k] == _interleave_by_string(*q[:, k])
+
+
+def test_row_order_hand_cases():
+    # the 8 corners of a box: x varies fastest, then y, then z
+    corners = np.array([[x, y, z] for z in (0.0, 2.0) for y in (0.0, 3.0) for x in (-1.0, 5.0)], np.float32).T
+    perm = np.array([6, 1, 7, 0, 3, 5, 2, 4])
+    order = mo.row_order(corners[:, perm])
+    assert np.array_equal(perm[order], np.arange(8))
+    cells = mo.morton_cells(corners)
+    assert set(cells.ravel().tolist()) == {0, 1023}  # the maximum is clamped into the last cell
+    # segments first, then space; equal points keep row order; a flat axis gives cell 0
+    m = np.array([[0, 1, 0, 1, 0], [0, 0, 0, 0, 0], [5, 5, 5, 5, 5]], np.float32)
+    seg = np.array([2, 1, 1, 2, -3])
+    assert mo.row_order(m, seg).tolist() == [4, 2, 1, 0, 3]
+    assert mo.morton_cells(m)[2].tolist() == [0] * 5
+
+
+def test_row_order_is_a_locality_preserving_permutation():
+    rng = np.random.default_rng(4)
+    m = rng.uniform(-50, 50, (3, 20000)).astype(np.float32)
+    seg = rng.integers(0, 4, 20000)
+    order = mo.row_order(m, seg)
+    assert np.array_equal(np.sort(order), np.arange(20000))
+    assert np.all(np.diff(seg[order]) >= 0)
+    step = np.linalg.norm(np.diff(m[:, order], axis=1), axis=0)
+    rand = np.linalg.norm(m[:, :-1] - m[:, 1:], axis=0)
+    assert np.median(step) < 0.1 * np.median(rand)
