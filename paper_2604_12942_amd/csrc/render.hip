@@ -26,8 +26,9 @@ __device__ __forceinline__ void stage_splat(const gsr_splat *__restrict__ splats
     C = make_float4(f2.y, f2.z, f2.w, 0.0f);
 }
 
-// Whitened exponent at the pixel centre (fx, fy) (32x32-block coordinates).  Forward and
-// backward both call this, so their contribute / skip decisions are bit-identical.
+// Whitened exponent at the pixel centre (fx, fy) (32x32-block coordinates).  The forward calls
+// this and the backward performs the same operations on the same operands, so their contribute /
+// skip decisions are bit-identical.
 __device__ __forceinline__ float blend_exponent(const float4 &A, float l22, float fx, float fy, float &dx, float &dy,
                                                 float &u1, float &u2) {
     dx = fx - A.x;
@@ -702,13 +703,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             const uint32_t cfront = (uint32_t)__builtin_amdgcn_readlane((int)pos, lastlane);
             float cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, go = 0.f;
             float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f;
+            const float kz = nln2 * B.z;
             // two pixels per group and iteration: their chains are independent, which keeps the
             // SIMD busy through the scan and transcendental latencies
             for (int p = 0; p < 64; p += 2 * NG) {
                 int q0 = p, q1 = p + 1;
                 uint32_t l0, l1;
                 float4 pg0, pg1;
-                float T0, S0, T1, S1, fx0, fy0, fx1, fy1;
+                float T0, S0, T1, S1, fx0, fy0, fx1;
                 if constexpr (NG == 1) {
                     l0 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
                     l1 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p + 1);
@@ -717,7 +719,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     pg1 = sPG[w][p + 1];
                     const float4 ps = *reinterpret_cast<const float4 *>(&sPS[w][p]);
                     T0 = ps.x, S0 = ps.y, T1 = ps.z, S1 = ps.w;
-                    fx0 = rdl(fx, p), fy0 = rdl(fy, p), fx1 = rdl(fx, p + 1), fy1 = rdl(fy, p + 1);
+                    fx0 = rdl(fx, p), fy0 = rdl(fy, p), fx1 = rdl(fx, p + 1);
                 } else {
                     q0 = p + grp;
                     q1 = p + NG + grp;
@@ -733,11 +735,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     const float fxp = fxw + (float)(p % TW);
                     fx0 = fxp + (float)grp;
                     fx1 = fxp + (float)(NG + grp);
-                    fy0 = fy1 = fyw + (float)(p / TW);
+                    fy0 = fyw + (float)(p / TW);
                 }
-                float dx0, dy0, dx1, dy1, t0, t1;
-                const float P0 = blend_exponent(A, B.x, fx0, fy0, dx0, dy0, t0, t1);
-                const float P1 = blend_exponent(A, B.x, fx1, fy1, dx1, dy1, t0, t1);
+                // The two pixels share a row (p is even and 2 NG divides TW), so dy and the
+                // terms of the exponent that depend on dy alone are formed once.  Each operation
+                // is the one blend_exponent performs: the exponents, and so every contribute /
+                // skip decision, are bit-identical to the forward's.
+                const float dy = fy0 - A.y;
+                const float l21dy = A.w * dy, u2 = B.x * dy, u22 = u2 * u2;
+                const float dx0 = fx0 - A.x, dx1 = fx1 - A.x;
+                const float u10 = __builtin_fmaf(A.z, dx0, l21dy), u11 = __builtin_fmaf(A.z, dx1, l21dy);
+                const float P0 = __builtin_fmaf(u10, u10, u22), P1 = __builtin_fmaf(u11, u11, u22);
                 const bool act0 = posv < l0 && P0 <= B.y;
                 const bool act1 = posv < l1 && P1 <= B.y;
                 if (__ballot(act0 || act1) == 0) continue;  // no Gaussian of the chunk reaches them
@@ -773,17 +781,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 cg = __builtin_fmaf(pg0.y, w0, __builtin_fmaf(pg1.y, w1, cg));
                 cb = __builtin_fmaf(pg0.z, w0, __builtin_fmaf(pg1.z, w1, cb));
                 cd = __builtin_fmaf(pg0.w, w0, __builtin_fmaf(pg1.w, w1, cd));
-                // unclamped alpha = o 2^-P: dL/dP = -ln2 alpha dL/da, dL/do = 2^-P dL/da
+                // unclamped alpha = o 2^-P: dL/do = 2^-P dL/da, dL/dP = -ln2 o (2^-P dL/da)
+                // (zero where the clamp holds alpha)
                 const bool lin0 = act0 && ar0 <= GSR_ALPHA_MAX, lin1 = act1 && ar1 <= GSR_ALPHA_MAX;
-                const float dP0 = lin0 ? (nln2 * ar0) * d0 : 0.f;
-                const float dP1 = lin1 ? (nln2 * ar1) * d1 : 0.f;
-                go = __builtin_fmaf(lin0 ? d0 : 0.f, e0, __builtin_fmaf(lin1 ? d1 : 0.f, e1, go));
+                const float g0 = (lin0 ? e0 : 0.f) * d0, g1 = (lin1 ? e1 : 0.f) * d1;
+                go += g0 + g1;
+                const float dP0 = kz * g0, dP1 = kz * g1;
                 mx = __builtin_fmaf(dP0, dx0, __builtin_fmaf(dP1, dx1, mx));
-                my = __builtin_fmaf(dP0, dy0, __builtin_fmaf(dP1, dy1, my));
+                const float sP = dP0 + dP1;
+                my = __builtin_fmaf(sP, dy, my);
                 const float qq0 = dP0 * dx0, qq1 = dP1 * dx1;
                 mxx = __builtin_fmaf(qq0, dx0, __builtin_fmaf(qq1, dx1, mxx));
-                mxy = __builtin_fmaf(qq0, dy0, __builtin_fmaf(qq1, dy1, mxy));
-                myy = __builtin_fmaf(dP0 * dy0, dy0, __builtin_fmaf(dP1 * dy1, dy1, myy));
+                mxy = __builtin_fmaf(qq0 + qq1, dy, mxy);
+                myy = __builtin_fmaf(sP * dy, dy, myy);
                 // the pixels' state in front of this chunk, kept by each group's frontmost lane
                 // (inactive lanes carry a = 0)
                 if (gl == GL - 1) {
