@@ -140,19 +140,40 @@ __global__ __launch_bounds__(256) void k_scan_write(const uint32_t *__restrict__
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                     uint32_t n_host, uint32_t cap, int shift, int nblocks,
                                                     uint32_t *__restrict__ hist) {
+    // Counts are order-free: each thread takes kSortItems consecutive keys (four 16-byte loads)
+    // and adds a run of equal digits to the block's LDS count in one atomic, so nearly sorted
+    // input (long runs) costs one add per run and shuffled input one per key.
     __shared__ uint32_t cnt[kRadix];
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t n = dev_count(n_dev, n_host, cap);
-    const uint32_t base = blockIdx.x * kSortTile;
-    if (base < n) {
-        for (int r = 0; r < kSortItems; r++) {
-            const uint32_t idx = base + r * kSortThreads + threadIdx.x;
-            const bool valid = idx < n;
-            const uint32_t d = valid ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
-            const uint64_t peers = match_digit8(d, valid);
-            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    const uint32_t first = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    if (first < n) {
+        uint32_t k[kSortItems];
+        if (first + kSortItems <= cap && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+#pragma unroll
+            for (int q = 0; q < kSortItems / 4; q++) {
+                const uint4 x = *reinterpret_cast<const uint4 *>(keys + first + 4 * q);
+                k[4 * q] = x.x, k[4 * q + 1] = x.y, k[4 * q + 2] = x.z, k[4 * q + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kSortItems; r++) k[r] = first + r < cap ? keys[first + r] : 0u;
         }
+        const uint32_t m = n - first < (uint32_t)kSortItems ? n - first : (uint32_t)kSortItems;
+        uint32_t d = (k[0] >> shift) & (kRadix - 1), run = 1;
+#pragma unroll
+        for (int r = 1; r < kSortItems; r++) {
+            if ((uint32_t)r >= m) break;
+            const uint32_t dr = (k[r] >> shift) & (kRadix - 1);
+            if (dr != d) {
+                atomicAdd(&cnt[d], run);
+                d = dr;
+                run = 0;
+            }
+            run++;
+        }
+        atomicAdd(&cnt[d], run);
     }
     __syncthreads();
     hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
