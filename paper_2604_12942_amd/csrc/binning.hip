@@ -135,8 +135,8 @@ __global__ __launch_bounds__(256) void k_scan_write(const uint32_t *__restrict__
 }
 
 // ---- stable LSD radix sort, 8-bit digits -----------------------------------------------------
-// Block b sorts items [b*4096, (b+1)*4096) in round-major order: item r*256 + t is held by
-// thread t in round r, so stability follows (round, thread) order.
+// Block b sorts items [b*4096, (b+1)*4096); the histogram counts each block's digits, and the
+// scatter ranks them stably (input order) inside the block.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                     uint32_t n_host, uint32_t cap, int shift, int nblocks,
                                                     uint32_t *__restrict__ hist) {
@@ -202,34 +202,38 @@ __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ 
     if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
+// Block b sorts items [b*4096, (b+1)*4096): wave w owns the 1024 items from b*4096 + w*1024 on,
+// 64 per round, so (wave, round, lane) order is input order and each wave ranks its items with
+// its own running digit counts, without a workgroup barrier per round; the four waves' counts
+// then give every digit's local start and each wave's offset inside it.
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                        uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                        const uint32_t *__restrict__ vin2, uint32_t *__restrict__ vout2,
                                                        const uint32_t *n_dev, uint32_t n_host, uint32_t cap, int shift,
                                                        int nblocks, const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ totals) {
+    constexpr int kWaveItems = kSortTile / 4;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_wcnt[4][kRadix];
-    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_wcnt[4][kRadix];  // per-wave running counts, then per-wave starts
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_w[4];
     const uint32_t n = dev_count(n_dev, n_host, cap);
     const uint32_t base = blockIdx.x * kSortTile;
     if (base >= n) return;
-    const int t = threadIdx.x, w = t >> 6;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     // global start of digit t for this block
     const uint32_t dtot = totals[t];
     const uint32_t dstart = block_excl_scan256(dtot, s_w, nullptr);
     s_gbase[t] = dstart + hist[t * nblocks + blockIdx.x];
-    s_run[t] = 0;
     for (int k = 0; k < 4; k++) s_wcnt[k][t] = 0;
     __syncthreads();
-    uint32_t mk[kSortItems], mv[kSortItems], mpos[kSortItems], mv2[kSortItems];
+    uint32_t mk[kSortItems], mv[kSortItems], mrank[kSortItems], mv2[kSortItems];
     const uint64_t lt = lanemask_lt();
+    const uint32_t wbase = base + w * kWaveItems;
     for (int r = 0; r < kSortItems; r++) {
-        const uint32_t idx = base + r * kSortThreads + t;
+        const uint32_t idx = wbase + r * 64 + lane;
         const bool valid = idx < n;
         mk[r] = valid ? kin[idx] : 0u;
         mv[r] = valid ? vin[idx] : 0u;
@@ -237,25 +241,25 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         const uint32_t d = (mk[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit8(d, valid);
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t prior = s_run[d];
-            for (int k = 0; k < w; k++) prior += s_wcnt[k][d];
-            mpos[r] = prior + rank;
-        }
-        __syncthreads();
-        s_run[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
-        s_wcnt[0][t] = s_wcnt[1][t] = s_wcnt[2][t] = s_wcnt[3][t] = 0;
-        __syncthreads();
+        // the wave's count of digit d so far (read by every lane before its leader adds)
+        const uint32_t before = s_wcnt[w][d];
+        mrank[r] = before + rank;
+        if (valid && rank == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
     }
-    s_lstart[t] = block_excl_scan256(s_run[t], s_w, nullptr);
+    __syncthreads();
+    {
+        const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t], c3 = s_wcnt[3][t];
+        const uint32_t ls = block_excl_scan256(c0 + c1 + c2 + c3, s_w, nullptr);
+        s_lstart[t] = ls;
+        s_wcnt[0][t] = ls;
+        s_wcnt[1][t] = ls + c0;
+        s_wcnt[2][t] = ls + c0 + c1;
+        s_wcnt[3][t] = ls + c0 + c1 + c2;
+    }
     __syncthreads();
     for (int r = 0; r < kSortItems; r++) {
-        const uint32_t idx = base + r * kSortThreads + t;
-        if (idx < n) {
-            const uint32_t d = (mk[r] >> shift) & (kRadix - 1);
-            const uint32_t p = s_lstart[d] + mpos[r];
+        if (wbase + r * 64 + lane < n) {
+            const uint32_t p = s_wcnt[w][(mk[r] >> shift) & (kRadix - 1)] + mrank[r];
             s_keys[p] = mk[r];
             s_vals[p] = mv[r];
         }
@@ -276,8 +280,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         // the second payload takes the same permutation through the same LDS staging
         __syncthreads();
         for (int r = 0; r < kSortItems; r++) {
-            const uint32_t idx = base + r * kSortThreads + t;
-            if (idx < n) s_vals[s_lstart[(mk[r] >> shift) & (kRadix - 1)] + mpos[r]] = mv2[r];
+            if (wbase + r * 64 + lane < n)
+                s_vals[s_wcnt[w][(mk[r] >> shift) & (kRadix - 1)] + mrank[r]] = mv2[r];
         }
         __syncthreads();
         for (int r = 0; r < kSortItems; r++) {
