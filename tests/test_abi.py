@@ -73,3 +73,9 @@ def test_new_entry_points_reject_invalid_arguments():
     assert 0 < small < big and L.gsr_render_fwd_sliced_workspace(1, c.byref(r), -1) == 0
     assert L.gsr_render_fwd_sliced(P, P, P, None, P, 1, c.byref(r), P, P, P, P, 1 << 16, None, small, None) == 1
     assert L.gsr_render_fwd_sliced(P, P, P, None, P, 1, c.byref(r), P, P, P, P, 1 << 16, P, small - 1, None) == 2
+    # storage order of the rows
+    wo = L.gsr_row_order_workspace(1000)
+    assert wo > 0 and L.gsr_row_order_workspace(-1) == 0
+    assert L.gsr_row_order(None, None, 1000, P, P, wo, None) == 1          # no means
+    assert L.gsr_row_order(P, None, -5, P, P, wo, None) == 1               # negative count
+    assert L.gsr_row_order(P, None, 1000, P, P, wo - 1, None) == 2         # workspace too small
