@@ -26,9 +26,15 @@ __global__ void k_fill_u32(uint32_t *__restrict__ dst, uint32_t value, int64_t n
 }
 
 // Exclusive scan in place of nb (small) block sums by one 1024-thread block; writes the total.
-__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *__restrict__ v, int nb, uint32_t *__restrict__ total) {
+// With lim, only the first ceil(*lim / per) sums are scanned (the rest are zero and unread).
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t *__restrict__ v, int nb, uint32_t *__restrict__ total,
+                                                     const uint32_t *__restrict__ lim = nullptr, uint32_t per = 1) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
+    if (lim) {
+        const uint32_t used = (*lim + per - 1) / per;
+        nb = used < (uint32_t)nb ? (int)used : nb;
+    }
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
     for (int base = 0; base < nb; base += 1024) {
@@ -184,12 +190,31 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
 __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ hist, int nblocks,
                                                          uint32_t *__restrict__ totals) {
     // one digit's row per workgroup; each thread owns a contiguous run of the row: sum it, one
-    // workgroup scan of the run sums, then rewrite the run as exclusive prefixes
+    // workgroup scan of the run sums, then rewrite the run as exclusive prefixes.  Runs of up to
+    // 16 entries (rows of up to 4096 blocks) stay in registers, loaded all at once.
     __shared__ uint32_t s_w[4];
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
     const int per = (nblocks + 255) / 256;
     const int b0 = threadIdx.x * per;
     const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    if (per <= 16) {
+        uint32_t x[16];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            x[k] = b0 + k < b1 ? row[b0 + k] : 0u;
+            sum += x[k];
+        }
+        uint32_t tot;
+        uint32_t run = block_excl_scan256(sum, s_w, &tot);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (b0 + k < b1) row[b0 + k] = run;
+            run += x[k];
+        }
+        if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+        return;
+    }
     uint32_t sum = 0;
     for (int idx = b0; idx < b1; idx++) sum += row[idx];
     uint32_t tot;
@@ -301,15 +326,14 @@ __global__ __launch_bounds__(256) void k_inst_count(const uint32_t *__restrict__
                                                     uint32_t *__restrict__ bsum) {
     __shared__ uint32_t s_w[4];
     const uint32_t n = dev_count(n_vis, 0, cap);
-    const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x * 256 >= n) {
-        if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
-        return;
+    // blocks of 256 pairs up to the visible count (grid-stride; later sums are never read)
+    for (uint32_t b = blockIdx.x; b * 256 < n; b += gridDim.x) {
+        const uint32_t idx = b * 256 + threadIdx.x;
+        const uint32_t c = idx < n ? ntiles[sorted_gid[idx]] : 0u;
+        uint32_t tot;
+        block_excl_scan256(c, s_w, &tot);
+        if (threadIdx.x == 0) bsum[b] = tot;
     }
-    const uint32_t c = idx < n ? ntiles[sorted_gid[idx]] : 0u;
-    uint32_t tot;
-    block_excl_scan256(c, s_w, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
 // Emission of the instances of 256 depth-ordered visible pairs per block, load-balanced: the
@@ -477,8 +501,8 @@ extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V
     if (s != GSR_OK) return s;
     // 3. instance counts in depth order, scan, emission
     const int nb_p = (int)ceil_div(VN > 0 ? VN : 1, 256);
-    k_inst_count<<<nb_p, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, w.cnt_b);
-    k_scan_small<<<1, 1024, 0, st>>>(w.cnt_b, nb_p, n_inst);
+    k_inst_count<<<nb_p < 4096 ? nb_p : 4096, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, w.cnt_b);
+    k_scan_small<<<1, 1024, 0, st>>>(w.cnt_b, nb_p, n_inst, w.n_vis, 256u);
     // the instance sort runs ceil(bits/8) passes; emit into the buffer that makes the last
     // pass land in the sorted-values output (inst_emit when asked for, else inst_gid)
     const int tbits = bit_length((uint64_t)V * T - 1) > 0 ? bit_length((uint64_t)V * T - 1) : 1;
