@@ -169,7 +169,7 @@ GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_
 
 /* ---- render forward with depth slices ------------------------------------------------------------
  * The same outputs as gsr_render_fwd (n_contrib excepted) with the long tiles split.  A view-tile
- * whose list holds more than 8192 instances is cut into slices of 2048 consecutive instances,
+ * whose list holds more than 8192 instances is cut into slices of 1024 consecutive instances,
  * composited by separate workgroups: a first pass forms each slice's per-pixel product of
  * (1 - a); every slice k then starts from T_in(k), the product over the slices in front of it,
  * and does nothing for a pixel with T_in(k) < 1e-4 (already terminated); a last pass adds the
@@ -180,7 +180,7 @@ GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_
  * composited exactly as by gsr_render_fwd.
  * capacity: the instance capacity the lists were built with (gsr_bin_sort's), which bounds the
  * number of slices.  ws: device workspace of gsr_render_fwd_sliced_workspace(V, r, capacity)
- * bytes (about 4.3 KiB per 1,000 instances of capacity), 256-byte aligned.  Errors: GSR_E_INVALID,
+ * bytes (about 7.7 KiB per 1,000 instances of capacity), 256-byte aligned.  Errors: GSR_E_INVALID,
  * GSR_E_CAPACITY (ws_bytes too small). */
 GSR_API size_t gsr_render_fwd_sliced_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity);
 GSR_API gsr_status gsr_render_fwd_sliced(const gsr_splat *splats, const uint32_t *inst_gid,

@@ -219,8 +219,8 @@ __device__ __forceinline__ void write_null_slot(float4 *sA, float4 *sB, float4 *
 // sums each pixel's slice results in order, stopping after the slice in which it terminated.
 // The results are those of the whole-tile walk up to the float rounding of the transmittance
 // products (which are associated per slice).
-constexpr uint32_t kSliceLen = 2048;
-constexpr uint32_t kSplitMin = 4 * kSliceLen;  // shorter tiles finish within the launch anyway
+constexpr uint32_t kSliceLen = 1024;
+constexpr uint32_t kSplitMin = 8 * kSliceLen;  // shorter tiles finish within the launch anyway
 constexpr uint32_t kNoSlice = 0xffffffffu;  // list entry of a slice that did not fit
 
 struct SliceArgs {
@@ -1004,11 +1004,11 @@ struct SliceWs {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Every sliced tile holds len > kSplitMin = 4 kSliceLen instances, so its ceil(len / kSliceLen)
-// slices number less than 1.25 len / kSliceLen: 1.25 capacity / kSliceLen + 1 always fit.
+// Every sliced tile holds len > kSplitMin = 8 kSliceLen instances, so its ceil(len / kSliceLen)
+// slices number less than 1.125 len / kSliceLen: 1.125 capacity / kSliceLen + 1 always fit.
 SliceWs slice_layout(void *base, int64_t VT, int64_t capacity) {
     SliceWs w{};
-    const int64_t cap = 5 * (capacity > 0 ? capacity : 1) / (4 * (int64_t)kSliceLen) + 1;
+    const int64_t cap = 9 * (capacity > 0 ? capacity : 1) / (8 * (int64_t)kSliceLen) + 1;
     w.cap = (uint32_t)(cap < 0x7fffffff ? cap : 0x7fffffff);
     char *p = static_cast<char *>(base);
     size_t off = 0;

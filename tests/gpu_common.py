@@ -97,7 +97,7 @@ def expected_instances(ti, n, V, raster, with_emission=False):
 def long_tile_scene(seed=11, W=64, H=64, f=60.0):
     """A vanishing-point pile-up on a 64x64 image: 48,000 small, faint Gaussians at depths 2-8 m
     crowd the four central 16x16 tiles (lists of about 11,000 instances, so the forward cuts them
-    into depth slices of 2048), and 600 nearly opaque ones at 4.5-5.5 m, past the 4,000th list
+    into depth slices of 1024), and 600 nearly opaque ones at 4.5-5.5 m, past the 4,000th list
     position, on which a few hundred central pixels terminate."""
     import synth
     faint = synth.random_gaussians(seed, 48_000, 1, xy_half=1.0, z_range=(2.0, 8.0), log_scale_mean=-2.3,

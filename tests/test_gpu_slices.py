@@ -1,7 +1,7 @@
 """Depth slices of long tiles (gsr_render_fwd_sliced): the front-to-back recurrence of Eq. 8
 regrouped by the associativity of the transmittance product, checked against the FP64 oracle
 and against the whole-tile forward on a vanishing-point pile-up whose central tiles hold about
-11,000 instances (tiles above 8192 are cut into slices of 2048), with pixels that terminate in a
+11,000 instances (tiles above 8192 are cut into slices of 1024), with pixels that terminate in a
 middle slice and pixels that walk every slice.  Tolerances and knife-edge exclusion as in the other parity tests."""
 import numpy as np
 import pytest
@@ -13,7 +13,7 @@ from gpu_common import GRAD_RTOL, KNIFE, grad_close, img_close, long_tile_scene,
 
 pytestmark = pytest.mark.gpu
 
-SLICE = 2048
+SLICE = 1024
 SPLIT_MIN = 8192
 G, CAM = long_tile_scene()
 _CACHE = {}
