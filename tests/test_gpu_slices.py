@@ -84,3 +84,18 @@ def test_backward_after_sliced_forward_matches_oracle():
         gk = grads[k].cpu().numpy().astype(np.float64)
         bad = grad_close(gk, o[k], mask=keep)
         assert bad.sum() == 0, (k, bad.sum())
+
+
+def test_slice_list_overflow_leaves_tiles_whole():
+    """A slice workspace sized for too small an instance capacity cannot hold the long tiles'
+    slices: those tiles are composited whole, exactly as by the whole-tile forward."""
+    import paper_2604_12942_amd as gsr
+    a, ra, *_ = run_forward(G, [CAM], sliced=False)
+    ws = torch.empty(gsr.render_fwd_sliced_workspace(1, ra.raster, 1), dtype=torch.uint8, device="cuda")
+    ct = gsr.camera_tensor([CAM])
+    gsr.render_fwd(ra.splats, ra.inst_gid, ra.tile_ranges, ct, 1, ra.raster, ra.rgb, ra.depth, ra.T_final, ra.last,
+                   tile_order=ra.tile_order, ws=ws, capacity=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(ra.rgb.cpu().numpy().astype(np.float64), a["rgb"])
+    assert np.array_equal(ra.T_final.cpu().numpy().astype(np.float64), a["T"])
+    assert np.array_equal(ra.last.cpu().numpy(), a["last"])
