@@ -150,9 +150,11 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     // and adds a run of equal digits to the block's LDS count in one atomic, so nearly sorted
     // input (long runs) costs one add per run and shuffled input one per key.
     __shared__ uint32_t cnt[kRadix];
+    const uint32_t n = dev_count(n_dev, n_host, cap);
+    // blocks past the live count write nothing: the row scan and the scatter skip them
+    if (blockIdx.x * (uint32_t)kSortTile >= n) return;
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t n = dev_count(n_dev, n_host, cap);
     const uint32_t first = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
     if (first < n) {
         uint32_t k[kSortItems];
@@ -185,18 +187,22 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Row d of hist (one row per digit, nblocks entries) is scanned exclusively in place; the row
-// total goes to totals[d].
+// Row d of hist (one row per digit, row stride nblocks) is scanned exclusively in place over the
+// blocks that hold live items; the row total goes to totals[d].
 __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ hist, int nblocks,
-                                                         uint32_t *__restrict__ totals) {
+                                                         uint32_t *__restrict__ totals, const uint32_t *n_dev,
+                                                         uint32_t n_host, uint32_t cap) {
     // one digit's row per workgroup; each thread owns a contiguous run of the row: sum it, one
     // workgroup scan of the run sums, then rewrite the run as exclusive prefixes.  Runs of up to
-    // 16 entries (rows of up to 4096 blocks) stay in registers, loaded all at once.
+    // 16 entries (up to 4096 live blocks) stay in registers, loaded all at once.
     __shared__ uint32_t s_w[4];
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
-    const int per = (nblocks + 255) / 256;
+    const uint32_t n = dev_count(n_dev, n_host, cap);
+    const int live = (int)((n + kSortTile - 1) / kSortTile);
+    const int nb = live < nblocks ? live : nblocks;
+    const int per = (nb + 255) / 256;
     const int b0 = threadIdx.x * per;
-    const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    const int b1 = b0 + per < nb ? b0 + per : nb;
     if (per <= 16) {
         uint32_t x[16];
         uint32_t sum = 0;
@@ -458,7 +464,7 @@ gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, 
     const int nb = (int)ceil_div(cap, kSortTile);
     for (int shift = 0; shift < bits; shift += kRadixBits) {
         k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, n_host, cap, shift, nb, hist);
-        k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals);
+        k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals, n_dev, n_host, cap);
         k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, w ? *w : nullptr, w ? *w2 : nullptr, n_dev,
                                                      n_host, cap, shift, nb, hist, totals);
         uint32_t *tk = k, *tv = v;
