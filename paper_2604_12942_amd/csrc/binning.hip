@@ -141,37 +141,39 @@ __global__ __launch_bounds__(256) void k_scan_write(const uint32_t *__restrict__
 }
 
 // ---- stable LSD radix sort, 8-bit digits -----------------------------------------------------
-// Block b sorts items [b*4096, (b+1)*4096); the histogram counts each block's digits, and the
-// scatter ranks them stably (input order) inside the block.
+// Block b sorts items [b*kRadixTile, (b+1)*kRadixTile); the histogram counts each block's digits,
+// and the scatter ranks them stably (input order) inside the block.
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kSortThreads * kRadixItems;
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                     uint32_t n_host, uint32_t cap, int shift, int nblocks,
                                                     uint32_t *__restrict__ hist) {
-    // Counts are order-free: each thread takes kSortItems consecutive keys (four 16-byte loads)
+    // Counts are order-free: each thread takes kRadixItems consecutive keys (four 16-byte loads)
     // and adds a run of equal digits to the block's LDS count in one atomic, so nearly sorted
     // input (long runs) costs one add per run and shuffled input one per key.
     __shared__ uint32_t cnt[kRadix];
     const uint32_t n = dev_count(n_dev, n_host, cap);
     // blocks past the live count write nothing: the row scan and the scatter skip them
-    if (blockIdx.x * (uint32_t)kSortTile >= n) return;
+    if (blockIdx.x * (uint32_t)kRadixTile >= n) return;
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t first = blockIdx.x * kSortTile + threadIdx.x * kSortItems;
+    const uint32_t first = blockIdx.x * kRadixTile + threadIdx.x * kRadixItems;
     if (first < n) {
-        uint32_t k[kSortItems];
-        if (first + kSortItems <= cap && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+        uint32_t k[kRadixItems];
+        if (first + kRadixItems <= cap && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
 #pragma unroll
-            for (int q = 0; q < kSortItems / 4; q++) {
+            for (int q = 0; q < kRadixItems / 4; q++) {
                 const uint4 x = *reinterpret_cast<const uint4 *>(keys + first + 4 * q);
                 k[4 * q] = x.x, k[4 * q + 1] = x.y, k[4 * q + 2] = x.z, k[4 * q + 3] = x.w;
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < kSortItems; r++) k[r] = first + r < cap ? keys[first + r] : 0u;
+            for (int r = 0; r < kRadixItems; r++) k[r] = first + r < cap ? keys[first + r] : 0u;
         }
-        const uint32_t m = n - first < (uint32_t)kSortItems ? n - first : (uint32_t)kSortItems;
+        const uint32_t m = n - first < (uint32_t)kRadixItems ? n - first : (uint32_t)kRadixItems;
         uint32_t d = (k[0] >> shift) & (kRadix - 1), run = 1;
 #pragma unroll
-        for (int r = 1; r < kSortItems; r++) {
+        for (int r = 1; r < kRadixItems; r++) {
             if ((uint32_t)r >= m) break;
             const uint32_t dr = (k[r] >> shift) & (kRadix - 1);
             if (dr != d) {
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ 
     __shared__ uint32_t s_w[4];
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
     const uint32_t n = dev_count(n_dev, n_host, cap);
-    const int live = (int)((n + kSortTile - 1) / kSortTile);
+    const int live = (int)((n + kRadixTile - 1) / kRadixTile);
     const int nb = live < nblocks ? live : nblocks;
     const int per = (nb + 255) / 256;
     const int b0 = threadIdx.x * per;
@@ -233,8 +235,8 @@ __global__ __launch_bounds__(256) void k_radix_scan_rows(uint32_t *__restrict__ 
     if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-// Block b sorts items [b*4096, (b+1)*4096): wave w owns the 1024 items from b*4096 + w*1024 on,
-// 64 per round, so (wave, round, lane) order is input order and each wave ranks its items with
+// Block b sorts items [b*kRadixTile, (b+1)*kRadixTile): wave w owns the quarter from
+// b*kRadixTile + w*kRadixTile/4 on, 64 per round, so (wave, round, lane) order is input order and each wave ranks its items with
 // its own running digit counts, without a workgroup barrier per round; the four waves' counts
 // then give every digit's local start and each wave's offset inside it.
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
@@ -243,15 +245,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
                                                        const uint32_t *n_dev, uint32_t n_host, uint32_t cap, int shift,
                                                        int nblocks, const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ totals) {
-    constexpr int kWaveItems = kSortTile / 4;
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    constexpr int kWaveItems = kRadixTile / 4;
+    __shared__ uint32_t s_keys[kRadixTile];
+    __shared__ uint32_t s_vals[kRadixTile];
     __shared__ uint32_t s_wcnt[4][kRadix];  // per-wave running counts, then per-wave starts
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_w[4];
     const uint32_t n = dev_count(n_dev, n_host, cap);
-    const uint32_t base = blockIdx.x * kSortTile;
+    const uint32_t base = blockIdx.x * kRadixTile;
     if (base >= n) return;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     // global start of digit t for this block
@@ -260,10 +262,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     s_gbase[t] = dstart + hist[t * nblocks + blockIdx.x];
     for (int k = 0; k < 4; k++) s_wcnt[k][t] = 0;
     __syncthreads();
-    uint32_t mk[kSortItems], mv[kSortItems], mrank[kSortItems], mv2[kSortItems];
+    uint32_t mk[kRadixItems], mv[kRadixItems], mrank[kRadixItems], mv2[kRadixItems];
     const uint64_t lt = lanemask_lt();
     const uint32_t wbase = base + w * kWaveItems;
-    for (int r = 0; r < kSortItems; r++) {
+    for (int r = 0; r < kRadixItems; r++) {
         const uint32_t idx = wbase + r * 64 + lane;
         const bool valid = idx < n;
         mk[r] = valid ? kin[idx] : 0u;
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         s_wcnt[3][t] = ls + c0 + c1 + c2;
     }
     __syncthreads();
-    for (int r = 0; r < kSortItems; r++) {
+    for (int r = 0; r < kRadixItems; r++) {
         if (wbase + r * 64 + lane < n) {
             const uint32_t p = s_wcnt[w][(mk[r] >> shift) & (kRadix - 1)] + mrank[r];
             s_keys[p] = mk[r];
@@ -296,8 +298,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         }
     }
     __syncthreads();
-    const uint32_t bn = (n - base) < (uint32_t)kSortTile ? (n - base) : (uint32_t)kSortTile;
-    for (int r = 0; r < kSortItems; r++) {
+    const uint32_t bn = (n - base) < (uint32_t)kRadixTile ? (n - base) : (uint32_t)kRadixTile;
+    for (int r = 0; r < kRadixItems; r++) {
         const uint32_t p = r * kSortThreads + t;
         if (p < bn) {
             const uint32_t k = s_keys[p];
@@ -310,12 +312,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     if (vin2) {
         // the second payload takes the same permutation through the same LDS staging
         __syncthreads();
-        for (int r = 0; r < kSortItems; r++) {
+        for (int r = 0; r < kRadixItems; r++) {
             if (wbase + r * 64 + lane < n)
                 s_vals[s_wcnt[w][(mk[r] >> shift) & (kRadix - 1)] + mrank[r]] = mv2[r];
         }
         __syncthreads();
-        for (int r = 0; r < kSortItems; r++) {
+        for (int r = 0; r < kRadixItems; r++) {
             const uint32_t p = r * kSortThreads + t;
             if (p < bn) {
                 const uint32_t d = (s_keys[p] >> shift) & (kRadix - 1);
@@ -438,10 +440,12 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 BinWs layout(void *base, int64_t VN, int64_t cap, int64_t VT) {
     BinWs w{};
-    const int64_t nb_vn = ceil_div(VN > 0 ? VN : 1, kSortTile), nb_cap = ceil_div(cap > 0 ? cap : 1, kSortTile);
-    const int64_t nb_vt = ceil_div(VT > 0 ? VT : 1, kSortTile);
-    int64_t nbm = nb_vn > nb_cap ? nb_vn : nb_cap;
-    nbm = nbm > nb_vt ? nbm : nb_vt;
+    const int64_t nb_vn = ceil_div(VN > 0 ? VN : 1, kSortTile);
+    // histogram rows are as long as the largest sort's block count
+    int64_t nbm = ceil_div(VN > 0 ? VN : 1, kRadixTile), nbc = ceil_div(cap > 0 ? cap : 1, kRadixTile);
+    nbm = nbm > nbc ? nbm : nbc;
+    nbc = ceil_div(VT > 0 ? VT : 1, kRadixTile);
+    nbm = nbm > nbc ? nbm : nbc;
     char *p = static_cast<char *>(base);
     size_t off = 0;
     auto take = [&](size_t words) {
@@ -461,7 +465,7 @@ BinWs layout(void *base, int64_t VN, int64_t cap, int64_t VT) {
 gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, const uint32_t *n_dev,
                       uint32_t n_host, uint32_t cap, int bits, uint32_t *hist, uint32_t *totals, hipStream_t st,
                       uint32_t **w = nullptr, uint32_t **w2 = nullptr) {
-    const int nb = (int)ceil_div(cap, kSortTile);
+    const int nb = (int)ceil_div(cap, kRadixTile);
     for (int shift = 0; shift < bits; shift += kRadixBits) {
         k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, n_host, cap, shift, nb, hist);
         k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals, n_dev, n_host, cap);
@@ -579,7 +583,7 @@ extern "C" gsr_status gsr_scan_launch(const uint32_t *in, int64_t n, uint32_t *o
 // ping-ponging between (k, v) and (k2, v2): the result is in (k, v) when ceil(bits / 8) is even,
 // else in (k2, v2).  ws: gsr_sort_pairs_ws_bytes(n).
 extern "C" size_t gsr_sort_pairs_ws_bytes(int64_t n) {
-    return (size_t)((int64_t)kRadix * ceil_div(n > 0 ? n : 1, kSortTile) * 4 + kRadix * 4 + 512);
+    return (size_t)((int64_t)kRadix * ceil_div(n > 0 ? n : 1, kRadixTile) * 4 + kRadix * 4 + 512);
 }
 
 // As gsr_sort_pairs_launch with the count read on the device (*n_dev, at most cap).
@@ -588,7 +592,7 @@ extern "C" gsr_status gsr_sort_pairs_dev_launch(uint32_t *k, uint32_t *v, uint32
                                                 hipStream_t st) {
     if (cap == 0) return GSR_OK;
     uint32_t *hist = static_cast<uint32_t *>(ws);
-    uint32_t *totals = hist + (size_t)kRadix * ceil_div(cap, kSortTile);
+    uint32_t *totals = hist + (size_t)kRadix * ceil_div(cap, kRadixTile);
     return radix_sort(k, v, k2, v2, n_dev, cap, cap, bits, hist, totals, st);
 }
 
@@ -596,7 +600,7 @@ extern "C" gsr_status gsr_sort_pairs_launch(uint32_t *k, uint32_t *v, uint32_t *
                                             void *ws, hipStream_t st) {
     if (n == 0) return GSR_OK;
     uint32_t *hist = static_cast<uint32_t *>(ws);
-    uint32_t *totals = hist + (size_t)kRadix * ceil_div(n, kSortTile);
+    uint32_t *totals = hist + (size_t)kRadix * ceil_div(n, kRadixTile);
     return radix_sort(k, v, k2, v2, nullptr, n, n, bits, hist, totals, st);
 }
 
