@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         const bool valid = idx < n;
         mk[r] = valid ? kin[idx] : 0u;
         mv[r] = valid ? vin[idx] : 0u;
-        mv2[r] = (valid && vin2) ? vin2[idx] : 0u;
+        mv2[r] = vin2 ? (valid ? vin2[idx] : 0u) : idx;
         const uint32_t d = (mk[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit8(d, valid);
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
@@ -309,8 +309,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
             vout[dst] = s_vals[p];
         }
     }
-    if (vin2) {
-        // the second payload takes the same permutation through the same LDS staging
+    if (vout2) {
+        // the second payload takes the same permutation through the same LDS staging (without
+        // vin2 it is each item's input position)
         __syncthreads();
         for (int r = 0; r < kRadixItems; r++) {
             if (wbase + r * 64 + lane < n)
@@ -349,12 +350,13 @@ __global__ __launch_bounds__(256) void k_inst_count(const uint32_t *__restrict__
 // k mod 256, which finds its pair by binary search over the pairs' offsets in LDS), so the
 // writes are coalesced.  A pair's tiles are emitted row-major and consecutively ("emission
 // order").  With pair_gid: the emission-ordered list of visible pairs and the emission index of
-// each pair's first instance, and the sort's second payload (each instance's emission index).
+// each pair's first instance.  (Each instance's emission index is its position here: the sort's
+// first pass generates it as the second payload.)
 __global__ __launch_bounds__(256) void k_inst_emit(const uint32_t *__restrict__ sorted_gid, const uint32_t *n_vis,
                                                    uint32_t cap_vis, const uint32_t *__restrict__ info, uint32_t VN,
                                                    uint32_t n, uint32_t T, uint32_t ntx,
                                                    const uint32_t *__restrict__ boff, uint32_t *__restrict__ ikey,
-                                                   uint32_t *__restrict__ ival, uint32_t *__restrict__ iemit,
+                                                   uint32_t *__restrict__ ival,
                                                    uint32_t *__restrict__ pair_gid, uint32_t *__restrict__ pair_first,
                                                    uint32_t cap) {
     __shared__ uint32_t s_w[4];
@@ -394,7 +396,6 @@ __global__ __launch_bounds__(256) void k_inst_emit(const uint32_t *__restrict__ 
         if (pos < cap) {
             ikey[pos] = (g / n) * T + (ty0 + ly) * ntx + tx0 + lx;
             ival[pos] = g;
-            if (iemit) iemit[pos] = pos;
         }
     }
 }
@@ -464,12 +465,15 @@ BinWs layout(void *base, int64_t VN, int64_t cap, int64_t VT) {
 
 gsr_status radix_sort(uint32_t *&k, uint32_t *&v, uint32_t *&k2, uint32_t *&v2, const uint32_t *n_dev,
                       uint32_t n_host, uint32_t cap, int bits, uint32_t *hist, uint32_t *totals, hipStream_t st,
-                      uint32_t **w = nullptr, uint32_t **w2 = nullptr) {
+                      uint32_t **w = nullptr, uint32_t **w2 = nullptr, bool w_is_position = false) {
     const int nb = (int)ceil_div(cap, kRadixTile);
     for (int shift = 0; shift < bits; shift += kRadixBits) {
         k_radix_hist<<<nb, kSortThreads, 0, st>>>(k, n_dev, n_host, cap, shift, nb, hist);
         k_radix_scan_rows<<<kRadix, 256, 0, st>>>(hist, nb, totals, n_dev, n_host, cap);
-        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, w ? *w : nullptr, w ? *w2 : nullptr, n_dev,
+        // w_is_position: the second payload starts as each item's input position, generated by
+        // the first pass instead of read
+        const uint32_t *win = w && !(w_is_position && shift == 0) ? *w : nullptr;
+        k_radix_scatter<<<nb, kSortThreads, 0, st>>>(k, v, k2, v2, win, w ? *w2 : nullptr, n_dev,
                                                      n_host, cap, shift, nb, hist, totals);
         uint32_t *tk = k, *tv = v;
         k = k2; v = v2; k2 = tk; v2 = tv;
@@ -523,12 +527,12 @@ extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V
     uint32_t *ew = inst_emit ? ((passes % 2 == 0) ? inst_emit : w.iw1) : nullptr;
     uint32_t *ow = inst_emit ? ((passes % 2 == 0) ? w.iw1 : inst_emit) : nullptr;
     k_inst_emit<<<nb_p, 256, 0, st>>>(v, w.n_vis, (uint32_t)(VN > 0 ? VN : 1), info, (uint32_t)VN, (uint32_t)n, T,
-                                      (uint32_t)ntx, w.cnt_b, ek, ev, ew, em ? em->pair_gid : nullptr,
+                                      (uint32_t)ntx, w.cnt_b, ek, ev, em ? em->pair_gid : nullptr,
                                       em ? em->pair_first : nullptr, (uint32_t)cap);
     if (em) k_copy_u32<<<1, 64, 0, st>>>(w.n_vis, em->n_pairs, 1);
     // 4. stable sort by view-tile (carrying the emission index along when asked for)
     s = radix_sort(ek, ev, ok, ov, n_inst, 0, (uint32_t)cap, passes * kRadixBits, w.hist, w.totals, st,
-                   inst_emit ? &ew : nullptr, inst_emit ? &ow : nullptr);
+                   inst_emit ? &ew : nullptr, inst_emit ? &ow : nullptr, true);
     if (s != GSR_OK) return s;
     // 5. per view-tile [start, end)
     k_fill_u32<<<(int)ceil_div(2 * (int64_t)V * T, 256) < 4096 ? (int)ceil_div(2 * (int64_t)V * T, 256) : 4096, 256, 0,
