@@ -142,3 +142,33 @@ def test_masked_ssim_loss_through_the_renderer():
     for k in gsr.PARAM_NAMES:
         bad = grad_close(grads[k].cpu().numpy(), ob[k], mask=keep)
         assert bad.sum() == 0, (k, int(bad.sum()))
+
+
+def test_full_loss_headline_size():
+    """The full loss in the timed step's configuration: 8 views of 1280x720 in one launch, the
+    support mask (tau_geo 0.5, erosion radius 2) and lambda = (0.8, 0.2, 0.2).  Every gradient
+    pixel of two views against the oracle; the last view's mask is empty, so its gradients are
+    exactly zero."""
+    import paper_2604_12942_amd as gsr
+    V, S, H, W = 8, 16, 720, 1280
+    rgb, trgb, dep, tdep, T, idx = _loss_inputs(12, V, S, H, W)
+    raster = gsr.Raster(W, H, 8, 32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    mask, count = gsr.support_mask(t(T), V, raster, 0.5, 2)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gC = torch.full((V, 3, H, W), np.nan, device="cuda")
+    gD = torch.full((V, H, W), np.nan, device="cuda")
+    gsr.loss(t(rgb), t(dep), t(trgb), t(tdep), V, raster, loss, gC, gD, mask=mask, count=count, lambda_rgb=0.8,
+             lambda_ssim=0.2, lambda_depth=0.2, target_index=t(idx))
+    torch.cuda.synchronize()
+    gC, gD = gC.cpu().numpy(), gD.cpu().numpy()
+    assert np.isfinite(loss.item()) and np.all(np.isfinite(gC)) and np.all(np.isfinite(gD))
+    for v in (0, 3):
+        M = lo.support_masks(T[v], 0.5, 2)[1]
+        assert 0 < M.sum() < M.size
+        _, eC, eD = lo.masked_loss(rgb[v], dep[v], trgb[idx[v]], tdep[idx[v]], M, 0.8, 0.2, 0.2)
+        for c in range(3):
+            bad = grad_close(gC[v, c], eC[c])
+            assert bad.sum() == 0, (v, c, int(bad.sum()))
+        assert grad_close(gD[v], eD).sum() == 0, v
+    assert not np.any(gC[V - 1]) and not np.any(gD[V - 1])
