@@ -54,7 +54,9 @@ def splat_fields(rast):
     """Decode the 48-byte splat records: u, v (float64), l11, l21, l22, opacity, depth, r, g, b."""
     raw = rast.splats.cpu().numpy().view(np.uint8).reshape(-1, 48)
     uv = raw[:, :16].copy().view(np.float64).reshape(-1, 2)
-    f = raw[:, 16:].copy().view(np.float32).reshape(-1, 8).astype(np.float64)
+    # records of pairs no tile uses are never written: their bytes may be signalling NaNs
+    with np.errstate(invalid="ignore"):
+        f = raw[:, 16:].copy().view(np.float32).reshape(-1, 8).astype(np.float64)
     return dict(u=uv[:, 0], v=uv[:, 1], l11=f[:, 0], l21=f[:, 1], l22=f[:, 2], opacity=f[:, 3], depth=f[:, 4],
                 r=f[:, 5], g=f[:, 6], b=f[:, 7])
 
