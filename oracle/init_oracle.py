@@ -187,11 +187,13 @@ def rot_to_quat(R):
 
 def prediction_valid(pred):
     """Eq. 3's "valid model prediction": every output finite and each log-scale within
-    [log 2 mm, log 0.5 m].  pred [V, 8] = (s[3], q[4], omega)."""
+    [log 2 mm, log 0.5 m].  pred [V, 8] = (s[3], q[4], omega).  The network's outputs are float32,
+    so the bound test is taken in float32: both the log-scale and the two bounds are rounded to
+    float32 before comparing (inclusive at both ends)."""
     pred = np.asarray(pred, np.float64)
     fin = np.all(np.isfinite(pred), axis=1) & (np.linalg.norm(pred[:, 3:7], axis=1) > 0)
-    s = pred[:, :3]
-    return fin & np.all((s >= LOG_S_MIN) & (s <= LOG_S_MAX), axis=1)
+    s = pred[:, :3].astype(np.float32)
+    return fin & np.all((s >= np.float32(LOG_S_MIN)) & (s <= np.float32(LOG_S_MAX)), axis=1)
 
 
 def cascade(points, colors, depth, segment, vox, pred=None, f=640.0, beta=None, sh_degree=0, anchored=False):

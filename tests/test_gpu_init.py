@@ -196,3 +196,36 @@ def test_voxel_pca_with_point_covariances_matches_oracle():
     bad = np.abs(g[sel] - exp[sel]) > 1e-4 * scale[sel] + 1e-12
     assert bad.sum() == 0, np.argwhere(bad)[:5]
     assert not g[o["cls"] == io.UNRELIABLE].any()
+
+
+def test_cascade_validity_bounds_match_oracle():
+    """Predictions exactly at the float32 log-scale bounds (valid) and one float32 step outside
+    them (invalid) take the oracle's branch: the bound test is inclusive and taken in float32."""
+    import paper_2604_12942_amd as gsr
+    n = 6000
+    pts, col, rng_, seg = _room_points(n, seed=3)
+    t, vox = _run(pts, 5)
+    o = io.voxel_pca(pts, 5)
+    nv = len(o["n"])
+    lo32, hi32 = np.float32(np.log(0.002)), np.float32(np.log(0.5))
+    edge = [lo32, np.nextafter(lo32, np.float32(-np.inf)), hi32, np.nextafter(hi32, np.float32(np.inf)),
+            np.nextafter(lo32, np.float32(0)), np.nextafter(hi32, np.float32(-1))]
+    pred = np.zeros((nv, 8), np.float32)
+    pred[:, :3] = np.log(0.05)
+    pred[:, 3] = 1.0
+    for v in range(nv):
+        pred[v, v % 3] = edge[v % len(edge)]
+    pred[5::11, 3:7] = 0.0  # zero quaternions
+    pt = np.zeros((8, n), np.float32)
+    pt[:, :nv] = pred.T
+    P, br = gsr.cascade(t, torch.from_numpy(np.ascontiguousarray(col.T)).cuda(), torch.from_numpy(rng_).cuda(), vox,
+                        pred=torch.from_numpy(pt).cuda(), focal=640.0, beta=0.0,
+                        segment=torch.from_numpy(seg).cuda(), n_segments=3, sh_degree=0)
+    torch.cuda.synchronize()
+    g = io.cascade(pts, col, rng_, seg, o, pred=pred.astype(np.float64), f=640.0, sh_degree=0)
+    valid = io.prediction_valid(pred.astype(np.float64))
+    assert valid.sum() > 0 and (~valid).sum() > 0
+    b = br.cpu().numpy()
+    assert np.array_equal(b == 0, valid[o["voxel"]])
+    ok = _margins_ok(o)[o["voxel"]]
+    assert np.array_equal(b[ok], g["branch"][ok])
