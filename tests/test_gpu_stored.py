@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from gpu_common import GRAD_RTOL, KNIFE, grad_close, run_forward
-from test_gpu_parity import SCENES, _upstream
+from test_gpu_parity import SCENES, _no_live_knife, _pose_close, _upstream
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +47,9 @@ def test_stored_backward_matches_oracle_and_recompute(name):
     import paper_2604_12942_amd as gsr
     g, cams = SCENES[name]
     cam = cams[0]
-    GC, GD = _upstream(cam, 5)
+    GC, GD = _upstream(g, cam, 5)
     o = oracle.render_bwd(g, cam, GC.astype(np.float64), GD.astype(np.float64))
+    assert _no_live_knife(o, GC, GD)
     res = {}
     for mode in ("recompute", "stored"):
         out, rast, P, ct = run_forward(g, cams, mode=mode)
@@ -58,21 +59,18 @@ def test_stored_backward_matches_oracle_and_recompute(name):
                               torch.from_numpy(GD[None]).cuda(), grads)
         torch.cuda.synchronize()
         res[mode] = (rast.dsplat_copy.cpu().numpy().astype(np.float64), grads, dpose.cpu().numpy())
-    keep = ~o["knife_g"]
     n = g["means"].shape[1]
     ds, grads, dpose = res["stored"]
     for e in range(10):
-        bad = grad_close(ds.reshape(-1, 10)[:n, e], o["screen"][:, e], mask=keep)
+        bad = grad_close(ds.reshape(-1, 10)[:n, e], o["screen"][:, e])
         assert bad.sum() == 0, ("screen", e, bad.sum())
     for k in gsr.PARAM_NAMES:
-        bad = grad_close(grads[k].cpu().numpy().astype(np.float64), o[k], mask=keep)
+        bad = grad_close(grads[k].cpu().numpy().astype(np.float64), o[k])
         assert bad.sum() == 0, (k, bad.sum())
     # the two modes differ only in float summation order
     dr = res["recompute"][0]
     assert np.all(np.abs(ds - dr) <= 1e-4 * (np.abs(dr) + np.sqrt(np.mean(dr ** 2))))
-    if o["n_knife"] == 0:
-        p = dpose[0]
-        assert np.all(np.abs(p - o["pose"]) <= GRAD_RTOL * (np.abs(o["pose"]) + np.sqrt(np.mean(o["pose"] ** 2))))
+    assert np.any(o["pose"] != 0) and _pose_close(dpose[0], o["pose"]), (dpose[0], o["pose"])
 
 
 def test_stored_list_capacity_regrow():
