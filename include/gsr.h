@@ -131,8 +131,13 @@ GSR_API gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams, i
  *   inst_gid    [capacity]  v*n + i of each instance, in sorted order
  *   tile_ranges [V*T][2]    [start, end) of each view-tile's instances
  *   *n_instances            (uint32) the REQUIRED instance count M.
- * If M > capacity nothing beyond capacity is written and the results are incomplete: the caller
- * compares *n_instances with capacity after synchronising and re-runs with more room.
+ * If M > capacity the lists would be incomplete, so the call leaves a frame in which nothing is
+ * visible instead: row 0 of tile_info is cleared (which is why tile_info is not const), every
+ * tile range is empty and em->n_pairs is 0.  Everything later in the step then does nothing:
+ * the renders write background images, the backward zero gradients and no pose gradient, and the
+ * fused Adam and the visible list find no row; no kernel reads past the capacity.  *n_instances
+ * still receives M: the caller compares it with capacity after synchronising, grows the buffers
+ * and runs gsr_project and gsr_bin_sort again (a captured step is captured again).
  * tile_order (device uint32 [V*T], may be NULL) receives the view-tiles sorted by descending
  * instance count (ties by index): the longest-processing-time-first launch order the render
  * kernels use to keep heavy tiles off the tail of the grid.
@@ -149,7 +154,7 @@ typedef struct {
     uint32_t *n_pairs;    /* [1]: number of listed pairs                                      */
 } gsr_emission;
 GSR_API size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t capacity, const gsr_raster *r);
-GSR_API gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
+GSR_API gsr_status gsr_bin_sort(uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
                                 uint32_t *inst_gid, const gsr_emission *em, int64_t capacity,
                                 uint32_t *tile_ranges, uint32_t *n_instances, uint32_t *tile_order, void *ws,
                                 size_t ws_bytes, gsr_stream stream);
@@ -227,8 +232,10 @@ GSR_API gsr_status gsr_render_bwd_stored(const gsr_splat *splats, const uint32_t
  * stores, at dinst[inst_emit[k]][0..9] (inst_emit = gsr_emission.inst_emit) (float32 [capacity][GSR_SPLAT_GRAD_FLOATS]), the
  * screen-space gradient that its tile's pixels give its (view, Gaussian) pair: plain stores, no
  * accumulation and no clearing needed.  A pair's gradient is the sum of its instances' records
- * (gsr_pair_grads, or inside gsr_project_bwd), taken in a fixed order, so results repeat
- * bit-for-bit from run to run. */
+ * (gsr_pair_grads, or inside gsr_project_bwd), taken in a fixed order.  Each record, though, is
+ * the sum of its tile's pixel terms formed by the four waves of a workgroup, whose adds into
+ * shared memory come in an order that varies from run to run: gradients repeat from run to run
+ * only up to float32 rounding, not bit for bit. */
 GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
                                   const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
                                   int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,

@@ -198,6 +198,7 @@ def visible_list(tile_info, n, n_views, out_list, out_count, ws):
                                  ws.numel() * ws.element_size(), _stream()), "gsr_visible_list")
 
 
+
 def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dinst, em, tile_info, m, v, lr, step_dev,
                      dpose, ws,
                      segment_id=None, min_segment=0, row_mask=None, beta1=0.9, beta2=0.999, eps=1e-15,
@@ -529,11 +530,17 @@ class Rasterizer:
         wsf = render_fwd_sliced_workspace(self.V, self.raster, self.capacity)
         self.fwd_ws = torch.empty((wsf + 255) // 256 * 64, dtype=torch.int32, device=self.device)
 
+    def project(self, P, sh_degree, cams):
+        """gsr_project into this rasterizer's buffers (remembered, so that a bin/sort whose
+        instances overflowed the capacity can project again after growing it)."""
+        self._proj_args = (P, sh_degree, cams)
+        project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
+
     def forward(self, P, sh_degree, cams, check_capacity=True, sliced=True):
         """project -> bin/sort -> render; returns (rgb, depth, T_final) views of the buffers.
         sliced=False composites every tile whole (gsr_render_fwd) instead of cutting long tiles
         into depth slices (gsr_render_fwd_sliced)."""
-        project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
+        self.project(P, sh_degree, cams)
         self.bin(check_capacity)
         if self.mode == "stored":
             self.render_stored(cams, check_capacity)
@@ -560,15 +567,21 @@ class Rasterizer:
         return int(self.n_contrib_total.item()) & 0xFFFFFFFF
 
     def bin(self, check_capacity=True):
+        """gsr_bin_sort.  An overflow of the instance capacity empties the frame (see gsr_bin_sort);
+        with check_capacity the buffers then grow and the projection and binning run again."""
         def run():
             bin_sort(self.tile_info, self.n, self.V, self.raster, self.inst_gid, self.capacity, self.tile_ranges,
                      self.n_instances, self.bin_ws, self.tile_order, self.em)
         run()
-        if check_capacity:
-            m = int(self.n_instances.item()) & 0xFFFFFFFF
-            if m > self.capacity:
-                self._alloc_instances(int(m * 1.25) + 1024)
-                run()
+        if check_capacity and self.overflowed():
+            self._alloc_instances(int(self.instances() * 1.25) + 1024)
+            P, sh_degree, cams = self._proj_args
+            project(P, sh_degree, cams, self.V, self.raster, self.splats, self.tile_info)
+            run()
+
+    def overflowed(self):
+        """Whether the last bin/sort needed more instances than the capacity (synchronises)."""
+        return self.instances() > self.capacity
 
     def instances(self):
         return int(self.n_instances.item()) & 0xFFFFFFFF

@@ -15,7 +15,7 @@ extern "C" size_t gsr_visible_list_ws_bytes(int64_t n);
 extern "C" gsr_status gsr_visible_list_launch(const uint32_t *, int64_t, int, uint32_t *, uint32_t *, void *,
                                               hipStream_t);
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT);
-extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *, int64_t, int, int, int, uint32_t *, const gsr_emission *,
+extern "C" gsr_status gsr_bin_sort_launch(uint32_t *, int64_t, int, int, int, uint32_t *, const gsr_emission *,
                                           int64_t, uint32_t *, uint32_t *, uint32_t *, void *, hipStream_t);
 extern "C" size_t gsr_render_fwd_ws_bytes(int, const gsr_raster *, int64_t);
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
@@ -138,7 +138,7 @@ extern "C" size_t gsr_bin_sort_workspace(int64_t n, int32_t n_views, int64_t cap
     return gsr_bin_sort_ws_bytes((int64_t)n_views * n, capacity, (int64_t)n_views * tiles(r));
 }
 
-extern "C" gsr_status gsr_bin_sort(const uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
+extern "C" gsr_status gsr_bin_sort(uint32_t *tile_info, int64_t n, int32_t n_views, const gsr_raster *r,
                                    uint32_t *inst_gid, const gsr_emission *em, int64_t capacity,
                                    uint32_t *tile_ranges, uint32_t *n_instances, uint32_t *tile_order, void *ws,
                                    size_t ws_bytes, gsr_stream stream) {

@@ -420,6 +420,20 @@ __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, const uint32_t 
     }
 }
 
+// An instance count above the capacity leaves incomplete lists.  Rather than render them, the
+// frame is emptied: no pair visible (tile_info row 0 cleared), every tile range empty and no
+// emitted pair, so the render, backward, pair sums, projection backward, fused Adam and visible
+// list that follow on the stream do nothing.  A no-op when the instances fit.
+__global__ void k_overflow_clear(const uint32_t *__restrict__ n_inst, uint32_t cap, uint32_t *__restrict__ ntiles,
+                                 uint32_t VN, uint32_t *__restrict__ ranges, uint32_t VT2,
+                                 uint32_t *__restrict__ n_pairs) {
+    if (*n_inst <= cap) return;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VN; i += stride) ntiles[i] = 0u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT2; i += stride) ranges[i] = 0u;
+    if (n_pairs && blockIdx.x == 0 && threadIdx.x == 0) *n_pairs = 0u;
+}
+
 }  // namespace gsr
 
 using namespace gsr;
@@ -496,7 +510,7 @@ int bit_length(uint64_t x) {
 
 extern "C" size_t gsr_bin_sort_ws_bytes(int64_t VN, int64_t cap, int64_t VT) { return layout(nullptr, VN, cap, VT).bytes; }
 
-extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V, int ntx, int nty,
+extern "C" gsr_status gsr_bin_sort_launch(uint32_t *info, int64_t n, int V, int ntx, int nty,
                                           uint32_t *inst_gid, const gsr_emission *em, int64_t cap,
                                           uint32_t *ranges, uint32_t *n_inst, uint32_t *tile_order, void *ws,
                                           hipStream_t st) {
@@ -539,6 +553,8 @@ extern "C" gsr_status gsr_bin_sort_launch(const uint32_t *info, int64_t n, int V
                  st>>>(ranges, 0u, 2 * (int64_t)V * T);
     const int nr = (int)(ceil_div(cap, 256) < 8192 ? ceil_div(cap, 256) : 8192);
     k_tile_ranges<<<nr, 256, 0, st>>>(ek, n_inst, (uint32_t)cap, ranges);
+    k_overflow_clear<<<256, 256, 0, st>>>(n_inst, (uint32_t)cap, info, (uint32_t)VN, ranges, (uint32_t)(2 * VT),
+                                          em ? em->n_pairs : nullptr);
     // 6. longest-processing-time order of the view-tiles (descending instance count)
     if (tile_order) {
         const int nt = (int)(ceil_div(VT, 256) < 4096 ? ceil_div(VT, 256) : 4096);

@@ -153,7 +153,7 @@ class MapOptimizer:
             self.view_idx32.copy_(self.view_idx)
 
         def proj():
-            project(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.tile_info)
+            r.project(self.P, self.sh_degree, self.cams)
 
         def binsort():
             r.bin(check_capacity)
@@ -224,6 +224,7 @@ class MapOptimizer:
         if not self.fused:
             raise ValueError("graph capture needs the fused step (its Adam step counter lives on the device)")
         fns = self._stage_fns(False)
+        self._split = tuple(split)
         cuts = [0] + [self.STAGES.index(c) for c in split] + [len(fns)]
         self.graphs = []
         torch.cuda.synchronize()
@@ -236,11 +237,34 @@ class MapOptimizer:
         torch.cuda.synchronize()
         return self.graphs
 
-    def replay(self, between=None):
+    def replay(self, between=None, check_capacity=True):
         """One step from the captured graphs; between(k) is called after part k (not after the
-        last)."""
+        last).  A step whose instances overflow the captured capacity changes nothing (the bin/sort
+        empties its frame); with check_capacity (one device synchronisation per step) that is
+        detected here, the capacity grows, the step is captured again and run again.  Without it
+        the caller checks overflowed() itself."""
         for k, g in enumerate(self.graphs):
             if k and between:
                 between(k)
             g.replay()
+        if check_capacity and self.rast.overflowed():
+            self.recapture()
+            for g in self.graphs:
+                g.replay()
+            if self.rast.overflowed():
+                raise RuntimeError("instance capacity still too small after regrowing")
         return self.loss
+
+    def overflowed(self):
+        """Whether the last step's instances overflowed the capacity (synchronises)."""
+        return self.rast.overflowed()
+
+    def recapture(self, headroom=1.25):
+        """Grow the instance capacity to headroom x the last required count and capture the step
+        again with the same cuts.  The overflowed step left no trace but its Adam step number,
+        which is taken back."""
+        r = self.rast
+        need = r.instances()
+        r._alloc_instances(max(int(need * headroom) + 1024, r.capacity))
+        self.step_dev -= 1
+        self.capture(self._split)

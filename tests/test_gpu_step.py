@@ -100,3 +100,74 @@ def test_graph_replay_matches_eager_step(full):
             pa, pb = a.P[name].cpu().numpy(), b.P[name].cpu().numpy()
             assert np.allclose(pa, pb, rtol=2e-6, atol=1e-6), (k, name)
     assert int(b.step_dev.item()) == len(views)
+
+
+def _three_views(seed):
+    c = synth.config4a()
+    rng = np.random.default_rng(seed)
+    cams = [c["cameras"][0]]
+    for k in range(2):
+        cams.append(synth.make_camera(synth.small_rotation(rng, 8.0), rng.uniform(-0.2, 0.2, 3), 125.0, 125.0, 80.0,
+                                      60.0, 160, 120))
+    H, W = 120, 160
+    trgb = torch.from_numpy(rng.uniform(0, 1, (3, 3, H, W)).astype(np.float32)).cuda()
+    tdep = torch.from_numpy(rng.uniform(2, 10, (3, H, W)).astype(np.float32)).cuda()
+    return c["gaussians"], cams, trgb, tdep
+
+
+def test_overflowed_bin_sort_changes_nothing():
+    """A bin/sort whose instances exceed the capacity empties its frame: no visible pair, empty
+    tile ranges, no emitted pair; the render is background and the fused backward + Adam step
+    leaves every parameter, moment and pose gradient untouched."""
+    import paper_2604_12942_amd as gsr
+    g, cams, trgb, tdep = _three_views(4)
+    o = _opt(True, g, cams, trgb, tdep, None, 0)
+    o.set_views([0, 1, 2])
+    o.step()  # sizes the buffers
+    torch.cuda.synchronize()
+    r = o.rast
+    need = r.instances()
+    r._alloc_instances(need // 2)
+    before = {k: o.P[k].clone() for k in gsr.PARAM_NAMES}
+    m_before = {k: o.m[k].clone() for k in gsr.PARAM_NAMES}
+    o.set_views([1, 2, 0])
+    o.step(check_capacity=False)
+    torch.cuda.synchronize()
+    assert r.overflowed() and r.instances() > r.capacity
+    assert torch.count_nonzero(r.tile_info.view(4, -1)[0]).item() == 0
+    assert torch.count_nonzero(r.tile_ranges).item() == 0
+    assert int(r.n_pairs.item()) == 0
+    assert torch.all(r.T_final == 1.0).item() and torch.count_nonzero(r.rgb).item() == 0
+    assert int(o.vis_count.item()) == 0 and torch.count_nonzero(o.row_mask).item() == 0
+    assert torch.count_nonzero(r.dpose).item() == 0
+    for k in gsr.PARAM_NAMES:
+        assert torch.equal(o.P[k], before[k]) and torch.equal(o.m[k], m_before[k]), k
+
+
+def test_replay_regrows_an_overflowed_capacity():
+    """A captured step whose view set needs more instances than the captured capacity is
+    detected after the replay, captured again with room and run again: the result follows the
+    eager optimiser that never overflowed."""
+    g, cams, trgb, tdep = _three_views(5)
+    a = _opt(True, g, cams, trgb, tdep, None, 0)
+    b = _opt(True, g, cams, trgb, tdep, None, 0)
+    views = [[0, 1, 2], [2, 0, 1], [1, 2, 0]]
+    for o in (a, b):
+        o.set_views(views[0])
+        o.step()
+    torch.cuda.synchronize()
+    b.rast._alloc_instances(b.rast.instances() // 2)
+    small = b.rast.capacity
+    b.capture(split=("render_bwd",))
+    for k in range(1, len(views)):
+        a.set_views(views[k])
+        la = float(a.step().item())
+        b.set_views(views[k])
+        lb = float(b.replay().item())
+        torch.cuda.synchronize()
+        assert abs(la - lb) <= 1e-6 * abs(la), (k, la, lb)
+    assert b.rast.capacity > small and not b.overflowed()
+    assert int(b.step_dev.item()) == len(views) == int(a.step_dev.item())
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        pa, pb = a.P[name].cpu().numpy(), b.P[name].cpu().numpy()
+        assert np.allclose(pa, pb, rtol=2e-6, atol=1e-6), name
