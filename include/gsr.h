@@ -304,6 +304,19 @@ GSR_API size_t gsr_visible_list_workspace(int64_t n);
 GSR_API gsr_status gsr_visible_list(const uint32_t *tile_info, int64_t n, int32_t n_views, uint32_t *list,
                                     uint32_t *count, void *ws, size_t ws_bytes, gsr_stream stream);
 
+/* gsr_visible_list for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same outputs, with no workspace argument.
+ * Its block counts live in a fixed device array inside the library (256 KiB, one copy on each GPU
+ * it runs on, held until the process ends), so n is limited to gsr_visible_list_noalloc_max()
+ * = 16,777,216 Gaussians; larger n returns GSR_E_CAPACITY before anything is launched.  The
+ * library allocates and frees nothing here.  The first call on a device looks the array's address
+ * up (no allocation); make that first call outside a graph capture.  All calls on one GPU share
+ * the array: calls that overlap in time on one GPU (two streams, two threads) race and must be
+ * ordered by the caller.  Errors as gsr_visible_list, plus GSR_E_HIP if the look-up fails. */
+GSR_API int64_t gsr_visible_list_noalloc_max(void);
+GSR_API gsr_status gsr_visible_list_noalloc(const uint32_t *tile_info, int64_t n, int32_t n_views, uint32_t *list,
+                                            uint32_t *count, gsr_stream stream);
+
 /* ---- sparse Adam -----------------------------------------------------------------------------
  * Sparse gradient optimiser of Sec. III-C (visible and unfrozen Gaussians only).  Up to 8
  * parameter groups, each a [cols][rows] component-major float32 tensor sharing the row count

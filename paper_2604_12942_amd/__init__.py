@@ -198,6 +198,12 @@ def visible_list(tile_info, n, n_views, out_list, out_count, ws):
                                  ws.numel() * ws.element_size(), _stream()), "gsr_visible_list")
 
 
+def visible_list_noalloc(tile_info, n, n_views, out_list, out_count):
+    """gsr_visible_list without a workspace (the library's fixed device scratch; n limited to
+    gsr_visible_list_noalloc_max())."""
+    check(lib().gsr_visible_list_noalloc(_ptr(tile_info), n, n_views, _ptr(out_list), _ptr(out_count), _stream()),
+          "gsr_visible_list_noalloc")
+
 
 def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dinst, em, tile_info, m, v, lr, step_dev,
                      dpose, ws,

@@ -95,6 +95,8 @@ _SIGS = {
                               P, P, P, C.c_int32, C.POINTER(AdamFused), P, P, P, C.c_size_t, P], C.c_int),
     "gsr_visible_list_workspace": ([C.c_int64], C.c_size_t),
     "gsr_visible_list": ([P, C.c_int64, C.c_int32, P, P, P, C.c_size_t, P], C.c_int),
+    "gsr_visible_list_noalloc_max": ([], C.c_int64),
+    "gsr_visible_list_noalloc": ([P, C.c_int64, C.c_int32, P, P, P], C.c_int),
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
     "gsr_loss_l1": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),

@@ -6,6 +6,8 @@
 // screen-space results within a rounding of the exact values of the float32 inputs.
 #include "gsr_internal.h"
 
+#include <mutex>
+
 namespace gsr {
 
 // Real spherical harmonics without Condon-Shortley phase, orthonormal, ordered (l, m = -l..l),
@@ -761,4 +763,46 @@ extern "C" gsr_status gsr_visible_list_launch(const uint32_t *info, int64_t n, i
     k_scan_blocks<<<1, 1024, 0, st>>>(bsum, nb, count);
     k_vis_any_write<<<nb, 256, 0, st>>>(info, n, V, bsum, list);
     return last_launch();
+}
+
+// ---- visible list without a workspace argument -------------------------------------------------
+// The block counts of gsr_visible_list live in a file-scope device array instead of a caller's
+// workspace.  Every GPU the library runs on holds its own copy until the process ends; its address
+// on each device is looked up once (hipGetSymbolAddress with that device current) and kept, and
+// only that address is ever handed to kernels.  Each of the first ceil(n / 256) words is written
+// by k_vis_any_count before k_scan_blocks reads it, so nothing has to be cleared between calls.
+namespace {
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 24;  // 16,777,216 Gaussians
+constexpr size_t kNoAllocWords = (size_t)(kNoAllocMaxN / 256) + 64;
+static_assert(kNoAllocWords * 4 >= (size_t)((kNoAllocMaxN / 256) * 4 + 256), "scratch covers the block counts");
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of the scratch array (nullptr on a HIP error).
+void *scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int64_t gsr_visible_list_noalloc_max(void) { return kNoAllocMaxN; }
+
+extern "C" gsr_status gsr_visible_list_noalloc(const uint32_t *tile_info, int64_t n, int32_t n_views, uint32_t *list,
+                                               uint32_t *count, gsr_stream stream) {
+    if (n < 0 || n_views < 1 || !count || (n > 0 && (!tile_info || !list))) return GSR_E_INVALID;
+    if (n > kNoAllocMaxN) return GSR_E_CAPACITY;
+    void *ws = scratch_on_current_device();
+    if (!ws) return GSR_E_HIP;
+    return gsr_visible_list_launch(tile_info, n, n_views, list, count, ws, static_cast<hipStream_t>(stream));
 }

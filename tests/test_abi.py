@@ -79,3 +79,15 @@ def test_new_entry_points_reject_invalid_arguments():
     assert L.gsr_row_order(None, None, 1000, P, P, wo, None) == 1          # no means
     assert L.gsr_row_order(P, None, -5, P, P, wo, None) == 1               # negative count
     assert L.gsr_row_order(P, None, 1000, P, P, wo - 1, None) == 2         # workspace too small
+
+
+def test_noalloc_visible_list_rejects_sizes_beyond_its_scratch():
+    # the allocation-free entry point checks n against its fixed scratch before any HIP call
+    from paper_2604_12942_amd import _abi
+    L = _abi.load()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the call is rejected on the host
+    big = L.gsr_visible_list_noalloc_max() + 1
+    assert L.gsr_visible_list_noalloc(fake, big, 1, fake, fake, None) == 2
+    assert L.gsr_visible_list_noalloc(fake, -1, 1, fake, fake, None) == 1
+    assert L.gsr_visible_list_noalloc(None, 10, 1, fake, fake, None) == 1
+    assert L.gsr_visible_list_noalloc(fake, 10, 0, fake, fake, None) == 1
