@@ -68,21 +68,57 @@ def voxel_inputs(points, vox):
     return X, F
 
 
-def forward(W, X, F, keep=False):
-    """Outputs [nv, 8]; with keep, also the intermediates the backward needs."""
+U32 = 2.0 ** -24  # float32 unit roundoff
+
+
+class Jitter:
+    """Knife-edge screen for the BF16 rounding points (test infrastructure, off by default).
+
+    A float32 evaluation of a sum of K terms in another order differs from the exact sum by at
+    most about K u S (u = 2^-24, S = the sum of the terms' magnitudes).  Where the exact value lies
+    that close to a BF16 rounding midpoint, the rounded value, and everything computed from it,
+    can differ by one BF16 step.  One Jitter realisation moves every value at a rounding point by
+    an independent uniform amount in [-c K u S, c K u S] before rounding (and before the ReLU
+    decision that precedes it); elements that move by more than a fraction of the parity
+    tolerance across a few seeded realisations are knife edges."""
+
+    def __init__(self, seed, c=1.0):
+        self.rng = np.random.default_rng(seed)
+        self.c = c
+
+    def __call__(self, a, K, S):
+        return a + self.rng.uniform(-1.0, 1.0, a.shape) * (self.c * K * U32) * S
+
+
+def _dense(x, w, b, jit):
+    """x @ w + b, moved by one jitter realisation if given."""
+    a = x @ w + b
+    if jit is not None:
+        a = jit(a, w.shape[0] + 1, np.abs(x) @ np.abs(w) + np.abs(b))
+    return a
+
+
+def forward(W, X, F, keep=False, jitter=None):
+    """Outputs [nv, 8]; with keep, also the intermediates the backward needs.  jitter: a Jitter
+    (knife-edge screen only; None for the definition)."""
     Wb = {k: bf16(W[k]) for k, _, _, _ in LAYERS}
     b = {bk: np.asarray(W[bk], np.float64) for _, bk, _, _ in LAYERS}
+    X = np.asarray(X, np.float64)
+    F = np.asarray(F, np.float64)
+    if jitter is not None:
+        X = jitter(X, 1, np.abs(X))
+        F = jitter(F, 2, np.abs(F))
     x = bf16(X)                                   # [nv, 32, 3]
-    a1 = x @ Wb["W1"] + b["b1"]
+    a1 = _dense(x, Wb["W1"], b["b1"], jitter)
     h1 = bf16(np.maximum(a1, 0))
-    a2 = h1 @ Wb["W2"] + b["b2"]
+    a2 = _dense(h1, Wb["W2"], b["b2"], jitter)
     h2 = bf16(np.maximum(a2, 0))
-    a3 = h2 @ Wb["W3"] + b["b3"]
+    a3 = _dense(h2, Wb["W3"], b["b3"], jitter)
     h3 = np.maximum(a3, 0)
     arg = np.argmax(h3, axis=1)                   # first maximum = lowest row on ties
     g = np.take_along_axis(h3, arg[:, None, :], axis=1)[:, 0, :]
     z = bf16(np.concatenate([g, F], axis=1))      # [nv, 76]
-    a4 = z @ Wb["W4"] + b["b4"]
+    a4 = _dense(z, Wb["W4"], b["b4"], jitter)
     h4 = bf16(np.maximum(a4, 0))
     y = h4 @ Wb["W5"] + b["b5"]
     if not keep:
@@ -144,20 +180,28 @@ def loss(y, cov_t, o_t):
     return L, dy
 
 
-def backward(W, keep, dy, round_grads=True):
-    """Gradients of the parameters given dL/dy [nv, 8] and forward(..., keep=True)'s record."""
+def backward(W, keep, dy, round_grads=True, jitter=None):
+    """Gradients of the parameters given dL/dy [nv, 8] and forward(..., keep=True)'s record.
+    jitter: a Jitter applied to every value before its BF16 rounding (knife-edge screen only)."""
     r = bf16 if round_grads else (lambda a: a)
+
+    def dmat(g, w):  # g @ w.T, jittered like a forward layer
+        d = g @ w.T
+        if jitter is not None:
+            d = jitter(d, w.shape[1], np.abs(g) @ np.abs(w.T))
+        return d
+
     Wb = keep["Wb"]
     G = {}
-    dyr = r(dy)
+    dyr = r(dy if jitter is None else jitter(dy, 4, np.abs(dy)))
     G["W5"] = np.einsum("nk,nj->kj", keep["h4"], dyr)
     G["b5"] = dy.sum(0)
-    dh4 = dyr @ Wb["W5"].T
+    dh4 = dmat(dyr, Wb["W5"])
     da4 = dh4 * (keep["a4"] > 0)
     da4r = r(da4)
     G["W4"] = np.einsum("nk,nj->kj", keep["z"], da4r)
     G["b4"] = da4.sum(0)
-    dz = da4r @ Wb["W4"].T
+    dz = dmat(da4r, Wb["W4"])
     dg = dz[:, :WIDTH]
     nv = dy.shape[0]
     dh3 = np.zeros((nv, ROWS, WIDTH))
@@ -166,16 +210,39 @@ def backward(W, keep, dy, round_grads=True):
     da3r = r(da3)
     G["W3"] = np.einsum("nrk,nrj->kj", keep["h2"], da3r)
     G["b3"] = da3.sum((0, 1))
-    dh2 = da3r @ Wb["W3"].T
+    dh2 = dmat(da3r, Wb["W3"])
     da2 = dh2 * (keep["a2"] > 0)
     da2r = r(da2)
     G["W2"] = np.einsum("nrk,nrj->kj", keep["h1"], da2r)
     G["b2"] = da2.sum((0, 1))
-    dh1 = da2r @ Wb["W2"].T
+    dh1 = dmat(da2r, Wb["W2"])
     da1 = dh1 * (keep["a1"] > 0)
     G["W1"] = np.einsum("nrk,nrj->kj", keep["x"], r(da1))
     G["b1"] = da1.sum((0, 1))
     return G
+
+
+def knife_spread(W, X, F, realisations=12, seed=0, cov_t=None, o_t=None):
+    """Largest change of every output (and, with targets, of every weight gradient of the
+    training loss) over seeded Jitter realisations of the forward (and backward): the yardstick
+    of the BF16 knife-edge screen.  Returns (y_spread [nv, 8], grad_spread dict or None)."""
+    y0, k0 = forward(W, X, F, keep=True)
+    G0 = None
+    if cov_t is not None:
+        _, dy0 = loss(y0, cov_t, o_t)
+        G0 = backward(W, k0, dy0)
+    ys = np.zeros_like(y0)
+    gs = {k: np.zeros_like(v) for k, v in G0.items()} if G0 is not None else None
+    for j in range(realisations):
+        jit = Jitter(seed * 1000 + j)
+        y, kp = forward(W, X, F, keep=True, jitter=jit)
+        ys = np.maximum(ys, np.abs(y - y0))
+        if G0 is not None:
+            _, dy = loss(y, cov_t, o_t)
+            G = backward(W, kp, dy, jitter=jit)
+            for k in gs:
+                gs[k] = np.maximum(gs[k], np.abs(G[k] - G0[k]))
+    return ys, gs
 
 
 def targets_from_gaussians(vox, gauss_log_scales, gauss_quats, gauss_logits, point_ids):

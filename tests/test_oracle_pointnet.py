@@ -100,3 +100,23 @@ def test_rounded_backward_stays_close_to_exact():
     for k in W:
         scale = np.abs(Ge[k]).max() + 1e-30
         assert np.abs(Gr[k] - Ge[k]).max() <= 2e-2 * scale, k
+
+
+def test_knife_screen_flags_a_rounding_midpoint_and_nothing_without_jitter():
+    """The BF16 knife-edge screen: with zero jitter nothing moves; a first-layer activation placed
+    exactly on a BF16 rounding midpoint (1 + 2^-8) moves the outputs that depend on it."""
+    W, X, F, cov, o = _inputs(6, nv=3)
+    ys, gs = pn.knife_spread(W, X, F, realisations=3, seed=0, cov_t=cov, o_t=o)
+    assert ys.shape == (3, 8) and set(gs) == set(W)
+    zero = pn.Jitter(0, c=0.0)
+    y0 = pn.forward(W, X, F)
+    np.testing.assert_array_equal(pn.forward(W, X, F, jitter=zero), y0)
+    W2 = {k: v.copy() for k, v in W.items()}
+    X2 = np.zeros_like(X)
+    X2[0, :, 0] = 1.0                     # voxel 0: every row is (1, 0, 0)
+    W2["W1"][:, 0] = [1.0, 0.0, 0.0]
+    W2["b1"][0] = 2.0 ** -8               # a1[..., 0] = 1 + 2^-8: a BF16 midpoint
+    _, keep = pn.forward(W2, X2, F, keep=True)
+    assert np.all(keep["a1"][0, :, 0] == 1.0 + 2.0 ** -8)
+    spread, _ = pn.knife_spread(W2, X2, F, realisations=8, seed=1)
+    assert spread[0].max() > 0.0
