@@ -241,6 +241,35 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
                                   int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,
                                   const float *dL_drgb, const float *dL_ddepth, float *dinst, gsr_stream stream);
 
+/* ---- fused step: render forward, L1 loss and render backward in one persistent launch ----------
+ * The batched optimisation step of Sec. III-C with the loss of Eq. 9-10 restricted to its
+ * per-pixel terms (all-ones mask, lambda_ssim = 0): for every view-tile, the front-to-back
+ * compositing of gsr_render_fwd_sliced, then L_v = (1/P) sum_x sum_ch |C - C~| + lambda_depth
+ * (1/P) sum_x |D - D~| with dL/dC = sign(C - C~)/P, dL/dD = lambda_depth sign(D - D~)/P
+ * (sign(0) = 0), then the records of gsr_render_bwd for that upstream gradient.  One workgroup
+ * takes a view-tile through all three, so the images and the loss gradient stay on chip between
+ * the forward and the backward.  Work items come from a device queue: the depth slices of the long
+ * tiles first (as in gsr_render_fwd_sliced; the workgroup that completes a tile's last slice
+ * merges them and runs that tile's loss and backward), then the view-tiles in tile_order
+ * (longest first; NULL = natural order).  Results equal those of gsr_render_fwd_sliced,
+ * gsr_loss_l1 and gsr_render_bwd called in turn (images and loss gradient bit for bit, records up
+ * to the float rounding of their four-wave LDS sums).
+ * Inputs as gsr_render_fwd_sliced and gsr_render_bwd; targets as gsr_loss_l1 (target_rgb
+ * [S][3][H][W], target_depth [S][H][W] or NULL, target_index [V] or NULL = slot v).  Outputs:
+ * rgb, depth, T_final, last as gsr_render_fwd; *loss (device float64) ACCUMULATED, summed over the
+ * view-tiles in a fixed order; dinst as gsr_render_bwd.  capacity: the instance capacity of the
+ * lists.  ws: gsr_render_step_workspace(V, r, capacity) bytes, 256-byte aligned (the slice
+ * workspace plus per view-tile loss sums and the queue counters, cleared by the call itself).
+ * Errors: GSR_E_INVALID (NULL pointers, bad sizes, lambda_depth < 0), GSR_E_CAPACITY (ws_bytes
+ * too small), GSR_E_HIP. */
+GSR_API size_t gsr_render_step_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity);
+GSR_API gsr_status gsr_render_step(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                   const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
+                                   int32_t n_views, const gsr_raster *r, const float *target_rgb,
+                                   const float *target_depth, const int32_t *target_index, float lambda_depth,
+                                   float *rgb, float *depth, float *T_final, uint32_t *last, double *loss,
+                                   float *dinst, int64_t capacity, void *ws, size_t ws_bytes, gsr_stream stream);
+
 /* Screen-space gradient per (view, Gaussian): dsplat [V*n][10] (OVERWRITTEN) = the sum, in
  * emission order, of the pair's instance records in dinst (from gsr_render_bwd); the pairs and
  * their first records come from em (gsr_bin_sort), their counts from tile_info row 0

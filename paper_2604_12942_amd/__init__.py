@@ -148,6 +148,21 @@ def render_bwd(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, 
                                _ptr(dL_ddepth), _ptr(dinst), _stream()), "gsr_render_bwd")
 
 
+def render_step_workspace(n_views, raster, capacity):
+    return int(lib().gsr_render_step_workspace(n_views, C.byref(raster.c), capacity))
+
+
+def render_step(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, target_rgb, target_depth,
+                lambda_depth, rgb, depth, T_final, last, loss, dinst, capacity, ws, tile_order=None,
+                target_index=None):
+    """Fused forward + L1 loss + backward of every view-tile (gsr_render_step); loss is accumulated."""
+    check(lib().gsr_render_step(_ptr(splats), _ptr(inst_gid), _ptr(inst_emit), _ptr(tile_ranges), _ptr(tile_order),
+                                _ptr(cams), n_views, C.byref(raster.c), _ptr(target_rgb), _ptr(target_depth),
+                                _ptr(target_index), float(lambda_depth), _ptr(rgb), _ptr(depth), _ptr(T_final),
+                                _ptr(last), _ptr(loss), _ptr(dinst), capacity, _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream()), "gsr_render_step")
+
+
 def render_fwd_stored_workspace(n_views, raster):
     return int(lib().gsr_render_fwd_stored_workspace(n_views, C.byref(raster.c)))
 
@@ -533,7 +548,9 @@ class Rasterizer:
         self.em = emission(self.inst_emit, self.pair_gid, self.pair_first, self.n_pairs)
         wsb = bin_sort_workspace(self.n, self.V, self.capacity, self.raster)
         self.bin_ws = torch.empty((wsb + 255) // 256 * 64, dtype=torch.int32, device=self.device)
-        wsf = render_fwd_sliced_workspace(self.V, self.raster, self.capacity)
+        # the fused step's workspace begins with the sliced forward's, so one buffer serves both
+        wsf = max(render_fwd_sliced_workspace(self.V, self.raster, self.capacity),
+                  render_step_workspace(self.V, self.raster, self.capacity))
         self.fwd_ws = torch.empty((wsf + 255) // 256 * 64, dtype=torch.int32, device=self.device)
 
     def project(self, P, sh_degree, cams):

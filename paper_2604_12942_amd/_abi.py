@@ -88,6 +88,9 @@ _SIGS = {
     "gsr_render_bwd_stored": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, C.c_int64, P, P, P, P],
                               C.c_int),
     "gsr_pair_grads": ([P, C.POINTER(Emission), P, C.c_int64, C.c_int32, P, P], C.c_int),
+    "gsr_render_step_workspace": ([C.c_int32, C.POINTER(Raster), C.c_int64], C.c_size_t),
+    "gsr_render_step": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, C.c_float, P, P, P, P, P, P,
+                         C.c_int64, P, C.c_size_t, P], C.c_int),
     "gsr_project_bwd_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
     "gsr_project_bwd": ([C.POINTER(Gaussians), P, C.c_int32, C.POINTER(Raster), P, P, C.POINTER(Emission), P,
                          C.POINTER(ParamGrads), P, P, C.c_int32, P, P, C.c_size_t, P], C.c_int),

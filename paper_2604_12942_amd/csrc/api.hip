@@ -21,6 +21,11 @@ extern "C" size_t gsr_render_fwd_ws_bytes(int, const gsr_raster *, int64_t);
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
                                             uint32_t *, uint32_t *, int64_t, void *, hipStream_t);
+extern "C" size_t gsr_render_step_ws_bytes(int, const gsr_raster *, int64_t);
+extern "C" gsr_status gsr_render_step_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
+                                             const uint32_t *, const gsr_camera *, int, const gsr_raster *,
+                                             const float *, const float *, const int32_t *, float, float *, float *,
+                                             float *, uint32_t *, double *, float *, int64_t, void *, hipStream_t);
 extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const uint32_t *, const gsr_camera *, int, const gsr_raster *, const float *,
                                             const uint32_t *, const float *, const float *, float *, hipStream_t);
@@ -207,6 +212,29 @@ extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *in
         return GSR_E_INVALID;
     return gsr_render_bwd_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, T_final, last,
                                  dL_drgb, dL_ddepth, dinst, S(stream));
+}
+
+extern "C" size_t gsr_render_step_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity) {
+    if (!raster_ok(r) || n_views < 1 || capacity < 1) return 0;
+    return gsr_render_step_ws_bytes(n_views, r, capacity);
+}
+
+extern "C" gsr_status gsr_render_step(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                      const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
+                                      int32_t n_views, const gsr_raster *r, const float *target_rgb,
+                                      const float *target_depth, const int32_t *target_index, float lambda_depth,
+                                      float *rgb, float *depth, float *T_final, uint32_t *last, double *loss,
+                                      float *dinst, int64_t capacity, void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1 || capacity < 1 || capacity >= (int64_t)UINT32_MAX) return GSR_E_INVALID;
+    if (!splats || !inst_gid || !inst_emit || !tile_ranges || !cams || !target_rgb || !rgb || !depth || !T_final ||
+        !last || !loss || !dinst || !ws)
+        return GSR_E_INVALID;
+    if (!(lambda_depth >= 0.f)) return GSR_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
+    if (ws_bytes < gsr_render_step_ws_bytes(n_views, r, capacity)) return GSR_E_CAPACITY;
+    return gsr_render_step_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, target_rgb,
+                                  target_depth, target_index, lambda_depth, rgb, depth, T_final, last, loss, dinst,
+                                  capacity, ws, S(stream));
 }
 
 extern "C" size_t gsr_render_fwd_stored_workspace(int32_t n_views, const gsr_raster *r) {

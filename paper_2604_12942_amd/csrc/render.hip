@@ -581,36 +581,58 @@ __device__ __forceinline__ float rdl(float v, int lane) {
 // Gaussian) pair are contiguous there, and the projection backward sums them in a fixed order,
 // so no global atomics are needed.  The four waves' adds to one slot come in a run-dependent
 // order, so gradients repeat from run to run only up to float rounding.
+// Shared memory of the backward of one tile (the staged splats keep the forward's null slot 256).
+struct BwdLds {
+    float4 sA[257], sB[257], sC[257];
+    float sAcc[10][256];
+    uint8_t sList[4][256];
+    float4 sPG[4][64];    // dL/dC (3), dL/dD
+    float2 sPS[4][64];    // transmittance and suffix sum behind the chunks done so far
+    uint32_t sPL[4][64];  // last composited position of each pixel
+    uint32_t s_max;
+};
+
+// The calling lane's pixel state for the backward: final transmittance, last composited position
+// (0 for a pixel outside the image) and upstream gradients dL/dC, dL/dD.
+struct PixelGrad {
+    float Tr, G0, G1, G2, GD;
+    uint32_t last;
+};
+
+// Backward of one (view, tile) work item, Gaussian-major.  The tile's instances up to the deepest
+// pixel's last contributor are staged back to front in batches of 256.  Each wave compacts the
+// batch to the Gaussians that reach its pixel sub-rectangle and cuts them, deepest first, into
+// chunks of 64: lane l holds the l-th deepest.  For each of the wave's 64 pixels every lane
+// evaluates its Gaussian; a wave-wide inclusive product scan of 1 / (1 - a) recovers the
+// transmittance in front of each Gaussian from the pixel's transmittance behind the chunk, and an
+// inclusive sum scan of w (dL/dC . c + dL/dD z) gives what lies behind it.  Pixel state (upstream
+// gradient, transmittance and suffix behind the chunks done so far) sits in LDS and is read by
+// broadcast; the pixel centre by readlane.  Per lane, the mean and conic gradients accumulate as
+// the five moments sum dP (dx, dy, dx^2, dx dy, dy^2) of the exponent gradient dP, mapped through
+// the Cholesky factor once per chunk.  Gradients then accumulate in LDS across waves (ds_add_f32
+// per staged slot) and leave as one plain 40-byte record per instance, stored at the instance's
+// emission index: the records of one (view, Gaussian) pair are contiguous there, and the
+// projection backward sums them in a fixed order, so no global atomics are needed.  The four
+// waves' adds to one slot come in a run-dependent order, so gradients repeat from run to run only
+// up to float rounding.  Block-uniform arguments except the pixel state pg.
 template <int TW, int TH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(const gsr_splat *__restrict__ splats,
-                                                    const uint32_t *__restrict__ inst,
-                                                    const uint32_t *__restrict__ inst_emit,
-                                                    const uint32_t *__restrict__ ranges,
-                                                    const uint32_t *__restrict__ order,
-                                                    const gsr_camera *__restrict__ cams, int W, int H, int ntx,
-                                                    int T, const float *__restrict__ Tfin,
-                                                    const uint32_t *__restrict__ last,
-                                                    const float *__restrict__ dLdrgb,
-                                                    const float *__restrict__ dLddepth,
-                                                    float *__restrict__ dinst) {
-    __shared__ float4 sA[256], sB[256], sC[256];
-    __shared__ float sAcc[10][256];
-    __shared__ uint8_t sList[4][256];
-    __shared__ float4 sPG[4][64];  // dL/dC (3), dL/dD
-    __shared__ float2 sPS[4][64];  // transmittance and suffix sum behind the chunks done so far
-    __shared__ uint32_t sPL[4][64];  // last composited position of each pixel
-    __shared__ uint32_t s_max;
-    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
-    const int v = item / T, tile = item % T;
+__device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst,
+                                              const uint32_t *__restrict__ inst_emit, uint32_t item, uint32_t start,
+                                              uint32_t end, int ntx, int T, const gsr_camera &cam,
+                                              const PixelGrad &pg, BwdLds &L, float *__restrict__ dinst) {
+    float4 *const sA = L.sA, *const sB = L.sB, *const sC = L.sC;
+    auto &sAcc = L.sAcc;
+    auto &sList = L.sList;
+    auto &sPG = L.sPG;
+    auto &sPS = L.sPS;
+    auto &sPL = L.sPL;
+    uint32_t &s_max = L.s_max;
+    const int tile = item % T;
     const int tx = tile % ntx, ty = tile / ntx;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < W && py < H;
-    const uint32_t start = ranges[2 * item], end = ranges[2 * item + 1];
     const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
     const double ox = (double)bx, oy = (double)by;
-    const int64_t P = (int64_t)W * H;
-    const int64_t pix = (int64_t)py * W + px;
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     float wx0, wx1, wy0, wy1;
     wave_box<TW>(tx * TW - bx, ty * TH - by, w, wx0, wx1, wy0, wy1);
@@ -618,22 +640,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     // centre of the wave's first pixel (the wave's 64 pixels are TW-wide rows)
     static_assert(TW % 8 == 0, "packed chunks assume 8 | TW");
     const float fxw = (float)(tx * TW - bx) + 0.5f, fyw = (float)(ty * TH - by + w * (64 / TW)) + 0.5f;
-    uint32_t mylast = 0;
+    const uint32_t mylast = pg.last;
     {
-        float Tr = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f;
-        if (inside) {
-            Tr = Tfin[(int64_t)v * P + pix];
-            mylast = last[(int64_t)v * P + pix];
-            G0 = dLdrgb[(int64_t)v * 3 * P + pix];
-            G1 = dLdrgb[(int64_t)v * 3 * P + P + pix];
-            G2 = dLdrgb[(int64_t)v * 3 * P + 2 * P + pix];
-            if (dLddepth) GD = dLddepth[(int64_t)v * P + pix];
-        }
-        const gsr_camera &cam = cams[v];
         // the suffix starts with the background term T_final (dL/dC . bg)
-        const float S = Tr * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
-        sPG[w][lane] = make_float4(G0, G1, G2, GD);
-        sPS[w][lane] = make_float2(Tr, S);
+        const float S = pg.Tr * (pg.G0 * cam.bg[0] + pg.G1 * cam.bg[1] + pg.G2 * cam.bg[2]);
+        sPG[w][lane] = make_float4(pg.G0, pg.G1, pg.G2, pg.GD);
+        sPS[w][lane] = make_float2(pg.Tr, S);
         sPL[w][lane] = mylast;
         if (threadIdx.x == 0) s_max = 0;
     }
@@ -856,6 +868,206 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     }
 }
 
+template <int TW, int TH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(
+    const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst, const uint32_t *__restrict__ inst_emit,
+    const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ order, const gsr_camera *__restrict__ cams, int W,
+    int H, int ntx, int T, const float *__restrict__ Tfin, const uint32_t *__restrict__ last,
+    const float *__restrict__ dLdrgb, const float *__restrict__ dLddepth, float *__restrict__ dinst) {
+    __shared__ BwdLds L;
+    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
+    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
+    const int64_t P = (int64_t)W * H;
+    const int64_t pix = (int64_t)t.py * W + t.px;
+    PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
+    if (t.inside) {
+        pg.Tr = Tfin[(int64_t)t.v * P + pix];
+        pg.last = last[(int64_t)t.v * P + pix];
+        pg.G0 = dLdrgb[(int64_t)t.v * 3 * P + pix];
+        pg.G1 = dLdrgb[(int64_t)t.v * 3 * P + P + pix];
+        pg.G2 = dLdrgb[(int64_t)t.v * 3 * P + 2 * P + pix];
+        if (dLddepth) pg.GD = dLddepth[(int64_t)t.v * P + pix];
+    }
+    tile_backward<TW, TH>(splats, inst, inst_emit, item, ranges[2 * item], ranges[2 * item + 1], ntx, T, cams[t.v], pg,
+                          L, dinst);
+}
+
+// ---- fused persistent step: forward, L1 loss gradient and backward of each tile ----------------
+// Eq. 9-10 with the all-ones mask and lambda_ssim = 0 is a per-pixel loss, so one workgroup can
+// composite a tile, form its pixels' loss gradient in registers and run the tile's backward at
+// once: the images and the loss gradient never make a round trip through memory for the
+// backward.  Work items come from a device queue: first the depth slices of the long tiles, then
+// the view-tiles in longest-first order.  A long tile is finished by the workgroup that completes
+// its last slice (the completion counter tells it which): it merges the slices, forms the loss
+// gradient and runs the tile's backward, so no workgroup ever waits for another.
+struct StepArgs {
+    const float *trgb, *tdepth;  // targets [S][3][H][W], [S][H][W] (tdepth may be null)
+    const int32_t *tidx;         // [V] target slot of each view (null: slot v)
+    float lam;                   // depth weight lambda_d
+    double *item_loss;           // [V*T] sum over the view-tile's pixels of their loss terms
+    uint32_t *queue;             // [1] next work item, 0 before the launch
+    uint32_t *slices_done;       // [V*T] finished slices of each long tile, 0 before the launch
+};
+
+// L1 loss term of one pixel (colour channels summed, plus lambda_d times the depth term) and its
+// gradient: dL/dC = sign(C - C~) / P, dL/dD = lambda_d sign(D - D~) / P, sign(0) = 0.
+__device__ __forceinline__ float l1_pixel(const StepArgs &a, int v, int64_t P, int64_t pix, float r, float g, float b,
+                                          float d, PixelGrad &pg) {
+    const int64_t slot = a.tidx ? (int64_t)a.tidx[v] : (int64_t)v;
+    const float invP = 1.0f / (float)P;
+    const float c[3] = {r, g, b};
+    float gr[3];
+    float l = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        const float dl = c[ch] - a.trgb[slot * 3 * P + ch * P + pix];
+        l += fabsf(dl);
+        gr[ch] = dl > 0.f ? invP : (dl < 0.f ? -invP : 0.f);
+    }
+    pg.G0 = gr[0];
+    pg.G1 = gr[1];
+    pg.G2 = gr[2];
+    pg.GD = 0.f;
+    if (a.tdepth) {
+        const float dl = d - a.tdepth[slot * P + pix];
+        l += a.lam * fabsf(dl);
+        pg.GD = a.lam * (dl > 0.f ? invP : (dl < 0.f ? -invP : 0.f));
+    }
+    return l;
+}
+
+// Writes the pixel's outputs, forms its loss gradient, and stores the view-tile's loss sum.
+__device__ __forceinline__ void finish_pixels(const TileGeom &t, uint32_t item, const gsr_camera &cam, int W, int H,
+                                              float Tr, float c0, float c1, float c2, float dd, uint32_t lst,
+                                              float *__restrict__ rgb, float *__restrict__ depth,
+                                              float *__restrict__ Tfin, uint32_t *__restrict__ last,
+                                              const StepArgs &a, PixelGrad &pg, double *s_red) {
+    const int64_t P = (int64_t)W * H;
+    const int64_t pix = (int64_t)t.py * W + t.px;
+    pg = PixelGrad{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
+    double l = 0.0;
+    if (t.inside) {
+        const float r = __builtin_fmaf(Tr, cam.bg[0], c0);
+        const float g = __builtin_fmaf(Tr, cam.bg[1], c1);
+        const float b = __builtin_fmaf(Tr, cam.bg[2], c2);
+        rgb[(int64_t)t.v * 3 * P + pix] = r;
+        rgb[(int64_t)t.v * 3 * P + P + pix] = g;
+        rgb[(int64_t)t.v * 3 * P + 2 * P + pix] = b;
+        depth[(int64_t)t.v * P + pix] = dd;
+        Tfin[(int64_t)t.v * P + pix] = Tr;
+        last[(int64_t)t.v * P + pix] = lst;
+        l = (double)l1_pixel(a, t.v, P, pix, r, g, b, dd, pg);
+        pg.Tr = Tr;
+        pg.last = lst;
+    }
+    l = wave_sum_d(l);
+    if (__lane_id() == 0) s_red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) a.item_loss[item] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_step(
+    const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst, const uint32_t *__restrict__ inst_emit,
+    const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ order, const gsr_camera *__restrict__ cams,
+    int W, int H, int ntx, int T, uint32_t VT, float *__restrict__ rgb, float *__restrict__ depth,
+    float *__restrict__ Tfin, uint32_t *__restrict__ last, float *__restrict__ dinst, SliceArgs sl, StepArgs a) {
+    __shared__ BwdLds L;
+    __shared__ uint32_t s_item, s_flag;
+    __shared__ double s_red[4];
+    write_null_slot(L.sA, L.sB, L.sC);
+    const uint32_t n_sl = sl.grid ? min(*sl.count, sl.cap) : 0u;
+    const uint32_t total = n_sl + VT;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();  // every lane has read the item before thread 0 fetches the next one
+        if (it >= total) break;
+        PixelGrad pg;
+        uint32_t item, start, end;
+        TileGeom t;
+        if (it < n_sl) {
+            // one depth slice of a long tile, composited from the transmittance in front of it
+            const uint2 si = sl.info[it];
+            if (si.x == kNoSlice) continue;
+            item = si.x;
+            t = tile_geom<TW, TH>(item, T, ntx, W, H);
+            start = ranges[2 * item];
+            end = ranges[2 * item + 1];
+            const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
+            const float Tin = slice_T_in(sl, it, si.y);
+            PixelWalk pw = walk_start(t, Tin);
+            composite<false>(splats, inst, start, lo, hi, t, L.sA, L.sB, L.sC, pw, nullptr, 0u, 0u);
+            const bool term = t.inside && Tin >= GSR_T_MIN && pw.fxl == kGone;
+            sl.part[(size_t)it * 256 + threadIdx.x] = make_float4(pw.c0, pw.c1, pw.c2, pw.dd);
+            sl.part2[(size_t)it * 256 + threadIdx.x] = make_uint2(__float_as_uint(term ? -pw.Tr : pw.Tr), pw.lst);
+            // release the slice's results, then count it; the workgroup that completes the tile's
+            // last slice acquires every slice's results and finishes the tile
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t K = sl.tile_slices[item];
+                s_flag = atomicAdd(&a.slices_done[item], 1u) + 1u == K ? 1u : 0u;
+                __threadfence();
+            }
+            __syncthreads();
+            if (!s_flag) continue;
+            __threadfence();
+            const uint32_t j0 = it - si.y, K = sl.tile_slices[item];
+            float Tin2 = 1.0f, Tr = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dd = 0.f;
+            uint32_t lst = 0;
+            if (t.inside) {
+                for (uint32_t k = 0; k < K; k++) {
+                    if (Tin2 < GSR_T_MIN) break;  // terminated in an earlier slice
+                    const size_t q = (size_t)(j0 + k) * 256 + threadIdx.x;
+                    const float4 pc = sl.part[q];
+                    const uint2 p2 = sl.part2[q];
+                    c0 += pc.x;
+                    c1 += pc.y;
+                    c2 += pc.z;
+                    dd += pc.w;
+                    const float To = __uint_as_float(p2.x);
+                    Tr = fabsf(To);
+                    lst = p2.y ? p2.y : lst;
+                    if (To < 0.0f) break;  // terminated in this slice
+                    if (k + 1 < K) Tin2 *= sl.tprod[q];
+                }
+            }
+            finish_pixels(t, item, cams[t.v], W, H, Tr, c0, c1, c2, dd, lst, rgb, depth, Tfin, last, a, pg, s_red);
+        } else {
+            item = order ? order[it - n_sl] : it - n_sl;
+            if (sl.grid && sl.tile_slices[item]) continue;  // composited in slices
+            t = tile_geom<TW, TH>(item, T, ntx, W, H);
+            start = ranges[2 * item];
+            end = ranges[2 * item + 1];
+            PixelWalk pw = walk_start(t, 1.0f);
+            composite<false>(splats, inst, start, start, end, t, L.sA, L.sB, L.sC, pw, nullptr, 0u, 0u);
+            finish_pixels(t, item, cams[t.v], W, H, pw.Tr, pw.c0, pw.c1, pw.c2, pw.dd, pw.lst, rgb, depth, Tfin, last,
+                          a, pg, s_red);
+        }
+        tile_backward<TW, TH>(splats, inst, inst_emit, item, start, end, ntx, T, cams[t.v], pg, L, dinst);
+        __syncthreads();  // the backward's last flush reads LDS the next item overwrites
+    }
+}
+
+// Loss of the step: the view-tiles' sums in a fixed order, divided by the pixels per view, added
+// to *loss.
+__global__ __launch_bounds__(1024) void k_step_loss(const double *__restrict__ item_loss, uint32_t VT, double invP,
+                                                    double *__restrict__ loss) {
+    __shared__ double s_w[16];
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < VT; i += 1024) acc += item_loss[i];
+    acc = wave_sum_d(acc);
+    if (__lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < 16; k++) s += s_w[k];
+        *loss += s * invP;
+    }
+}
+
 // Backward of the stored-contributor mode, pixel-major: every lane walks its own pixel's list of
 // composited tile positions back to front (no re-evaluation of Gaussians that did not blend),
 // recovering the transmittance in front of each contributor by division.  The tile's instances
@@ -988,6 +1200,7 @@ using namespace gsr;
 
 extern "C" size_t gsr_scan_ws_bytes(int64_t n);
 extern "C" gsr_status gsr_scan_launch(const uint32_t *, int64_t, uint32_t *, uint32_t *, void *, hipStream_t);
+extern "C" gsr_status gsr_fill_u32_launch(void *, uint32_t, int64_t, hipStream_t);
 
 namespace {
 
@@ -1072,6 +1285,62 @@ extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *splats, const uint3
     else if (r->tile_w == 8) GSR_RF(8, 32);
     else GSR_RF(32, 8);
 #undef GSR_RF
+    return last_launch();
+}
+
+// Workspace of the fused step: the depth-slice workspace, then per view-tile loss sums (double),
+// then the work-queue counter and per view-tile slice completion counters.
+extern "C" size_t gsr_render_step_ws_bytes(int V, const gsr_raster *r, int64_t capacity) {
+    const int64_t VT = (int64_t)V * ceil_div(r->width, r->tile_w) * ceil_div(r->height, r->tile_h);
+    return slice_layout(nullptr, VT, capacity).bytes + al256((size_t)VT * 8) + al256((size_t)(VT + 1) * 4);
+}
+
+namespace {
+// Resident workgroups of a kernel on the current device (the persistent grid).
+int persistent_grid(const void *kernel) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess) return 0;
+    return ncu * (per > 0 ? per : 1);
+}
+}  // namespace
+
+extern "C" gsr_status gsr_render_step_launch(const gsr_splat *splats, const uint32_t *inst, const uint32_t *inst_emit,
+                                             const uint32_t *ranges, const uint32_t *order, const gsr_camera *cams,
+                                             int V, const gsr_raster *r, const float *trgb, const float *tdepth,
+                                             const int32_t *tidx, float lam, float *rgb, float *depth, float *Tfin,
+                                             uint32_t *last, double *loss, float *dinst, int64_t capacity, void *ws,
+                                             hipStream_t st) {
+    const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
+    const int T = ntx * nty;
+    const int nb = V * T;
+    const SliceWs w = slice_layout(ws, nb, capacity);
+    double *item_loss = reinterpret_cast<double *>(static_cast<char *>(ws) + w.bytes);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + w.bytes + al256((size_t)nb * 8));
+    const int g = (int)(ceil_div(nb, 256) < 1024 ? ceil_div(nb, 256) : 1024);
+    k_slice_count<<<g, 256, 0, st>>>(ranges, (uint32_t)nb, w.tile_slices);
+    gsr_status s = gsr_scan_launch(w.tile_slices, nb, w.off, w.count, w.scan, st);
+    if (s != GSR_OK) return s;
+    k_slice_emit<<<g, 256, 0, st>>>(w.tile_slices, w.off, (uint32_t)nb, w.cap, w.info);
+    s = gsr_fill_u32_launch(counters, 0u, (int64_t)nb + 1, st);
+    if (s != GSR_OK) return s;
+    const SliceArgs sl{w.tile_slices, w.info, w.count, w.tprod, w.part, w.part2, w.cap, w.cap < 2048u ? w.cap : 2048u};
+    const StepArgs a{trgb, tdepth, tidx, lam, item_loss, counters, counters + 1};
+#define GSR_RSTEP(TW, TH)                                                                                          \
+    do {                                                                                                           \
+        const int grid = persistent_grid(reinterpret_cast<const void *>(&k_render_step<TW, TH>));                 \
+        if (grid <= 0) return GSR_E_HIP;                                                                          \
+        k_slice_prod<TW, TH><<<sl.grid, 256, 0, st>>>(splats, inst, ranges, r->width, r->height, ntx, T, sl);      \
+        k_render_step<TW, TH><<<grid, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width,         \
+                                                    r->height, ntx, T, (uint32_t)nb, rgb, depth, Tfin, last, dinst, \
+                                                    sl, a);                                                        \
+    } while (0)
+    if (r->tile_w == 16) GSR_RSTEP(16, 16);
+    else if (r->tile_w == 8) GSR_RSTEP(8, 32);
+    else GSR_RSTEP(32, 8);
+#undef GSR_RSTEP
+    k_step_loss<<<1, 1024, 0, st>>>(item_loss, (uint32_t)nb, 1.0 / ((double)r->width * r->height), loss);
     return last_launch();
 }
 

@@ -21,11 +21,14 @@ DEFAULT_LR = dict(means=5e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, 
 class MapOptimizer:
     def __init__(self, params, sh_degree, cam_pool, target_rgb, target_depth, raster, n_views, lambda_depth=0.2,
                  lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda", fused=True,
-                 lambda_rgb=1.0, lambda_ssim=0.0, support=None):
+                 lambda_rgb=1.0, lambda_ssim=0.0, support=None, fused_render=True):
         """params: dict of float32 [c, n] device tensors (optimised in place); cam_pool: device
         uint8 [S*96] gsr_camera records; target_rgb [S,3,H,W], target_depth [S,H,W] (or None).
         support = (tau_geo, r_erode) supervises only inside the interior mask of Eq. 7 computed
-        from this step's own render; None uses every pixel."""
+        from this step's own render; None uses every pixel.  fused_render: with the per-pixel L1
+        loss, render, loss and render backward run as one persistent launch (gsr_render_step; the
+        loss gradient images g_rgb, g_depth are then not written); the full loss (mask, SSIM)
+        always runs them separately."""
         self.P = params
         self.sh_degree = int(sh_degree)
         self.n = params["means"].shape[1]
@@ -47,6 +50,7 @@ class MapOptimizer:
         self.g_rgb = torch.empty(self.V, 3, H, W, device=device)
         self.g_depth = torch.empty(self.V, H, W, device=device)
         self.full_loss = support is not None or self.lambda_ssim != 0.0 or self.lambda_rgb != 1.0
+        self.fused_render = bool(fused_render) and not self.full_loss
         self.sup_mask = torch.ones(self.V, H, W, dtype=torch.uint8, device=device)
         self.sup_count = torch.zeros(self.V, dtype=torch.int32, device=device)
         from . import loss_workspace
@@ -145,7 +149,7 @@ class MapOptimizer:
     def _stage_fns(self, check_capacity):
         """The step as an ordered list of (name, fn): every fn only enqueues device work (no host
         synchronisation when check_capacity is False), so any run of stages can be captured."""
-        from . import project, render_fwd, render_bwd, project_bwd, project_bwd_adam, visible_list
+        from . import project, render_fwd, render_bwd, render_step, project_bwd, project_bwd_adam, visible_list
         r = self.rast
 
         def gather():
@@ -159,10 +163,21 @@ class MapOptimizer:
             r.bin(check_capacity)
 
         def fwd():
+            if self.fused_render:
+                # forward, loss and backward of every view-tile in one persistent launch
+                self.loss.zero_()
+                gd = self.target_depth
+                render_step(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster,
+                            self.target_rgb, gd, self.lambda_depth if gd is not None else 0.0, r.rgb, r.depth,
+                            r.T_final, r.last, self.loss, r.dinst, r.capacity, r.fwd_ws, tile_order=r.tile_order,
+                            target_index=self.view_idx32)
+                return
             render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth,
                        r.T_final, r.last, tile_order=r.tile_order, ws=r.fwd_ws, capacity=r.capacity)
 
         def loss_stage():
+            if self.fused_render:
+                return
             self.loss.zero_()
             gd = self.g_depth if self.target_depth is not None else None
             if not self.full_loss:
@@ -178,6 +193,8 @@ class MapOptimizer:
                  lambda_depth=self.lambda_depth, target_index=self.view_idx32, ws=self.loss_ws)
 
         def bwd():
+            if self.fused_render:
+                return
             render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
                        r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,
                        tile_order=r.tile_order)
@@ -268,3 +285,31 @@ class MapOptimizer:
         r._alloc_instances(max(int(need * headroom) + 1024, r.capacity))
         self.step_dev -= 1
         self.capture(self._split)
+
+
+def autotune_tile(make_opt, set_views, shapes=((16, 16), (8, 32), (32, 8)), warm=2, timed=3):
+    """Tile-shape autotuner of the batched step: for each shape, make_opt(shape) builds an
+    optimiser on the same map; warm eager steps (with capacity checks) size its buffers, then
+    `timed` eager steps are timed between two device synchronisations.  set_views(opt, k) selects
+    the views of step k (the same k for every shape).  Returns (fastest shape, {shape: s/step}).
+
+    Whole-tile images are bit-identical across the shapes; tiles long enough to be composited in
+    depth slices are cut at different list positions under different shapes, so there the images
+    (and gradients) of the chosen shape differ from another shape's by float rounding only."""
+    import time
+    res = {}
+    for sh in shapes:
+        o = make_opt(sh)
+        for k in range(warm):
+            set_views(o, k)
+            o.step(check_capacity=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(timed):
+            set_views(o, warm + k)
+            o.step(check_capacity=False)
+        torch.cuda.synchronize()
+        res[tuple(sh)] = (time.perf_counter() - t0) / timed
+        del o
+        torch.cuda.empty_cache()
+    return min(res, key=res.get), res

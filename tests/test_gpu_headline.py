@@ -116,3 +116,72 @@ def test_headline_backward_sampled_pixels_match_oracle(headline):
         gk = grads[k].cpu().numpy().astype(np.float64)
         bad = grad_close(gk, exp[k])
         assert bad.sum() == 0, (k, int(bad.sum()), touched)
+
+
+def test_headline_fused_step_matches_separate_render_and_oracle(headline):
+    """The fused persistent step (forward + L1 loss + backward per view-tile, depth slices of the
+    long tiles finished by the workgroup that completes their last slice) at the headline size.
+    Targets equal the separate forward's images except at the sampled pixels of two views, where
+    they are moved by +-0.1: the loss gradient is exactly zero elsewhere (sign(0) = 0), so the
+    fused images must equal the separate forward's bit for bit, the loss must be the sampled
+    pixels' terms, and every parameter and pose gradient must match the oracle's backward of the
+    upstream gradient sign / P at those pixels."""
+    import paper_2604_12942_amd as gsr
+    h = headline
+    g, cams, rast, P, ct = h["g"], h["cams"], h["rast"], h["P"], h["ct"]
+    V = len(cams)
+    H, W = cams[0]["height"], cams[0]["width"]
+    Pn = W * H
+    lam = 0.2
+    views = (1, V - 2)
+    rng = np.random.default_rng(4242)
+    trgb = h["rgb"].astype(np.float32).copy()
+    tdep = h["depth"].astype(np.float32).copy()
+    GC = np.zeros((V, 3, H, W))
+    GD = np.zeros((V, H, W))
+    exp_loss = 0.0
+    for v in views:
+        px = h["pix"][v]
+        px = px[oracle.render(g, cams[v], pixels=px)["margin"] >= KNIFE]
+        x, y = px[:, 0], px[:, 1]
+        sc = rng.choice([-1.0, 1.0], (3, x.size)).astype(np.float32)
+        sd = rng.choice([-1.0, 1.0], x.size).astype(np.float32)
+        trgb[v][:, y, x] += np.float32(0.1) * sc
+        tdep[v][y, x] += np.float32(0.1) * sd
+        GC[v][:, y, x] = -sc / Pn
+        GD[v][y, x] = -lam * sd / Pn
+        dC = h["rgb"][v][:, y, x].astype(np.float32) - trgb[v][:, y, x]
+        dD = h["depth"][v][y, x].astype(np.float32) - tdep[v][y, x]
+        exp_loss += (np.abs(dC).astype(np.float64).sum() + lam * np.abs(dD).astype(np.float64).sum()) / Pn
+    r = rast
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty((gsr.render_step_workspace(V, r.raster, r.capacity) + 255) // 256 * 64, dtype=torch.int32,
+                     device="cuda")
+    gsr.render_step(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, r.raster, torch.from_numpy(trgb).cuda(),
+                    torch.from_numpy(tdep).cuda(), lam, r.rgb, r.depth, r.T_final, r.last, loss, r.dinst, r.capacity,
+                    ws, tile_order=r.tile_order)
+    torch.cuda.synchronize()
+    assert np.array_equal(r.rgb.cpu().numpy(), h["rgb"].astype(np.float32))
+    assert np.array_equal(r.depth.cpu().numpy(), h["depth"].astype(np.float32))
+    assert np.array_equal(r.T_final.cpu().numpy(), h["T"].astype(np.float32))
+    assert abs(loss.item() - exp_loss) <= 1e-5 * exp_loss, (loss.item(), exp_loss)
+    grads = {k: torch.zeros_like(P[k]) for k in gsr.PARAM_NAMES}
+    gsr.project_bwd(P, g["sh_degree"], ct, V, r.raster, r.splats, r.dinst, r.em, r.tile_info, grads, r.dpose,
+                    r.pose_ws)
+    torch.cuda.synchronize()
+    exp = {k: 0.0 for k in gsr.PARAM_NAMES}
+    pz = r.dpose.cpu().numpy()
+    for v in views:
+        o = oracle.render_bwd(g, cams[v], GC[v], GD[v])
+        live = (np.abs(GC[v]).sum(axis=0) + np.abs(GD[v])) > 0
+        assert not np.any(o["knife_px"] & live), v
+        for k in gsr.PARAM_NAMES:
+            exp[k] = exp[k] + o[k]
+        assert np.all(np.abs(pz[v] - o["pose"]) <= GRAD_RTOL * (np.abs(o["pose"]) + np.sqrt(np.mean(o["pose"] ** 2)))), v
+    for v in range(V):
+        if v not in views:
+            assert np.all(pz[v] == 0), v
+    for k in gsr.PARAM_NAMES:
+        gk = grads[k].cpu().numpy().astype(np.float64)
+        bad = grad_close(gk, exp[k])
+        assert bad.sum() == 0, (k, int(bad.sum()))

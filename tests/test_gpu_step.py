@@ -171,3 +171,52 @@ def test_replay_regrows_an_overflowed_capacity():
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         pa, pb = a.P[name].cpu().numpy(), b.P[name].cpu().numpy()
         assert np.allclose(pa, pb, rtol=2e-6, atol=1e-6), name
+
+
+@pytest.mark.parametrize("scene", ["three_views", "pile_up"])
+def test_fused_render_step_equals_separate_launches(scene):
+    """gsr_render_step against gsr_render_fwd_sliced + gsr_loss_l1 + gsr_render_bwd: images and
+    last positions bit for bit, the loss to float64 summation order, the per-pair screen-space
+    gradients to the float rounding of the backward's LDS sums; the pile-up has tiles long enough
+    to be composited in depth slices (finished by the workgroup that completes their last slice)."""
+    import paper_2604_12942_amd as gsr
+    from gpu_common import long_tile_scene
+    if scene == "three_views":
+        g, cams, _, _ = _three_views(6)
+    else:
+        g, cam = long_tile_scene()
+        cams = [cam, synth.make_camera(synth.small_rotation(np.random.default_rng(1), 3.0), np.zeros(3), 60.0, 60.0,
+                                       32.0, 32.0, 64, 64)]
+    V = len(cams)
+    H, W = cams[0]["height"], cams[0]["width"]
+    rng = np.random.default_rng(11)
+    trgb = torch.from_numpy(rng.uniform(0, 1, (V, 3, H, W)).astype(np.float32)).cuda()
+    tdep = torch.from_numpy(rng.uniform(2, 10, (V, H, W)).astype(np.float32)).cuda()
+    raster = gsr.Raster(W, H, 16, 16)
+    P = gsr.gaussians_to_device(g)
+    ct = gsr.camera_tensor(cams)
+    r = gsr.Rasterizer(P["means"].shape[1], V, raster)
+    r.forward(P, g["sh_degree"], ct, sliced=True)
+    loss_a = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gC = torch.empty(V, 3, H, W, device="cuda")
+    gD = torch.empty(V, H, W, device="cuda")
+    gsr.loss_l1(r.rgb, r.depth, trgb, tdep, V, raster, 0.2, loss_a, gC, gD)
+    r.render_backward(ct, gC, gD)
+    torch.cuda.synchronize()
+    ref = dict(rgb=r.rgb.clone(), depth=r.depth.clone(), T=r.T_final.clone(), last=r.last.clone())
+    ds_a = r.screen_grads().cpu().numpy().astype(np.float64)
+    if scene == "pile_up":
+        lens = (r.tile_ranges.view(-1, 2)[:, 1] - r.tile_ranges.view(-1, 2)[:, 0]).cpu().numpy()
+        assert lens.max() > 8192, lens.max()
+    for k in (r.rgb, r.depth, r.T_final, r.last, r.dinst):
+        k.fill_(-7)
+    loss_b = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gsr.render_step(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, raster, trgb, tdep, 0.2, r.rgb,
+                    r.depth, r.T_final, r.last, loss_b, r.dinst, r.capacity, r.fwd_ws, tile_order=r.tile_order)
+    torch.cuda.synchronize()
+    assert torch.equal(r.rgb, ref["rgb"]) and torch.equal(r.depth, ref["depth"])
+    assert torch.equal(r.T_final, ref["T"]) and torch.equal(r.last, ref["last"])
+    assert abs(loss_a.item() - loss_b.item()) <= 1e-12 * abs(loss_a.item())
+    ds_b = r.screen_grads().cpu().numpy().astype(np.float64)
+    rms = np.sqrt(np.mean(ds_a.reshape(-1, 10) ** 2, axis=0))
+    assert np.all(np.abs(ds_b - ds_a).reshape(-1, 10) <= 1e-4 * (np.abs(ds_a).reshape(-1, 10) + rms))
