@@ -29,11 +29,14 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # without packed FP32 (not generated in this build): 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_PEAK_NONPACKED_TFLOPS = 78.6
-# algorithmic float operations per composited (pixel, Gaussian) pair
-FLOP_PER_BLEND_FWD = 23
-FLOP_PER_BLEND_BWD = 48
+# algorithmic float operations per composited (pixel, Gaussian) pair, plus one exp each (not
+# counted): forward 20, backward 45 (the fused step does both)
+FLOP_PER_BLEND_FWD = 20
+FLOP_PER_BLEND_BWD = 45
+# optimiser iterations from the initialisation to the timed (steady) state of the map
+STEADY_ITERS = 500
 # the kernel each timed stage launches (its name in rocprofv3 kernel traces)
-KERNEL_OF_STAGE = dict(project="k_project", bin_sort="gsr_bin_sort (11 kernels)", render_fwd="k_render_fwd",
+KERNEL_OF_STAGE = dict(project="k_project", bin_sort="gsr_bin_sort (12 kernels)", render_fwd="k_render_fwd",
                        loss="k_loss_l1", render_bwd="k_render_bwd", project_bwd="k_project_bwd")
 # HBM bytes per launch of a kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counters on this
 # workload, each scaled by the counter's reading for a 256 MiB device copy (fetch x1.9997, write x1.0);
@@ -72,6 +75,7 @@ def parse():
     ap.add_argument("--no-full-loss", action="store_true",
                     help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
+    ap.add_argument("--no-c2", action="store_true", help="skip the one-view 300k-Gaussian room leg")
     ap.add_argument("--contrib-compare", action="store_true",
                     help="instead of the step: stored vs recomputed contributor lists on the 4M-Gaussian 1080p view")
     ap.add_argument("--init-compare", action="store_true",
@@ -88,6 +92,26 @@ def parse():
 def _render_target(args):
     scene, cam = args
     return scene.render_gt(cam)
+
+
+def cascade_map(c, seg, dev, seed=1):
+    """Gaussians of the LiDAR points from the voxel-PCA cascade on the GPU (voxel fit, then Eq. 3
+    without a model: PCA branch with the per-segment beta of Eq. 5, else the heuristic branch of
+    Eq. 6 at the point's range over the keyframes' focal length); higher-order SH from the
+    generator (N(0, 0.05^2)) so that the full degree-3 colour work is exercised."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    pc = c["points"]
+    pts = torch.from_numpy(np.ascontiguousarray(pc["points"].T)).to(dev)
+    col = torch.from_numpy(np.ascontiguousarray(pc["colors"].T)).to(dev)
+    depth = torch.from_numpy(np.ascontiguousarray(pc["ranges"])).to(dev)
+    vox = gsr.voxel_pca(pts, seed)
+    P, _ = gsr.cascade(pts, col, depth, vox, focal=640.0, beta=0.0, segment=seg, n_segments=int(c["n_segments"]),
+                       sh_degree=3)
+    P["sh"][3:] = torch.from_numpy(c["gaussians"]["sh"][3:]).to(dev)
+    torch.cuda.synchronize()
+    return P
 
 
 def build_workload(n_points, workers):
@@ -108,6 +132,18 @@ def views_for_step(step):
     return np.concatenate([rng.choice(8, 4, replace=False), 8 + rng.choice(8, 4, replace=False)])
 
 
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(c, pool_cams, tg, step_views, n_sample=4):
     """FP64 oracle on n_sample of the 8 views of one step (forward + L1 loss + backward incl. pose,
     over all Gaussians at full resolution), scaled to a whole step."""
@@ -123,6 +159,7 @@ def cpu_baseline(c, pool_cams, tg, step_views, n_sample=4):
     dt = time.perf_counter() - t0
     V = len(step_views)
     return dict(value=round(n_sample / (V * dt), 5), unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+                nproc=len(os.sched_getaffinity(0)), cpu_model=cpu_model(),
                 sample="%d of the %d views of one step (forward + L1 loss + backward incl. pose, all %d Gaussians, "
                        "%dx%d), %.1f s, scaled to %d views" % (n_sample, V, g["means"].shape[1], pool_cams[0]["width"],
                                                               pool_cams[0]["height"], dt, V))
@@ -558,6 +595,121 @@ def init_leg(dev, reps=5):
     return res
 
 
+def render_modes_leg(make_opt, sv, tile, params, stages, stream, first_step, k=5):
+    """The same steps (same map, same views) with the render, L1 loss and render backward as three
+    launches, as two (the loss inside the render backward) and as one persistent launch: the sum
+    of those stages' times in ms per step (HIP events on the launch stream, eager steps)."""
+    import torch
+    res = {}
+    for mode in ("separate", "two_pass", "persistent"):
+        o = make_opt(tile, params=params, render=mode)
+        for s in range(3):
+            sv(o, first_step + s)
+            o.step(check_capacity=True)
+        tot = 0.0
+        for s in range(k):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+            def mark(name, ev=ev):
+                if name == "bin_sort":
+                    ev[0].record(stream)
+                elif name == "render_bwd":
+                    ev[1].record(stream)
+
+            sv(o, first_step + 3 + s)
+            o.step(check_capacity=False, timer=mark)
+            torch.cuda.synchronize()
+            tot += ev[0].elapsed_time(ev[1])
+        res[mode] = round(tot / k, 4)
+        del o
+        torch.cuda.empty_cache()
+    print("render modes (fwd + loss + bwd ms/step): %s" % res, file=sys.stderr, flush=True)
+    return res
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of 1 GiB: (read + write bytes) / time in GB/s, the measured ceiling the
+    step's algorithmic bytes are also compared with."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def c2_leg(a, dev, steps=20):
+    """The one-view room configuration: 300k Gaussians at SH degree 3 from the voxel-PCA cascade,
+    one 1280x720 view, the step (forward + L1 rgb + 0.2 L1 depth + backward + sparse Adam),
+    captured; iterations/s, blends/s and the render forward + loss + backward share of the step."""
+    import torch
+
+    import paper_2604_12942_amd as gsr
+    from paper_2604_12942_amd.optimize import MapOptimizer
+    c = synth.config2()
+    cam = c["cameras"][0]
+    W, H = cam["width"], cam["height"]
+    seg = torch.zeros(c["gaussians"]["means"].shape[1], dtype=torch.int32, device=dev)
+    P = cascade_map(dict(c, n_segments=1), seg, dev)
+    trgb = torch.from_numpy(c["target_rgb"][0][None]).to(dev)
+    tdep = torch.from_numpy(c["target_depth"][0][None]).to(dev)
+    o = MapOptimizer(P, 3, gsr.camera_tensor([cam], dev), trgb, tdep, gsr.Raster(W, H, 16, 16), 1, lambda_depth=0.2,
+                     device=dev)
+    o.set_views([0])
+    for _ in range(3):
+        o.step(check_capacity=True)
+    o.capture(split=("render_fwd", "project_bwd"))
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rend = 0.0
+    for _ in range(steps):
+        e[0].record(stream)
+
+        def between(k):
+            if k == 1:
+                e[1].record(stream)
+            elif k == 2:
+                e[2].record(stream)
+
+        o.replay(between=between, check_capacity=False)
+        torch.cuda.synchronize()
+        rend += e[1].elapsed_time(e[2])
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    if o.overflowed():
+        print("instance capacity exceeded in the C2 leg", file=sys.stderr)
+        sys.exit(3)
+    r = o.rast
+    ncon = torch.empty(1, H, W, dtype=torch.int32, device=dev)
+    gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, o.cams, 1, o.raster, r.rgb, r.depth, r.T_final, r.last,
+                   ncon, tile_order=r.tile_order)
+    torch.cuda.synchronize()
+    blends = int(ncon.sum().item())
+    rend /= steps
+    ach = blends * (FLOP_PER_BLEND_FWD + FLOP_PER_BLEND_BWD) / (rend / 1000.0) / 1e12
+    res = dict(workload="room, %d Gaussians SH3 from the voxel-PCA cascade, one 1280x720 view, L1 rgb + 0.2 L1 "
+                        "depth, sparse Adam, captured step (%s render)" % (P["means"].shape[1], o.render),
+               iters_per_s=round(1000.0 / ms, 3), ms_per_step=round(ms, 4), blends_per_step=blends,
+               blends_per_s=round(blends / (ms / 1000.0), 1), instances=r.instances(),
+               render_fwd_loss_bwd_ms=round(rend, 4),
+               render_roofline=dict(bound="alu", achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                    frac=round(ach / FP32_PEAK_TFLOPS, 4), flop_per_blend=FLOP_PER_BLEND_FWD +
+                                    FLOP_PER_BLEND_BWD))
+    print("C2: %s" % res, file=sys.stderr, flush=True)
+    del o
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.init_compare:
@@ -590,11 +742,10 @@ def main():
     import torch
 
     import paper_2604_12942_amd as gsr
-    from paper_2604_12942_amd.optimize import MapOptimizer
+    from paper_2604_12942_amd.optimize import MapOptimizer, autotune_tile
 
     dev = "cuda"
-    g = c["gaussians"]
-    n = g["means"].shape[1]
+    n = c["gaussians"]["means"].shape[1]
     V = 8
     H, W = pool_cams[0]["height"], pool_cams[0]["width"]
     trgb = torch.from_numpy(np.stack([x[0] for x in tg])).to(dev)
@@ -602,17 +753,21 @@ def main():
     cam_pool = gsr.camera_tensor(pool_cams, dev)
     seg = torch.from_numpy(c["segment_id"]).to(dev)
     min_seg = int(c["n_segments"]) - 5
+    # the map: the LiDAR points initialised on the GPU by the voxel-PCA cascade (Eq. 3, 5, 6)
+    P0 = cascade_map(c, seg, dev)
+    g = {k: P0[k].cpu().numpy() for k in gsr.PARAM_NAMES}
+    g["sh_degree"] = 3
 
-    def make_opt(tile, **kw):
-        P = gsr.gaussians_to_device(g, dev)
+    def make_opt(tile, params=None, **kw):
+        P = {k: (params or P0)[k].clone() for k in gsr.PARAM_NAMES}
         raster = gsr.Raster(W, H, *tile)
-        o = MapOptimizer(P, g["sh_degree"], cam_pool, trgb, tdep, raster, V, lambda_depth=0.2, segment_id=seg,
+        o = MapOptimizer(P, 3, cam_pool, trgb, tdep, raster, V, lambda_depth=0.2, segment_id=seg,
                          min_segment=min_seg, device=dev, **kw)
         o.reorder()  # the map's rows in storage order: by segment, Morton order inside a segment
         return o
 
     # the view schedule of every step, resident on the device (no host round-trip per step)
-    n_main = max(a.warmup + a.steps, 10)
+    n_main = a.warmup + 2 * (10 + max(a.steps, 10)) + STEADY_ITERS + 16
     sched = torch.from_numpy(np.stack([views_for_step(s) for s in range(n_main)] +
                                       [views_for_step(10_000 + s) for s in range(2)] +
                                       [views_for_step(10_100 + s) for s in range(3)])).to(dev)
@@ -632,24 +787,15 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / k
 
-    # project-written autotuner: the same warm state timed under each tile shape
+    # project-written autotuner (package: paper_2604_12942_amd.optimize.autotune_tile)
     shapes = [(16, 16), (8, 32), (32, 8)] if a.tile == "auto" else [tuple(int(x) for x in a.tile.split("x"))]
-    tune = {}
     if len(shapes) > 1:
-        for sh in shapes:
-            o = make_opt(sh)
-            for s in range(2):
-                sv(o, 10_000 + s)
-                o.step(check_capacity=True)
-            tune["%dx%d" % sh] = timed_steps(o, 3, 10_100)
-            del o
-            torch.cuda.empty_cache()
-        tile = min(shapes, key=lambda s: tune["%dx%d" % s])
+        tile, tune = autotune_tile(make_opt, lambda o, s: sv(o, 10_000 + s if s < 2 else 10_100 + s - 2), shapes)
+        tune = {"%dx%d" % k: v for k, v in tune.items()}
     else:
-        tile = shapes[0]
+        tile, tune = shapes[0], {}
     print("tile autotune (s/step): %s -> %dx%d" % (tune, *tile), file=sys.stderr, flush=True)
 
-    opt = make_opt(tile)
     stages = list(MapOptimizer.STAGES)
     stream = torch.cuda.current_stream()
 
@@ -671,58 +817,46 @@ def main():
             recs.append((e0, evs))
         return recs
 
-    opt = make_opt(tile)
-    # warmup with capacity checks (instance buffer grows to fit), then fix the capacity
-    m_max = 0
-    for s in range(a.warmup):
-        sv(opt, s)
-        opt.step(check_capacity=True)
-        m_max = max(m_max, opt.rast.instances())
-    if opt.rast.capacity < int(m_max * 1.3):
-        opt.rast._alloc_instances(int(m_max * 1.3))
+    def fit_capacity(o, first_step, k):
+        """k eager steps with capacity checks, then room for 1.3 x the largest instance count."""
+        m_max = 0
+        for s in range(k):
+            sv(o, first_step + s)
+            o.step(check_capacity=True)
+            m_max = max(m_max, o.rast.instances())
+        if o.rast.capacity < int(m_max * 1.3):
+            o.rast._alloc_instances(int(m_max * 1.3))
 
-    # per-stage breakdown (its own pass: events between every stage perturb the wall clock)
-    recs = staged_steps(opt, max(3, min(a.steps, 10)), 0)
-    torch.cuda.synchronize()
-    stage_ms = {k: 0.0 for k in stages}
-    for e0, evs in recs:
-        prev = e0
-        for k in stages:
-            stage_ms[k] += prev.elapsed_time(evs[k])
-            prev = evs[k]
-    stage_ms = {k: v / len(recs) for k, v in stage_ms.items()}
-    dom = max(stage_ms, key=stage_ms.get)
-    before = stages[stages.index(dom) - 1]
-
-    # eager step time without events (for reference)
-    k_eager = max(3, min(a.steps, 10))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(k_eager):
-        sv(opt, s)
-        opt.step(check_capacity=False)
-    torch.cuda.synchronize()
-    eager_ms = 1000.0 * (time.perf_counter() - t0) / k_eager
-
-    # timed region: K steps; HIP events only around the dominant kernel's stage, recorded on the
-    # launch stream between the captured parts (or between eager stages)
-    i_dom = stages.index(dom)
-    use_graph = not a.no_graph
-    if use_graph:
+    def measure(o, first_step, k_timed):
+        """Stage breakdown (its own pass), then k_timed captured steps with HIP events on the launch
+        stream: around every step (percentiles) and around the dominant kernel's stage."""
+        recs = staged_steps(o, max(3, min(k_timed, 10)), first_step)
+        torch.cuda.synchronize()
+        stage_ms = {k: 0.0 for k in stages}
+        for e0, evs in recs:
+            prev = e0
+            for k in stages:
+                stage_ms[k] += prev.elapsed_time(evs[k])
+                prev = evs[k]
+        stage_ms = {k: v / len(recs) for k, v in stage_ms.items()}
+        dom = max(stage_ms, key=stage_ms.get)
+        i_dom = stages.index(dom)
         split = (dom,) + ((stages[i_dom + 1],) if i_dom + 1 < len(stages) else ())
         if i_dom == 0:
             split = split[1:]
-        opt.capture(split=split)
+        o.capture(split=split)
         dom_part = 0 if i_dom == 0 else 1
-    m_seen = torch.zeros(a.steps, dtype=torch.int32, device=dev)
-    ev_pairs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(a.steps):
-        e_a = torch.cuda.Event(enable_timing=True)
-        e_b = torch.cuda.Event(enable_timing=True)
-        sv(opt, a.warmup + s)
-        if use_graph:
+        m_seen = torch.zeros(k_timed, dtype=torch.int32, device=dev)
+        ev_dom, ev_step = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(k_timed):
+            e_a = torch.cuda.Event(enable_timing=True)
+            e_b = torch.cuda.Event(enable_timing=True)
+            e_s = torch.cuda.Event(enable_timing=True)
+            e_s.record(stream)
+            ev_step.append(e_s)
+            sv(o, first_step + len(recs) + s)
             if dom_part == 0:
                 e_a.record(stream)
 
@@ -732,44 +866,63 @@ def main():
                 elif k == dom_part + 1:
                     e_b.record(stream)
 
-            opt.replay(between=between, check_capacity=False)
-            if dom_part + 1 == len(opt.graphs):
+            o.replay(between=between, check_capacity=False)
+            if dom_part + 1 == len(o.graphs):
                 e_b.record(stream)
-        else:
-            def mark(name, e_a=e_a, e_b=e_b):
-                if name == before:
-                    e_a.record(stream)
-                elif name == dom:
-                    e_b.record(stream)
+            m_seen[s:s + 1].copy_(o.rast.n_instances)
+            ev_dom.append((e_a, e_b))
+        e_end = torch.cuda.Event(enable_timing=True)
+        e_end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        m_all = m_seen.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        if m_all.max() > o.rast.capacity:
+            print("instance capacity exceeded in the timed region", file=sys.stderr)
+            sys.exit(3)
+        per_step = [a_.elapsed_time(b_) for a_, b_ in zip(ev_step, ev_step[1:] + [e_end])]
+        dom_ms = sum(e_a.elapsed_time(e_b) for e_a, e_b in ev_dom) / k_timed
+        return dict(ms_per_step=1000.0 * wall / k_timed, per_step=per_step, stage_ms=stage_ms, dom=dom,
+                    dom_ms=dom_ms, last_step=first_step + len(recs) + k_timed - 1)
 
-            if i_dom == 0:
-                e_a.record(stream)
-            opt.step(check_capacity=False, timer=mark)
-        m_seen[s:s + 1].copy_(opt.rast.n_instances)
-        ev_pairs.append((e_a, e_b))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1000.0 * wall / a.steps
-    dom_ms = sum(e_a.elapsed_time(e_b) for e_a, e_b in ev_pairs) / a.steps
-    m_all = m_seen.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
-    if m_all.max() > opt.rast.capacity:
-        print("instance capacity exceeded in the timed region", file=sys.stderr)
-        sys.exit(3)
+    def workload_stats(o, step):
+        """Blends, instances, visible pairs and updated rows of one step (same views)."""
+        sv(o, step)
+        r = o.rast
+        ncon = torch.empty(V, H, W, dtype=torch.int32, device=dev)
+        r.project(o.P, o.sh_degree, o.cams)
+        r.bin(True)
+        gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, o.cams, V, o.raster, r.rgb, r.depth, r.T_final, r.last,
+                       ncon, tile_order=r.tile_order)
+        torch.cuda.synchronize()
+        ti = r.tile_info.view(4, -1)
+        return dict(blends=int(ncon.sum().item()), M=r.instances(), Nv=int((ti[0] > 0).sum().item()),
+                    Nu=int(o.row_mask.sum().item()))
 
-    # workload statistics of one representative step (same views as the last timed step)
-    sv(opt, a.warmup + a.steps - 1)
-    r = opt.rast
-    ncon = torch.empty(V, H, W, dtype=torch.int32, device=dev)
-    r.project(opt.P, opt.sh_degree, opt.cams)
-    r.bin(True)
-    gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, opt.cams, V, opt.raster, r.rgb, r.depth, r.T_final, r.last,
-                   ncon, tile_order=r.tile_order)
-    torch.cuda.synchronize()
-    blends = int(ncon.sum().item())
-    M = r.instances()
-    ti = r.tile_info.view(4, -1)
-    Nv = int((ti[0] > 0).sum().item())
-    Nu = int(opt.row_mask.sum().item())
+    opt = make_opt(tile)
+    fit_capacity(opt, 0, a.warmup)
+    # the map as initialised: a shorter timed run
+    k_init = max(3, min(a.steps, 10))
+    at_init = measure(opt, a.warmup, k_init)
+    wl_init = workload_stats(opt, at_init["last_step"])
+    # steady state: STEADY_ITERS optimiser iterations from the initialisation, then the timed run
+    s0 = at_init["last_step"] + 1
+    for s in range(STEADY_ITERS):
+        sv(opt, s0 + s)
+        opt.replay(check_capacity=True)
+    s0 += STEADY_ITERS
+    fit_capacity(opt, s0, 3)
+    res = measure(opt, s0 + 3, a.steps)
+    wl = workload_stats(opt, res["last_step"])
+    stage_ms, dom, dom_ms, ms_per_step = res["stage_ms"], res["dom"], res["dom_ms"], res["ms_per_step"]
+    blends, M, Nv, Nu = wl["blends"], wl["M"], wl["Nv"], wl["Nu"]
+    g = {k: opt.P[k].cpu().numpy() for k in gsr.PARAM_NAMES}  # the map the CPU baseline renders
+    g["sh_degree"] = 3
+    c = dict(c, gaussians=g)
+
+    # eager step time without events (for reference)
+    eager_ms = 1000.0 * timed_steps(opt, max(3, min(a.steps, 10)), 0)
+    use_graph = True
+
     Pf = 59
     P = W * H
     T = opt.raster.tiles
@@ -781,22 +934,37 @@ def main():
              adam=Nu * 4 * Pf * 8)
     B_alg = sum(B.values())
     step_s = ms_per_step / 1000.0
-    kname = KERNEL_OF_STAGE[dom]
+    fused = opt.fused_render
+    render_mode = opt.render
+    kname = "k_render_step" if (fused and dom == "render_fwd") else KERNEL_OF_STAGE[dom]
+    if opt.render == "two_pass" and dom == "render_bwd":
+        kname = "k_render_bwd_l1"
     if dom in ("render_fwd", "render_bwd"):
-        fl = blends * (FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
+        fpb = (FLOP_PER_BLEND_FWD + FLOP_PER_BLEND_BWD) if (fused and dom == "render_fwd") else \
+            (FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
+        fl = blends * fpb
         ach = fl / (dom_ms / 1000.0) / 1e12
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
                     frac_of_nonpacked_peak=round(ach / FP32_PEAK_NONPACKED_TFLOPS, 4),
                     kernel=kname, launch_ms=round(dom_ms, 4), units_per_launch=blends, unit_kind="blend",
-                    flop_per_unit=FLOP_PER_BLEND_FWD if dom == "render_fwd" else FLOP_PER_BLEND_BWD)
+                    flop_per_unit=fpb)
     else:
         ach = B[dom] / (dom_ms / 1000.0) / 1e9
         roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
                     kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
+    pct = np.percentile(np.asarray(res["per_step"]), [10, 50, 90])
+    init_pct = np.percentile(np.asarray(at_init["per_step"]), [10, 50, 90])
+    at_init_out = dict(iters_per_s=round(1000.0 / at_init["ms_per_step"], 3),
+                       ms_per_step=round(at_init["ms_per_step"], 3),
+                       step_ms_p10_p50_p90=[round(float(x), 4) for x in init_pct],
+                       stage_ms={k: round(v, 4) for k, v in at_init["stage_ms"].items()},
+                       blends_per_step=wl_init["blends"], instances_per_step=wl_init["M"],
+                       blends_per_s=round(wl_init["blends"] / (at_init["ms_per_step"] / 1000.0), 1))
 
     loss_last = float(opt.loss.item())
+    modes = render_modes_leg(make_opt, sv, tile, opt.P, stages, stream, s0)
     maint = loopr = initr = None
     if not a.no_maintenance:
         maint = maintenance_leg(g, seg, min_seg, dev)
@@ -808,6 +976,8 @@ def main():
         torch.cuda.empty_cache()
         full = full_loss_leg(make_opt, sv, a, tile, stages, stream, V * P)
 
+    copy_gbs = copy_bandwidth()
+    c2 = None if a.no_c2 else c2_leg(a, dev)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(c, pool_cams, tg, views_for_step(a.warmup + a.steps - 1))
@@ -825,9 +995,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "loop corridor, %d Gaussians SH3, 8 views 1280x720 per step, L1 rgb + 0.2 L1 depth, "
-                               "sparse Adam over 5 latest segments" % n, "gaussians": n, "views_per_step": V,
+        "config": {"workload": "loop corridor, %d Gaussians SH3 from the voxel-PCA cascade after %d optimiser "
+                               "iterations, 8 views 1280x720 per step, L1 rgb + 0.2 L1 depth, sparse Adam over 5 "
+                               "latest segments" % (n, STEADY_ITERS), "gaussians": n, "views_per_step": V,
                    "width": W, "height": H, "tile": "%dx%d" % tile},
+        "step_ms_p10_p50_p90": [round(float(x), 4) for x in pct],
+        "iters_per_s_at_median": round(1000.0 / float(pct[1]), 3),
+        "render_mode": render_mode,
+        "render_modes_ms": modes,
+        "at_init": at_init_out,
         "blends_per_s": round(blends / step_s, 1),
         "blends_per_step": blends,
         "instances_per_step": M,
@@ -838,6 +1014,8 @@ def main():
         "eager_ms_per_step": round(eager_ms, 3),
         "step_alg_bytes": B_alg,
         "step_hbm_frac": round(B_alg / step_s / (HBM_PEAK_GBS * 1e9), 4),
+        "step_hbm_frac_of_measured_copy": round(B_alg / step_s / (copy_gbs * 1e9), 4) if copy_gbs else None,
+        "copy_GBps": round(copy_gbs, 1) if copy_gbs else None,
         "tile_autotune_s_per_step": {k: round(v, 5) for k, v in tune.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -846,6 +1024,7 @@ def main():
         "maintenance": maint,
         "loop_registration": loopr,
         "init_path": initr,
+        "c2": c2,
     }
     print(json.dumps(out), flush=True)
 

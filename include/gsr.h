@@ -241,6 +241,23 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
                                   int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,
                                   const float *dL_drgb, const float *dL_ddepth, float *dinst, gsr_stream stream);
 
+/* ---- render backward of the per-pixel L1 loss ---------------------------------------------------
+ * gsr_loss_l1 followed by gsr_render_bwd in one launch: each workgroup forms its view-tile's pixel
+ * terms L_v = (1/P) sum_ch |C - C~| + lambda_depth (1/P) |D - D~| and gradients sign(C - C~)/P,
+ * lambda_depth sign(D - D~)/P (sign(0) = 0) from the forward's rgb and depth and the targets in
+ * registers (no gradient image is written or read), then writes the tile's backward records
+ * exactly as gsr_render_bwd does for that upstream gradient (Sec. III-C, Eq. 8-10).  Inputs as
+ * gsr_render_bwd plus the forward's rgb [V][3][H][W] and depth [V][H][W]; targets as gsr_loss_l1.
+ * *loss (device float64) is ACCUMULATED, summed over the view-tiles in a fixed order.  ws:
+ * gsr_render_bwd_l1_workspace(V, r) bytes (one float64 per view-tile), 256-byte aligned. */
+GSR_API size_t gsr_render_bwd_l1_workspace(int32_t n_views, const gsr_raster *r);
+GSR_API gsr_status gsr_render_bwd_l1(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                     const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
+                                     int32_t n_views, const gsr_raster *r, const float *rgb, const float *depth,
+                                     const float *T_final, const uint32_t *last, const float *target_rgb,
+                                     const float *target_depth, const int32_t *target_index, float lambda_depth,
+                                     double *loss, float *dinst, void *ws, size_t ws_bytes, gsr_stream stream);
+
 /* ---- fused step: render forward, L1 loss and render backward in one persistent launch ----------
  * The batched optimisation step of Sec. III-C with the loss of Eq. 9-10 restricted to its
  * per-pixel terms (all-ones mask, lambda_ssim = 0): for every view-tile, the front-to-back
@@ -577,6 +594,18 @@ GSR_API gsr_status gsr_cascade_anchored(const float *points, const float *colors
                                         const float *pred, float focal, float beta, int32_t sh_degree,
                                         const gsr_params *out, uint8_t *branch, void *ws, size_t ws_bytes,
                                         gsr_stream stream);
+
+/* ---- training targets of the model branch (Sec. III-B) ------------------------------------------
+ * The point network learns what the plain optimiser makes of the Gaussians a voxel's points seed.
+ * For every voxel v of gsr_voxel_pca (arrays sized n, stride n): over ALL the voxel's points i (one
+ * Gaussian per point, row i of gauss: log_scales [3][n], quats [4][n] raw (w, x, y, z),
+ * opacity_logits [n]; means and sh are not read), the mean covariance
+ * R(q_i / |q_i|) diag(exp(2 s_i)) R^T as cov_t [6][n] (xx, xy, xz, yy, yz, zz) and the mean opacity
+ * 1 / (1 + exp(-logit_i)) as o_t [n]; has [n] = 1 for a voxel with points, 0 (and zero targets)
+ * for rows at or past the voxel count.  Sums in float64 in the voxel's point order (fixed), so the
+ * targets repeat exactly.  Errors: GSR_E_INVALID for bad sizes or NULL pointers. */
+GSR_API gsr_status gsr_voxel_targets(const gsr_params *gauss, int64_t n, const gsr_voxels *vox, float *cov_t,
+                                     float *o_t, uint8_t *has, gsr_stream stream);
 
 /* ---- point network of the model branch (Sec. III-B, Eq. 3) ------------------------------------
  * Per voxel of gsr_voxel_pca: 32 input rows (the fitting points repeated cyclically, centred on the

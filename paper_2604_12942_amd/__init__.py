@@ -148,6 +148,20 @@ def render_bwd(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, 
                                _ptr(dL_ddepth), _ptr(dinst), _stream()), "gsr_render_bwd")
 
 
+def render_bwd_l1_workspace(n_views, raster):
+    return int(lib().gsr_render_bwd_l1_workspace(n_views, C.byref(raster.c)))
+
+
+def render_bwd_l1(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last,
+                  target_rgb, target_depth, lambda_depth, loss, dinst, ws, tile_order=None, target_index=None):
+    """Render backward of the per-pixel L1 loss (gsr_render_bwd_l1); loss is accumulated."""
+    check(lib().gsr_render_bwd_l1(_ptr(splats), _ptr(inst_gid), _ptr(inst_emit), _ptr(tile_ranges),
+                                  _ptr(tile_order), _ptr(cams), n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth),
+                                  _ptr(T_final), _ptr(last), _ptr(target_rgb), _ptr(target_depth),
+                                  _ptr(target_index), float(lambda_depth), _ptr(loss), _ptr(dinst), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream()), "gsr_render_bwd_l1")
+
+
 def render_step_workspace(n_views, raster, capacity):
     return int(lib().gsr_render_step_workspace(n_views, C.byref(raster.c), capacity))
 
@@ -467,6 +481,22 @@ def cascade(points, colors, depth, vox, pred=None, focal=640.0, beta=0.0, segmen
              int(n_segments), n, C.byref(V), _ptr(pred), float(focal), float(beta), sh_degree, C.byref(O), _ptr(branch),
              _ptr(ws), ws.numel() * 4, _stream()), "gsr_cascade")
     return P, branch[:n]
+
+
+def voxel_targets(P, vox, cov_t=None, o_t=None, has=None):
+    """Per-voxel training targets (gsr_voxel_targets) of the Gaussians P (one per point of vox's
+    cloud): (cov_t [6, n], o_t [n], has [n] uint8)."""
+    n = P["log_scales"].shape[1]
+    dev = P["log_scales"].device
+    cov_t = torch.empty(6, max(1, n), dtype=torch.float32, device=dev) if cov_t is None else cov_t
+    o_t = torch.empty(max(1, n), dtype=torch.float32, device=dev) if o_t is None else o_t
+    has = torch.empty(max(1, n), dtype=torch.uint8, device=dev) if has is None else has
+    prm = _abi.Params(None, _ptr(P["log_scales"].contiguous()), _ptr(P["quats"].contiguous()),
+                      _ptr(P["opacity_logits"].contiguous()), None)
+    V = _abi.Voxels(*[_ptr(vox[k]) for k in VOXEL_FIELDS])
+    check(lib().gsr_voxel_targets(C.byref(prm), n, C.byref(V), _ptr(cov_t), _ptr(o_t), _ptr(has), _stream()),
+          "gsr_voxel_targets")
+    return cov_t, o_t, has
 
 
 def pointnet_weight_count():

@@ -88,6 +88,9 @@ _SIGS = {
     "gsr_render_bwd_stored": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, C.c_int64, P, P, P, P],
                               C.c_int),
     "gsr_pair_grads": ([P, C.POINTER(Emission), P, C.c_int64, C.c_int32, P, P], C.c_int),
+    "gsr_render_bwd_l1_workspace": ([C.c_int32, C.POINTER(Raster)], C.c_size_t),
+    "gsr_render_bwd_l1": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P, P, C.c_float, P, P, P,
+                           C.c_size_t, P], C.c_int),
     "gsr_render_step_workspace": ([C.c_int32, C.POINTER(Raster), C.c_int64], C.c_size_t),
     "gsr_render_step": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, C.c_float, P, P, P, P, P, P,
                          C.c_int64, P, C.c_size_t, P], C.c_int),
@@ -123,6 +126,7 @@ _SIGS = {
     "gsr_voxel_pca_workspace": ([C.c_int64], C.c_size_t),
     "gsr_voxel_pca": ([P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, C.c_size_t, P], C.c_int),
     "gsr_voxel_pca_cov": ([P, P, C.c_int64, C.c_uint64, C.POINTER(Voxels), P, P, C.c_size_t, P], C.c_int),
+    "gsr_voxel_targets": ([C.POINTER(Params), C.c_int64, C.POINTER(Voxels), P, P, P, P], C.c_int),
     "gsr_pointnet_weight_count": ([], C.c_int),
     "gsr_pointnet_fwd": ([P, C.c_int64, C.POINTER(Voxels), P, P, P], C.c_int),
     "gsr_pointnet_bwd_workspace": ([C.c_int32], C.c_size_t),

@@ -21,6 +21,12 @@ extern "C" size_t gsr_render_fwd_ws_bytes(int, const gsr_raster *, int64_t);
 extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const gsr_camera *, int, const gsr_raster *, float *, float *, float *,
                                             uint32_t *, uint32_t *, int64_t, void *, hipStream_t);
+extern "C" size_t gsr_render_bwd_l1_ws_bytes(int, const gsr_raster *);
+extern "C" gsr_status gsr_render_bwd_l1_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
+                                               const uint32_t *, const gsr_camera *, int, const gsr_raster *,
+                                               const float *, const float *, const float *, const uint32_t *,
+                                               const float *, const float *, const int32_t *, float, double *, float *,
+                                               void *, hipStream_t);
 extern "C" size_t gsr_render_step_ws_bytes(int, const gsr_raster *, int64_t);
 extern "C" gsr_status gsr_render_step_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                              const uint32_t *, const gsr_camera *, int, const gsr_raster *,
@@ -51,6 +57,8 @@ extern "C" size_t gsr_cascade_ws_bytes(int nseg);
 extern "C" gsr_status gsr_cascade_launch(const float *, const float *, const float *, const int32_t *, int, int64_t,
                                          const gsr_voxels *, const float *, float, float, int, const gsr_params *,
                                          uint8_t *, void *, hipStream_t, int);
+extern "C" gsr_status gsr_voxel_targets_launch(const gsr_params *, int64_t, const gsr_voxels *, float *, float *,
+                                              uint8_t *, hipStream_t);
 extern "C" int gsr_pointnet_weight_count(void);
 extern "C" gsr_status gsr_pointnet_fwd_launch(const float *, int64_t, const gsr_voxels *, const float *, float *,
                                               hipStream_t);
@@ -212,6 +220,30 @@ extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *in
         return GSR_E_INVALID;
     return gsr_render_bwd_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, T_final, last,
                                  dL_drgb, dL_ddepth, dinst, S(stream));
+}
+
+extern "C" size_t gsr_render_bwd_l1_workspace(int32_t n_views, const gsr_raster *r) {
+    if (!raster_ok(r) || n_views < 1) return 0;
+    return gsr_render_bwd_l1_ws_bytes(n_views, r);
+}
+
+extern "C" gsr_status gsr_render_bwd_l1(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
+                                        const uint32_t *tile_ranges, const uint32_t *tile_order,
+                                        const gsr_camera *cams, int32_t n_views, const gsr_raster *r, const float *rgb,
+                                        const float *depth, const float *T_final, const uint32_t *last,
+                                        const float *target_rgb, const float *target_depth,
+                                        const int32_t *target_index, float lambda_depth, double *loss, float *dinst,
+                                        void *ws, size_t ws_bytes, gsr_stream stream) {
+    if (!raster_ok(r) || n_views < 1) return GSR_E_INVALID;
+    if (!splats || !inst_gid || !inst_emit || !tile_ranges || !cams || !rgb || !depth || !T_final || !last ||
+        !target_rgb || !loss || !dinst || !ws)
+        return GSR_E_INVALID;
+    if (!(lambda_depth >= 0.f)) return GSR_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
+    if (ws_bytes < gsr_render_bwd_l1_ws_bytes(n_views, r)) return GSR_E_CAPACITY;
+    return gsr_render_bwd_l1_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, rgb, depth,
+                                    T_final, last, target_rgb, target_depth, target_index, lambda_depth, loss, dinst,
+                                    ws, S(stream));
 }
 
 extern "C" size_t gsr_render_step_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity) {
@@ -571,3 +603,12 @@ extern "C" gsr_status gsr_pointnet_bwd(const float *points, int64_t n, const gsr
                                    S(stream));
 }
 
+
+extern "C" gsr_status gsr_voxel_targets(const gsr_params *gauss, int64_t n, const gsr_voxels *vox, float *cov_t,
+                                       float *o_t, uint8_t *has, gsr_stream stream) {
+    if (n < 0 || n >= (int64_t)UINT32_MAX || !gauss || !vox) return GSR_E_INVALID;
+    if (n > 0 && (!gauss->log_scales || !gauss->quats || !gauss->opacity_logits || !vox->n_voxels || !vox->start ||
+                  !vox->count || !vox->point_order || !cov_t || !o_t || !has))
+        return GSR_E_INVALID;
+    return gsr_voxel_targets_launch(gauss, n, vox, cov_t, o_t, has, S(stream));
+}

@@ -475,6 +475,42 @@ __global__ void k_cascade(const float *__restrict__ pts, const float *__restrict
     }
 }
 
+// Training targets of the point network (Sec. III-B): for every voxel, the mean covariance
+// R(q/|q|) diag(exp(2 s)) R^T (xx, xy, xz, yy, yz, zz) and the mean opacity sigmoid(logit) of the
+// Gaussians seeded one per point, over all the voxel's points.  One thread per voxel sums in float64
+// in the voxel's point order (fixed, so the targets repeat exactly); rows at or past the voxel count
+// are zero with has = 0.
+__global__ void k_voxel_targets(const float *__restrict__ ls, const float *__restrict__ qs,
+                                const float *__restrict__ lo, int64_t n, gsr_voxels V, float *__restrict__ cov,
+                                float *__restrict__ ot, uint8_t *__restrict__ has) {
+    const uint32_t nv = *V.n_voxels;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, op = 0.0;
+        const uint32_t c = v < nv ? V.count[v] : 0u;
+        const uint32_t s0 = c ? V.start[v] : 0u;
+        for (uint32_t k = 0; k < c; k++) {
+            const int64_t i = V.point_order[s0 + k];
+            double w = qs[i], x = qs[n + i], y = qs[2 * n + i], z = qs[3 * n + i];
+            const double nq = sqrt(w * w + x * x + y * y + z * z);
+            w /= nq, x /= nq, y /= nq, z /= nq;
+            const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                                    {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                                    {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+            const double e[3] = {exp(2.0 * (double)ls[i]), exp(2.0 * (double)ls[n + i]), exp(2.0 * (double)ls[2 * n + i])};
+            int q = 0;
+            for (int a = 0; a < 3; a++)
+                for (int b = a; b < 3; b++, q++)
+                    acc[q] += R[a][0] * e[0] * R[b][0] + R[a][1] * e[1] * R[b][1] + R[a][2] * e[2] * R[b][2];
+            op += 1.0 / (1.0 + exp(-(double)lo[i]));
+        }
+        const double inv = c ? 1.0 / (double)c : 0.0;
+        for (int q = 0; q < 6; q++) cov[q * n + v] = (float)(acc[q] * inv);
+        ot[v] = (float)(op * inv);
+        has[v] = c ? 1 : 0;
+    }
+}
+
+
 }  // namespace gsr
 
 extern "C" size_t gsr_cascade_ws_bytes(int nseg) { return (size_t)(2 * (nseg > 0 ? nseg : 1) * 4 + 512); }
@@ -492,5 +528,14 @@ extern "C" gsr_status gsr_cascade_launch(const float *pts, const float *col, con
     k_seg_counts<<<g < 1024 ? g : 1024, 256, 0, st>>>(vox->point_voxel, vox->reliable, pred, n, seg, nseg, cnt, fb);
     k_cascade<<<g, 256, 0, st>>>(pts, col, depth, seg, nseg, n, *vox, pred, focal, beta, cnt, fb,
                                  (sh_degree + 1) * (sh_degree + 1), *out, branch, anchored);
+    return last_launch();
+}
+
+extern "C" gsr_status gsr_voxel_targets_launch(const gsr_params *g, int64_t n, const gsr_voxels *vox, float *cov,
+                                              float *ot, uint8_t *has, hipStream_t st) {
+    if (n == 0) return GSR_OK;
+    const int64_t nb = ceil_div(n, 256);
+    k_voxel_targets<<<(int)(nb < 4096 ? nb : 4096), 256, 0, st>>>(g->log_scales, g->quats, g->opacity_logits, n,
+                                                                   *vox, cov, ot, has);
     return last_launch();
 }

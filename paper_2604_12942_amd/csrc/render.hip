@@ -1068,6 +1068,38 @@ __global__ __launch_bounds__(1024) void k_step_loss(const double *__restrict__ i
     }
 }
 
+// The render backward of the per-pixel L1 loss (Eq. 9-10, all-ones mask, lambda_ssim = 0): each
+// lane forms its pixel's loss term and gradient from the forward's image and the targets (so no
+// gradient image is written or read), the workgroup stores its view-tile's loss sum, then runs the
+// tile's backward.  One workgroup per view-tile, longest first.
+template <int TW, int TH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd_l1(
+    const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst, const uint32_t *__restrict__ inst_emit,
+    const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ order, const gsr_camera *__restrict__ cams, int W,
+    int H, int ntx, int T, const float *__restrict__ rgb, const float *__restrict__ depth,
+    const float *__restrict__ Tfin, const uint32_t *__restrict__ last, float *__restrict__ dinst, StepArgs a) {
+    __shared__ BwdLds L;
+    __shared__ double s_red[4];
+    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
+    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
+    const int64_t P = (int64_t)W * H;
+    const int64_t pix = (int64_t)t.py * W + t.px;
+    PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
+    double l = 0.0;
+    if (t.inside) {
+        const int64_t b = (int64_t)t.v * 3 * P + pix;
+        l = (double)l1_pixel(a, t.v, P, pix, rgb[b], rgb[b + P], rgb[b + 2 * P], depth[(int64_t)t.v * P + pix], pg);
+        pg.Tr = Tfin[(int64_t)t.v * P + pix];
+        pg.last = last[(int64_t)t.v * P + pix];
+    }
+    l = wave_sum_d(l);
+    if (__lane_id() == 0) s_red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) a.item_loss[item] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+    tile_backward<TW, TH>(splats, inst, inst_emit, item, ranges[2 * item], ranges[2 * item + 1], ntx, T, cams[t.v], pg,
+                          L, dinst);
+}
+
 // Backward of the stored-contributor mode, pixel-major: every lane walks its own pixel's list of
 // composited tile positions back to front (no re-evaluation of Gaussians that did not blend),
 // recovering the transmittance in front of each contributor by division.  The tile's instances
@@ -1340,6 +1372,33 @@ extern "C" gsr_status gsr_render_step_launch(const gsr_splat *splats, const uint
     else if (r->tile_w == 8) GSR_RSTEP(8, 32);
     else GSR_RSTEP(32, 8);
 #undef GSR_RSTEP
+    k_step_loss<<<1, 1024, 0, st>>>(item_loss, (uint32_t)nb, 1.0 / ((double)r->width * r->height), loss);
+    return last_launch();
+}
+
+extern "C" size_t gsr_render_bwd_l1_ws_bytes(int V, const gsr_raster *r) {
+    return al256((size_t)V * ceil_div(r->width, r->tile_w) * ceil_div(r->height, r->tile_h) * 8);
+}
+
+extern "C" gsr_status gsr_render_bwd_l1_launch(const gsr_splat *splats, const uint32_t *inst,
+                                               const uint32_t *inst_emit, const uint32_t *ranges,
+                                               const uint32_t *order, const gsr_camera *cams, int V,
+                                               const gsr_raster *r, const float *rgb, const float *depth,
+                                               const float *Tfin, const uint32_t *last, const float *trgb,
+                                               const float *tdepth, const int32_t *tidx, float lam, double *loss,
+                                               float *dinst, void *ws, hipStream_t st) {
+    const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
+    const int T = ntx * nty;
+    const int nb = V * T;
+    double *item_loss = static_cast<double *>(ws);
+    const StepArgs a{trgb, tdepth, tidx, lam, item_loss, nullptr, nullptr};
+#define GSR_RBL(TW, TH)                                                                                             \
+    k_render_bwd_l1<TW, TH><<<nb, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width, r->height, \
+                                                ntx, T, rgb, depth, Tfin, last, dinst, a)
+    if (r->tile_w == 16) GSR_RBL(16, 16);
+    else if (r->tile_w == 8) GSR_RBL(8, 32);
+    else GSR_RBL(32, 8);
+#undef GSR_RBL
     k_step_loss<<<1, 1024, 0, st>>>(item_loss, (uint32_t)nb, 1.0 / ((double)r->width * r->height), loss);
     return last_launch();
 }

@@ -9,8 +9,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (PARAM_NAMES, adam_step, cascade, pointnet_backward, pointnet_forward, pointnet_weight_count,
-               voxel_pca)
+from . import (adam_step, cascade, pointnet_backward, pointnet_forward, pointnet_weight_count,
+               voxel_pca, voxel_targets)
 
 # readings: He-uniform initial weights, Adam at 1e-3 for the network
 NET_LR = 1e-3
@@ -50,27 +50,9 @@ class SceneInit:
 
     def targets(self, P):
         """Per-voxel training targets from optimised Gaussians seeded one per point: the mean
-        covariance (xx, xy, xz, yy, yz, zz) and mean opacity over the voxel's points."""
-        n = self.n
-        q = P["quats"] / P["quats"].norm(dim=0, keepdim=True)
-        w, x, y, z = q[0], q[1], q[2], q[3]
-        R = torch.stack([torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]),
-                         torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)]),
-                         torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)])])
-        s2 = torch.exp(2 * P["log_scales"])  # [3, n]
-        cov = torch.einsum("ajn,jn,bjn->abn", R, s2, R)
-        six = torch.stack([cov[0, 0], cov[0, 1], cov[0, 2], cov[1, 1], cov[1, 2], cov[2, 2]])
-        op = torch.sigmoid(P["opacity_logits"])
-        v = self.vox["point_voxel"][:n].long()
-        inside = v >= 0
-        vv = v[inside]
-        cnt = torch.zeros(n, dtype=torch.float32, device=v.device).index_add_(0, vv, torch.ones_like(vv, dtype=torch.float32))
-        cov_t = torch.zeros(6, n, dtype=torch.float32, device=v.device).index_add_(1, vv, six[:, inside])
-        o_t = torch.zeros(n, dtype=torch.float32, device=v.device).index_add_(0, vv, op[inside])
-        has = cnt > 0
-        cov_t[:, has] /= cnt[has]
-        o_t[has] /= cnt[has]
-        return cov_t, o_t, has.to(torch.uint8)
+        covariance (xx, xy, xz, yy, yz, zz) and mean opacity over the voxel's points
+        (gsr_voxel_targets)."""
+        return voxel_targets(P, self.vox)
 
 
 def train_pointnet(scenes, targets, weights, steps, lr=NET_LR, blocks=512, log=None):

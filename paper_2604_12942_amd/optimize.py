@@ -21,14 +21,16 @@ DEFAULT_LR = dict(means=5e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, 
 class MapOptimizer:
     def __init__(self, params, sh_degree, cam_pool, target_rgb, target_depth, raster, n_views, lambda_depth=0.2,
                  lr=None, segment_id=None, min_segment=0, capacity=None, device="cuda", fused=True,
-                 lambda_rgb=1.0, lambda_ssim=0.0, support=None, fused_render=True):
+                 lambda_rgb=1.0, lambda_ssim=0.0, support=None, render="two_pass"):
         """params: dict of float32 [c, n] device tensors (optimised in place); cam_pool: device
         uint8 [S*96] gsr_camera records; target_rgb [S,3,H,W], target_depth [S,H,W] (or None).
         support = (tau_geo, r_erode) supervises only inside the interior mask of Eq. 7 computed
-        from this step's own render; None uses every pixel.  fused_render: with the per-pixel L1
-        loss, render, loss and render backward run as one persistent launch (gsr_render_step; the
-        loss gradient images g_rgb, g_depth are then not written); the full loss (mask, SSIM)
-        always runs them separately."""
+        from this step's own render; None uses every pixel.  render: how the per-pixel L1 loss is
+        rendered and differentiated: "two_pass" (default) the forward launch, then one launch that
+        forms the loss gradient in registers and runs the render backward (gsr_render_bwd_l1);
+        "persistent" all of it in one persistent launch (gsr_render_step); "separate" forward, loss
+        and backward as three launches.  Only "separate" writes the gradient images g_rgb, g_depth.
+        The full loss (mask, SSIM) always runs separately."""
         self.P = params
         self.sh_degree = int(sh_degree)
         self.n = params["means"].shape[1]
@@ -50,7 +52,11 @@ class MapOptimizer:
         self.g_rgb = torch.empty(self.V, 3, H, W, device=device)
         self.g_depth = torch.empty(self.V, H, W, device=device)
         self.full_loss = support is not None or self.lambda_ssim != 0.0 or self.lambda_rgb != 1.0
-        self.fused_render = bool(fused_render) and not self.full_loss
+        if render not in ("two_pass", "persistent", "separate"):
+            raise ValueError("render must be 'two_pass', 'persistent' or 'separate'")
+        self.render = "separate" if self.full_loss else render
+        self.fused_render = self.render == "persistent"
+        self.bwd_ws = None
         self.sup_mask = torch.ones(self.V, H, W, dtype=torch.uint8, device=device)
         self.sup_count = torch.zeros(self.V, dtype=torch.int32, device=device)
         from . import loss_workspace
@@ -149,8 +155,12 @@ class MapOptimizer:
     def _stage_fns(self, check_capacity):
         """The step as an ordered list of (name, fn): every fn only enqueues device work (no host
         synchronisation when check_capacity is False), so any run of stages can be captured."""
-        from . import project, render_fwd, render_bwd, render_step, project_bwd, project_bwd_adam, visible_list
+        from . import (project, render_bwd, render_bwd_l1, render_bwd_l1_workspace, render_fwd, render_step,
+                       project_bwd, project_bwd_adam, visible_list)
         r = self.rast
+        if self.render == "two_pass" and self.bwd_ws is None:
+            self.bwd_ws = torch.empty((render_bwd_l1_workspace(self.V, self.raster) + 255) // 256 * 64,
+                                      dtype=torch.int32, device=self.loss.device)
 
         def gather():
             torch.index_select(self.cam_pool, 0, self.view_idx, out=self.cams.view(-1, 96))
@@ -176,9 +186,11 @@ class MapOptimizer:
                        r.T_final, r.last, tile_order=r.tile_order, ws=r.fwd_ws, capacity=r.capacity)
 
         def loss_stage():
-            if self.fused_render:
+            if self.render == "persistent":
                 return
             self.loss.zero_()
+            if self.render == "two_pass":
+                return  # the loss and its gradient are formed inside the render backward
             gd = self.g_depth if self.target_depth is not None else None
             if not self.full_loss:
                 loss_l1(r.rgb, r.depth, self.target_rgb, self.target_depth, self.V, self.raster, self.lambda_depth,
@@ -193,7 +205,14 @@ class MapOptimizer:
                  lambda_depth=self.lambda_depth, target_index=self.view_idx32, ws=self.loss_ws)
 
         def bwd():
-            if self.fused_render:
+            if self.render == "persistent":
+                return
+            if self.render == "two_pass":
+                gd = self.target_depth
+                render_bwd_l1(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.rgb,
+                              r.depth, r.T_final, r.last, self.target_rgb, gd,
+                              self.lambda_depth if gd is not None else 0.0, self.loss, r.dinst, self.bwd_ws,
+                              tile_order=r.tile_order, target_index=self.view_idx32)
                 return
             render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
                        r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,

@@ -175,10 +175,11 @@ def test_replay_regrows_an_overflowed_capacity():
 
 @pytest.mark.parametrize("scene", ["three_views", "pile_up"])
 def test_fused_render_step_equals_separate_launches(scene):
-    """gsr_render_step against gsr_render_fwd_sliced + gsr_loss_l1 + gsr_render_bwd: images and
-    last positions bit for bit, the loss to float64 summation order, the per-pair screen-space
-    gradients to the float rounding of the backward's LDS sums; the pile-up has tiles long enough
-    to be composited in depth slices (finished by the workgroup that completes their last slice)."""
+    """gsr_render_step (one persistent launch) and gsr_render_bwd_l1 (the loss inside the render
+    backward) against gsr_render_fwd_sliced + gsr_loss_l1 + gsr_render_bwd: images and last
+    positions bit for bit, the loss to float64 summation order, the per-pair screen-space gradients
+    to the float rounding of the backward's LDS sums; the pile-up has tiles long enough to be
+    composited in depth slices (finished by the workgroup that completes their last slice)."""
     import paper_2604_12942_amd as gsr
     from gpu_common import long_tile_scene
     if scene == "three_views":
@@ -220,3 +221,13 @@ def test_fused_render_step_equals_separate_launches(scene):
     ds_b = r.screen_grads().cpu().numpy().astype(np.float64)
     rms = np.sqrt(np.mean(ds_a.reshape(-1, 10) ** 2, axis=0))
     assert np.all(np.abs(ds_b - ds_a).reshape(-1, 10) <= 1e-4 * (np.abs(ds_a).reshape(-1, 10) + rms))
+    # the two-launch form: the loss formed inside the render backward (gsr_render_bwd_l1)
+    r.dinst.fill_(-7)
+    loss_c = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty((gsr.render_bwd_l1_workspace(V, raster) + 255) // 256 * 64, dtype=torch.int32, device="cuda")
+    gsr.render_bwd_l1(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, raster, r.rgb, r.depth, r.T_final,
+                      r.last, trgb, tdep, 0.2, loss_c, r.dinst, ws, tile_order=r.tile_order)
+    torch.cuda.synchronize()
+    assert abs(loss_a.item() - loss_c.item()) <= 1e-12 * abs(loss_a.item())
+    ds_c = r.screen_grads().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(ds_c - ds_a).reshape(-1, 10) <= 1e-4 * (np.abs(ds_a).reshape(-1, 10) + rms))
