@@ -76,6 +76,8 @@ def parse():
                     help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
     ap.add_argument("--no-c2", action="store_true", help="skip the one-view 300k-Gaussian room leg")
+    ap.add_argument("--no-init-compare", action="store_true",
+                    help="skip the learned vs voxel-PCA init comparison leg (iterations to a PSNR target)")
     ap.add_argument("--contrib-compare", action="store_true",
                     help="instead of the step: stored vs recomputed contributor lists on the 4M-Gaussian 1080p view")
     ap.add_argument("--init-compare", action="store_true",
@@ -233,9 +235,23 @@ def _c5_scene(seed):
     return c
 
 
-def init_compare(a):
+def init_compare_scenes(a):
+    """The training and test scenes of the init comparison, built in worker processes (before the
+    GPU is used in this process)."""
+    t0 = time.perf_counter()
+    train_seeds = list(range(100, 100 + a.train_scenes))
+    test_seeds = list(range(200, 200 + a.test_scenes))
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        data = dict(zip(train_seeds + test_seeds, ex.map(_c5_scene, train_seeds + test_seeds)))
+    print("init-compare scenes built in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    return train_seeds, test_seeds, data
+
+
+def init_compare(a, scenes=None):
     """Iterations to a held-out PSNR target from the learned-cascade init versus the voxel-PCA
-    cascade (beta grid-tuned on the training scenes), identical optimiser settings (one JSON line)."""
+    cascade (beta grid-tuned on the training scenes), identical optimiser settings.  Returns the
+    summary dict."""
+    train_seeds, test_seeds, data = scenes if scenes is not None else init_compare_scenes(a)
     import torch
 
     import paper_2604_12942_amd as gsr
@@ -244,11 +260,6 @@ def init_compare(a):
 
     dev = "cuda"
     t0 = time.perf_counter()
-    train_seeds = list(range(100, 100 + a.train_scenes))
-    test_seeds = list(range(200, 200 + a.test_scenes))
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        data = dict(zip(train_seeds + test_seeds, ex.map(_c5_scene, train_seeds + test_seeds)))
-    print("scenes built in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     V = 4
     every = 25
 
@@ -333,7 +344,7 @@ def init_compare(a):
     wins = sum(1 for r in res if r["iters_learned"] is not None and
                (r["iters_pca"] is None or r["iters_learned"] < r["iters_pca"]))
     ratios = [r["iters_learned"] / r["iters_pca"] for r in res if r["iters_learned"] and r["iters_pca"]]
-    out = {"metric": "iterations to held-out PSNR target, learned vs voxel-PCA init",
+    return {"metric": "iterations to held-out PSNR target, learned vs voxel-PCA init",
            "config": {"workload": "room scenes, 100k LiDAR points, 24 keyframes 640x360 (every 10th held out), "
                                   "4 views per iteration, SH3", "train_scenes": len(train_seeds),
                       "test_scenes": len(test_seeds), "iterations": a.init_iters, "net_steps": a.net_steps},
@@ -341,8 +352,10 @@ def init_compare(a):
            "net_final_loss": round(net_loss, 5), "tests": res, "learned_wins": wins,
            "mean_iter_ratio": round(float(np.mean(ratios)), 4) if ratios else None,
            "gate": bool(wins >= max(1, (4 * len(res) + 4) // 5) and ratios and float(np.mean(ratios)) < 1.0),
+           "mean_psnr_gain_at": {str(k): round(float(np.mean([r["psnr_learned"][k] - r["psnr_pca"][k] for r in res
+                                                              if k in r["psnr_learned"] and k in r["psnr_pca"]])), 3)
+                                 for k in (0, 100, 300, 1000, a.init_iters)},
            "seconds": round(time.perf_counter() - t0, 1)}
-    print(json.dumps(out), flush=True)
 
 
 FULL_LOSS = dict(lambda_rgb=0.8, lambda_ssim=0.2, support=(0.5, 2))
@@ -713,7 +726,7 @@ def c2_leg(a, dev, steps=20):
 def main():
     a = parse()
     if a.init_compare:
-        init_compare(a)
+        print(json.dumps(init_compare(a)), flush=True)
         return
     if a.contrib_compare:
         if a.gpus != 1:
@@ -737,6 +750,7 @@ def main():
     t_gen = time.perf_counter()
     workers = min(8, os.cpu_count() or 1)
     c, pool_cams, tg = build_workload(a.points, workers)
+    ic_scenes = None if a.no_init_compare else init_compare_scenes(a)
     print("workload built in %.1f s" % (time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
     import torch
@@ -978,6 +992,14 @@ def main():
 
     copy_gbs = copy_bandwidth()
     c2 = None if a.no_c2 else c2_leg(a, dev)
+    ic = None
+    if not a.no_init_compare:
+        full_ic = init_compare(a, ic_scenes)
+        ic = {k: full_ic[k] for k in ("learned_wins", "mean_iter_ratio", "gate", "mean_psnr_gain_at", "beta_tuned",
+                                      "net_final_loss", "seconds")}
+        ic["iters_pca_learned"] = [[r["iters_pca"], r["iters_learned"]] for r in full_ic["tests"]]
+        ic["config"] = full_ic["config"]
+        print("init compare: %s" % json.dumps(full_ic), file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(c, pool_cams, tg, views_for_step(a.warmup + a.steps - 1))
@@ -1025,6 +1047,7 @@ def main():
         "loop_registration": loopr,
         "init_path": initr,
         "c2": c2,
+        "learned_vs_pca_init": ic,
     }
     print(json.dumps(out), flush=True)
 
