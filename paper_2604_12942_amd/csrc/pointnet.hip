@@ -212,139 +212,254 @@ __device__ void forward_tile(const float *pts, int64_t n, const gsr_voxels &V, u
 }
 
 // ---- forward (inference) ------------------------------------------------------------------------
-// Persistent: each workgroup converts the weights once and loops over tiles of 8 voxels.  Each
-// wave owns two voxels (64 rows) end to end, so the layers need no workgroup barrier:
-//   layer 1 on the matrix cores with K padded from 3 to 16 (A built in registers from the
-//   gathered points, B = W1 from registers);
-//   layers 2 and 3 with B from the transposed weights in LDS; between layers the wave turns its
-//   accumulators (D layout) into the next A operand through its own 64-row LDS block, in place;
-//   max-pool in registers, then the 76 -> 64 -> 8 head on the VALU from the wave's LDS.
+// Persistent, wave-independent: each wave takes an equal contiguous range of voxels (its share of
+// the whole batch, so that no wave runs a group more than another) in groups of 32.  Per voxel the
+// wave runs the
+// three shared layers on the matrix cores with the activations kept in registers:
+//   layers 1 and 2 transposed, out^T = W^T h^T (M = 64 output features in two row tiles, N = the
+//   voxel's 32 rows), so the accumulators hold, per lane, one row and 16 features of each tile;
+//   those 32 values, bias + ReLU + BF16, are directly the next layer's K-operand once K is taken in
+//   the order phi below (the weights are loaded in the same order; the contraction does not care);
+//   layer 3 the other way round, out = h2 W3 (M = the 32 rows), so that each lane holds one output
+//   column over 16 rows and the max-pool is 15 maxima and one cross-half exchange.
+// Biases enter as the accumulators' initial value.  The pooled features of the group's 32 voxels
+// and their 12 PCA features gather in the wave's LDS block; the head 76 -> 64 -> 8 then runs
+// transposed on the matrix cores for all 32 voxels at once (N = 32 voxels, the output's 8 rows
+// padded to 32).  Rounding points as everywhere: BF16 weights and layer inputs, FP32 bias, ReLU
+// and accumulation.
+//
+// K order of a 64-wide chained operand: position (kb, half, j) of k-block kb (16 wide), lane half
+// and element j (0..7) holds feature phi = 32 (kb / 2) + 16 (kb % 2) + 8 (j / 4) + 4 half + j % 4,
+// which is where the 32 x 32 accumulator layout keeps it (register 8 (kb % 2) + j of tile kb / 2).
+__device__ __forceinline__ int phi_k(int kb, int half, int j) {
+    return 32 * (kb >> 1) + 16 * (kb & 1) + 8 * (j >> 2) + 4 * half + (j & 3);
+}
+
+constexpr int kGrp = 32;   // voxels per wave group (the head's N)
+constexpr int kStage = 16; // voxels whose input rows are staged at once
+constexpr int kZld = 80;   // LDS row of the head input (76 used), bf16
+
 struct PnFwdShared {
-    __attribute__((aligned(16))) __bf16 h[4][2 * kRows][kLd];  // per wave: its 64 rows
-    __attribute__((aligned(16))) __bf16 w2t[kWidth][kLd];       // W2, W3 transposed: [out][in]
-    __attribute__((aligned(16))) __bf16 w3t[kWidth][kLd];
-    __bf16 w4[kWidth + kFeat][kWidth];
-    __bf16 w5[kWidth][kOut];
-    float b[kWidth * 4 + kOut];
-    __bf16 z[4][2][kWidth + kFeat];
-    __bf16 h4[4][2][kWidth];
+    bf16x8 a4[2][5][64];  // layer-4 A fragments (W4^T, K padded to 80)
+    bf16x8 a5[4][64];     // layer-5 A fragments (W5^T, M padded to 32, K in phi order)
+    float b1[kWidth], b2[kWidth], b4[kWidth], b5[kOut];
+    __attribute__((aligned(16))) __bf16 z[4][kGrp][kZld];            // per wave: head inputs
+    __attribute__((aligned(8))) __bf16 xs[4][kStage][kRows][4];      // per wave: staged input rows
 };
 
-__global__ __launch_bounds__(256) void k_pn_fwd(const float *__restrict__ pts, int64_t n, gsr_voxels V,
+__device__ __forceinline__ f32x16 bias_tile(const float *b, int rt, int half) {
+    // accumulator register r of row tile rt holds feature 32 rt + 8 (r / 4) + 4 half + r % 4
+    f32x16 c;
+    const float4 *p = reinterpret_cast<const float4 *>(b + 32 * rt + 4 * half);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const float4 v = p[2 * q];
+        c[4 * q] = v.x;
+        c[4 * q + 1] = v.y;
+        c[4 * q + 2] = v.z;
+        c[4 * q + 3] = v.w;
+    }
+    return c;
+}
+
+// bias already in the accumulators: h = bf16(relu(acc)), as the four k-blocks of the next layer.
+// The ReLU is taken after the rounding, on the BF16 bit patterns as signed 16-bit integers
+// (negative values and -0 have the sign bit set): rounding keeps the sign, so this equals
+// rounding the ReLU.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void relu_operands(const f32x16 d[2], bf16x8 h[4]) {
+#pragma unroll
+    for (int kb = 0; kb < 4; kb++) {
+        u32x4 u;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int r = 8 * (kb & 1) + 2 * i;
+            const f32x2 f = {d[kb >> 1][r], d[kb >> 1][r + 1]};
+            const bf16x2 b = __builtin_convertvector(f, bf16x2);  // round to nearest even
+            const i16x2 m = __builtin_elementwise_max(__builtin_bit_cast(i16x2, b), i16x2{});
+            u[i] = __builtin_bit_cast(uint32_t, m);
+        }
+        h[kb] = __builtin_bit_cast(bf16x8, u);
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pn_fwd(const float *__restrict__ pts, int64_t n, gsr_voxels V,
                                                 const float *__restrict__ W, float *__restrict__ y) {
     __shared__ PnFwdShared S;
     const uint32_t nv = *V.n_voxels;
     const int t = threadIdx.x, lane = __lane_id(), w = t >> 6, half = lane >> 5, l32 = lane & 31;
-    const uint32_t ntiles = (nv + kVox - 1) / kVox;
-    if (blockIdx.x >= ntiles) return;
-    for (int q = t; q < (kWidth + kFeat) * kWidth; q += 256) S.w4[q / kWidth][q % kWidth] = tobf(W[oW4 + q]);
-    for (int q = t; q < kWidth * kOut; q += 256) S.w5[q / kOut][q % kOut] = tobf(W[oW5 + q]);
-    S.b[t] = t < 64 ? W[oB1 + t] : (t < 128 ? W[oB2 + t - 64] : (t < 192 ? W[oB3 + t - 128] : W[oB4 + t - 192]));
-    if (t < kOut) S.b[256 + t] = W[oB5 + t];
-    for (int q = t; q < kWidth * kWidth; q += 256) {
-        const int k = q / kWidth, o = q % kWidth;
-        S.w2t[o][k] = tobf(W[oW2 + q]);
-        S.w3t[o][k] = tobf(W[oW3 + q]);
+    const uint32_t nwaves = gridDim.x * 4, gw = blockIdx.x * 4 + w;
+    const uint32_t vbeg = (uint32_t)((uint64_t)gw * nv / nwaves), vend = (uint32_t)((uint64_t)(gw + 1) * nv / nwaves);
+    // head fragments and biases
+    for (int q = t; q < 2 * 5 * 64; q += 256) {
+        const int rt = q / 320, kb = (q / 64) % 5, ln = q % 64, h = ln >> 5, o = 32 * rt + (ln & 31);
+        bf16x8 f;
+        for (int j = 0; j < 8; j++) {
+            const int k = 16 * kb + 8 * h + j;
+            f[j] = tobf(k < kWidth + kFeat ? W[oW4 + k * kWidth + o] : 0.f);
+        }
+        S.a4[rt][kb][ln] = f;
     }
-    // layer 1's B fragment: W1 padded to K = 16 (only k < 3 non-zero, in the first half-wave)
-    bf16x8 b1[2];
-    for (int ct = 0; ct < 2; ct++)
-        for (int j = 0; j < 8; j++) b1[ct][j] = tobf(half == 0 && j < 3 ? W[oW1 + j * kWidth + 32 * ct + l32] : 0.f);
+    for (int q = t; q < 4 * 64; q += 256) {
+        const int kb = q / 64, ln = q % 64, h = ln >> 5, o = ln & 31;
+        bf16x8 f;
+        for (int j = 0; j < 8; j++) f[j] = tobf(o < kOut ? W[oW5 + phi_k(kb, h, j) * kOut + o] : 0.f);
+        S.a5[kb][ln] = f;
+    }
+    if (t < kWidth) {
+        S.b1[t] = W[oB1 + t];
+        S.b2[t] = W[oB2 + t];
+        S.b4[t] = W[oB4 + t];
+    }
+    if (t < kOut) S.b5[t] = W[oB5 + t];
+    for (int q = lane; q < kGrp * (kZld - kWidth - kFeat); q += 64)
+        S.z[w][q / (kZld - kWidth - kFeat)][kWidth + kFeat + q % (kZld - kWidth - kFeat)] = tobf(0.f);
+    // shared-layer fragments in registers: W1^T (K = 3 padded to 16), W2^T and W3 in phi order
+    bf16x8 a1[2], a2[2][4], b3[2][4];
+    for (int rt = 0; rt < 2; rt++) {
+        for (int j = 0; j < 8; j++) a1[rt][j] = tobf(half == 0 && j < 3 ? W[oW1 + j * kWidth + 32 * rt + l32] : 0.f);
+        for (int kb = 0; kb < 4; kb++)
+            for (int j = 0; j < 8; j++) {
+                const int k = phi_k(kb, half, j);
+                a2[rt][kb][j] = tobf(W[oW2 + k * kWidth + 32 * rt + l32]);
+                b3[rt][kb][j] = tobf(W[oW3 + k * kWidth + 32 * rt + l32]);
+            }
+    }
+    const float bb3[2] = {W[oB3 + l32], W[oB3 + 32 + l32]};
+    float *const y4 = y + 4 * n;  // outputs 4..7
     __syncthreads();
-    __bf16(*H)[kLd] = S.h[w];
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t vb = tile * kVox + 2 * w;  // this wave's first voxel
-        // layer 1: A rows = the voxel's fitting points, repeated cyclically, centred and scaled
-        bf16x8 a1[2];
-        for (int rt = 0; rt < 2; rt++) {
-            const uint32_t v = vb + rt;
-            float x[3] = {0.f, 0.f, 0.f};
-            if (half == 0 && v < nv) {
-                const uint32_t cnt = V.count[v];
-                const uint32_t m = cnt < (uint32_t)kRows ? cnt : (uint32_t)kRows;
-                const uint32_t p = V.point_order[V.start[v] + (uint32_t)l32 % m];
-                for (int c = 0; c < 3; c++) x[c] = (pts[c * n + p] - V.mu[c * n + v]) / 0.5f;
-            }
-            for (int j = 0; j < 8; j++) a1[rt][j] = tobf(j < 3 ? x[j] : 0.f);
-        }
-        f32x16 acc[4];
-        for (int rt = 0; rt < 2; rt++)
-            for (int ct = 0; ct < 2; ct++)
-                acc[2 * rt + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[rt], b1[ct], f32x16{}, 0, 0, 0);
-        // layers 2 and 3: bias + ReLU of the previous layer into the wave's LDS rows, then GEMM
-        for (int layer = 0; layer < 2; layer++) {
-            for (int rt = 0; rt < 2; rt++)
-                for (int ct = 0; ct < 2; ct++) {
-                    const int col = 32 * ct + l32;
-                    const float bb = S.b[64 * layer + col];
-                    for (int r = 0; r < 16; r++)
-                        H[32 * rt + 8 * (r >> 2) + 4 * half + (r & 3)][col] =
-                            tobf(fmaxf(acc[2 * rt + ct][r] + bb, 0.f));
-                }
-            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
-            __builtin_amdgcn_wave_barrier();
-            for (int q = 0; q < 4; q++) acc[q] = f32x16{};
-            const __bf16(*Bt)[kLd] = layer == 0 ? S.w2t : S.w3t;
-            for (int kb = 0; kb < 4; kb++) {
-                const int k0 = 16 * kb + 8 * half;
-                bf16x8 a[2], b[2];
-                for (int rt = 0; rt < 2; rt++) a[rt] = *reinterpret_cast<const bf16x8 *>(&H[32 * rt + l32][k0]);
-                for (int ct = 0; ct < 2; ct++) b[ct] = *reinterpret_cast<const bf16x8 *>(&Bt[32 * ct + l32][k0]);
-                for (int rt = 0; rt < 2; rt++)
-                    for (int ct = 0; ct < 2; ct++)
-                        acc[2 * rt + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b[ct], acc[2 * rt + ct], 0, 0, 0);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        // layer-3 bias + ReLU and the max-pool over each voxel's 32 rows
-        for (int rt = 0; rt < 2; rt++)
-            for (int ct = 0; ct < 2; ct++) {
-                const int col = 32 * ct + l32;
-                const float bb = S.b[128 + col];
-                float best = 0.f;
-                for (int r = 0; r < 16; r++) best = fmaxf(best, fmaxf(acc[2 * rt + ct][r] + bb, 0.f));
-                best = fmaxf(best, __shfl_xor(best, 32));
-                if (half == 0) S.z[w][rt][col] = tobf(best);
-            }
-        // the 12 voxel features: log(max(lambda, floor) / 0.25) ascending, then v_min, v_mid, v_max
-        if (lane < 24) {
-            const int rt = lane / 12, f = lane % 12;
-            const uint32_t v = vb + rt;
-            float val = 0.f;
-            if (v < nv) {
-                if (f < 3) {
-                    val = logf(fmaxf(V.evals[f * n + v], 0.005f * 0.005f) / 0.25f);
+    __bf16(*Z)[kZld] = S.z[w];
+    for (uint32_t vg = vbeg; vg < vend; vg += kGrp) {
+        const int ng = (int)min((uint32_t)kGrp, vend - vg);  // voxels of this group
+        for (int s0 = 0; s0 < ng; s0 += kStage) {
+            // stage the input rows of kStage voxels: lane -> voxel lane / 4, rows 8 (lane % 4) ..
+            {
+                const int sv = lane >> 2, r0 = 8 * (lane & 3);
+                const uint32_t v = vg + s0 + sv;
+                float x[8][3];
+                if (s0 + sv < ng) {
+                    const uint32_t cnt = V.count[v], st = V.start[v];
+                    const uint32_t m = cnt < (uint32_t)kRows ? cnt : (uint32_t)kRows;
+                    const float m0 = V.mu[v], m1 = V.mu[n + v], m2 = V.mu[2 * n + v];
+                    uint32_t p[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) p[i] = V.point_order[st + (uint32_t)(r0 + i) % m];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        x[i][0] = (pts[p[i]] - m0) / 0.5f;
+                        x[i][1] = (pts[n + p[i]] - m1) / 0.5f;
+                        x[i][2] = (pts[2 * n + p[i]] - m2) / 0.5f;
+                    }
                 } else {
-                    const int col = 2 - (f - 3) / 3, row = (f - 3) % 3;
-                    val = V.R[(row * 3 + col) * n + v];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) x[i][0] = x[i][1] = x[i][2] = 0.f;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    __bf16 *d = S.xs[w][sv][r0 + i];
+                    d[0] = tobf(x[i][0]);
+                    d[1] = tobf(x[i][1]);
+                    d[2] = tobf(x[i][2]);
+                    d[3] = tobf(0.f);
                 }
             }
-            S.z[w][rt][kWidth + f] = tobf(val);
-        }
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        __builtin_amdgcn_wave_barrier();
-        // layer 4 (76 -> 64): lane = output column, both voxels
-        {
-            float a0 = S.b[192 + lane], a1v = a0;
-            for (int k = 0; k < kWidth + kFeat; k++) {
-                const float wk = fbf(S.w4[k][lane]);
-                a0 = __builtin_fmaf(fbf(S.z[w][0][k]), wk, a0);
-                a1v = __builtin_fmaf(fbf(S.z[w][1][k]), wk, a1v);
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+            __builtin_amdgcn_wave_barrier();
+            const int s1 = min(s0 + kStage, ng);
+            for (int s = s0; s < s1; s++) {
+                // layer 1: B = the voxel's rows (K = 3 of 16, first half-wave)
+                bf16x8 bx = bf16x8{};
+                if (half == 0) {
+                    // the staged row: three BF16 coordinates and a zero
+                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                    const bf16x4 xr = *reinterpret_cast<const bf16x4 *>(S.xs[w][s - s0][l32]);
+                    bx[0] = xr[0];
+                    bx[1] = xr[1];
+                    bx[2] = xr[2];
+                }
+                f32x16 d[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; rt++)
+                    d[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[rt], bx, bias_tile(S.b1, rt, half), 0, 0, 0);
+                bf16x8 h[4];
+                relu_operands(d, h);
+                // layer 2
+#pragma unroll
+                for (int rt = 0; rt < 2; rt++) {
+                    f32x16 acc = bias_tile(S.b2, rt, half);
+#pragma unroll
+                    for (int kb = 0; kb < 4; kb++)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[rt][kb], h[kb], acc, 0, 0, 0);
+                    d[rt] = acc;
+                }
+                relu_operands(d, h);
+                // layer 3 (rows = the voxel's points) and the max-pool: relu(max_r acc + b) equals
+                // max_r relu(acc + b), rounding included (both maps are monotone)
+#pragma unroll
+                for (int ct = 0; ct < 2; ct++) {
+                    f32x16 acc = f32x16{};
+#pragma unroll
+                    for (int kb = 0; kb < 4; kb++)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h[kb], b3[ct][kb], acc, 0, 0, 0);
+                    float best = acc[0];
+#pragma unroll
+                    for (int r = 1; r < 16; r++) best = fmaxf(best, acc[r]);
+                    best = fmaxf(best, __shfl_xor(best, 32));
+                    if (half == 0) Z[s][32 * ct + l32] = tobf(fmaxf(best + bb3[ct], 0.f));
+                }
             }
-            S.h4[w][0][lane] = tobf(fmaxf(a0, 0.f));
-            S.h4[w][1][lane] = tobf(fmaxf(a1v, 0.f));
+            __builtin_amdgcn_wave_barrier();  // the next stage overwrites the rows just read
+        }
+        // the 12 voxel features: log(max(lambda, floor) / 0.25) ascending, then v_min, v_mid, v_max
+        if (half == 0) {
+            const uint32_t v = vg + l32;
+            float f[kFeat];
+            for (int q = 0; q < kFeat; q++) f[q] = 0.f;
+            if (l32 < ng) {
+                for (int q = 0; q < 3; q++) f[q] = logf(fmaxf(V.evals[q * n + v], 0.005f * 0.005f) / 0.25f);
+                for (int q = 3; q < kFeat; q++) {
+                    const int col = 2 - (q - 3) / 3, row = (q - 3) % 3;  // R_pca columns: v_max, v_mid, v_min
+                    f[q] = V.R[(row * 3 + col) * n + v];
+                }
+            }
+            for (int q = 0; q < kFeat; q++) Z[l32][kWidth + q] = tobf(f[q]);
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
-        // layer 5 (64 -> 8): lanes 0..15 = (voxel, output)
-        if (lane < 2 * kOut) {
-            const int rt = lane / kOut, j = lane % kOut;
-            float a = S.b[256 + j];
-            for (int k = 0; k < kWidth; k++) a = __builtin_fmaf(fbf(S.h4[w][rt][k]), fbf(S.w5[k][j]), a);
-            const uint32_t v = vb + rt;
-            if (v < nv) y[(int64_t)j * n + v] = a;
+        // layer 4 (76 -> 64), transposed over the 32 voxels
+        f32x16 d[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++) {
+            f32x16 acc = bias_tile(S.b4, rt, half);
+#pragma unroll
+            for (int kb = 0; kb < 5; kb++) {
+                const bf16x8 bz = *reinterpret_cast<const bf16x8 *>(&Z[l32][16 * kb + 8 * half]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a4[rt][kb][lane], bz, acc, 0, 0, 0);
+            }
+            d[rt] = acc;
         }
-        __builtin_amdgcn_wave_barrier();
+        bf16x8 h[4];
+        relu_operands(d, h);
+        // layer 5 (64 -> 8; rows 8..31 are padding): lane holds outputs 4 half .. 4 half + 3 of voxel l32
+        f32x16 acc = f32x16{};
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[r] = S.b5[4 * half + r];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a5[kb][lane], h[kb], acc, 0, 0, 0);
+        const uint32_t v = vg + l32;
+        // (one store path per half-wave, each from a uniform base)
+        if (l32 < ng && half == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) y[(int64_t)r * n + v] = acc[r];
+        }
+        if (l32 < ng && half == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) y4[(int64_t)r * n + v] = acc[r];
+        }
+        __builtin_amdgcn_wave_barrier();  // the next group overwrites the head inputs
     }
 }
 
@@ -593,13 +708,14 @@ extern "C" int gsr_pointnet_weight_count(void) { return kNW; }
 extern "C" gsr_status gsr_pointnet_fwd_launch(const float *pts, int64_t n, const gsr_voxels *vox, const float *W,
                                               float *y, hipStream_t st) {
     if (n == 0) return GSR_OK;
-    // persistent: two workgroups per compute unit (the LDS allows two), each loops over tiles
+    // persistent: three workgroups per compute unit (the LDS allows three), each wave loops over
+    // groups of 32 voxels
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    const int64_t tiles = ceil_div(n, kVox);
-    const int nb = (int)(tiles < 2 * cus ? tiles : 2 * cus);
+    const int64_t blocks = ceil_div(ceil_div(n, kGrp), 4);
+    const int nb = (int)(blocks < 3 * cus ? blocks : 3 * cus);
     k_pn_fwd<<<nb, 256, 0, st>>>(pts, n, *vox, W, y);
     return last_launch();
 }

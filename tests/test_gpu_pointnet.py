@@ -127,3 +127,55 @@ def test_pointnet_backward_matches_oracle():
           % (n_over, n_total), stats)
     assert all(b == 0 for _, b, _ in stats.values()), stats
     assert n_over <= 1e-3 * n_total, stats
+
+
+def _inputs_from_gpu_arrays(pts, vox, ids):
+    """Network inputs of the voxels ids, in float32 as the GPU forms them, from the GPU's own voxel
+    arrays (start, count, point order, means, eigenvalues, frames)."""
+    n = pts.shape[0]
+    start = vox["start"][:n].cpu().numpy().astype(np.int64)
+    count = vox["count"][:n].cpu().numpy().astype(np.int64)
+    order = vox["point_order"][:n].cpu().numpy().astype(np.int64)
+    mu = vox["mu"].view(3, -1)[:, :n].cpu().numpy().T[ids]
+    m = np.minimum(count[ids], pn.ROWS)
+    rows = order[start[ids][:, None] + np.arange(pn.ROWS)[None, :] % m[:, None]]
+    X = (np.asarray(pts, np.float32)[rows] - mu[:, None, :]) / np.float32(0.5)
+    lam = vox["evals"].view(3, -1)[:, :n].cpu().numpy().T[ids].astype(np.float32)
+    R = vox["R"].view(9, -1)[:, :n].cpu().numpy().T[ids].reshape(-1, 3, 3)
+    logl = np.log(np.maximum(lam, np.float32(0.005) * np.float32(0.005)) / np.float32(0.25)).astype(np.float32)
+    F = np.concatenate([logl, R[:, :, 2], R[:, :, 1], R[:, :, 0]], axis=1)
+    return X.astype(np.float64), F.astype(np.float64)
+
+
+def test_pointnet_forward_full_batch_sampled():
+    """The timed batch (200k voxels of 32 points, 6.4M points) in the timed launch: the outputs of
+    every voxel of the first and last three waves' ranges (whole and partial groups of 32, both
+    staging halves) and of 2,048 random voxels against the oracle, under the same gate."""
+    import synth
+    import paper_2604_12942_amd as gsr
+    pts, _, _, _ = synth.voxel_batch(0)
+    t = torch.from_numpy(np.ascontiguousarray(pts.T)).cuda()
+    vox = gsr.voxel_pca(t, 1)
+    nv = int(vox["n_voxels"].item())
+    assert nv == 200_000
+    rng = np.random.default_rng(7)
+    W = pn.init_weights(7)
+    for k in ("b1", "b2", "b3", "b4", "b5"):
+        W[k] = (rng.standard_normal(W[k].shape) * 0.1).astype(np.float32)
+    flat = np.concatenate([W[k].ravel() for k in ORDER]).astype(np.float32)
+    y = gsr.pointnet_forward(t, vox, torch.from_numpy(flat).cuda())
+    torch.cuda.synchronize()
+    # the launch's wave ranges: persistent grid of min(ceil(ceil(n / 32) / 4), 3 CUs) workgroups
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = pts.shape[0]
+    nwaves = 4 * min(-(-(-(-n // 32)) // 4), 3 * cus)
+    edge = [np.arange(g * nv // nwaves, (g + 1) * nv // nwaves) for g in (0, 1, 2, nwaves - 3, nwaves - 2, nwaves - 1)]
+    ids = np.unique(np.concatenate(edge + [rng.choice(nv, 2048, replace=False)]))
+    X, F = _inputs_from_gpu_arrays(pts, vox, ids)
+    got = y.view(8, -1)[:, ids].cpu().numpy().T.astype(np.float64)
+    exp = pn.forward(W, X, F)
+    over, bad, total = _gate(got, exp, lambda: pn.knife_spread(W, X, F, realisations=16, seed=3)[0], axis=0)
+    print("point network forward, %d sampled voxels of 200k: %d of %d outputs outside 1e-3, all BF16 knife edges"
+          % (len(ids), over, total))
+    assert bad == 0, (over, bad)
+    assert over <= 1e-3 * total, over
