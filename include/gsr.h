@@ -249,14 +249,23 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
  * exactly as gsr_render_bwd does for that upstream gradient (Sec. III-C, Eq. 8-10).  Inputs as
  * gsr_render_bwd plus the forward's rgb [V][3][H][W] and depth [V][H][W]; targets as gsr_loss_l1.
  * *loss (device float64) is ACCUMULATED, summed over the view-tiles in a fixed order.  ws:
- * gsr_render_bwd_l1_workspace(V, r) bytes (one float64 per view-tile), 256-byte aligned. */
+ * gsr_render_bwd_l1_workspace(V, r) bytes (one float64 per view-tile), 256-byte aligned.
+ * fwd_ws: NULL, or the workspace (fwd_ws_bytes long, 256-byte aligned) of the gsr_render_fwd_sliced
+ * call, with this capacity and these lists, that produced rgb, depth, T_final and last.  Then each
+ * view-tile that forward composited in depth slices also runs its backward in those slices, one
+ * workgroup per slice, each starting from the transmittance behind its slice and the colour and
+ * depth composited behind it, which that forward's slice merge leaves in fwd_ws.  The records are
+ * those of the whole-tile walk up to float rounding.  The slice contents of fwd_ws are read, not
+ * changed.  Errors: GSR_E_INVALID (NULL pointers, lambda_depth < 0, a misaligned ws or fwd_ws, a
+ * bad capacity), GSR_E_CAPACITY (ws_bytes or fwd_ws_bytes too small). */
 GSR_API size_t gsr_render_bwd_l1_workspace(int32_t n_views, const gsr_raster *r);
 GSR_API gsr_status gsr_render_bwd_l1(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
                                      const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
                                      int32_t n_views, const gsr_raster *r, const float *rgb, const float *depth,
                                      const float *T_final, const uint32_t *last, const float *target_rgb,
                                      const float *target_depth, const int32_t *target_index, float lambda_depth,
-                                     double *loss, float *dinst, void *ws, size_t ws_bytes, gsr_stream stream);
+                                     double *loss, float *dinst, void *ws, size_t ws_bytes, void *fwd_ws,
+                                     size_t fwd_ws_bytes, int64_t capacity, gsr_stream stream);
 
 /* ---- fused step: render forward, L1 loss and render backward in one persistent launch ----------
  * The batched optimisation step of Sec. III-C with the loss of Eq. 9-10 restricted to its

@@ -153,13 +153,18 @@ def render_bwd_l1_workspace(n_views, raster):
 
 
 def render_bwd_l1(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, rgb, depth, T_final, last,
-                  target_rgb, target_depth, lambda_depth, loss, dinst, ws, tile_order=None, target_index=None):
-    """Render backward of the per-pixel L1 loss (gsr_render_bwd_l1); loss is accumulated."""
+                  target_rgb, target_depth, lambda_depth, loss, dinst, ws, tile_order=None, target_index=None,
+                  fwd_ws=None, capacity=0):
+    """Render backward of the per-pixel L1 loss (gsr_render_bwd_l1); loss is accumulated.  fwd_ws /
+    capacity: the workspace and capacity of the sliced forward that produced the images (the long
+    tiles then run their backward in its depth slices); None runs whole tiles."""
     check(lib().gsr_render_bwd_l1(_ptr(splats), _ptr(inst_gid), _ptr(inst_emit), _ptr(tile_ranges),
                                   _ptr(tile_order), _ptr(cams), n_views, C.byref(raster.c), _ptr(rgb), _ptr(depth),
                                   _ptr(T_final), _ptr(last), _ptr(target_rgb), _ptr(target_depth),
                                   _ptr(target_index), float(lambda_depth), _ptr(loss), _ptr(dinst), _ptr(ws),
-                                  ws.numel() * ws.element_size(), _stream()), "gsr_render_bwd_l1")
+                                  ws.numel() * ws.element_size(), _ptr(fwd_ws),
+                                  0 if fwd_ws is None else fwd_ws.numel() * fwd_ws.element_size(), int(capacity),
+                                  _stream()), "gsr_render_bwd_l1")
 
 
 def render_step_workspace(n_views, raster, capacity):

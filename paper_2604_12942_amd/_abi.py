@@ -90,7 +90,7 @@ _SIGS = {
     "gsr_pair_grads": ([P, C.POINTER(Emission), P, C.c_int64, C.c_int32, P, P], C.c_int),
     "gsr_render_bwd_l1_workspace": ([C.c_int32, C.POINTER(Raster)], C.c_size_t),
     "gsr_render_bwd_l1": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P, P, C.c_float, P, P, P,
-                           C.c_size_t, P], C.c_int),
+                           C.c_size_t, P, C.c_size_t, C.c_int64, P], C.c_int),
     "gsr_render_step_workspace": ([C.c_int32, C.POINTER(Raster), C.c_int64], C.c_size_t),
     "gsr_render_step": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, C.c_float, P, P, P, P, P, P,
                          C.c_int64, P, C.c_size_t, P], C.c_int),

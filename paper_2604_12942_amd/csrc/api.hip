@@ -26,7 +26,7 @@ extern "C" gsr_status gsr_render_bwd_l1_launch(const gsr_splat *, const uint32_t
                                                const uint32_t *, const gsr_camera *, int, const gsr_raster *,
                                                const float *, const float *, const float *, const uint32_t *,
                                                const float *, const float *, const int32_t *, float, double *, float *,
-                                               void *, hipStream_t);
+                                               void *, void *, int64_t, hipStream_t);
 extern "C" size_t gsr_render_step_ws_bytes(int, const gsr_raster *, int64_t);
 extern "C" gsr_status gsr_render_step_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                              const uint32_t *, const gsr_camera *, int, const gsr_raster *,
@@ -233,7 +233,8 @@ extern "C" gsr_status gsr_render_bwd_l1(const gsr_splat *splats, const uint32_t 
                                         const float *depth, const float *T_final, const uint32_t *last,
                                         const float *target_rgb, const float *target_depth,
                                         const int32_t *target_index, float lambda_depth, double *loss, float *dinst,
-                                        void *ws, size_t ws_bytes, gsr_stream stream) {
+                                        void *ws, size_t ws_bytes, void *fwd_ws, size_t fwd_ws_bytes,
+                                        int64_t capacity, gsr_stream stream) {
     if (!raster_ok(r) || n_views < 1) return GSR_E_INVALID;
     if (!splats || !inst_gid || !inst_emit || !tile_ranges || !cams || !rgb || !depth || !T_final || !last ||
         !target_rgb || !loss || !dinst || !ws)
@@ -241,9 +242,14 @@ extern "C" gsr_status gsr_render_bwd_l1(const gsr_splat *splats, const uint32_t 
     if (!(lambda_depth >= 0.f)) return GSR_E_INVALID;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GSR_E_INVALID;
     if (ws_bytes < gsr_render_bwd_l1_ws_bytes(n_views, r)) return GSR_E_CAPACITY;
+    if (fwd_ws) {
+        if (capacity < 0 || capacity >= (int64_t)UINT32_MAX || (reinterpret_cast<uintptr_t>(fwd_ws) & 255) != 0)
+            return GSR_E_INVALID;
+        if (fwd_ws_bytes < gsr_render_fwd_ws_bytes(n_views, r, capacity)) return GSR_E_CAPACITY;
+    }
     return gsr_render_bwd_l1_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, rgb, depth,
                                     T_final, last, target_rgb, target_depth, target_index, lambda_depth, loss, dinst,
-                                    ws, S(stream));
+                                    ws, fwd_ws, capacity, S(stream));
 }
 
 extern "C" size_t gsr_render_step_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity) {

@@ -284,7 +284,11 @@ __global__ __launch_bounds__(256) void k_slice_prod(const gsr_splat *__restrict_
     }
 }
 
-// Pass 3: per pixel, the slices' results in order.
+// Pass 3: per pixel, the slices' results in order.  Afterwards each slice's colour and depth
+// result is replaced by the sum of those behind it (up to the slice in which the pixel
+// terminated; zero for slices it never reached), and each slice's transmittance by the one behind
+// it (T_final for the terminating slice and those after it): the state from which the backward
+// starts a slice.
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_slice_merge(const uint32_t *__restrict__ ranges,
                                                      const gsr_camera *__restrict__ cams, int W, int H, int ntx,
@@ -299,9 +303,12 @@ __global__ __launch_bounds__(256) void k_slice_merge(const uint32_t *__restrict_
         if (!t.inside) continue;
         const uint32_t K = sl.tile_slices[si.x];
         float Tin = 1.0f, Tr = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dd = 0.f;
-        uint32_t lst = 0;
+        uint32_t lst = 0, kt = K - 1;  // kt: the last slice the pixel composited
         for (uint32_t k = 0; k < K; k++) {
-            if (Tin < GSR_T_MIN) break;  // terminated in an earlier slice
+            if (Tin < GSR_T_MIN) {  // terminated in an earlier slice
+                kt = k - 1;
+                break;
+            }
             const size_t q = (size_t)(j + k) * 256 + threadIdx.x;
             const float4 pc = sl.part[q];
             const uint2 p2 = sl.part2[q];
@@ -312,8 +319,29 @@ __global__ __launch_bounds__(256) void k_slice_merge(const uint32_t *__restrict_
             const float To = __uint_as_float(p2.x);
             Tr = fabsf(To);
             lst = p2.y ? p2.y : lst;
-            if (To < 0.0f) break;  // terminated in this slice
+            if (To < 0.0f) {  // terminated in this slice
+                kt = k;
+                break;
+            }
             if (k + 1 < K) Tin *= sl.tprod[q];
+        }
+        {
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (uint32_t k = K; k-- > 0;) {
+                const size_t q = (size_t)(j + k) * 256 + threadIdx.x;
+                if (k > kt) {
+                    sl.part[q] = acc;
+                    sl.part2[q].x = __float_as_uint(Tr);
+                    continue;
+                }
+                const float4 pc = sl.part[q];
+                sl.part[q] = acc;
+                if (k == kt) sl.part2[q].x = __float_as_uint(Tr);
+                acc.x += pc.x;
+                acc.y += pc.y;
+                acc.z += pc.z;
+                acc.w += pc.w;
+            }
         }
         const gsr_camera &cam = cams[t.v];
         const int64_t P = (int64_t)W * H;
@@ -599,6 +627,11 @@ struct PixelGrad {
     uint32_t last;
 };
 
+// The suffix behind a whole tile: the background term T_final (dL/dC . bg).
+__device__ __forceinline__ float bg_suffix(const PixelGrad &pg, const gsr_camera &cam) {
+    return pg.Tr * (pg.G0 * cam.bg[0] + pg.G1 * cam.bg[1] + pg.G2 * cam.bg[2]);
+}
+
 // Backward of one (view, tile) work item, Gaussian-major.  The tile's instances up to the deepest
 // pixel's last contributor are staged back to front in batches of 256.  Each wave compacts the
 // batch to the Gaussians that reach its pixel sub-rectangle and cuts them, deepest first, into
@@ -614,12 +647,16 @@ struct PixelGrad {
 // emission index: the records of one (view, Gaussian) pair are contiguous there, and the
 // projection backward sums them in a fixed order, so no global atomics are needed.  The four
 // waves' adds to one slot come in a run-dependent order, so gradients repeat from run to run only
-// up to float rounding.  Block-uniform arguments except the pixel state pg.
+// up to float rounding.  Block-uniform arguments except the pixel state pg and S0.
+// [lo, hi) (positions in the tile's list) is the part of the tile this call handles: the whole tile,
+// or one depth slice of a long tile.  pg.Tr is the pixel's transmittance behind that part and S0
+// the suffix behind it: T_final (dL/dC . bg) for the whole tile, plus dL/dC . C_behind + dL/dD
+// D_behind (the colour and depth composited behind the slice) for a slice.
 template <int TW, int TH>
 __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst,
                                               const uint32_t *__restrict__ inst_emit, uint32_t item, uint32_t start,
-                                              uint32_t end, int ntx, int T, const gsr_camera &cam,
-                                              const PixelGrad &pg, BwdLds &L, float *__restrict__ dinst) {
+                                              uint32_t lo, uint32_t hi, int ntx, int T, const gsr_camera &cam,
+                                              const PixelGrad &pg, float S0, BwdLds &L, float *__restrict__ dinst) {
     float4 *const sA = L.sA, *const sB = L.sB, *const sC = L.sC;
     auto &sAcc = L.sAcc;
     auto &sList = L.sList;
@@ -642,10 +679,8 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
     const float fxw = (float)(tx * TW - bx) + 0.5f, fyw = (float)(ty * TH - by + w * (64 / TW)) + 0.5f;
     const uint32_t mylast = pg.last;
     {
-        // the suffix starts with the background term T_final (dL/dC . bg)
-        const float S = pg.Tr * (pg.G0 * cam.bg[0] + pg.G1 * cam.bg[1] + pg.G2 * cam.bg[2]);
         sPG[w][lane] = make_float4(pg.G0, pg.G1, pg.G2, pg.GD);
-        sPS[w][lane] = make_float2(pg.Tr, S);
+        sPS[w][lane] = make_float2(pg.Tr, S0);
         sPL[w][lane] = mylast;
         if (threadIdx.x == 0) s_max = 0;
     }
@@ -657,17 +692,17 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, off));
     __syncthreads();
-    const uint32_t nl = min(s_max, end - start);
+    const uint32_t nl = min(s_max, hi);
     // instances behind every pixel's last contributor receive a zero record
-    for (uint32_t k = start + nl + threadIdx.x; k < end; k += 256) {
+    for (uint32_t k = start + max(nl, lo) + threadIdx.x; k < start + hi; k += 256) {
         float2 *rec = reinterpret_cast<float2 *>(dinst + (int64_t)inst_emit[k] * GSR_SPLAT_GRAD_FLOATS);
 #pragma unroll
         for (int e = 0; e < 5; e++) rec[e] = make_float2(0.f, 0.f);
     }
     const float kap = (float)GSR_KAPPA;
     const float nln2 = -(float)GSR_LN2;
-    for (int bend = (int)nl; bend > 0; bend -= 256) {
-        const int b0 = bend > 256 ? bend - 256 : 0;
+    for (int bend = (int)nl; bend > (int)lo; bend -= 256) {
+        const int b0 = bend - 256 > (int)lo ? bend - 256 : (int)lo;
         const int cnt = bend - b0;
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
@@ -888,8 +923,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         pg.G2 = dLdrgb[(int64_t)t.v * 3 * P + 2 * P + pix];
         if (dLddepth) pg.GD = dLddepth[(int64_t)t.v * P + pix];
     }
-    tile_backward<TW, TH>(splats, inst, inst_emit, item, ranges[2 * item], ranges[2 * item + 1], ntx, T, cams[t.v], pg,
-                          L, dinst);
+    const uint32_t start = ranges[2 * item];
+    tile_backward<TW, TH>(splats, inst, inst_emit, item, start, 0u, ranges[2 * item + 1] - start, ntx, T, cams[t.v], pg,
+                          bg_suffix(pg, cams[t.v]), L, dinst);
 }
 
 // ---- fused persistent step: forward, L1 loss gradient and backward of each tile ----------------
@@ -1046,7 +1082,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             finish_pixels(t, item, cams[t.v], W, H, pw.Tr, pw.c0, pw.c1, pw.c2, pw.dd, pw.lst, rgb, depth, Tfin, last,
                           a, pg, s_red);
         }
-        tile_backward<TW, TH>(splats, inst, inst_emit, item, start, end, ntx, T, cams[t.v], pg, L, dinst);
+        tile_backward<TW, TH>(splats, inst, inst_emit, item, start, 0u, end - start, ntx, T, cams[t.v], pg,
+                              bg_suffix(pg, cams[t.v]), L, dinst);
         __syncthreads();  // the backward's last flush reads LDS the next item overwrites
     }
 }
@@ -1077,12 +1114,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst, const uint32_t *__restrict__ inst_emit,
     const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ order, const gsr_camera *__restrict__ cams, int W,
     int H, int ntx, int T, const float *__restrict__ rgb, const float *__restrict__ depth,
-    const float *__restrict__ Tfin, const uint32_t *__restrict__ last, float *__restrict__ dinst, StepArgs a) {
+    const float *__restrict__ Tfin, const uint32_t *__restrict__ last, float *__restrict__ dinst, StepArgs a,
+    SliceArgs sl) {
     __shared__ BwdLds L;
     __shared__ double s_red[4];
-    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
-    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
     const int64_t P = (int64_t)W * H;
+    if (blockIdx.x < sl.grid) {
+        // the depth slices of the long tiles, each from the state behind it that the forward's
+        // slice merge left in the slice results
+        const uint32_t n = min(*sl.count, sl.cap);
+        for (uint32_t j = blockIdx.x; j < n; j += sl.grid) {
+            const uint2 si = sl.info[j];
+            if (si.x == kNoSlice) continue;
+            __syncthreads();  // every lane has left the previous slice's shared state
+            const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
+            const int64_t pix = (int64_t)t.py * W + t.px;
+            const gsr_camera &cam = cams[t.v];
+            const uint32_t start = ranges[2 * si.x], len = ranges[2 * si.x + 1] - start;
+            const uint32_t lo = si.y * kSliceLen, hi = min(lo + kSliceLen, len);
+            PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
+            float S0 = 0.f;
+            if (t.inside) {
+                const int64_t b = (int64_t)t.v * 3 * P + pix;
+                l1_pixel(a, t.v, P, pix, rgb[b], rgb[b + P], rgb[b + 2 * P], depth[(int64_t)t.v * P + pix], pg);
+                pg.last = last[(int64_t)t.v * P + pix];
+                const size_t q = (size_t)j * 256 + threadIdx.x;
+                pg.Tr = fabsf(__uint_as_float(sl.part2[q].x));  // transmittance behind the slice
+                const float4 cb = sl.part[q];                    // colour and depth behind it
+                PixelGrad fin = pg;
+                fin.Tr = Tfin[(int64_t)t.v * P + pix];
+                S0 = bg_suffix(fin, cam) +
+                     (pg.G0 * cb.x + pg.G1 * cb.y + pg.G2 * cb.z + pg.GD * cb.w);
+            }
+            tile_backward<TW, TH>(splats, inst, inst_emit, si.x, start, lo, hi, ntx, T, cam, pg, S0, L, dinst);
+        }
+        return;
+    }
+    const uint32_t bk = blockIdx.x - sl.grid, nb = gridDim.x - sl.grid;
+    const uint32_t item = order ? order[bk] : xcd_remap(bk, nb);
+    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
     const int64_t pix = (int64_t)t.py * W + t.px;
     PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
     double l = 0.0;
@@ -1096,8 +1166,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     if (__lane_id() == 0) s_red[threadIdx.x >> 6] = l;
     __syncthreads();
     if (threadIdx.x == 0) a.item_loss[item] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
-    tile_backward<TW, TH>(splats, inst, inst_emit, item, ranges[2 * item], ranges[2 * item + 1], ntx, T, cams[t.v], pg,
-                          L, dinst);
+    if (sl.grid && sl.tile_slices[item]) return;  // its backward runs in depth slices
+    const uint32_t start = ranges[2 * item];
+    tile_backward<TW, TH>(splats, inst, inst_emit, item, start, 0u, ranges[2 * item + 1] - start, ntx, T, cams[t.v], pg,
+                          bg_suffix(pg, cams[t.v]), L, dinst);
 }
 
 // Backward of the stored-contributor mode, pixel-major: every lane walks its own pixel's list of
@@ -1386,15 +1458,22 @@ extern "C" gsr_status gsr_render_bwd_l1_launch(const gsr_splat *splats, const ui
                                                const gsr_raster *r, const float *rgb, const float *depth,
                                                const float *Tfin, const uint32_t *last, const float *trgb,
                                                const float *tdepth, const int32_t *tidx, float lam, double *loss,
-                                               float *dinst, void *ws, hipStream_t st) {
+                                               float *dinst, void *ws, void *fwd_ws, int64_t capacity,
+                                               hipStream_t st) {
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     const int T = ntx * nty;
     const int nb = V * T;
     double *item_loss = static_cast<double *>(ws);
     const StepArgs a{trgb, tdepth, tidx, lam, item_loss, nullptr, nullptr};
-#define GSR_RBL(TW, TH)                                                                                             \
-    k_render_bwd_l1<TW, TH><<<nb, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width, r->height, \
-                                                ntx, T, rgb, depth, Tfin, last, dinst, a)
+    // the long tiles run in the depth slices of the sliced forward that produced the images
+    SliceArgs sl{};
+    if (fwd_ws) {
+        const SliceWs w = slice_layout(fwd_ws, nb, capacity);
+        sl = SliceArgs{w.tile_slices, w.info, w.count, w.tprod, w.part, w.part2, w.cap, w.cap < 2048u ? w.cap : 2048u};
+    }
+#define GSR_RBL(TW, TH)                                                                                         \
+    k_render_bwd_l1<TW, TH><<<nb + sl.grid, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width, \
+                                                          r->height, ntx, T, rgb, depth, Tfin, last, dinst, a, sl)
     if (r->tile_w == 16) GSR_RBL(16, 16);
     else if (r->tile_w == 8) GSR_RBL(8, 32);
     else GSR_RBL(32, 8);

@@ -212,7 +212,8 @@ class MapOptimizer:
                 render_bwd_l1(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.rgb,
                               r.depth, r.T_final, r.last, self.target_rgb, gd,
                               self.lambda_depth if gd is not None else 0.0, self.loss, r.dinst, self.bwd_ws,
-                              tile_order=r.tile_order, target_index=self.view_idx32)
+                              tile_order=r.tile_order, target_index=self.view_idx32, fwd_ws=r.fwd_ws,
+                              capacity=r.capacity)
                 return
             render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
                        r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,

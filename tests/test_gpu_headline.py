@@ -118,23 +118,19 @@ def test_headline_backward_sampled_pixels_match_oracle(headline):
         assert bad.sum() == 0, (k, int(bad.sum()), touched)
 
 
-def test_headline_fused_step_matches_separate_render_and_oracle(headline):
-    """The fused persistent step (forward + L1 loss + backward per view-tile, depth slices of the
-    long tiles finished by the workgroup that completes their last slice) at the headline size.
-    Targets equal the separate forward's images except at the sampled pixels of two views, where
+def _l1_step_vs_oracle(h, views, seed, run):
+    """Targets equal the separate forward's images except at the sampled pixels of two views, where
     they are moved by +-0.1: the loss gradient is exactly zero elsewhere (sign(0) = 0), so the
-    fused images must equal the separate forward's bit for bit, the loss must be the sampled
-    pixels' terms, and every parameter and pose gradient must match the oracle's backward of the
-    upstream gradient sign / P at those pixels."""
+    images must equal the separate forward's bit for bit, the loss must be the sampled pixels'
+    terms, and every parameter and pose gradient must match the oracle's backward of the upstream
+    gradient sign / P at those pixels.  run(trgb, tdep, lam, loss) renders and leaves the records."""
     import paper_2604_12942_amd as gsr
-    h = headline
     g, cams, rast, P, ct = h["g"], h["cams"], h["rast"], h["P"], h["ct"]
     V = len(cams)
     H, W = cams[0]["height"], cams[0]["width"]
     Pn = W * H
     lam = 0.2
-    views = (1, V - 2)
-    rng = np.random.default_rng(4242)
+    rng = np.random.default_rng(seed)
     trgb = h["rgb"].astype(np.float32).copy()
     tdep = h["depth"].astype(np.float32).copy()
     GC = np.zeros((V, 3, H, W))
@@ -155,11 +151,7 @@ def test_headline_fused_step_matches_separate_render_and_oracle(headline):
         exp_loss += (np.abs(dC).astype(np.float64).sum() + lam * np.abs(dD).astype(np.float64).sum()) / Pn
     r = rast
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    ws = torch.empty((gsr.render_step_workspace(V, r.raster, r.capacity) + 255) // 256 * 64, dtype=torch.int32,
-                     device="cuda")
-    gsr.render_step(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, r.raster, torch.from_numpy(trgb).cuda(),
-                    torch.from_numpy(tdep).cuda(), lam, r.rgb, r.depth, r.T_final, r.last, loss, r.dinst, r.capacity,
-                    ws, tile_order=r.tile_order)
+    run(torch.from_numpy(trgb).cuda(), torch.from_numpy(tdep).cuda(), lam, loss)
     torch.cuda.synchronize()
     assert np.array_equal(r.rgb.cpu().numpy(), h["rgb"].astype(np.float32))
     assert np.array_equal(r.depth.cpu().numpy(), h["depth"].astype(np.float32))
@@ -185,3 +177,41 @@ def test_headline_fused_step_matches_separate_render_and_oracle(headline):
         gk = grads[k].cpu().numpy().astype(np.float64)
         bad = grad_close(gk, exp[k])
         assert bad.sum() == 0, (k, int(bad.sum()))
+
+
+def test_headline_fused_step_matches_separate_render_and_oracle(headline):
+    """The fused persistent step (forward + L1 loss + backward per view-tile, depth slices of the
+    long tiles finished by the workgroup that completes their last slice) at the headline size."""
+    import paper_2604_12942_amd as gsr
+    h = headline
+    r, ct, V = h["rast"], h["ct"], len(h["cams"])
+    ws = torch.empty((gsr.render_step_workspace(V, r.raster, r.capacity) + 255) // 256 * 64, dtype=torch.int32,
+                     device="cuda")
+
+    def run(trgb, tdep, lam, loss):
+        gsr.render_step(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, r.raster, trgb, tdep, lam, r.rgb,
+                        r.depth, r.T_final, r.last, loss, r.dinst, r.capacity, ws, tile_order=r.tile_order)
+
+    _l1_step_vs_oracle(h, (1, V - 2), 4242, run)
+
+
+def test_headline_two_pass_step_matches_oracle(headline):
+    """The timed step's render at the headline size: the sliced forward, then the L1 backward with
+    the long tiles in the forward's depth slices (gsr_render_bwd_l1 given the forward's
+    workspace).  The most loaded tile of every view is composited and back-propagated in slices."""
+    import paper_2604_12942_amd as gsr
+    h = headline
+    r, ct, V = h["rast"], h["ct"], len(h["cams"])
+    # the two views with the longest tiles; both are composited and back-propagated in slices
+    views = tuple(int(v) for v in np.argsort(h["longest"])[::-1][:2])
+    assert min(h["longest"][v] for v in views) > 8192, h["longest"]
+    ws = torch.empty((gsr.render_bwd_l1_workspace(V, r.raster) + 255) // 256 * 64, dtype=torch.int32, device="cuda")
+
+    def run(trgb, tdep, lam, loss):
+        gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, ct, V, r.raster, r.rgb, r.depth, r.T_final, r.last,
+                       tile_order=r.tile_order, ws=r.fwd_ws, capacity=r.capacity)
+        gsr.render_bwd_l1(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, r.raster, r.rgb, r.depth,
+                          r.T_final, r.last, trgb, tdep, lam, loss, r.dinst, ws, tile_order=r.tile_order,
+                          fwd_ws=r.fwd_ws, capacity=r.capacity)
+
+    _l1_step_vs_oracle(h, views, 4343, run)

@@ -231,3 +231,17 @@ def test_fused_render_step_equals_separate_launches(scene):
     assert abs(loss_a.item() - loss_c.item()) <= 1e-12 * abs(loss_a.item())
     ds_c = r.screen_grads().cpu().numpy().astype(np.float64)
     assert np.all(np.abs(ds_c - ds_a).reshape(-1, 10) <= 1e-4 * (np.abs(ds_a).reshape(-1, 10) + rms))
+    # the timed step's form: the sliced forward, then the L1 backward with the long tiles in its depth
+    # slices (the forward's workspace handed over)
+    r.dinst.fill_(-7)
+    gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, ct, V, raster, r.rgb, r.depth, r.T_final, r.last,
+                   tile_order=r.tile_order, ws=r.fwd_ws, capacity=r.capacity)
+    loss_d = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gsr.render_bwd_l1(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, ct, V, raster, r.rgb, r.depth, r.T_final,
+                      r.last, trgb, tdep, 0.2, loss_d, r.dinst, ws, tile_order=r.tile_order, fwd_ws=r.fwd_ws,
+                      capacity=r.capacity)
+    torch.cuda.synchronize()
+    assert torch.equal(r.rgb, ref["rgb"]) and torch.equal(r.T_final, ref["T"]) and torch.equal(r.last, ref["last"])
+    assert abs(loss_a.item() - loss_d.item()) <= 1e-12 * abs(loss_a.item())
+    ds_d = r.screen_grads().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(ds_d - ds_a).reshape(-1, 10) <= 1e-4 * (np.abs(ds_a).reshape(-1, 10) + rms))
