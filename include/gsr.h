@@ -185,8 +185,11 @@ GSR_API gsr_status gsr_render_fwd(const gsr_splat *splats, const uint32_t *inst_
  * composited exactly as by gsr_render_fwd.
  * capacity: the instance capacity the lists were built with (gsr_bin_sort's), which bounds the
  * number of slices.  ws: device workspace of gsr_render_fwd_sliced_workspace(V, r, capacity)
- * bytes (about 7.7 KiB per 1,000 instances of capacity), 256-byte aligned.  Errors: GSR_E_INVALID,
- * GSR_E_CAPACITY (ws_bytes too small). */
+ * bytes (about 7.7 KiB per 1,000 instances of capacity), 256-byte aligned.  After the call ws
+ * holds, per slice and pixel, the transmittance behind the slice and the colour and depth
+ * composited behind it: gsr_render_bwd and gsr_render_bwd_l1 given this ws run the backward of
+ * the split tiles in the same slices.  Errors: GSR_E_INVALID, GSR_E_CAPACITY (ws_bytes too
+ * small). */
 GSR_API size_t gsr_render_fwd_sliced_workspace(int32_t n_views, const gsr_raster *r, int64_t capacity);
 GSR_API gsr_status gsr_render_fwd_sliced(const gsr_splat *splats, const uint32_t *inst_gid,
                                          const uint32_t *tile_ranges, const uint32_t *tile_order,
@@ -235,11 +238,20 @@ GSR_API gsr_status gsr_render_bwd_stored(const gsr_splat *splats, const uint32_t
  * (gsr_pair_grads, or inside gsr_project_bwd), taken in a fixed order.  Each record, though, is
  * the sum of its tile's pixel terms formed by the four waves of a workgroup, whose adds into
  * shared memory come in an order that varies from run to run: gradients repeat from run to run
- * only up to float32 rounding, not bit for bit. */
+ * only up to float32 rounding, not bit for bit.
+ * fwd_ws: NULL, or the workspace (fwd_ws_bytes long, 256-byte aligned) of the gsr_render_fwd_sliced
+ * call, with this capacity and these lists, that produced T_final and last.  Then each view-tile
+ * that forward composited in depth slices also runs its backward in those slices, one workgroup per
+ * slice, each starting from the transmittance behind its slice and the colour and depth composited
+ * behind it, which that forward's slice merge leaves in fwd_ws (read, not changed): the records
+ * equal those of the whole-tile walk up to float rounding, and a long tile no longer holds one
+ * workgroup for the whole launch.  Errors: GSR_E_INVALID (NULL pointers, a misaligned fwd_ws, a bad
+ * capacity), GSR_E_CAPACITY (fwd_ws_bytes too small). */
 GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
                                   const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
                                   int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,
-                                  const float *dL_drgb, const float *dL_ddepth, float *dinst, gsr_stream stream);
+                                  const float *dL_drgb, const float *dL_ddepth, float *dinst, void *fwd_ws,
+                                  size_t fwd_ws_bytes, int64_t capacity, gsr_stream stream);
 
 /* ---- render backward of the per-pixel L1 loss ---------------------------------------------------
  * gsr_loss_l1 followed by gsr_render_bwd in one launch: each workgroup forms its view-tile's pixel
@@ -250,13 +262,9 @@ GSR_API gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_
  * gsr_render_bwd plus the forward's rgb [V][3][H][W] and depth [V][H][W]; targets as gsr_loss_l1.
  * *loss (device float64) is ACCUMULATED, summed over the view-tiles in a fixed order.  ws:
  * gsr_render_bwd_l1_workspace(V, r) bytes (one float64 per view-tile), 256-byte aligned.
- * fwd_ws: NULL, or the workspace (fwd_ws_bytes long, 256-byte aligned) of the gsr_render_fwd_sliced
- * call, with this capacity and these lists, that produced rgb, depth, T_final and last.  Then each
- * view-tile that forward composited in depth slices also runs its backward in those slices, one
- * workgroup per slice, each starting from the transmittance behind its slice and the colour and
- * depth composited behind it, which that forward's slice merge leaves in fwd_ws.  The records are
- * those of the whole-tile walk up to float rounding.  The slice contents of fwd_ws are read, not
- * changed.  Errors: GSR_E_INVALID (NULL pointers, lambda_depth < 0, a misaligned ws or fwd_ws, a
+ * fwd_ws, fwd_ws_bytes, capacity: as for gsr_render_bwd (the sliced forward that produced rgb,
+ * depth, T_final and last; its depth slices then carry the long tiles' backward; NULL: whole
+ * tiles).  Errors: GSR_E_INVALID (NULL pointers, lambda_depth < 0, a misaligned ws or fwd_ws, a
  * bad capacity), GSR_E_CAPACITY (ws_bytes or fwd_ws_bytes too small). */
 GSR_API size_t gsr_render_bwd_l1_workspace(int32_t n_views, const gsr_raster *r);
 GSR_API gsr_status gsr_render_bwd_l1(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,

@@ -142,10 +142,15 @@ def render_fwd_sliced_workspace(n_views, raster, capacity):
 
 
 def render_bwd(splats, inst_gid, inst_emit, tile_ranges, cams, n_views, raster, T_final, last, dL_drgb, dL_ddepth,
-               dinst, tile_order=None):
+               dinst, tile_order=None, fwd_ws=None, capacity=0):
+    """gsr_render_bwd.  fwd_ws / capacity: the workspace and capacity of the sliced forward that
+    produced T_final and last (the long tiles then run their backward in its depth slices); None
+    runs whole tiles."""
     check(lib().gsr_render_bwd(_ptr(splats), _ptr(inst_gid), _ptr(inst_emit), _ptr(tile_ranges), _ptr(tile_order),
                                _ptr(cams), n_views, C.byref(raster.c), _ptr(T_final), _ptr(last), _ptr(dL_drgb),
-                               _ptr(dL_ddepth), _ptr(dinst), _stream()), "gsr_render_bwd")
+                               _ptr(dL_ddepth), _ptr(dinst), _ptr(fwd_ws),
+                               0 if fwd_ws is None else fwd_ws.numel() * fwd_ws.element_size(), int(capacity),
+                               _stream()), "gsr_render_bwd")
 
 
 def render_bwd_l1_workspace(n_views, raster):
@@ -587,6 +592,7 @@ class Rasterizer:
         wsf = max(render_fwd_sliced_workspace(self.V, self.raster, self.capacity),
                   render_step_workspace(self.V, self.raster, self.capacity))
         self.fwd_ws = torch.empty((wsf + 255) // 256 * 64, dtype=torch.int32, device=self.device)
+        self.fwd_sliced = False  # whether fwd_ws holds the slice results of the last sliced forward
 
     def project(self, P, sh_degree, cams):
         """gsr_project into this rasterizer's buffers (remembered, so that a bin/sort whose
@@ -606,6 +612,8 @@ class Rasterizer:
             ws = self.fwd_ws if sliced else None
             render_fwd(self.splats, self.inst_gid, self.tile_ranges, cams, self.V, self.raster, self.rgb, self.depth,
                        self.T_final, self.last, tile_order=self.tile_order, ws=ws, capacity=self.capacity)
+        # the sliced forward leaves in fwd_ws what the backward of its slices starts from
+        self.fwd_sliced = self.mode != "stored" and sliced
         return self.rgb, self.depth, self.T_final
 
     def render_stored(self, cams, check_capacity=True):
@@ -663,7 +671,8 @@ class Rasterizer:
                               dL_drgb.contiguous(), gd, self.dinst, tile_order=self.tile_order)
         else:
             render_bwd(self.splats, self.inst_gid, self.inst_emit, self.tile_ranges, cams, self.V, self.raster,
-                       self.T_final, self.last, dL_drgb.contiguous(), gd, self.dinst, tile_order=self.tile_order)
+                       self.T_final, self.last, dL_drgb.contiguous(), gd, self.dinst, tile_order=self.tile_order,
+                       fwd_ws=self.fwd_ws if self.fwd_sliced else None, capacity=self.capacity)
 
     def screen_grads(self):
         """Per-pair screen-space gradients [V*n*10] of the last backward."""

@@ -78,7 +78,8 @@ _SIGS = {
     "gsr_bin_sort": ([P, C.c_int64, C.c_int32, C.POINTER(Raster), P, C.POINTER(Emission), C.c_int64, P, P, P, P,
                       C.c_size_t, P], C.c_int),
     "gsr_render_fwd": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
-    "gsr_render_bwd": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P], C.c_int),
+    "gsr_render_bwd": ([P, P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, P, P, C.c_size_t, C.c_int64, P],
+                       C.c_int),
     "gsr_render_fwd_sliced_workspace": ([C.c_int32, C.POINTER(Raster), C.c_int64], C.c_size_t),
     "gsr_render_fwd_sliced": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), P, P, P, P, C.c_int64, P, C.c_size_t, P],
                               C.c_int),

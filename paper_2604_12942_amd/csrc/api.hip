@@ -34,7 +34,8 @@ extern "C" gsr_status gsr_render_step_launch(const gsr_splat *, const uint32_t *
                                              float *, uint32_t *, double *, float *, int64_t, void *, hipStream_t);
 extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
                                             const uint32_t *, const gsr_camera *, int, const gsr_raster *, const float *,
-                                            const uint32_t *, const float *, const float *, float *, hipStream_t);
+                                            const uint32_t *, const float *, const float *, float *, void *, int64_t,
+                                            hipStream_t);
 extern "C" gsr_status gsr_pair_grads_launch(const float *, const gsr_emission *, const uint32_t *, int64_t, float *,
                                             bool, hipStream_t);
 extern "C" gsr_status gsr_render_store_launch(const gsr_splat *, const uint32_t *, const uint32_t *, const uint32_t *,
@@ -214,12 +215,18 @@ extern "C" gsr_status gsr_render_fwd_sliced(const gsr_splat *splats, const uint3
 extern "C" gsr_status gsr_render_bwd(const gsr_splat *splats, const uint32_t *inst_gid, const uint32_t *inst_emit,
                                      const uint32_t *tile_ranges, const uint32_t *tile_order, const gsr_camera *cams,
                                      int32_t n_views, const gsr_raster *r, const float *T_final, const uint32_t *last,
-                                     const float *dL_drgb, const float *dL_ddepth, float *dinst, gsr_stream stream) {
+                                     const float *dL_drgb, const float *dL_ddepth, float *dinst, void *fwd_ws,
+                                     size_t fwd_ws_bytes, int64_t capacity, gsr_stream stream) {
     if (!raster_ok(r) || n_views < 1 || !cams || !tile_ranges || !T_final || !last || !dL_drgb || !dinst ||
         !inst_emit || !inst_gid || !splats)
         return GSR_E_INVALID;
+    if (fwd_ws) {
+        if (capacity < 0 || capacity >= (int64_t)UINT32_MAX || (reinterpret_cast<uintptr_t>(fwd_ws) & 255) != 0)
+            return GSR_E_INVALID;
+        if (fwd_ws_bytes < gsr_render_fwd_ws_bytes(n_views, r, capacity)) return GSR_E_CAPACITY;
+    }
     return gsr_render_bwd_launch(splats, inst_gid, inst_emit, tile_ranges, tile_order, cams, n_views, r, T_final, last,
-                                 dL_drgb, dL_ddepth, dinst, S(stream));
+                                 dL_drgb, dL_ddepth, dinst, fwd_ws, capacity, S(stream));
 }
 
 extern "C" size_t gsr_render_bwd_l1_workspace(int32_t n_views, const gsr_raster *r) {

@@ -903,25 +903,72 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
     }
 }
 
+// The depth slices of the long tiles, for the first sl.grid workgroups of a backward launch: each
+// slice's backward from the state behind it that the sliced forward's merge left in the slice
+// results (transmittance behind the slice; colour and depth composited behind it).
+// grad(t, pix, pg) fills the pixel's upstream gradient pg.G0..GD.
+template <int TW, int TH, class Grad>
+__device__ __forceinline__ void slices_backward(const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst,
+                                                const uint32_t *__restrict__ inst_emit,
+                                                const uint32_t *__restrict__ ranges,
+                                                const gsr_camera *__restrict__ cams, int W, int H, int ntx, int T,
+                                                const float *__restrict__ Tfin, const uint32_t *__restrict__ last,
+                                                const SliceArgs &sl, BwdLds &L, float *__restrict__ dinst, Grad grad) {
+    const int64_t P = (int64_t)W * H;
+    const uint32_t n = min(*sl.count, sl.cap);
+    for (uint32_t j = blockIdx.x; j < n; j += sl.grid) {
+        const uint2 si = sl.info[j];
+        if (si.x == kNoSlice) continue;
+        __syncthreads();  // every lane has left the previous slice's shared state
+        const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
+        const int64_t pix = (int64_t)t.py * W + t.px;
+        const gsr_camera &cam = cams[t.v];
+        const uint32_t start = ranges[2 * si.x], len = ranges[2 * si.x + 1] - start;
+        const uint32_t lo = si.y * kSliceLen, hi = min(lo + kSliceLen, len);
+        PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
+        float S0 = 0.f;
+        if (t.inside) {
+            grad(t, pix, pg);
+            pg.last = last[(int64_t)t.v * P + pix];
+            const size_t q = (size_t)j * 256 + threadIdx.x;
+            const float4 cb = sl.part[q];  // colour and depth behind the slice
+            PixelGrad fin = pg;
+            fin.Tr = Tfin[(int64_t)t.v * P + pix];
+            S0 = bg_suffix(fin, cam) + (pg.G0 * cb.x + pg.G1 * cb.y + pg.G2 * cb.z + pg.GD * cb.w);
+            pg.Tr = fabsf(__uint_as_float(sl.part2[q].x));  // transmittance behind the slice
+        }
+        tile_backward<TW, TH>(splats, inst, inst_emit, si.x, start, lo, hi, ntx, T, cam, pg, S0, L, dinst);
+    }
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(
     const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst, const uint32_t *__restrict__ inst_emit,
     const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ order, const gsr_camera *__restrict__ cams, int W,
     int H, int ntx, int T, const float *__restrict__ Tfin, const uint32_t *__restrict__ last,
-    const float *__restrict__ dLdrgb, const float *__restrict__ dLddepth, float *__restrict__ dinst) {
+    const float *__restrict__ dLdrgb, const float *__restrict__ dLddepth, float *__restrict__ dinst, SliceArgs sl) {
     __shared__ BwdLds L;
-    const uint32_t item = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
-    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
     const int64_t P = (int64_t)W * H;
+    auto grad = [&](const TileGeom &t, int64_t pix, PixelGrad &pg) {
+        pg.G0 = dLdrgb[(int64_t)t.v * 3 * P + pix];
+        pg.G1 = dLdrgb[(int64_t)t.v * 3 * P + P + pix];
+        pg.G2 = dLdrgb[(int64_t)t.v * 3 * P + 2 * P + pix];
+        if (dLddepth) pg.GD = dLddepth[(int64_t)t.v * P + pix];
+    };
+    if (blockIdx.x < sl.grid) {
+        slices_backward<TW, TH>(splats, inst, inst_emit, ranges, cams, W, H, ntx, T, Tfin, last, sl, L, dinst, grad);
+        return;
+    }
+    const uint32_t bk = blockIdx.x - sl.grid, nb = gridDim.x - sl.grid;
+    const uint32_t item = order ? order[bk] : xcd_remap(bk, nb);
+    if (sl.grid && sl.tile_slices[item]) return;  // its backward runs in depth slices
+    const TileGeom t = tile_geom<TW, TH>(item, T, ntx, W, H);
     const int64_t pix = (int64_t)t.py * W + t.px;
     PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
     if (t.inside) {
         pg.Tr = Tfin[(int64_t)t.v * P + pix];
         pg.last = last[(int64_t)t.v * P + pix];
-        pg.G0 = dLdrgb[(int64_t)t.v * 3 * P + pix];
-        pg.G1 = dLdrgb[(int64_t)t.v * 3 * P + P + pix];
-        pg.G2 = dLdrgb[(int64_t)t.v * 3 * P + 2 * P + pix];
-        if (dLddepth) pg.GD = dLddepth[(int64_t)t.v * P + pix];
+        grad(t, pix, pg);
     }
     const uint32_t start = ranges[2 * item];
     tile_backward<TW, TH>(splats, inst, inst_emit, item, start, 0u, ranges[2 * item + 1] - start, ntx, T, cams[t.v], pg,
@@ -1120,34 +1167,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     __shared__ double s_red[4];
     const int64_t P = (int64_t)W * H;
     if (blockIdx.x < sl.grid) {
-        // the depth slices of the long tiles, each from the state behind it that the forward's
-        // slice merge left in the slice results
-        const uint32_t n = min(*sl.count, sl.cap);
-        for (uint32_t j = blockIdx.x; j < n; j += sl.grid) {
-            const uint2 si = sl.info[j];
-            if (si.x == kNoSlice) continue;
-            __syncthreads();  // every lane has left the previous slice's shared state
-            const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
-            const int64_t pix = (int64_t)t.py * W + t.px;
-            const gsr_camera &cam = cams[t.v];
-            const uint32_t start = ranges[2 * si.x], len = ranges[2 * si.x + 1] - start;
-            const uint32_t lo = si.y * kSliceLen, hi = min(lo + kSliceLen, len);
-            PixelGrad pg{1.f, 0.f, 0.f, 0.f, 0.f, 0u};
-            float S0 = 0.f;
-            if (t.inside) {
-                const int64_t b = (int64_t)t.v * 3 * P + pix;
-                l1_pixel(a, t.v, P, pix, rgb[b], rgb[b + P], rgb[b + 2 * P], depth[(int64_t)t.v * P + pix], pg);
-                pg.last = last[(int64_t)t.v * P + pix];
-                const size_t q = (size_t)j * 256 + threadIdx.x;
-                pg.Tr = fabsf(__uint_as_float(sl.part2[q].x));  // transmittance behind the slice
-                const float4 cb = sl.part[q];                    // colour and depth behind it
-                PixelGrad fin = pg;
-                fin.Tr = Tfin[(int64_t)t.v * P + pix];
-                S0 = bg_suffix(fin, cam) +
-                     (pg.G0 * cb.x + pg.G1 * cb.y + pg.G2 * cb.z + pg.GD * cb.w);
-            }
-            tile_backward<TW, TH>(splats, inst, inst_emit, si.x, start, lo, hi, ntx, T, cam, pg, S0, L, dinst);
-        }
+        slices_backward<TW, TH>(splats, inst, inst_emit, ranges, cams, W, H, ntx, T, Tfin, last, sl, L, dinst,
+                                [&](const TileGeom &t, int64_t pix, PixelGrad &pg) {
+                                    const int64_t b = (int64_t)t.v * 3 * P + pix;
+                                    l1_pixel(a, t.v, P, pix, rgb[b], rgb[b + P], rgb[b + 2 * P],
+                                             depth[(int64_t)t.v * P + pix], pg);
+                                });
         return;
     }
     const uint32_t bk = blockIdx.x - sl.grid, nb = gridDim.x - sl.grid;
@@ -1505,13 +1530,19 @@ extern "C" gsr_status gsr_render_bwd_launch(const gsr_splat *splats, const uint3
                                             const uint32_t *ranges, const uint32_t *order, const gsr_camera *cams,
                                             int V, const gsr_raster *r, const float *Tfin, const uint32_t *last,
                                             const float *dLdrgb, const float *dLddepth, float *dinst,
-                                            hipStream_t st) {
+                                            void *fwd_ws, int64_t capacity, hipStream_t st) {
     const int ntx = (int)ceil_div(r->width, r->tile_w), nty = (int)ceil_div(r->height, r->tile_h);
     const int T = ntx * nty;
     const int nb = V * T;
-#define GSR_RB(TW, TH)                                                                                              \
-    k_render_bwd<TW, TH><<<nb, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width, r->height, ntx, \
-                                             T, Tfin, last, dLdrgb, dLddepth, dinst)
+    // the long tiles run in the depth slices of the sliced forward that produced T_final and last
+    SliceArgs sl{};
+    if (fwd_ws) {
+        const SliceWs w = slice_layout(fwd_ws, nb, capacity);
+        sl = SliceArgs{w.tile_slices, w.info, w.count, w.tprod, w.part, w.part2, w.cap, w.cap < 2048u ? w.cap : 2048u};
+    }
+#define GSR_RB(TW, TH)                                                                                            \
+    k_render_bwd<TW, TH><<<nb + sl.grid, 256, 0, st>>>(splats, inst, inst_emit, ranges, order, cams, r->width,     \
+                                                       r->height, ntx, T, Tfin, last, dLdrgb, dLddepth, dinst, sl)
     if (r->tile_w == 16) GSR_RB(16, 16);
     else if (r->tile_w == 8) GSR_RB(8, 32);
     else GSR_RB(32, 8);

@@ -181,9 +181,11 @@ class MapOptimizer:
                             self.target_rgb, gd, self.lambda_depth if gd is not None else 0.0, r.rgb, r.depth,
                             r.T_final, r.last, self.loss, r.dinst, r.capacity, r.fwd_ws, tile_order=r.tile_order,
                             target_index=self.view_idx32)
+                r.fwd_sliced = False  # the fused step keeps its own slice results in fwd_ws
                 return
             render_fwd(r.splats, r.inst_gid, r.tile_ranges, self.cams, self.V, self.raster, r.rgb, r.depth,
                        r.T_final, r.last, tile_order=r.tile_order, ws=r.fwd_ws, capacity=r.capacity)
+            r.fwd_sliced = True
 
         def loss_stage():
             if self.render == "persistent":
@@ -217,7 +219,7 @@ class MapOptimizer:
                 return
             render_bwd(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster, r.T_final,
                        r.last, self.g_rgb, self.g_depth if self.target_depth is not None else None, r.dinst,
-                       tile_order=r.tile_order)
+                       tile_order=r.tile_order, fwd_ws=r.fwd_ws, capacity=r.capacity)
 
         def pbwd():
             if self.fused:
