@@ -170,18 +170,50 @@ def cpu_baseline(c, pool_cams, tg, step_views, n_sample=4):
     oracle.lib()
     g = c["gaussians"]
     t0 = time.perf_counter()
+    blends = 0
     for k in step_views[:n_sample]:
         cam = pool_cams[k]
         r = oracle.render(g, cam)
+        blends += int(r["n"].sum())
         _, gC, gD = oracle.l1_loss(r["rgb"], r["depth"], tg[k][0], tg[k][1], 0.2)
         oracle.render_bwd(g, cam, gC, gD)
     dt = time.perf_counter() - t0
     V = len(step_views)
-    return dict(value=round(n_sample / (V * dt), 5), unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+    return dict(value=round(n_sample / (V * dt), 5), unit="iters/s", blends_per_s=round(blends / dt, 1),
+                cores=oracle.num_threads(), kind="oracle",
                 nproc=len(os.sched_getaffinity(0)), cpu_model=cpu_model(),
                 sample="%d of the %d views of one step (forward + L1 loss + backward incl. pose, all %d Gaussians, "
                        "%dx%d), %.1f s, scaled to %d views" % (n_sample, V, g["means"].shape[1], pool_cams[0]["width"],
                                                               pool_cams[0]["height"], dt, V))
+
+
+def oracle_step_time(g, cam, trgb, tdep, lam):
+    """The FP64 oracle's fwd + bwd step of one view (full render, L1 loss, backward with pose):
+    (seconds, blends)."""
+    import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    r = oracle.render(g, cam)
+    _, gC, gD = oracle.l1_loss(r["rgb"], r["depth"], trgb, tdep if lam > 0 else None, lam)
+    oracle.render_bwd(g, cam, gC, gD if lam > 0 else None)
+    return time.perf_counter() - t0, int(r["n"].sum())
+
+
+def cpu_baseline_configs():
+    """The oracle's one-view step on C1 (2,000 Gaussians SH0, 128x96, its own target) and C2 (the
+    300k-Gaussian room, one 1280x720 view, a constant grey target: the timing does not depend on
+    it).  C4b's is in the --contrib-compare line.  Returns {config: {iters_per_s, blends_per_s, ...}}."""
+    out = {}
+    for name, c in (("c1", synth.config1()), ("c2", synth.config2(with_targets=False))):
+        g, cam = c["gaussians"], c["cameras"][0]
+        H, W = cam["height"], cam["width"]
+        trgb = c["target_rgb"][0] if c["target_rgb"][0] is not None else np.full((3, H, W), 0.5, np.float32)
+        tdep = c["target_depth"][0] if c["target_depth"][0] is not None else np.full((H, W), 5.0, np.float32)
+        dt, blends = oracle_step_time(g, cam, trgb, tdep, c.get("lambda_depth") or 0.0)
+        out[name] = dict(gaussians=int(g["means"].shape[1]), pixels=W * H, iters_per_s=round(1.0 / dt, 4),
+                         blends_per_s=round(blends / dt, 1), seconds=round(dt, 2))
+        print("cpu baseline %s: %s" % (name, out[name]), file=sys.stderr, flush=True)
+    return out
 
 
 def contrib_compare(a):
@@ -243,6 +275,14 @@ def contrib_compare(a):
            "config": {"workload": "loop corridor, %d Gaussians SH3, one 1920x1080 view, L1 rgb + 0.2 L1 depth" % n,
                       "tile": "16x16"},
            "data": "synthetic", "dtype": "f32", "modes": res}
+    if not a.no_cpu_baseline:
+        # the FP64 oracle's step of the same view (host cores, one step)
+        import oracle
+        dt, blends = oracle_step_time(g, cam, c["target_rgb"][0], c["target_depth"][0], 0.2)
+        out["cpu_baseline"] = dict(value=round(1.0 / dt, 5), unit="iters/s", blends_per_s=round(blends / dt, 1),
+                                   cores=oracle.num_threads(), nproc=len(os.sched_getaffinity(0)),
+                                   cpu_model=cpu_model(), kind="oracle",
+                                   sample="one full fwd + L1 loss + bwd (with pose) step, %.1f s" % dt)
     print(json.dumps(out), flush=True)
 
 
@@ -1029,6 +1069,7 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(c, pool_cams, tg, views_for_step(a.warmup + a.steps - 1))
+        cpu["configs"] = cpu_baseline_configs()
 
     out = {
         "metric": "fwd+bwd iters/s @1.5M Gaussians, 8x720p",
