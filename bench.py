@@ -420,6 +420,10 @@ FULL_LOSS = dict(lambda_rgb=0.8, lambda_ssim=0.2, support=(0.5, 2))
 # (rgb 12, targets 16, depth 4, mask 1, gradients 16), SSIM forward (images 24, mask 1, three
 # derivative maps per channel 36), SSIM backward (maps 36, images 24, mask 1, gradient RMW 24)
 FULL_LOSS_BYTES_PER_PX = 5 + 49 + 61 + 85
+# float operations per pixel of the stage's dominant kernels: the SSIM forward (separable 11-tap
+# filters of five moments, the SSIM map and its three derivative maps, about 190 per channel) and
+# backward (the filters' adjoints and the chain rule, about 110 per channel), three channels
+FULL_LOSS_FLOP_PER_PX = 3 * (190 + 110)
 
 
 def full_loss_leg(make_opt, sv, a, tile, stages, stream, pixels):
@@ -461,12 +465,16 @@ def full_loss_leg(make_opt, sv, a, tile, stages, stream, pixels):
         sys.exit(3)
     ms = 1000.0 * (time.perf_counter() - t0) / a.steps
     ach = FULL_LOSS_BYTES_PER_PX * pixels / (stage_ms["loss"] / 1000.0) / 1e9
+    fl = FULL_LOSS_FLOP_PER_PX * pixels / (stage_ms["loss"] / 1000.0) / 1e12
     res = dict(lambda_rgb=FULL_LOSS["lambda_rgb"], lambda_ssim=FULL_LOSS["lambda_ssim"], lambda_depth=0.2,
                tau_geo=FULL_LOSS["support"][0], r_erode=FULL_LOSS["support"][1], iters_per_s=round(1000.0 / ms, 3),
                ms_per_step=round(ms, 3), stage_ms={st: round(v, 4) for st, v in stage_ms.items()},
                mask_pixels=int(o.sup_count.sum().item()), loss_last=float(o.loss.item()),
-               loss_roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                                  frac=round(ach / HBM_PEAK_GBS, 4),
+               loss_roofline=dict(bound="alu", achieved=round(fl, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                  frac=round(fl / FP32_PEAK_TFLOPS, 4),
+                                  frac_of_nonpacked_peak=round(fl / FP32_PEAK_NONPACKED_TFLOPS, 4),
+                                  flop_per_pixel=FULL_LOSS_FLOP_PER_PX,
+                                  hbm_achieved_GBps=round(ach, 1), hbm_frac=round(ach / HBM_PEAK_GBS, 4),
                                   kernels="k_support_mask, k_loss_masked, k_ssim_fwd, k_ssim_bwd",
                                   alg_bytes_per_launch=FULL_LOSS_BYTES_PER_PX * pixels))
     print("full loss: %s" % res, file=sys.stderr, flush=True)
