@@ -117,3 +117,80 @@ def test_sliced_forward_two_views():
         assert img_close(b["rgb"][v], a["rgb"][v], mask=np.broadcast_to(ok, a["rgb"][v].shape)).sum() == 0
         assert img_close(b["T"][v], a["T"][v], mask=ok).sum() == 0
         assert np.array_equal(b["last"][v][ok], a["last"][v][ok])
+
+
+def _one_tile_scene(n, opaque_front, seed=21):
+    """n small Gaussians inside one 16x16 tile (a 16x16 image, f = 16), each within 3 pixels of
+    the centre so that every one reaches only that tile, at distinct depths 2-8 m, faint (opacity
+    0.01) so that the walk reaches the back of the list; with opaque_front, 40 nearly opaque
+    ones lie at 2.0-2.1 m, so that most pixels terminate inside the first slice."""
+    rng = np.random.default_rng(seed)
+    f, W = 16.0, 16
+    z = rng.permutation(np.linspace(2.0, 8.0, n))
+    px = rng.uniform(5.0, 11.0, (2, n))
+    means = np.stack([(px[0] - W / 2) * z / f, (px[1] - W / 2) * z / f, z])
+    log_scales = np.log(np.full((3, n), 0.7) * z / f)
+    logit = np.full(n, np.log(0.01 / 0.99))
+    if opaque_front:
+        k = 40
+        z2 = np.linspace(2.0, 2.1, k)
+        p2 = rng.uniform(4.0, 12.0, (2, k))
+        means[:, :k] = np.stack([(p2[0] - W / 2) * z2 / f, (p2[1] - W / 2) * z2 / f, z2])
+        log_scales[:, :k] = np.log(np.full((3, k), 2.5) * z2 / f)
+        logit[:k] = 6.0
+    quats = np.zeros((4, n))
+    quats[0] = 1.0
+    sh = rng.standard_normal((3, n))
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    g = dict(means=f32(means), log_scales=f32(log_scales), quats=f32(quats), opacity_logits=f32(logit), sh=f32(sh),
+             sh_degree=0)
+    import synth
+    cam = synth.make_camera(np.eye(3), np.zeros(3), f, f, W / 2.0, W / 2.0, W, W)
+    return g, cam
+
+
+@pytest.mark.parametrize("opaque_front", [False, True])
+def test_slice_boundary_backward(opaque_front):
+    """A tile one instance above the split (8193: nine slices, the last holding one instance) runs
+    the L1 backward in the forward's slices (gsr_render_bwd_l1 given the sliced forward's
+    workspace): records equal the whole-tile backward's to float rounding and the forward the
+    oracle; with an opaque front most pixels terminate in the first slice, so the eight slices
+    behind it must leave zero records."""
+    import paper_2604_12942_amd as gsr
+    n = SPLIT_MIN + 1
+    g, cam = _one_tile_scene(n, opaque_front)
+    out, rast, P, ct = run_forward(g, [cam])
+    assert _lengths(rast)[0] == n, _lengths(rast)[0]
+    o = oracle.render(g, cam)
+    ok = o["margin"] >= KNIFE
+    assert img_close(out["rgb"][0], o["rgb"], mask=np.broadcast_to(ok, o["rgb"].shape)).sum() == 0
+    assert img_close(1 - out["T"][0], o["alpha"], mask=ok).sum() == 0
+    if opaque_front:
+        assert (out["last"][0] <= SLICE).mean() > 0.5
+    else:
+        assert (out["last"][0] > 8 * SLICE).sum() > 0  # pixels that reach the one-instance slice
+    rng = np.random.default_rng(3)
+    trgb = torch.from_numpy(rng.uniform(0, 1, (1, 3, 16, 16)).astype(np.float32)).cuda()
+    tdep = torch.from_numpy(rng.uniform(2, 8, (1, 16, 16)).astype(np.float32)).cuda()
+    ws = torch.empty((gsr.render_bwd_l1_workspace(1, rast.raster) + 255) // 256 * 64, dtype=torch.int32, device="cuda")
+    recs = {}
+    for sliced in (False, True):
+        rast.forward(P, g["sh_degree"], ct, sliced=sliced)
+        rast.dinst.fill_(-7)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gsr.render_bwd_l1(rast.splats, rast.inst_gid, rast.inst_emit, rast.tile_ranges, ct, 1, rast.raster, rast.rgb,
+                          rast.depth, rast.T_final, rast.last, trgb, tdep, 0.2, loss, rast.dinst, ws,
+                          tile_order=rast.tile_order, fwd_ws=rast.fwd_ws if sliced else None, capacity=rast.capacity)
+        torch.cuda.synchronize()
+        recs[sliced] = (rast.screen_grads().cpu().numpy().astype(np.float64).reshape(-1, 10), loss.item())
+    a, la = recs[False]
+    b, lb = recs[True]
+    assert abs(la - lb) <= 1e-6 * abs(la)
+    rms = np.sqrt(np.mean(a ** 2, axis=0))
+    assert np.all(np.abs(b - a) <= 1e-4 * (np.abs(a) + rms))
+    if opaque_front:
+        # Gaussians behind every pixel's last contributor get exactly zero
+        last_max = int(out["last"][0].max())
+        order = rast.inst_gid.cpu().numpy()[:n]
+        behind = order[last_max:]
+        assert behind.size > 0 and np.all(a[behind] == 0) and np.all(b[behind] == 0)
