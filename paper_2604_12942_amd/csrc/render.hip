@@ -410,100 +410,19 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     if (ncon) ncon[(int64_t)t.v * P + pix] = pw.nc;
 }
 
-// ---- wave64 inclusive scans over lane order ---------------------------------------------------
+// ---- inclusive scans over lane order, in groups of 32 or 16 lanes ----------------------------
 // In place, one DPP-sourced VALU op per step: row shifts by 1, 2, 4, 8 scan each 16-lane row,
-// then the row broadcasts of lanes 15 and 31 carry the row totals forward.  A lane whose source
-// lies outside its row (row_shr without bound_ctrl) or whose row is masked off (row_mask) is not
-// written and keeps its value, which is exactly the identity step of the scan.  Each step is
-// preceded by s_nop 1: two wait states between a VALU write of the register and its DPP read.
+// then (for groups of 32) the row broadcast of lane 15 carries row 0's total into row 1 and row
+// 2's into row 3.  A lane whose source lies outside its row (row_shr without bound_ctrl) or whose
+// row is masked off (row_mask) is not written and keeps its value, which is exactly the identity
+// step of the scan.  A VALU write of a register needs two wait states before a DPP read of it.
 // The whole wave must be active.
-__device__ __forceinline__ float wave_incl_prod(float v) {
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
-        : "+v"(v));
-    return v;
-}
-__device__ __forceinline__ float wave_incl_sum(float v) {
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
-        : "+v"(v));
-    return v;
-}
-
-// Two independent scans interleaved: each DPP op's source was written two instructions earlier
-// (the other scan's op and an s_nop 0), which covers the same two wait states.  ka and kb are
-// values the caller derived from the inputs and needs afterwards: naming them as operands makes
-// them ready before the scan, so the scanned registers need no saved copies.
-__device__ __forceinline__ void wave_incl_prod2(float &a, float &b, float ka, float kb) {
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
-        "v_mul_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
-        : "+v"(a), "+v"(b)
-        : "v"(ka), "v"(kb));
-}
-__device__ __forceinline__ void wave_incl_sum2(float &a, float &b, float ka, float kb) {
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "v_add_f32_dpp %1, %1, %1 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-        "v_add_f32_dpp %1, %1, %1 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-        "v_add_f32_dpp %1, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-        "v_add_f32_dpp %1, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-        "s_nop 0\n\t"
-        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
-        "v_add_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf"
-        : "+v"(a), "+v"(b)
-        : "v"(ka), "v"(kb));
-}
-// The same two scans over independent groups of 32 lanes (rows 0-1 and rows 2-3: the lane-15
-// broadcast is the last step) or of 16 lanes (each row on its own: the row shifts alone).
+// Two independent scans run interleaved: each DPP op's source was written two instructions
+// earlier (the other scan's op and an s_nop 0), which covers the same two wait states.  ka and
+// kb are values the caller derived from the inputs and needs afterwards: naming them as operands
+// makes them ready before the scan, so the scanned registers need no saved copies.
+// half_*: groups of 32 lanes (rows 0-1 and rows 2-3: the lane-15 broadcast is the last step);
+// row_*: groups of 16 lanes (each row on its own: the row shifts alone).
 __device__ __forceinline__ void half_incl_prod2(float &a, float &b, float ka, float kb) {
     asm volatile(
         "s_nop 1\n\t"
@@ -580,35 +499,17 @@ __device__ __forceinline__ void row_incl_sum2(float &a, float &b, float ka, floa
 }
 template <int GL>
 __device__ __forceinline__ void group_incl_prod2(float &a, float &b, float ka, float kb) {
-    if constexpr (GL == 64) wave_incl_prod2(a, b, ka, kb);
-    else if constexpr (GL == 32) half_incl_prod2(a, b, ka, kb);
+    static_assert(GL == 32 || GL == 16, "lane groups of 32 or 16");
+    if constexpr (GL == 32) half_incl_prod2(a, b, ka, kb);
     else row_incl_prod2(a, b, ka, kb);
 }
 template <int GL>
 __device__ __forceinline__ void group_incl_sum2(float &a, float &b, float ka, float kb) {
-    if constexpr (GL == 64) wave_incl_sum2(a, b, ka, kb);
-    else if constexpr (GL == 32) half_incl_sum2(a, b, ka, kb);
+    static_assert(GL == 32 || GL == 16, "lane groups of 32 or 16");
+    if constexpr (GL == 32) half_incl_sum2(a, b, ka, kb);
     else row_incl_sum2(a, b, ka, kb);
 }
-__device__ __forceinline__ float rdl(float v, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
 
-// Backward, Gaussian-major.  The tile's instances up to the deepest pixel's last contributor are
-// staged back to front in batches of 256.  Each wave compacts the batch to the Gaussians that
-// reach its pixel sub-rectangle and cuts them, deepest first, into chunks of 64: lane l holds the
-// l-th deepest.  For each of the wave's 64 pixels every lane evaluates its Gaussian; a wave-wide
-// inclusive product scan of 1 / (1 - a) recovers the transmittance in front of each Gaussian from
-// the pixel's transmittance behind the chunk, and an inclusive sum scan of w (dL/dC . c + dL/dD z)
-// gives what lies behind it.  Pixel state (upstream gradient, transmittance and suffix behind
-// the chunks done so far) sits in LDS and is read by broadcast; the pixel centre by readlane.
-// Per lane, the mean and conic gradients accumulate as the five moments sum dP (dx, dy, dx^2, dx dy, dy^2) of the
-// exponent gradient dP, mapped through the Cholesky factor once per chunk.  Gradients then
-// accumulate in LDS across waves (ds_add_f32 per staged slot) and leave as one plain 40-byte
-// record per instance, stored at the instance's emission index: the records of one (view,
-// Gaussian) pair are contiguous there, and the projection backward sums them in a fixed order,
-// so no global atomics are needed.  The four waves' adds to one slot come in a run-dependent
-// order, so gradients repeat from run to run only up to float rounding.
 // Shared memory of the backward of one tile (the staged splats keep the forward's null slot 256).
 struct BwdLds {
     float4 sA[257], sB[257], sC[257];
@@ -635,12 +536,14 @@ __device__ __forceinline__ float bg_suffix(const PixelGrad &pg, const gsr_camera
 // Backward of one (view, tile) work item, Gaussian-major.  The tile's instances up to the deepest
 // pixel's last contributor are staged back to front in batches of 256.  Each wave compacts the
 // batch to the Gaussians that reach its pixel sub-rectangle and cuts them, deepest first, into
-// chunks of 64: lane l holds the l-th deepest.  For each of the wave's 64 pixels every lane
-// evaluates its Gaussian; a wave-wide inclusive product scan of 1 / (1 - a) recovers the
-// transmittance in front of each Gaussian from the pixel's transmittance behind the chunk, and an
-// inclusive sum scan of w (dL/dC . c + dL/dD z) gives what lies behind it.  Pixel state (upstream
-// gradient, transmittance and suffix behind the chunks done so far) sits in LDS and is read by
-// broadcast; the pixel centre by readlane.  Per lane, the mean and conic gradients accumulate as
+// chunks of 32 (the last one of 16 when at most 16 remain): lane l holds the (l % 32)-th deepest,
+// and the two halves of the wave (four quarters for a chunk of 16) work on different pixels of
+// the same Gaussians.  For each of its pixels every lane evaluates its Gaussian; an inclusive
+// product scan of 1 / (1 - a) over the lane group recovers the transmittance in front of each
+// Gaussian from the pixel's transmittance behind the chunk, and an inclusive sum scan of
+// w (dL/dC . c + dL/dD z) gives what lies behind it.  Pixel state (upstream gradient,
+// transmittance and suffix behind the chunks done so far) sits in LDS and is read by broadcast.
+// Per lane, the mean and conic gradients accumulate as
 // the five moments sum dP (dx, dy, dx^2, dx dy, dy^2) of the exponent gradient dP, mapped through
 // the Cholesky factor once per chunk.  Gradients then accumulate in LDS across waves (ds_add_f32
 // per staged slot) and leave as one plain 40-byte record per instance, stored at the instance's
@@ -666,14 +569,11 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
     uint32_t &s_max = L.s_max;
     const int tile = item % T;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int px = tx * TW + lx, py = ty * TH + ly;
     const int bx = (tx * TW) & ~31, by = (ty * TH) & ~31;
     const double ox = (double)bx, oy = (double)by;
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     float wx0, wx1, wy0, wy1;
     wave_box<TW>(tx * TW - bx, ty * TH - by, w, wx0, wx1, wy0, wy1);
-    const float fx = (float)(px - bx) + 0.5f, fy = (float)(py - by) + 0.5f;  // pixel centre
     // centre of the wave's first pixel (the wave's 64 pixels are TW-wide rows)
     static_assert(TW % 8 == 0, "packed chunks assume 8 | TW");
     const float fxw = (float)(tx * TW - bx) + 0.5f, fyw = (float)(ty * TH - by + w * (64 / TW)) + 0.5f;
@@ -730,9 +630,11 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
         }
         __builtin_amdgcn_wave_barrier();  // the wave reads back what its lanes just wrote
         // One chunk of the compacted list, c0 onwards: lane l holds the chunk's (l % GL)-th
-        // deepest Gaussian for pixel group l / GL.  A full chunk runs as one group (GL = 64);
-        // when at most 32 or 16 Gaussians remain, 2 or 4 groups of lanes work on different
-        // pixels of the same Gaussians at once, and their sums meet before the LDS adds.
+        // deepest Gaussian for pixel group l / GL.  The 2 (GL = 32) or 4 (GL = 16) groups of
+        // lanes work on different pixels of the same Gaussians at once, and their sums meet
+        // before the LDS adds.  Chunks of 32 rather than one of 64 across the wave: the last,
+        // partial chunk of a wave's list leaves fewer lanes empty, and a 32-lane scan is one
+        // DPP step shorter.
         auto chunk = [&](auto glc, int c0) {
             constexpr int GL = decltype(glc)::value;
             constexpr int NG = 64 / GL;
@@ -754,36 +656,18 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
             // two pixels per group and iteration: their chains are independent, which keeps the
             // SIMD busy through the scan and transcendental latencies
             for (int p = 0; p < 64; p += 2 * NG) {
-                int q0 = p, q1 = p + 1;
-                uint32_t l0, l1;
-                float4 pg0, pg1;
-                float T0, S0, T1, S1, fx0, fy0, fx1;
-                if constexpr (NG == 1) {
-                    l0 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p);
-                    l1 = (uint32_t)__builtin_amdgcn_readlane((int)mylast, p + 1);
-                    if (cfront >= l0 && cfront >= l1) continue;
-                    pg0 = sPG[w][p];  // LDS broadcasts
-                    pg1 = sPG[w][p + 1];
-                    const float4 ps = *reinterpret_cast<const float4 *>(&sPS[w][p]);
-                    T0 = ps.x, S0 = ps.y, T1 = ps.z, S1 = ps.w;
-                    fx0 = rdl(fx, p), fy0 = rdl(fy, p), fx1 = rdl(fx, p + 1);
-                } else {
-                    q0 = p + grp;
-                    q1 = p + NG + grp;
-                    l0 = sPL[w][q0];
-                    l1 = sPL[w][q1];
-                    if (__ballot(cfront < l0 || cfront < l1) == 0) continue;
-                    pg0 = sPG[w][q0];
-                    pg1 = sPG[w][q1];
-                    const float2 s0 = sPS[w][q0], s1 = sPS[w][q1];
-                    T0 = s0.x, S0 = s0.y, T1 = s1.x, S1 = s1.y;
-                    // the wave's pixels lie row-major in a TW-wide box and 2 NG divides TW, so
-                    // q0 and q1 sit in the row of p, at columns p % TW + grp and + NG
-                    const float fxp = fxw + (float)(p % TW);
-                    fx0 = fxp + (float)grp;
-                    fx1 = fxp + (float)(NG + grp);
-                    fy0 = fyw + (float)(p / TW);
-                }
+                // this group's two pixels: the wave's pixels lie row-major in a TW-wide box and
+                // 2 NG divides TW, so q0 and q1 sit in the row of p, at columns p % TW + grp and
+                // + NG
+                const int q0 = p + grp, q1 = p + NG + grp;
+                const uint32_t l0 = sPL[w][q0], l1 = sPL[w][q1];
+                if (__ballot(cfront < l0 || cfront < l1) == 0) continue;
+                const float4 pg0 = sPG[w][q0], pg1 = sPG[w][q1];
+                const float2 s0 = sPS[w][q0], s1 = sPS[w][q1];
+                const float T0 = s0.x, S0 = s0.y, T1 = s1.x, S1 = s1.y;
+                const float fxp = fxw + (float)(p % TW);
+                const float fx0 = fxp + (float)grp, fx1 = fxp + (float)(NG + grp);
+                const float fy0 = fyw + (float)(p / TW);
                 // The two pixels share a row (p is even and 2 NG divides TW), so dy and the
                 // terms of the exponent that depend on dy alone are formed once.  Each operation
                 // is the one blend_exponent performs: the exponents, and so every contribute /
@@ -844,15 +728,11 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
                 // the pixels' state in front of this chunk, kept by each group's frontmost lane
                 // (inactive lanes carry a = 0)
                 if (gl == GL - 1) {
-                    if constexpr (NG == 1) {
-                        *reinterpret_cast<float4 *>(&sPS[w][p]) = make_float4(Tb0, S0 + in0, Tb1, S1 + in1);
-                    } else {
-                        sPS[w][q0] = make_float2(Tb0, S0 + in0);
-                        sPS[w][q1] = make_float2(Tb1, S1 + in1);
-                    }
+                    sPS[w][q0] = make_float2(Tb0, S0 + in0);
+                    sPS[w][q1] = make_float2(Tb1, S1 + in1);
                 }
             }
-            if constexpr (NG > 1) {
+            {
                 // the groups' sums for one Gaussian meet in the first group
                 float *const sums[10] = {&cr, &cg, &cb, &cd, &go, &mx, &my, &mxx, &mxy, &myy};
 #pragma unroll
@@ -883,11 +763,14 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
                     if (acc[e] != 0.f) atomicAdd(&sAcc[e][slot], acc[e]);
             }
         };
-        for (int c0 = 0; c0 < nw; c0 += 64) {
-            const int rem = nw - c0;
-            if (rem > 32) chunk(std::integral_constant<int, 64>{}, c0);
-            else if (rem > 16) chunk(std::integral_constant<int, 32>{}, c0);
-            else chunk(std::integral_constant<int, 16>{}, c0);
+        for (int c0 = 0; c0 < nw;) {
+            if (nw - c0 > 16) {
+                chunk(std::integral_constant<int, 32>{}, c0);
+                c0 += 32;
+            } else {
+                chunk(std::integral_constant<int, 16>{}, c0);
+                c0 += 16;
+            }
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
