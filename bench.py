@@ -75,6 +75,8 @@ def parse():
                     help="skip the leg with the support mask and the SSIM term in the loss")
     ap.add_argument("--points", type=int, default=1_500_000)
     ap.add_argument("--no-c2", action="store_true", help="skip the one-view 300k-Gaussian room leg")
+    ap.add_argument("--no-disc-map", action="store_true",
+                    help="skip the step on the flat-disc stand-in map (opacity 0.1)")
     ap.add_argument("--no-init-compare", action="store_true",
                     help="skip the learned vs voxel-PCA init comparison leg (iterations to a PSNR target)")
     ap.add_argument("--contrib-compare", action="store_true",
@@ -706,6 +708,38 @@ def render_modes_leg(make_opt, sv, tile, params, stages, stream, first_step, k=5
     return res
 
 
+def disc_map_leg(params, make_opt, tile, fit_capacity, measure, workload_stats, a):
+    """The same captured step (same views, same loss, same optimiser) on a simpler map of the same
+    corridor: one flat disc per LiDAR point, aligned with the surface (in-plane scale about 0.1 m,
+    normal scale 2 cm), opacity 0.1 everywhere, as generated (no optimiser iterations before the
+    timed steps).  Reports iterations/s, the stages, the workload and the render backward's rate
+    by the blend count."""
+    import torch
+    o = make_opt(tile, params=params)
+    del params
+    fit_capacity(o, 0, a.warmup)
+    k = max(3, min(a.steps, 10))
+    r = measure(o, a.warmup, k)
+    wl = workload_stats(o, r["last_step"])
+    bwd_ms = r["stage_ms"]["render_bwd"]
+    kname = "k_render_bwd_l1" if o.render == "two_pass" else "k_render_bwd"
+    ach = wl["blends"] * FLOP_PER_BLEND_BWD / (bwd_ms / 1000.0) / 1e12
+    out = dict(workload="loop corridor, %d flat-disc Gaussians SH3 at opacity 0.1 as generated, 8 views 1280x720 per "
+                        "step, the headline's step" % int(o.P["means"].shape[1]),
+               iters_per_s=round(1000.0 / r["ms_per_step"], 3), ms_per_step=round(r["ms_per_step"], 3),
+               stage_ms={kk: round(v, 4) for kk, v in r["stage_ms"].items()},
+               blends_per_step=wl["blends"], instances_per_step=wl["M"], visible_pairs_per_step=wl["Nv"],
+               render_bwd_roofline=dict(kernel=kname, bound="alu", stage_ms=round(bwd_ms, 4),
+                                        achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                        frac=round(ach / FP32_PEAK_TFLOPS, 4),
+                                        frac_of_nonpacked_peak=round(ach / FP32_PEAK_NONPACKED_TFLOPS, 4),
+                                        flop_per_unit=FLOP_PER_BLEND_BWD))
+    print("disc map: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    del o
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=5):
     """Device-to-device copy of 1 GiB: (read + write bytes) / time in GB/s, the measured ceiling the
     step's algorithmic bytes are also compared with."""
@@ -1005,7 +1039,7 @@ def main():
     blends, M, Nv, Nu = wl["blends"], wl["M"], wl["Nv"], wl["Nu"]
     g = {k: opt.P[k].cpu().numpy() for k in gsr.PARAM_NAMES}  # the map the CPU baseline renders
     g["sh_degree"] = 3
-    c = dict(c, gaussians=g)
+    c = dict(c, gaussians=g, disc_gaussians=c["gaussians"])
 
     # eager step time without events (for reference)
     eager_ms = 1000.0 * timed_steps(opt, max(3, min(a.steps, 10)), 0)
@@ -1053,6 +1087,10 @@ def main():
 
     loss_last = float(opt.loss.item())
     modes = render_modes_leg(make_opt, sv, tile, opt.P, stages, stream, s0)
+    disc = None
+    if not a.no_disc_map:
+        disc = disc_map_leg(gsr.gaussians_to_device(c["disc_gaussians"], dev), make_opt, tile, fit_capacity, measure,
+                            workload_stats, a)
     maint = loopr = initr = None
     if not a.no_maintenance:
         maint = maintenance_leg(g, seg, min_seg, dev)
@@ -1123,6 +1161,7 @@ def main():
         "init_path": initr,
         "c2": c2,
         "learned_vs_pca_init": ic,
+        "disc_map": disc,
     }
     print(json.dumps(out), flush=True)
 

@@ -306,8 +306,9 @@ GSR_API gsr_status gsr_render_step(const gsr_splat *splats, const uint32_t *inst
 
 /* Screen-space gradient per (view, Gaussian): dsplat [V*n][10] (OVERWRITTEN) = the sum, in
  * emission order, of the pair's instance records in dinst (from gsr_render_bwd); the pairs and
- * their first records come from em (gsr_bin_sort), their counts from tile_info row 0
- * (gsr_project); zero for pairs that were not rendered. */
+ * their first records come from em (gsr_bin_sort): a pair's records end where the next pair's
+ * begin, and the last pair's count is its tile count in tile_info row 0 (gsr_project); zero for
+ * pairs that were not rendered. */
 GSR_API gsr_status gsr_pair_grads(const float *dinst, const gsr_emission *em, const uint32_t *tile_info, int64_t n,
                                   int32_t n_views, float *dsplat, gsr_stream stream);
 

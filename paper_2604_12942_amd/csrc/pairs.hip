@@ -31,8 +31,10 @@ __global__ __launch_bounds__(256) void k_pair_grads(const float *__restrict__ di
         const uint32_t q = w0 + lane;
         const bool live = q < np;
         const uint32_t gid = live ? pair_gid[q] : 0u;
-        const uint32_t cnt = live ? ntiles[gid] : 0u;
         const uint32_t first = live ? pair_first[q] : 0u;
+        // a pair's records end where the next pair's begin (a coalesced read instead of a gather
+        // of the pair's tile count, which only the last pair needs)
+        const uint32_t cnt = !live ? 0u : q + 1 < np ? pair_first[q + 1] - first : ntiles[gid];
         const bool small = cnt <= kSmallPair;
         if (live && small) {
             const float2 *rec = reinterpret_cast<const float2 *>(dinst + (int64_t)first * GSR_SPLAT_GRAD_FLOATS);
