@@ -64,8 +64,8 @@ def traffic_of(kernel, tile):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", default="auto", help="auto | 16x16 | 8x32 | 32x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured step")
@@ -708,7 +708,7 @@ def render_modes_leg(make_opt, sv, tile, params, stages, stream, first_step, k=5
     return res
 
 
-def disc_map_leg(params, make_opt, tile, fit_capacity, measure, workload_stats, a):
+def disc_map_leg(params, make_opt, tile, fit_capacity, measure, sampled_workload, a):
     """The same captured step (same views, same loss, same optimiser) on a simpler map of the same
     corridor: one flat disc per LiDAR point, aligned with the surface (in-plane scale about 0.1 m,
     normal scale 2 cm), opacity 0.1 everywhere, as generated (no optimiser iterations before the
@@ -720,15 +720,17 @@ def disc_map_leg(params, make_opt, tile, fit_capacity, measure, workload_stats, 
     fit_capacity(o, 0, a.warmup)
     k = max(3, min(a.steps, 10))
     r = measure(o, a.warmup, k)
-    wl = workload_stats(o, r["last_step"])
-    bwd_ms = r["stage_ms"]["render_bwd"]
+    wl = sampled_workload(o, r)
+    # the timed steps' own render-backward times when that stage dominates, else the stage pass's
+    bwd_ms = wl["dom_ms"] if r["dom"] == "render_bwd" else r["stage_ms"]["render_bwd"]
     kname = "k_render_bwd_l1" if o.render == "two_pass" else "k_render_bwd"
     ach = wl["blends"] * FLOP_PER_BLEND_BWD / (bwd_ms / 1000.0) / 1e12
     out = dict(workload="loop corridor, %d flat-disc Gaussians SH3 at opacity 0.1 as generated, 8 views 1280x720 per "
                         "step, the headline's step" % int(o.P["means"].shape[1]),
                iters_per_s=round(1000.0 / r["ms_per_step"], 3), ms_per_step=round(r["ms_per_step"], 3),
                stage_ms={kk: round(v, 4) for kk, v in r["stage_ms"].items()},
-               blends_per_step=wl["blends"], instances_per_step=wl["M"], visible_pairs_per_step=wl["Nv"],
+               blends_per_step=int(round(wl["blends"])), instances_per_step=int(round(wl["M"])),
+               visible_pairs_per_step=int(round(wl["Nv"])),
                render_bwd_roofline=dict(kernel=kname, bound="alu", stage_ms=round(bwd_ms, 4),
                                         achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                                         frac=round(ach / FP32_PEAK_TFLOPS, 4),
@@ -931,13 +933,30 @@ def main():
             recs.append((e0, evs))
         return recs
 
+    def worst_views_instances(o):
+        """Instances of the heaviest step the view schedule can draw: each pool view's own count
+        (the 8 recent, then the 8 history keyframes, binned as one step each), the 4 largest of
+        each window summed."""
+        fns = dict(o._stage_fns(True))
+        T = o.raster.tiles
+        per = []
+        for half in range(2):
+            o.set_views(torch.arange(8 * half, 8 * half + 8, device=dev))
+            for name in ("gather", "project", "bin_sort"):
+                fns[name]()
+            rg = o.rast.tile_ranges.view(V, T, 2).to(torch.int64) & 0xFFFFFFFF
+            per.append(sorted((rg[:, :, 1] - rg[:, :, 0]).sum(dim=1).tolist()))
+        return sum(per[0][-4:]) + sum(per[1][-4:])
+
     def fit_capacity(o, first_step, k):
-        """k eager steps with capacity checks, then room for 1.3 x the largest instance count."""
+        """k eager steps with capacity checks, then room for 1.3 x the larger of their largest
+        instance count and the heaviest step the schedule can draw."""
         m_max = 0
         for s in range(k):
             sv(o, first_step + s)
             o.step(check_capacity=True)
             m_max = max(m_max, o.rast.instances())
+        m_max = max(m_max, worst_views_instances(o))
         if o.rast.capacity < int(m_max * 1.3):
             o.rast._alloc_instances(int(m_max * 1.3))
 
@@ -1002,13 +1021,16 @@ def main():
             print("instance capacity exceeded in the timed region", file=sys.stderr)
             sys.exit(3)
         per_step = [a_.elapsed_time(b_) for a_, b_ in zip(ev_step, ev_step[1:] + [e_end])]
-        dom_ms = sum(e_a.elapsed_time(e_b) for e_a, e_b in ev_dom) / k_timed
+        dom_per_step = [e_a.elapsed_time(e_b) for e_a, e_b in ev_dom]
         return dict(ms_per_step=1000.0 * wall / k_timed, per_step=per_step, stage_ms=stage_ms, dom=dom,
-                    dom_ms=dom_ms, last_step=first_step + len(recs) + k_timed - 1)
+                    dom_ms=sum(dom_per_step) / k_timed, dom_per_step=dom_per_step,
+                    first_timed=first_step + len(recs), last_step=first_step + len(recs) + k_timed - 1)
 
     def workload_stats(o, step):
-        """Blends, instances, visible pairs and updated rows of one step (same views)."""
+        """Blends, instances, visible pairs and updated rows (visible in a view and in one of the
+        unfrozen segments) of one step's views on the current map."""
         sv(o, step)
+        dict(o._stage_fns(False))["gather"]()  # the step's cameras
         r = o.rast
         ncon = torch.empty(V, H, W, dtype=torch.int32, device=dev)
         r.project(o.P, o.sh_degree, o.cams)
@@ -1016,16 +1038,32 @@ def main():
         gsr.render_fwd(r.splats, r.inst_gid, r.tile_ranges, o.cams, V, o.raster, r.rgb, r.depth, r.T_final, r.last,
                        ncon, tile_order=r.tile_order)
         torch.cuda.synchronize()
-        ti = r.tile_info.view(4, -1)
-        return dict(blends=int(ncon.sum().item()), M=r.instances(), Nv=int((ti[0] > 0).sum().item()),
-                    Nu=int(o.row_mask.sum().item()))
+        vis = r.tile_info.view(4, V, -1)[0] > 0
+        upd = vis.any(dim=0)
+        if o.segment_id is not None:
+            upd &= o.segment_id >= o.min_segment
+        return dict(blends=int(ncon.sum().item()), M=r.instances(), Nv=int(vis.sum().item()),
+                    Nu=int(upd.sum().item()))
+
+    def sampled_workload(o, r, n_sample=10):
+        """The workload of up to n_sample of the timed steps, evenly spaced: the means of their
+        blends, instances, visible pairs and updated rows, with the mean of the same steps'
+        dominant-stage times.  Each step's views are rendered again after the timed run, so the map
+        is the one the run ended with: it moved on by at most that many optimiser iterations."""
+        k = len(r["dom_per_step"])
+        idx = sorted(set(int(round(x)) for x in np.linspace(0, k - 1, min(n_sample, k))))
+        ws = [workload_stats(o, r["first_timed"] + s) for s in idx]
+        out = {key: float(np.mean([w[key] for w in ws])) for key in ("blends", "M", "Nv", "Nu")}
+        out["dom_ms"] = float(np.mean([r["dom_per_step"][s] for s in idx]))
+        out["steps"] = len(idx)
+        return out
 
     opt = make_opt(tile)
     fit_capacity(opt, 0, a.warmup)
     # the map as initialised: a shorter timed run
     k_init = max(3, min(a.steps, 10))
     at_init = measure(opt, a.warmup, k_init)
-    wl_init = workload_stats(opt, at_init["last_step"])
+    wl_init = sampled_workload(opt, at_init)
     # steady state: STEADY_ITERS optimiser iterations from the initialisation, then the timed run
     s0 = at_init["last_step"] + 1
     for s in range(STEADY_ITERS):
@@ -1034,9 +1072,10 @@ def main():
     s0 += STEADY_ITERS
     fit_capacity(opt, s0, 3)
     res = measure(opt, s0 + 3, a.steps, profiled=True)
-    wl = workload_stats(opt, res["last_step"])
-    stage_ms, dom, dom_ms, ms_per_step = res["stage_ms"], res["dom"], res["dom_ms"], res["ms_per_step"]
-    blends, M, Nv, Nu = wl["blends"], wl["M"], wl["Nv"], wl["Nu"]
+    wl = sampled_workload(opt, res)
+    # the roofline pairs the sampled steps' dominant-stage times with their own workload
+    stage_ms, dom, dom_ms, ms_per_step = res["stage_ms"], res["dom"], wl["dom_ms"], res["ms_per_step"]
+    blends, M, Nv, Nu = (int(round(wl[k])) for k in ("blends", "M", "Nv", "Nu"))
     g = {k: opt.P[k].cpu().numpy() for k in gsr.PARAM_NAMES}  # the map the CPU baseline renders
     g["sh_degree"] = 3
     c = dict(c, gaussians=g, disc_gaussians=c["gaussians"])
@@ -1070,19 +1109,20 @@ def main():
                     frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
                     frac_of_nonpacked_peak=round(ach / FP32_PEAK_NONPACKED_TFLOPS, 4),
                     kernel=kname, launch_ms=round(dom_ms, 4), units_per_launch=blends, unit_kind="blend",
-                    flop_per_unit=fpb)
+                    flop_per_unit=fpb, sampled_steps=wl["steps"], launch_ms_all_steps=round(res["dom_ms"], 4))
     else:
         ach = B[dom] / (dom_ms / 1000.0) / 1e9
         roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_of(kname, "%dx%d" % tile),
-                    kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom])
+                    kernel=kname, launch_ms=round(dom_ms, 4), alg_bytes_per_launch=B[dom], sampled_steps=wl["steps"],
+                    launch_ms_all_steps=round(res["dom_ms"], 4))
     pct = np.percentile(np.asarray(res["per_step"]), [10, 50, 90])
     init_pct = np.percentile(np.asarray(at_init["per_step"]), [10, 50, 90])
     at_init_out = dict(iters_per_s=round(1000.0 / at_init["ms_per_step"], 3),
                        ms_per_step=round(at_init["ms_per_step"], 3),
                        step_ms_p10_p50_p90=[round(float(x), 4) for x in init_pct],
                        stage_ms={k: round(v, 4) for k, v in at_init["stage_ms"].items()},
-                       blends_per_step=wl_init["blends"], instances_per_step=wl_init["M"],
+                       blends_per_step=int(round(wl_init["blends"])), instances_per_step=int(round(wl_init["M"])),
                        blends_per_s=round(wl_init["blends"] / (at_init["ms_per_step"] / 1000.0), 1))
 
     loss_last = float(opt.loss.item())
@@ -1090,7 +1130,7 @@ def main():
     disc = None
     if not a.no_disc_map:
         disc = disc_map_leg(gsr.gaussians_to_device(c["disc_gaussians"], dev), make_opt, tile, fit_capacity, measure,
-                            workload_stats, a)
+                            sampled_workload, a)
     maint = loopr = initr = None
     if not a.no_maintenance:
         maint = maintenance_leg(g, seg, min_seg, dev)
