@@ -653,33 +653,25 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
             float cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, go = 0.f;
             float mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f;
             const float kz = nln2 * B.z;
-            // two pixels per group and iteration: their chains are independent, which keeps the
-            // SIMD busy through the scan and transcendental latencies
-            for (int p = 0; p < 64; p += 2 * NG) {
-                // this group's two pixels: the wave's pixels lie row-major in a TW-wide box and
-                // 2 NG divides TW, so q0 and q1 sit in the row of p, at columns p % TW + grp and
-                // + NG
-                const int q0 = p + grp, q1 = p + NG + grp;
+            // One iteration: this group's pixels q0 and q1 of one row, their offsets dx0, dx1 from
+            // the mean and the row's dy terms.  Returns false when no Gaussian of the chunk reaches
+            // either pixel; else g0, g1 = 2^-P dL/da of the lane's Gaussian at the two pixels (zero
+            // where it does not blend or the clamp holds alpha), with the colour and depth sums and
+            // the pixels' state updated.
+            auto pixel_pair = [&](int q0, int q1, float dx0, float dx1, float l21dy, float u22, float &g0,
+                                  float &g1) -> bool {
                 const uint32_t l0 = sPL[w][q0], l1 = sPL[w][q1];
-                if (__ballot(cfront < l0 || cfront < l1) == 0) continue;
+                if (__ballot(cfront < l0 || cfront < l1) == 0) return false;
                 const float4 pg0 = sPG[w][q0], pg1 = sPG[w][q1];
                 const float2 s0 = sPS[w][q0], s1 = sPS[w][q1];
                 const float T0 = s0.x, S0 = s0.y, T1 = s1.x, S1 = s1.y;
-                const float fxp = fxw + (float)(p % TW);
-                const float fx0 = fxp + (float)grp, fx1 = fxp + (float)(NG + grp);
-                const float fy0 = fyw + (float)(p / TW);
-                // The two pixels share a row (p is even and 2 NG divides TW), so dy and the
-                // terms of the exponent that depend on dy alone are formed once.  Each operation
-                // is the one blend_exponent performs: the exponents, and so every contribute /
-                // skip decision, are bit-identical to the forward's.
-                const float dy = fy0 - A.y;
-                const float l21dy = A.w * dy, u2 = B.x * dy, u22 = u2 * u2;
-                const float dx0 = fx0 - A.x, dx1 = fx1 - A.x;
+                // Each operation is the one blend_exponent performs: the exponents, and so every
+                // contribute / skip decision, are bit-identical to the forward's.
                 const float u10 = __builtin_fmaf(A.z, dx0, l21dy), u11 = __builtin_fmaf(A.z, dx1, l21dy);
                 const float P0 = __builtin_fmaf(u10, u10, u22), P1 = __builtin_fmaf(u11, u11, u22);
                 const bool act0 = posv < l0 && P0 <= B.y;
                 const bool act1 = posv < l1 && P1 <= B.y;
-                if (__ballot(act0 || act1) == 0) continue;  // no Gaussian of the chunk reaches them
+                if (__ballot(act0 || act1) == 0) return false;  // no Gaussian of the chunk reaches them
                 const float e0 = act0 ? __builtin_amdgcn_exp2f(-P0) : 0.f;
                 const float e1 = act1 ? __builtin_amdgcn_exp2f(-P1) : 0.f;
                 const float ar0 = B.z * e0, ar1 = B.z * e1;
@@ -715,21 +707,88 @@ __device__ __forceinline__ void tile_backward(const gsr_splat *__restrict__ spla
                 // unclamped alpha = o 2^-P: dL/do = 2^-P dL/da, dL/dP = -ln2 o (2^-P dL/da)
                 // (zero where the clamp holds alpha)
                 const bool lin0 = act0 && ar0 <= GSR_ALPHA_MAX, lin1 = act1 && ar1 <= GSR_ALPHA_MAX;
-                const float g0 = (lin0 ? e0 : 0.f) * d0, g1 = (lin1 ? e1 : 0.f) * d1;
-                go += g0 + g1;
-                const float dP0 = kz * g0, dP1 = kz * g1;
-                mx = __builtin_fmaf(dP0, dx0, __builtin_fmaf(dP1, dx1, mx));
-                const float sP = dP0 + dP1;
-                my = __builtin_fmaf(sP, dy, my);
-                const float qq0 = dP0 * dx0, qq1 = dP1 * dx1;
-                mxx = __builtin_fmaf(qq0, dx0, __builtin_fmaf(qq1, dx1, mxx));
-                mxy = __builtin_fmaf(qq0 + qq1, dy, mxy);
-                myy = __builtin_fmaf(sP * dy, dy, myy);
+                g0 = (lin0 ? e0 : 0.f) * d0;
+                g1 = (lin1 ? e1 : 0.f) * d1;
                 // the pixels' state in front of this chunk, kept by each group's frontmost lane
                 // (inactive lanes carry a = 0)
                 if (gl == GL - 1) {
                     sPS[w][q0] = make_float2(Tb0, S0 + in0);
                     sPS[w][q1] = make_float2(Tb1, S1 + in1);
+                }
+                return true;
+            };
+            // The wave's pixels lie row-major in a TW-wide box.  Each iteration takes two pixels
+            // per group, NG apart in one row: group grp covers the columns grp + NG k of every
+            // row.  Their chains are independent, which keeps the SIMD busy through the scan and
+            // transcendental latencies.
+            if constexpr (TW / NG <= 4) {
+                // Few columns per lane: their offsets dx from the mean are formed once per chunk,
+                // the dy terms once per row, and the exponent-gradient moments accumulate per
+                // column (sum of g) and per row (sums of g and g dx), with kappa_z = -ln2 o
+                // applied once at the end.
+                constexpr int HPR = TW / (2 * NG), NCOL = 2 * HPR;
+                float dxc[NCOL], Gc[NCOL];
+                const float fxg = fxw + (float)grp;  // exact: pixel centres are small half-integers
+#pragma unroll
+                for (int k = 0; k < NCOL; k++) {
+                    dxc[k] = (fxg + (float)(NG * k)) - A.x;
+                    Gc[k] = 0.f;
+                }
+                float fyr = fyw;
+                for (int r = 0; r < 64 / TW; r++, fyr += 1.0f) {
+                    const float dy = fyr - A.y;
+                    const float l21dy = A.w * dy, u2 = B.x * dy, u22 = u2 * u2;
+                    float rs = 0.f, rx = 0.f;
+#pragma unroll
+                    for (int h = 0; h < HPR; h++) {
+                        const int q0 = r * TW + 2 * NG * h + grp;
+                        float g0, g1;
+                        if (!pixel_pair(q0, q0 + NG, dxc[2 * h], dxc[2 * h + 1], l21dy, u22, g0, g1)) continue;
+                        Gc[2 * h] += g0;
+                        Gc[2 * h + 1] += g1;
+                        rs += g0 + g1;
+                        rx = __builtin_fmaf(g0, dxc[2 * h], __builtin_fmaf(g1, dxc[2 * h + 1], rx));
+                    }
+                    my = __builtin_fmaf(rs, dy, my);
+                    myy = __builtin_fmaf(rs * dy, dy, myy);
+                    mxy = __builtin_fmaf(rx, dy, mxy);
+                }
+#pragma unroll
+                for (int k = 0; k < NCOL; k++) {
+                    go += Gc[k];
+                    const float t = Gc[k] * dxc[k];
+                    mx += t;
+                    mxx = __builtin_fmaf(t, dxc[k], mxx);
+                }
+                mx *= kz;
+                my *= kz;
+                mxx *= kz;
+                mxy *= kz;
+                myy *= kz;
+            } else {
+                for (int p = 0; p < 64; p += 2 * NG) {
+                    // this group's two pixels: 2 NG divides TW, so q0 and q1 sit in the row of p,
+                    // at columns p % TW + grp and + NG
+                    const int q0 = p + grp, q1 = p + NG + grp;
+                    const float fxp = fxw + (float)(p % TW);
+                    const float fx0 = fxp + (float)grp, fx1 = fxp + (float)(NG + grp);
+                    const float fy0 = fyw + (float)(p / TW);
+                    // the two pixels share a row, so dy and the terms of the exponent that depend
+                    // on dy alone are formed once
+                    const float dy = fy0 - A.y;
+                    const float l21dy = A.w * dy, u2 = B.x * dy, u22 = u2 * u2;
+                    const float dx0 = fx0 - A.x, dx1 = fx1 - A.x;
+                    float g0, g1;
+                    if (!pixel_pair(q0, q1, dx0, dx1, l21dy, u22, g0, g1)) continue;
+                    go += g0 + g1;
+                    const float dP0 = kz * g0, dP1 = kz * g1;
+                    mx = __builtin_fmaf(dP0, dx0, __builtin_fmaf(dP1, dx1, mx));
+                    const float sP = dP0 + dP1;
+                    my = __builtin_fmaf(sP, dy, my);
+                    const float qq0 = dP0 * dx0, qq1 = dP1 * dx1;
+                    mxx = __builtin_fmaf(qq0, dx0, __builtin_fmaf(qq1, dx1, mxx));
+                    mxy = __builtin_fmaf(qq0 + qq1, dy, mxy);
+                    myy = __builtin_fmaf(sP * dy, dy, myy);
                 }
             }
             {
