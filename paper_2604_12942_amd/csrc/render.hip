@@ -136,9 +136,14 @@ __device__ __forceinline__ PixelWalk walk_start(const TileGeom &t, float T0) {
 // paired with the null slot).  A wave stops at the first step after which all its pixels have
 // finished, the workgroup at the first batch none of its pixels needs.  Block-uniform arguments;
 // the null slot must have been written before the call.
-// STORE: the second pass of the stored-contributor mode; each pixel writes the tile-list positions
-// of its composited Gaussians, front to back, at clist[cbase ...] (skipped beyond ccap).
-template <bool STORE>
+// What a walk keeps besides the transmittance and the termination, from least to most: nothing
+// (the depth slices' transmittance products), the colour, depth and last contributor (an image),
+// also the number of contributors, or also (the second pass of the stored-contributor mode) the
+// tile-list positions of the composited Gaussians, front to back, at clist[cbase ...] (skipped
+// beyond ccap).
+enum WalkKeeps : int { kKeepTrans = 0, kKeepImage = 1, kKeepCount = 2, kKeepStore = 3 };
+
+template <int KEEP>
 __device__ __forceinline__ void composite(const gsr_splat *__restrict__ splats, const uint32_t *__restrict__ inst,
                                           uint32_t start, uint32_t lo, uint32_t hi, const TileGeom &t,
                                           float4 *sA, float4 *sB, float4 *sC, PixelWalk &pw,
@@ -168,16 +173,20 @@ __device__ __forceinline__ void composite(const gsr_splat *__restrict__ splats, 
             const bool term = Tn < GSR_T_MIN;
             pw.fxl = term ? kGone : pw.fxl;
             const float a = term ? 0.0f : a0;
-            const float wgt = a * pw.Tr;
-            pw.c0 = __builtin_fmaf(wgt, C.x, pw.c0);
-            pw.c1 = __builtin_fmaf(wgt, C.y, pw.c1);
-            pw.c2 = __builtin_fmaf(wgt, C.z, pw.c2);
-            pw.dd = __builtin_fmaf(wgt, B.w, pw.dd);
+            if constexpr (KEEP >= kKeepImage) {
+                const float wgt = a * pw.Tr;
+                pw.c0 = __builtin_fmaf(wgt, C.x, pw.c0);
+                pw.c1 = __builtin_fmaf(wgt, C.y, pw.c1);
+                pw.c2 = __builtin_fmaf(wgt, C.z, pw.c2);
+                pw.dd = __builtin_fmaf(wgt, B.w, pw.dd);
+            }
             pw.Tr = term ? pw.Tr : Tn;
-            const bool used = a > 0.0f;
-            if (STORE && used && cbase + pw.nc < ccap) clist[cbase + pw.nc] = pos0 - 1 + (uint32_t)j;
-            pw.lst = used ? pos0 + (uint32_t)j : pw.lst;
-            pw.nc += used ? 1u : 0u;
+            if constexpr (KEEP >= kKeepImage) {
+                const bool used = a > 0.0f;
+                if (KEEP == kKeepStore && used && cbase + pw.nc < ccap) clist[cbase + pw.nc] = pos0 - 1 + (uint32_t)j;
+                pw.lst = used ? pos0 + (uint32_t)j : pw.lst;
+                if constexpr (KEEP >= kKeepCount) pw.nc += used ? 1u : 0u;
+            }
         };
         for (int g = 0; g < 4 && g * 64 < cnt; g++) {
             if (__ballot(pw.fxl != kGone) == 0) break;
@@ -279,7 +288,7 @@ __global__ __launch_bounds__(256) void k_slice_prod(const gsr_splat *__restrict_
         const uint32_t start = ranges[2 * si.x], end = ranges[2 * si.x + 1];
         const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
         PixelWalk pw = walk_start(t, 1.0f);
-        composite<false>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
+        composite<kKeepTrans>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
         sl.tprod[(size_t)j * 256 + threadIdx.x] = (t.inside && pw.fxl == kGone) ? 0.0f : pw.Tr;
     }
 }
@@ -357,8 +366,9 @@ __global__ __launch_bounds__(256) void k_slice_merge(const uint32_t *__restrict_
 
 // One 256-lane workgroup per (view, tile) in `order` (longest list first), one pixel per lane.
 // With slices (sl.grid > 0) the first sl.grid workgroups composite the slices of the long tiles
-// (pass 2), and the long tiles' own workgroups return at once.
-template <int TW, int TH, bool STORE>
+// (pass 2), and the long tiles' own workgroups return at once.  COUNT: the contributor counts are
+// written to ncon (no slices then).
+template <int TW, int TH, bool STORE, bool COUNT = false>
 __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict__ splats,
                                                     const uint32_t *__restrict__ inst,
                                                     const uint32_t *__restrict__ ranges,
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
             const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
             const float Tin = slice_T_in(sl, j, si.y);
             PixelWalk pw = walk_start(t, Tin);
-            composite<false>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
+            composite<kKeepImage>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
             const bool term = t.inside && Tin >= GSR_T_MIN && pw.fxl == kGone;
             sl.part[(size_t)j * 256 + threadIdx.x] = make_float4(pw.c0, pw.c1, pw.c2, pw.dd);
             sl.part2[(size_t)j * 256 + threadIdx.x] = make_uint2(__float_as_uint(term ? -pw.Tr : pw.Tr), pw.lst);
@@ -396,7 +406,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     uint32_t cbase = 0;
     if (STORE && t.inside) cbase = coff[(int64_t)t.v * W * H + (int64_t)t.py * W + t.px];
     PixelWalk pw = walk_start(t, 1.0f);
-    composite<STORE>(splats, inst, start, start, end, t, sA, sB, sC, pw, clist, cbase, ccap);
+    constexpr int KEEP = STORE ? kKeepStore : COUNT ? kKeepCount : kKeepImage;
+    composite<KEEP>(splats, inst, start, start, end, t, sA, sB, sC, pw, clist, cbase, ccap);
     if (!t.inside || STORE) return;
     const gsr_camera &cam = cams[t.v];
     const int64_t P = (int64_t)W * H;
@@ -407,7 +418,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const gsr_splat *__restrict_
     depth[(int64_t)t.v * P + pix] = pw.dd;
     Tfin[(int64_t)t.v * P + pix] = pw.Tr;
     last[(int64_t)t.v * P + pix] = pw.lst;
-    if (ncon) ncon[(int64_t)t.v * P + pix] = pw.nc;
+    if (COUNT) ncon[(int64_t)t.v * P + pix] = pw.nc;
 }
 
 // ---- inclusive scans over lane order, in groups of 32 or 16 lanes ----------------------------
@@ -1023,7 +1034,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
             const float Tin = slice_T_in(sl, it, si.y);
             PixelWalk pw = walk_start(t, Tin);
-            composite<false>(splats, inst, start, lo, hi, t, L.sA, L.sB, L.sC, pw, nullptr, 0u, 0u);
+            composite<kKeepImage>(splats, inst, start, lo, hi, t, L.sA, L.sB, L.sC, pw, nullptr, 0u, 0u);
             const bool term = t.inside && Tin >= GSR_T_MIN && pw.fxl == kGone;
             sl.part[(size_t)it * 256 + threadIdx.x] = make_float4(pw.c0, pw.c1, pw.c2, pw.dd);
             sl.part2[(size_t)it * 256 + threadIdx.x] = make_uint2(__float_as_uint(term ? -pw.Tr : pw.Tr), pw.lst);
@@ -1067,7 +1078,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             start = ranges[2 * item];
             end = ranges[2 * item + 1];
             PixelWalk pw = walk_start(t, 1.0f);
-            composite<false>(splats, inst, start, start, end, t, L.sA, L.sB, L.sC, pw, nullptr, 0u, 0u);
+            composite<kKeepImage>(splats, inst, start, start, end, t, L.sA, L.sB, L.sC, pw, nullptr, 0u, 0u);
             finish_pixels(t, item, cams[t.v], W, H, pw.Tr, pw.c0, pw.c1, pw.c2, pw.dd, pw.lst, rgb, depth, Tfin, last,
                           a, pg, s_red);
         }
@@ -1345,9 +1356,14 @@ extern "C" gsr_status gsr_render_fwd_launch(const gsr_splat *splats, const uint3
     do {                                                                                                          \
         if (sl.grid)                                                                                              \
             k_slice_prod<TW, TH><<<sl.grid, 256, 0, st>>>(splats, inst, ranges, r->width, r->height, ntx, T, sl); \
-        k_render_fwd<TW, TH, false><<<nb + sl.grid, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width,     \
-                                                                  r->height, ntx, T, rgb, depth, Tfin, last, ncon, \
-                                                                  nullptr, nullptr, 0u, sl);                       \
+        if (ncon)                                                                                                 \
+            k_render_fwd<TW, TH, false, true><<<nb + sl.grid, 256, 0, st>>>(                                      \
+                splats, inst, ranges, order, cams, r->width, r->height, ntx, T, rgb, depth, Tfin, last, ncon,     \
+                nullptr, nullptr, 0u, sl);                                                                        \
+        else                                                                                                      \
+            k_render_fwd<TW, TH, false><<<nb + sl.grid, 256, 0, st>>>(splats, inst, ranges, order, cams, r->width, \
+                                                                      r->height, ntx, T, rgb, depth, Tfin, last,  \
+                                                                      nullptr, nullptr, nullptr, 0u, sl);         \
         if (sl.grid)                                                                                              \
             k_slice_merge<TW, TH><<<sl.grid, 256, 0, st>>>(ranges, cams, r->width, r->height, ntx, T, sl, rgb,    \
                                                            depth, Tfin, last);                                    \
