@@ -10,13 +10,24 @@ __global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
         dst[i] = 0.f;
 }
 
-// Per-pair screen-space gradient: the fixed-order sum of the pair's instance records.  Each
-// wave takes 64 consecutive visible pairs in emission order.  A pair of at most kSmallPair
-// records is summed by its own lane, four records in flight; the wave's larger pairs (near
-// Gaussians cover hundreds of tiles) are then summed one after the other by the whole wave, each
-// lane striding over the records and a lane tree adding the 64 partial sums.  Either way the
-// order of the additions is fixed by the data, so the result repeats exactly.
+// Per-pair screen-space gradient: the fixed-order sum of the pair's instance records.
+// Small pairs (at most kSmallPair records): each wave takes 64 consecutive visible pairs in
+// emission order, and each lane sums its own pair's records in order, four records in flight.
+// Large pairs (near Gaussians cover hundreds of tiles, and depth order puts them first): each is
+// summed by one whole wave, each lane striding over the records and a lane tree adding the 64
+// partial sums.  The large pairs are dealt out across the grid: lane l of wave w looks at pair
+// w + l W (W waves in the grid), so the large pairs at the front of the list go to different waves
+// rather than queueing in the first ones.  Either way the order of the additions is fixed by the
+// data, so the result repeats exactly.
 constexpr uint32_t kSmallPair = 32;
+
+__device__ __forceinline__ uint32_t pair_count(const uint32_t *__restrict__ pair_gid,
+                                               const uint32_t *__restrict__ pair_first,
+                                               const uint32_t *__restrict__ ntiles, uint32_t q, uint32_t np,
+                                               uint32_t first) {
+    // a pair's records end where the next pair's begin (the last pair: its tile count)
+    return q + 1 < np ? pair_first[q + 1] - first : ntiles[pair_gid[q]];
+}
 
 __global__ __launch_bounds__(256) void k_pair_grads(const float *__restrict__ dinst,
                                                     const uint32_t *__restrict__ pair_gid,
@@ -25,56 +36,61 @@ __global__ __launch_bounds__(256) void k_pair_grads(const float *__restrict__ di
                                                     const uint32_t *__restrict__ ntiles, float *__restrict__ dsplat) {
     const uint32_t np = *n_pairs;
     const int lane = __lane_id();
-    const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u;
-    const uint32_t wstride = gridDim.x * blockDim.x;
-    for (uint32_t w0 = wave0; w0 < np; w0 += wstride) {
+    const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    // small pairs, one per lane
+    for (uint32_t w0 = gw * 64; w0 < np; w0 += nwaves * 64) {
         const uint32_t q = w0 + lane;
-        const bool live = q < np;
-        const uint32_t gid = live ? pair_gid[q] : 0u;
-        const uint32_t first = live ? pair_first[q] : 0u;
-        // a pair's records end where the next pair's begin (a coalesced read instead of a gather
-        // of the pair's tile count, which only the last pair needs)
-        const uint32_t cnt = !live ? 0u : q + 1 < np ? pair_first[q + 1] - first : ntiles[gid];
-        const bool small = cnt <= kSmallPair;
-        if (live && small) {
-            const float2 *rec = reinterpret_cast<const float2 *>(dinst + (int64_t)first * GSR_SPLAT_GRAD_FLOATS);
-            float acc[GSR_SPLAT_GRAD_FLOATS];
+        if (q >= np) continue;
+        const uint32_t first = pair_first[q];
+        const uint32_t cnt = pair_count(pair_gid, pair_first, ntiles, q, np, first);
+        if (cnt > kSmallPair) continue;
+        const uint32_t gid = pair_gid[q];
+        const float2 *rec = reinterpret_cast<const float2 *>(dinst + (int64_t)first * GSR_SPLAT_GRAD_FLOATS);
+        float acc[GSR_SPLAT_GRAD_FLOATS];
 #pragma unroll
-            for (int e = 0; e < GSR_SPLAT_GRAD_FLOATS; e++) acc[e] = 0.f;
-            uint32_t j = 0;
-            for (; j + 4 <= cnt; j += 4) {
-                float2 x[4][5];
+        for (int e = 0; e < GSR_SPLAT_GRAD_FLOATS; e++) acc[e] = 0.f;
+        uint32_t j = 0;
+        for (; j + 4 <= cnt; j += 4) {
+            float2 x[4][5];
 #pragma unroll
-                for (int u = 0; u < 4; u++)
+            for (int u = 0; u < 4; u++)
 #pragma unroll
-                    for (int e = 0; e < 5; e++) x[u][e] = rec[(j + u) * 5 + e];
+                for (int e = 0; e < 5; e++) x[u][e] = rec[(j + u) * 5 + e];
 #pragma unroll
-                for (int u = 0; u < 4; u++)
-#pragma unroll
-                    for (int e = 0; e < 5; e++) {
-                        acc[2 * e] += x[u][e].x;
-                        acc[2 * e + 1] += x[u][e].y;
-                    }
-            }
-            for (; j < cnt; j++)
+            for (int u = 0; u < 4; u++)
 #pragma unroll
                 for (int e = 0; e < 5; e++) {
-                    const float2 x = rec[j * 5 + e];
-                    acc[2 * e] += x.x;
-                    acc[2 * e + 1] += x.y;
+                    acc[2 * e] += x[u][e].x;
+                    acc[2 * e + 1] += x[u][e].y;
                 }
-            float2 *out = reinterpret_cast<float2 *>(dsplat + (int64_t)gid * GSR_SPLAT_GRAD_FLOATS);
-#pragma unroll
-            for (int e = 0; e < 5; e++) out[e] = make_float2(acc[2 * e], acc[2 * e + 1]);
         }
-        // the wave's large pairs, one at a time
-        uint64_t big = __ballot(live && !small);
+        for (; j < cnt; j++)
+#pragma unroll
+            for (int e = 0; e < 5; e++) {
+                const float2 x = rec[j * 5 + e];
+                acc[2 * e] += x.x;
+                acc[2 * e + 1] += x.y;
+            }
+        float2 *out = reinterpret_cast<float2 *>(dsplat + (int64_t)gid * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+        for (int e = 0; e < 5; e++) out[e] = make_float2(acc[2 * e], acc[2 * e + 1]);
+    }
+    // large pairs, one per wave, dealt out across the grid
+    for (uint32_t k0 = 0; (uint64_t)k0 * nwaves + gw < np; k0 += 64) {
+        const uint64_t qq = (uint64_t)(k0 + lane) * nwaves + gw;
+        const bool live = qq < np;
+        const uint32_t q = live ? (uint32_t)qq : 0u;
+        const uint32_t first = live ? pair_first[q] : 0u;
+        const uint32_t cnt = live ? pair_count(pair_gid, pair_first, ntiles, q, np, first) : 0u;
+        uint64_t big = __ballot(live && cnt > kSmallPair);
         while (big) {
             const int src = __builtin_ctzll(big);
             big &= big - 1;
+            const uint32_t bq = (uint32_t)__builtin_amdgcn_readlane((int)q, src);
             const uint32_t bf = (uint32_t)__builtin_amdgcn_readlane((int)first, src);
             const uint32_t bc = (uint32_t)__builtin_amdgcn_readlane((int)cnt, src);
-            const uint32_t bg = (uint32_t)__builtin_amdgcn_readlane((int)gid, src);
+            const uint32_t bg = pair_gid[bq];
             float acc[GSR_SPLAT_GRAD_FLOATS];
 #pragma unroll
             for (int e = 0; e < GSR_SPLAT_GRAD_FLOATS; e++) acc[e] = 0.f;
