@@ -73,24 +73,37 @@ __device__ __forceinline__ void sh_colour_unrolled(float x, float y, float z, co
     }
 }
 
-// backward of the colour: gh[k][ch] += gcol[ch] Y_k, gdir += (sum_ch gcol[ch] h_k,ch) grad Y_k
+// backward of the colour: gh[k][ch] += gcol[ch] Y_k, gdir += (sum_ch gcol[ch] h_k,ch) grad Y_k.
+// Software-pipelined: the next term's three coefficients are loaded while the current term is
+// worked, so the walk does not wait out one memory round trip per term.
 template <int K>
 __device__ __forceinline__ void sh_colour_bwd(float x, float y, float z, const float *__restrict__ sh, int64_t n,
                                               int64_t i, const float gcol[3], float *gh, int stride, float gdir[3]) {
+    float h0 = sh[i], h1 = sh[n + i], h2 = sh[2 * n + i];
 #pragma unroll 1
     for (int k = 0; k < K; k++) {
+        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+        if (k + 1 < K) {
+            n0 = sh[(3 * k + 3) * n + i];
+            n1 = sh[(3 * k + 4) * n + i];
+            n2 = sh[(3 * k + 5) * n + i];
+        }
         float gx, gy, gz;
         const float Yk = sh_term(k, x, y, z, gx, gy, gz);
+        const float hk[3] = {h0, h1, h2};
         float sk = 0.f;
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
             float &acc = gh[(3 * k + ch) * stride];
             acc = __builtin_fmaf(gcol[ch], Yk, acc);
-            sk = __builtin_fmaf(gcol[ch], sh[(3 * k + ch) * n + i], sk);
+            sk = __builtin_fmaf(gcol[ch], hk[ch], sk);
         }
         gdir[0] = __builtin_fmaf(sk, gx, gdir[0]);
         gdir[1] = __builtin_fmaf(sk, gy, gdir[1]);
         gdir[2] = __builtin_fmaf(sk, gz, gdir[2]);
+        h0 = n0;
+        h1 = n1;
+        h2 = n2;
     }
 }
 
@@ -375,11 +388,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
     }
     const bool live = t < cnt;
     const int64_t i = live ? (vlist ? (int64_t)vlist[t] : t) : 0;
-    bool anyvis = live;
-    if (live) {
-        anyvis = false;
-        for (int vi = 0; vi < V; vi++) anyvis |= tile_info[(int64_t)vi * n + i] > 0;
-    }
+    // the views that rendered this Gaussian (bit vi; at most 32 views are tracked this way, the
+    // rest are read where they are needed)
+    uint32_t vmask = 0;
+    bool anyvis = false;
+    if (live)
+        for (int vi = 0; vi < V; vi++) {
+            const bool vis = tile_info[(int64_t)vi * n + i] > 0;
+            anyvis |= vis;
+            if (vi < 32) vmask |= (vis ? 1u : 0u) << vi;
+        }
     float *gh = &s_gh[0][threadIdx.x];
 #pragma unroll
     for (int e = 0; e < 3 * K; e++) gh[e * 256] = 0.f;
@@ -403,7 +421,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
         bool any = false;
         if (anyvis) {
             // only rendered pairs hold gradients (summed per pair beforehand)
-            const bool vis = tile_info[(int64_t)vi * n + i] > 0;
+            const bool vis = vi < 32 ? ((vmask >> vi) & 1u) != 0 : tile_info[(int64_t)vi * n + i] > 0;
             visible |= vis;
 #pragma unroll
             for (int e = 0; e < 10; e++) gs[e] = 0.f;
