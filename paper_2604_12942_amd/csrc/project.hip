@@ -13,8 +13,9 @@ namespace gsr {
 // Real spherical harmonics without Condon-Shortley phase, orthonormal, ordered (l, m = -l..l),
 // as polynomials of the unit direction (x, y, z).
 // Term k in float, with its polynomial gradient.  k is wave-uniform and the callers loop over it
-// without unrolling, so one term (three coefficients) is live at a time: unrolling the basis
-// would keep every coefficient load in flight and cap occupancy.
+// without unrolling, so one term's three coefficients (two terms' in the pipelined backward) are
+// live at a time: unrolling the basis would keep every coefficient load in flight and cap
+// occupancy.
 __device__ __forceinline__ float sh_term(int k, float x, float y, float z, float &gx, float &gy, float &gz) {
     constexpr float a = 0.4886025119029199f;
     constexpr float b = 1.0925484305920792f, c = 0.31539156525252005f, d = 0.5462742152960396f;
