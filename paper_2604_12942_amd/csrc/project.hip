@@ -60,7 +60,9 @@ __device__ __forceinline__ void sh_colour(float x, float y, float z, const float
     }
 }
 
-// the same sum fully unrolled (the forward projection has registers to spare for it)
+// the same sum fully unrolled: the forward projection keeps every coefficient load in flight.
+// That costs registers (two waves per SIMD at degree 3), but a pipelined loop at four waves per
+// SIMD was measured 25 % slower: the stage streams parameters, and loads in flight matter more.
 template <int K, int k = 0>
 __device__ __forceinline__ void sh_colour_unrolled(float x, float y, float z, const float *__restrict__ sh, int64_t n,
                                                    int64_t i, float pre[3]) {
@@ -215,22 +217,27 @@ __device__ __forceinline__ bool view_geom(const double mu[3], const Sym3 &Sig, c
     return true;
 }
 
-__device__ __forceinline__ void load_quat(const gsr_gaussians &g, int64_t i, double qn[4], double &qnorm) {
-    const int64_t n = g.n;
+// unit quaternion and the norm of the stored one
+__device__ __forceinline__ void unit_quat(const float qf[4], double qn[4], double &qnorm) {
     double q[4];
-    for (int a = 0; a < 4; a++) q[a] = g.quats[a * n + i];
+    for (int a = 0; a < 4; a++) q[a] = qf[a];
     qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     for (int a = 0; a < 4; a++) qn[a] = q[a] / qnorm;
 }
 
-// Sigma = Rq S S^T Rq^T
-__device__ __forceinline__ Sym3 gaussian_sigma(const gsr_gaussians &g, int64_t i) {
+__device__ __forceinline__ void load_rotation_scale(const gsr_gaussians &g, int64_t i, float qf[4], float lsf[3]) {
     const int64_t n = g.n;
+    for (int a = 0; a < 4; a++) qf[a] = g.quats[a * n + i];
+    for (int a = 0; a < 3; a++) lsf[a] = g.log_scales[a * n + i];
+}
+
+// Sigma = Rq S S^T Rq^T from the stored quaternion and log-scales
+__device__ __forceinline__ Sym3 sigma_of(const float qf[4], const float lsf[3]) {
     double qn[4], qnorm, Rq[3][3], s2[3];
-    load_quat(g, i, qn, qnorm);
+    unit_quat(qf, qn, qnorm);
     quat_rot(qn[0], qn[1], qn[2], qn[3], Rq);
     for (int a = 0; a < 3; a++) {
-        const double sa = exp((double)g.log_scales[a * n + i]);
+        const double sa = exp((double)lsf[a]);
         s2[a] = sa * sa;
     }
     Sym3 S;
@@ -241,6 +248,12 @@ __device__ __forceinline__ Sym3 gaussian_sigma(const gsr_gaussians &g, int64_t i
     S.yz = Rq[1][0] * Rq[2][0] * s2[0] + Rq[1][1] * Rq[2][1] * s2[1] + Rq[1][2] * Rq[2][2] * s2[2];
     S.zz = Rq[2][0] * Rq[2][0] * s2[0] + Rq[2][1] * Rq[2][1] * s2[1] + Rq[2][2] * Rq[2][2] * s2[2];
     return S;
+}
+
+__device__ __forceinline__ Sym3 gaussian_sigma(const gsr_gaussians &g, int64_t i) {
+    float qf[4], lsf[3];
+    load_rotation_scale(g, i, qf, lsf);
+    return sigma_of(qf, lsf);
 }
 
 template <int DEG>
@@ -405,9 +418,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
     double mu[3] = {0, 0, 0};
     Sym3 Sig{1, 0, 0, 1, 0, 1};
     double o = 0;
+    // the stored rotation and scales, kept for the chain rule after the view loop
+    float qf[4] = {1.f, 0.f, 0.f, 0.f}, lsf[3] = {0.f, 0.f, 0.f};
     if (anyvis) {
         for (int a = 0; a < 3; a++) mu[a] = g.means[a * n + i];
-        Sig = gaussian_sigma(g, i);
+        load_rotation_scale(g, i, qf, lsf);
+        Sig = sigma_of(qf, lsf);
         o = 1.0 / (1.0 + exp(-(double)g.opacity_logits[i]));
     }
     Sym3 gSig{0, 0, 0, 0, 0, 0};
@@ -419,6 +435,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
         __asm__ __volatile__("" ::: "memory");
         double pose[6] = {0, 0, 0, 0, 0, 0};
         float gs[10];
+        float4 rgbz = make_float4(0.f, 0.f, 0.f, 0.f);
         bool any = false;
         if (anyvis) {
             // only rendered pairs hold gradients (summed per pair beforehand)
@@ -428,6 +445,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
             for (int e = 0; e < 10; e++) gs[e] = 0.f;
             if (vis) {
                 const float2 *s2 = reinterpret_cast<const float2 *>(dsplat + ((int64_t)vi * n + i) * GSR_SPLAT_GRAD_FLOATS);
+                // the splat's clamped colour, loaded with the gradients (one round trip per view)
+                rgbz = *(reinterpret_cast<const float4 *>(splats + (int64_t)vi * n + i) + 2);
 #pragma unroll
                 for (int e = 0; e < 5; e++) {
                     const float2 q = s2[e];
@@ -512,7 +531,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
             // colour: clamp at zero, SH coefficients, viewing direction.  The forward stored
             // max(0, pre-clamp colour) in the splat, so a zero channel is exactly a clamped one.
             const float dxf = (float)G.dir[0], dyf = (float)G.dir[1], dzf = (float)G.dir[2];
-            const float4 rgbz = *(reinterpret_cast<const float4 *>(splats + (int64_t)vi * n + i) + 2);
             float gcol[3], gdirf[3] = {0.f, 0.f, 0.f};
             gcol[0] = rgbz.y > 0.f ? gs[6] : 0.f;
             gcol[1] = rgbz.z > 0.f ? gs[7] : 0.f;
@@ -545,9 +563,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(gsr_gaussians g, const gsr_
     if (!anyvis || !(touched || (FUSED && visible && unfrozen))) return;
     // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 dL/dSigma M
     double qn[4], qnorm, Rq[3][3], sc[3];
-    load_quat(g, i, qn, qnorm);
+    unit_quat(qf, qn, qnorm);
     quat_rot(qn[0], qn[1], qn[2], qn[3], Rq);
-    for (int a = 0; a < 3; a++) sc[a] = exp((double)g.log_scales[a * n + i]);
+    for (int a = 0; a < 3; a++) sc[a] = exp((double)lsf[a]);
     double gRq[3][3];
     float gls[3];
     for (int c = 0; c < 3; c++) {
