@@ -139,8 +139,11 @@ GSR_API gsr_status gsr_project(const gsr_gaussians *g, const gsr_camera *cams, i
  * still receives M: the caller compares it with capacity after synchronising, grows the buffers
  * and runs gsr_project and gsr_bin_sort again (a captured step is captured again).
  * tile_order (device uint32 [V*T], may be NULL) receives the view-tiles sorted by descending
- * instance count (ties by index): the longest-processing-time-first launch order the render
- * kernels use to keep heavy tiles off the tail of the grid.
+ * instance count resolved to 1/16 of an octave (counts c with the same floor(log2 c) and the same
+ * four bits below the leading one tie; empty tiles tie with single-instance ones, and counts of
+ * 2^16 and more with the top step below 2^16; ties by index): the
+ * longest-processing-time-first launch order the render kernels use to keep heavy tiles off the
+ * tail of the grid.
  * em (may be NULL; needed by the backward) receives the emission bookkeeping, see gsr_emission.
  * ws: device workspace of at least gsr_bin_sort_workspace(n, n_views, capacity, r) bytes,
  * 256-byte aligned.  Errors: GSR_E_INVALID (bad pointers or sizes, capacity >= 2^32),

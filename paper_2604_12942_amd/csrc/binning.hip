@@ -400,12 +400,23 @@ __global__ __launch_bounds__(256) void k_inst_emit(const uint32_t *__restrict__ 
     }
 }
 
-// LPT key of every view-tile: descending instance count (ascending 0xffff - count), ties by index
+// LPT key of every view-tile, one byte: the instance count as a small float (the exponent
+// floor(log2 c) times 16 plus the next four bits below the leading one, so the key grows with the
+// count and resolves it to 1/16 of an octave; empty tiles share the key of a single instance,
+// counts of 2^16 and more the key of the top step below 2^16), stored as 255 minus that so that an
+// ascending stable sort puts the longest tiles first, ties by index.
+__device__ __forceinline__ uint32_t lpt_key(uint32_t c) {
+    if (c == 0) return 255u;
+    const uint32_t e = 31u - (uint32_t)__builtin_clz(c);  // 0 .. 31
+    if (e >= 16u) return 0u;
+    const uint32_t m = e >= 4u ? (c >> (e - 4u)) & 15u : (c << (4u - e)) & 15u;
+    return 255u - (e * 16u + m);
+}
+
 __global__ void k_tile_keys(const uint32_t *__restrict__ ranges, uint32_t VT, uint32_t *__restrict__ keys,
                             uint32_t *__restrict__ vals) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < VT; i += gridDim.x * blockDim.x) {
-        const uint32_t c = ranges[2 * i + 1] - ranges[2 * i];
-        keys[i] = 0xffffu - (c < 0xffffu ? c : 0xffffu);
+        keys[i] = lpt_key(ranges[2 * i + 1] - ranges[2 * i]);
         vals[i] = i;
     }
 }
@@ -555,12 +566,13 @@ extern "C" gsr_status gsr_bin_sort_launch(uint32_t *info, int64_t n, int V, int 
     k_tile_ranges<<<nr, 256, 0, st>>>(ek, n_inst, (uint32_t)cap, ranges);
     k_overflow_clear<<<256, 256, 0, st>>>(n_inst, (uint32_t)cap, info, (uint32_t)VN, ranges, (uint32_t)(2 * VT),
                                           em ? em->n_pairs : nullptr);
-    // 6. longest-processing-time order of the view-tiles (descending instance count)
+    // 6. longest-processing-time order of the view-tiles (descending instance count, to 1/16 of
+    // an octave): one 8-bit pass, whose values land in tile_order
     if (tile_order) {
         const int nt = (int)(ceil_div(VT, 256) < 4096 ? ceil_div(VT, 256) : 4096);
-        k_tile_keys<<<nt, 256, 0, st>>>(ranges, (uint32_t)VT, w.tk0, tile_order);
-        uint32_t *a = w.tk0, *b = tile_order, *c = w.tk1, *d = w.tv1;
-        s = radix_sort(a, b, c, d, nullptr, (uint32_t)VT, (uint32_t)VT, 16, w.hist, w.totals, st);
+        k_tile_keys<<<nt, 256, 0, st>>>(ranges, (uint32_t)VT, w.tk0, w.tv1);
+        uint32_t *a = w.tk0, *b = w.tv1, *c = w.tk1, *d = tile_order;
+        s = radix_sort(a, b, c, d, nullptr, (uint32_t)VT, (uint32_t)VT, 8, w.hist, w.totals, st);
         if (s != GSR_OK) return s;
     }
     return last_launch();

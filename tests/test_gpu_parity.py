@@ -120,6 +120,24 @@ def test_binning_order_bit_exact(name, tile):
         if idx.size:
             exp[t] = (idx[0], idx[-1] + 1)
     assert np.array_equal(rng, exp)
+    # launch order: a permutation of the view-tiles, by descending count to 1/16 of an octave
+    # (the count read as a float with a 4-bit mantissa), ties by index
+    order = rast.tile_order.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(T))
+    cnt = exp[:, 1] - exp[:, 0]
+    assert np.array_equal(order, np.lexsort((np.arange(T), -_count_octave16(cnt)))), "tile order"
+
+
+def _count_octave16(c):
+    """16 floor(log2 c) plus the four bits below the leading one (an empty tile shares 0 with a
+    single instance; counts of 2^16 and more share 255, the value of the top step below 2^16): the
+    resolution of the longest-first launch order."""
+    out = np.zeros(c.shape, np.int64)
+    for i, x in enumerate(c.tolist()):
+        if x > 0:
+            e = x.bit_length() - 1
+            out[i] = 255 if e >= 16 else 16 * e + (((x << 4) >> e) & 15)
+    return out
 
 
 def test_binning_multi_view_and_capacity_regrow():
