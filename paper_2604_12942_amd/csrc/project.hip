@@ -687,21 +687,37 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ v, 
 }
 
 // dpose[v][e] = sum over waves of the partial sums
-// One workgroup per (view, component): the sum of the per-wave partials of the waves that ran
-// (all nw waves, or those covering the first *vcount entries of the visible list), in a fixed
-// order, so this reduction adds no run-dependent rounding of its own.
-__global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ part, int64_t nw,
-                                                     const uint32_t *__restrict__ vcount,
-                                                     double *__restrict__ dpose) {
-    __shared__ double s_w[4];
+// One workgroup of 1024 threads per (view, component): the sum of the per-wave partials of the
+// waves that ran (all nw waves, or those covering the first *vcount entries of the visible list).
+// Each thread keeps four running sums over the partials w = t, t + 1024, t + 2048, t + 3072 (mod
+// 4096) so that four loads are in flight, and the sums meet in a fixed order (pairs, then a wave
+// tree, then the 16 waves in order), so this reduction adds no run-dependent rounding of its own.
+constexpr int kPoseThreads = 1024;
+__global__ __launch_bounds__(kPoseThreads) void k_pose_reduce(const double *__restrict__ part, int64_t nw,
+                                                              const uint32_t *__restrict__ vcount,
+                                                              double *__restrict__ dpose) {
+    __shared__ double s_w[kPoseThreads / 64];
     const int64_t live = vcount ? 4 * ceil_div((int64_t)*vcount, 256) : nw;
     const double *p = part + (int64_t)blockIdx.x * nw;
-    double acc = 0;
-    for (int64_t w = threadIdx.x; w < live; w += 256) acc += p[w];
-    acc = wave_sum_d(acc);
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int64_t w = threadIdx.x;
+    for (; w + 3 * kPoseThreads < live; w += 4 * kPoseThreads) {
+        a0 += p[w];
+        a1 += p[w + kPoseThreads];
+        a2 += p[w + 2 * kPoseThreads];
+        a3 += p[w + 3 * kPoseThreads];
+    }
+    if (w < live) a0 += p[w];
+    if (w + kPoseThreads < live) a1 += p[w + kPoseThreads];
+    if (w + 2 * kPoseThreads < live) a2 += p[w + 2 * kPoseThreads];
+    double acc = wave_sum_d((a0 + a1) + (a2 + a3));
     if (__lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) dpose[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int k = 0; k < kPoseThreads / 64; k++) t += s_w[k];
+        dpose[blockIdx.x] = t;
+    }
 }
 
 }  // namespace gsr
@@ -749,7 +765,7 @@ extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_c
     if (nb == 0) {
         if (dpose) {
             // no Gaussians: zero pose gradient
-            k_pose_reduce<<<V * 6, 256, 0, st>>>(static_cast<double *>(ws), 0, nullptr, dpose);
+            k_pose_reduce<<<V * 6, kPoseThreads, 0, st>>>(static_cast<double *>(ws), 0, nullptr, dpose);
         }
         return last_launch();
     }
@@ -786,7 +802,7 @@ extern "C" gsr_status gsr_project_bwd_launch(const gsr_gaussians *g, const gsr_c
     }
 #undef GSR_PBD
 #undef GSR_PB
-    if (dpose) k_pose_reduce<<<V * 6, 256, 0, st>>>(part, 4 * (int64_t)nb, vlist ? vcount : nullptr, dpose);
+    if (dpose) k_pose_reduce<<<V * 6, kPoseThreads, 0, st>>>(part, 4 * (int64_t)nb, vlist ? vcount : nullptr, dpose);
     return last_launch();
 }
 
