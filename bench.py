@@ -27,7 +27,8 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-# without packed FP32 (not generated in this build): 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+# without packed FP32 (the library is compiled without packed FP32 instructions):
+# 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_PEAK_NONPACKED_TFLOPS = 78.6
 # algorithmic float operations per composited (pixel, Gaussian) pair, plus one exp each (not
 # counted): forward 20, backward 45 (the fused step does both)
@@ -846,7 +847,7 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
         return
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     t_gen = time.perf_counter()

@@ -43,7 +43,7 @@ typedef enum {
     GSR_E_INVALID = 1,     /* bad argument, nothing launched */
     GSR_E_CAPACITY = 2,    /* a caller-provided workspace is too small */
     GSR_E_HIP = 3,         /* a HIP launch or runtime call failed */
-    GSR_E_UNSUPPORTED = 4  /* configuration this build does not handle */
+    GSR_E_UNSUPPORTED = 4  /* configuration the library does not handle */
 } gsr_status;
 
 typedef void *gsr_stream; /* a hipStream_t (NULL = the null stream) */
