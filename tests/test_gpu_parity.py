@@ -211,12 +211,16 @@ def _pose_close(got, exp):
     return np.all(np.abs(got - exp) <= GRAD_RTOL * (np.abs(exp) + np.sqrt(np.mean(exp ** 2))))
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 32), (32, 8)])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_render_backward_matches_oracle(name):
+def test_render_backward_matches_oracle(name, tile):
+    """Every tile shape: the backward's pixel loop takes a different form for 8 columns per tile
+    (offsets per column and sums per row) than for 16 and 32, and a chunk of 16 Gaussians another
+    than a chunk of 32."""
     import paper_2604_12942_amd as gsr
     g, cams = SCENES[name]
     cam = cams[0]
-    out, rast, P, ct = run_forward(g, cams)
+    out, rast, P, ct = run_forward(g, cams, tile=tile)
     GC, GD = _upstream(g, cam, 5)
     o = oracle.render_bwd(g, cam, GC.astype(np.float64), GD.astype(np.float64))
     assert _no_live_knife(o, GC, GD)
