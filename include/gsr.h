@@ -404,6 +404,21 @@ typedef struct {
 GSR_API gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, const uint8_t *row_mask, float beta1,
                          float beta2, float eps, int32_t step, gsr_stream stream);
 
+/* ---- per-step preparation of the batched optimiser (Sec. III-C: each iteration draws its views
+ * from the recent and history keyframe windows; sparse Adam) --------------------------------------
+ * One launch for the bookkeeping at the start of an optimisation step:
+ * cams [n_views] (device, OVERWRITTEN) = pool[view_idx[v]] (pool: device gsr_camera [n_pool];
+ * view_idx: device int64 [n_views], each in [0, n_pool); a record whose index lies outside is
+ * left unchanged); view_idx32 [n_views] (device int32, may be NULL) = view_idx, the slot indices
+ * the loss kernels read targets with; *loss (device float64, may be NULL) = 0; *step (device
+ * int32, may be NULL) += 1, the step number gsr_project_bwd_adam reads; row_mask [n] (device
+ * uint8, 16-byte aligned, may be NULL) = 0.
+ * Errors: GSR_E_INVALID (a NULL pool, view_idx or cams, n_pool < 1, n_views < 1, n < 0, or an
+ * unaligned row_mask). */
+GSR_API gsr_status gsr_step_prep(const gsr_camera *pool, int32_t n_pool, const int64_t *view_idx, int32_t n_views,
+                                 gsr_camera *cams, int32_t *view_idx32, double *loss, int32_t *step,
+                                 uint8_t *row_mask, int64_t n, gsr_stream stream);
+
 /* ---- L1 loss ---------------------------------------------------------------------------------
  * Eq. 9, 10, 12 with lambda_rgb = 1, lambda_ssim = 0 and the all-ones mask, per view v:
  * L_v = (1/P) sum_x sum_ch |C - C~| + lambda_depth (1/P) sum_x |D - D~|, P = W H; the loss is

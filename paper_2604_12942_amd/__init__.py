@@ -264,6 +264,20 @@ def project_bwd_adam(P, sh_degree, cams, n_views, raster, splats, dinst, em, til
           "gsr_project_bwd_adam")
 
 
+def step_prep(cam_pool, view_idx, cams, view_idx32=None, loss=None, step=None, row_mask=None):
+    """gsr_step_prep: cams (uint8 [V*96]) = the pool's records (uint8 [S*96]) at view_idx (int64
+    [V]); view_idx32 = view_idx as int32; loss = 0; step += 1; row_mask = 0 (each optional)."""
+    V = view_idx.numel()
+    if cams.numel() != V * _abi.CAMERA_BYTES or cam_pool.numel() % _abi.CAMERA_BYTES:
+        raise GsrError("camera records are %d bytes" % _abi.CAMERA_BYTES)
+    if view_idx.dtype != torch.int64 or (view_idx32 is not None and view_idx32.dtype != torch.int32):
+        raise GsrError("view_idx int64, view_idx32 int32")
+    n = row_mask.numel() if row_mask is not None else 0
+    check(lib().gsr_step_prep(_ptr(cam_pool), cam_pool.numel() // _abi.CAMERA_BYTES, _ptr(view_idx), V, _ptr(cams),
+                              _ptr(view_idx32), _ptr(loss), _ptr(step), _ptr(row_mask), n, _stream()),
+          "gsr_step_prep")
+
+
 def adam_step(groups, rows, row_mask, beta1=0.9, beta2=0.999, eps=1e-15, step=1):
     """groups: list of (param, grad, m, v, lr) float32 [cols, rows] device tensors."""
     G = _abi.AdamGroups()

@@ -64,6 +64,7 @@ class Params(C.Structure):
 
 
 assert C.sizeof(Camera) == 96
+CAMERA_BYTES = C.sizeof(Camera)
 assert C.sizeof(Gaussians) == 56
 
 SPLAT_BYTES = 48
@@ -105,6 +106,7 @@ _SIGS = {
     "gsr_visible_list_noalloc_max": ([], C.c_int64),
     "gsr_visible_list_noalloc": ([P, C.c_int64, C.c_int32, P, P, P], C.c_int),
     "gsr_adam_step": ([C.POINTER(AdamGroups), C.c_int64, P, C.c_float, C.c_float, C.c_float, C.c_int32, P], C.c_int),
+    "gsr_step_prep": ([P, C.c_int32, P, C.c_int32, P, P, P, P, P, C.c_int64, P], C.c_int),
     "gsr_loss_l1": ([P, P, P, P, P, C.c_int32, C.POINTER(Raster), C.c_float, P, P, P, P], C.c_int),
     "gsr_fill_u32": ([P, C.c_uint32, C.c_int64, P], C.c_int),
     "gsr_support_mask": ([P, C.c_int32, C.POINTER(Raster), C.c_float, C.c_int32, P, P, P], C.c_int),

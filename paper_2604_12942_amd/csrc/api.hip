@@ -380,6 +380,18 @@ extern "C" gsr_status gsr_visible_list(const uint32_t *tile_info, int64_t n, int
     return gsr_visible_list_launch(tile_info, n, n_views, list, count, ws, S(stream));
 }
 
+extern "C" gsr_status gsr_step_prep_launch(const gsr_camera *, int32_t, const int64_t *, int32_t, gsr_camera *,
+                                           int32_t *, double *, int32_t *, uint8_t *, int64_t, hipStream_t);
+
+extern "C" gsr_status gsr_step_prep(const gsr_camera *pool, int32_t n_pool, const int64_t *view_idx, int32_t n_views,
+                                    gsr_camera *cams, int32_t *view_idx32, double *loss, int32_t *step,
+                                    uint8_t *row_mask, int64_t n, gsr_stream stream) {
+    if (!pool || n_pool < 1 || !view_idx || n_views < 1 || !cams || n < 0) return GSR_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(row_mask) & 15u) return GSR_E_INVALID;  // cleared 16 bytes per store
+    return gsr_step_prep_launch(pool, n_pool, view_idx, n_views, cams, view_idx32, loss, step, row_mask, n,
+                                S(stream));
+}
+
 extern "C" gsr_status gsr_adam_step(const gsr_adam_groups *groups, int64_t rows, const uint8_t *row_mask, float beta1,
                                     float beta2, float eps, int32_t step, gsr_stream stream) {
     if (!groups || groups->n_groups < 1 || groups->n_groups > GSR_MAX_GROUPS || rows < 0 || step < 1)

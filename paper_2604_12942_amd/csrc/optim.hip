@@ -61,9 +61,52 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ rgb, 
     if (threadIdx.x == 0) atomicAdd(loss, (s_red[0] + s_red[1] + s_red[2] + s_red[3]) / (double)P);
 }
 
+// Per-step preparation of the batched optimiser in one launch: the step's camera records
+// gathered from the pool (96-byte records as 24 words), the view indices as int32, the loss sum
+// cleared, the Adam step number advanced and the row mask cleared (16 bytes per store where the
+// whole 16 lie inside).
+__global__ void k_step_prep(const uint32_t *__restrict__ pool, int32_t n_pool, const int64_t *__restrict__ view_idx,
+                            int32_t V, uint32_t *__restrict__ cams, int32_t *__restrict__ view_idx32,
+                            double *__restrict__ loss, int32_t *__restrict__ step, uint8_t *__restrict__ row_mask,
+                            int64_t n) {
+    constexpr int kWords = (int)(sizeof(gsr_camera) / 4);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = tid; k < (int64_t)V * kWords; k += stride) {
+        const int64_t v = k / kWords, w = k - v * kWords;
+        const int64_t s = view_idx[v];
+        if (s >= 0 && s < n_pool) cams[k] = pool[s * kWords + w];
+    }
+    if (view_idx32)
+        for (int64_t v = tid; v < V; v += stride) view_idx32[v] = (int32_t)view_idx[v];
+    if (tid == 0) {
+        if (loss) *loss = 0.0;
+        if (step) *step += 1;
+    }
+    if (row_mask) {
+        const int64_t n16 = n / 16;
+        uint4 *m16 = reinterpret_cast<uint4 *>(row_mask);
+        for (int64_t i = tid; i < n16; i += stride) m16[i] = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t i = n16 * 16 + tid; i < n; i += stride) row_mask[i] = 0;
+    }
+}
+
 }  // namespace gsr
 
 using namespace gsr;
+
+extern "C" gsr_status gsr_step_prep_launch(const gsr_camera *pool, int32_t n_pool, const int64_t *view_idx, int32_t V,
+                                           gsr_camera *cams, int32_t *view_idx32, double *loss, int32_t *step,
+                                           uint8_t *row_mask, int64_t n, hipStream_t st) {
+    static_assert(sizeof(gsr_camera) % 4 == 0, "camera records are whole words");
+    const int64_t cam_words = (int64_t)V * (int64_t)(sizeof(gsr_camera) / 4);
+    const int64_t mask_work = row_mask ? n / 16 : 0;
+    const int64_t work = mask_work > cam_words ? mask_work : cam_words;
+    const int nb = (int)(ceil_div(work, 256) < 1024 ? ceil_div(work, 256) : 1024);
+    k_step_prep<<<nb, 256, 0, st>>>(reinterpret_cast<const uint32_t *>(pool), n_pool, view_idx, V,
+                                    reinterpret_cast<uint32_t *>(cams), view_idx32, loss, step, row_mask, n);
+    return last_launch();
+}
 
 extern "C" gsr_status gsr_adam_launch(const gsr_adam_groups *g, int64_t rows, const uint8_t *mask, float b1, float b2,
                                       float eps, int step, hipStream_t st) {

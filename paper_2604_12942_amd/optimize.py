@@ -156,15 +156,17 @@ class MapOptimizer:
         """The step as an ordered list of (name, fn): every fn only enqueues device work (no host
         synchronisation when check_capacity is False), so any run of stages can be captured."""
         from . import (project, render_bwd, render_bwd_l1, render_bwd_l1_workspace, render_fwd, render_step,
-                       project_bwd, project_bwd_adam, visible_list)
+                       project_bwd, project_bwd_adam, step_prep, visible_list)
         r = self.rast
         if self.render == "two_pass" and self.bwd_ws is None:
             self.bwd_ws = torch.empty((render_bwd_l1_workspace(self.V, self.raster) + 255) // 256 * 64,
                                       dtype=torch.int32, device=self.loss.device)
 
         def gather():
-            torch.index_select(self.cam_pool, 0, self.view_idx, out=self.cams.view(-1, 96))
-            self.view_idx32.copy_(self.view_idx)
+            # the step's cameras and target slots, the loss sum cleared and, for the fused Adam,
+            # its step number advanced and the row mask cleared: one launch
+            step_prep(self.cam_pool, self.view_idx, self.cams, self.view_idx32, loss=self.loss,
+                      step=self.step_dev if self.fused else None, row_mask=self.row_mask if self.fused else None)
 
         def proj():
             r.project(self.P, self.sh_degree, self.cams)
@@ -175,7 +177,6 @@ class MapOptimizer:
         def fwd():
             if self.fused_render:
                 # forward, loss and backward of every view-tile in one persistent launch
-                self.loss.zero_()
                 gd = self.target_depth
                 render_step(r.splats, r.inst_gid, r.inst_emit, r.tile_ranges, self.cams, self.V, self.raster,
                             self.target_rgb, gd, self.lambda_depth if gd is not None else 0.0, r.rgb, r.depth,
@@ -190,7 +191,6 @@ class MapOptimizer:
         def loss_stage():
             if self.render == "persistent":
                 return
-            self.loss.zero_()
             if self.render == "two_pass":
                 return  # the loss and its gradient are formed inside the render backward
             gd = self.g_depth if self.target_depth is not None else None
@@ -223,10 +223,8 @@ class MapOptimizer:
 
         def pbwd():
             if self.fused:
-                self.step_dev += 1
                 lr = self.lr
                 visible_list(r.tile_info, self.n, self.V, self.vis_list, self.vis_count, self.vis_ws)
-                self.row_mask.zero_()
                 lrs = (lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"], lr["sh_rest"])
                 project_bwd_adam(self.P, self.sh_degree, self.cams, self.V, self.raster, r.splats, r.dinst, r.em,
                                  r.tile_info, self.m, self.v, lrs, self.step_dev, r.dpose, r.pose_ws,

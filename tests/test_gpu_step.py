@@ -245,3 +245,31 @@ def test_fused_render_step_equals_separate_launches(scene):
     assert abs(loss_a.item() - loss_d.item()) <= 1e-12 * abs(loss_a.item())
     ds_d = r.screen_grads().cpu().numpy().astype(np.float64)
     assert np.all(np.abs(ds_d - ds_a).reshape(-1, 10) <= 1e-4 * (np.abs(ds_a).reshape(-1, 10) + rms))
+
+
+@pytest.mark.parametrize("n", [0, 15, 4099])
+def test_step_prep_matches_torch(n):
+    """gsr_step_prep against the torch ops it stands for: the camera gather (index_select), the
+    int32 copy of the view indices, the cleared loss, the advanced step and the cleared row mask
+    (lengths with and without a partial 16-byte group)."""
+    import paper_2604_12942_amd as gsr
+    rng = np.random.default_rng(n)
+    S, V = 7, 5
+    pool = torch.from_numpy(rng.integers(0, 256, S * 96, dtype=np.uint8)).cuda()
+    idx = torch.tensor([3, 0, 6, 3, 1], dtype=torch.int64, device="cuda")
+    cams = torch.zeros(V * 96, dtype=torch.uint8, device="cuda")
+    idx32 = torch.full((V,), -1, dtype=torch.int32, device="cuda")
+    loss = torch.full((1,), 5.0, dtype=torch.float64, device="cuda")
+    step = torch.full((1,), 41, dtype=torch.int32, device="cuda")
+    mask = torch.ones(n, dtype=torch.uint8, device="cuda")
+    gsr.step_prep(pool, idx, cams, idx32, loss=loss, step=step, row_mask=mask if n else None)
+    ref = torch.index_select(pool.view(S, 96), 0, idx).reshape(-1)
+    assert torch.equal(cams, ref)
+    assert idx32.tolist() == idx.tolist()
+    assert loss.item() == 0.0 and step.item() == 42
+    assert int(mask.sum()) == 0
+    # only the camera gather: the optional outputs are left as they were
+    loss.fill_(3.0)
+    gsr.step_prep(pool, idx.flip(0).contiguous(), cams)
+    assert torch.equal(cams, torch.index_select(pool.view(S, 96), 0, idx.flip(0)).reshape(-1))
+    assert loss.item() == 3.0 and step.item() == 42
