@@ -12,7 +12,9 @@ __global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
 
 // Per-pair screen-space gradient: the fixed-order sum of the pair's instance records.
 // Small pairs (at most kSmallPair records): each wave takes 64 consecutive visible pairs in
-// emission order, and each lane sums its own pair's records in order, four records in flight.
+// emission order.  Their records form one contiguous run, which the wave streams through LDS
+// 64 records at a time with coalesced loads (one record per lane; a window that holds no record
+// of a small pair is not loaded), and each lane adds its own pair's records from there, in order.
 // Large pairs (near Gaussians cover hundreds of tiles, and depth order puts them first): each is
 // summed by one whole wave, each lane striding over the records and a lane tree adding the 64
 // partial sums.  The large pairs are dealt out across the grid: lane l of wave w looks at pair
@@ -20,6 +22,7 @@ __global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
 // rather than queueing in the first ones.  Either way the order of the additions is fixed by the
 // data, so the result repeats exactly.
 constexpr uint32_t kSmallPair = 32;
+constexpr int kPairWaves = 4;  // waves per workgroup
 
 __device__ __forceinline__ uint32_t pair_count(const uint32_t *__restrict__ pair_gid,
                                                const uint32_t *__restrict__ pair_first,
@@ -29,52 +32,64 @@ __device__ __forceinline__ uint32_t pair_count(const uint32_t *__restrict__ pair
     return q + 1 < np ? pair_first[q + 1] - first : ntiles[pair_gid[q]];
 }
 
-__global__ __launch_bounds__(256) void k_pair_grads(const float *__restrict__ dinst,
-                                                    const uint32_t *__restrict__ pair_gid,
-                                                    const uint32_t *__restrict__ pair_first,
-                                                    const uint32_t *__restrict__ n_pairs,
-                                                    const uint32_t *__restrict__ ntiles, float *__restrict__ dsplat) {
+__global__ __launch_bounds__(64 * kPairWaves) void k_pair_grads(const float *__restrict__ dinst,
+                                                                const uint32_t *__restrict__ pair_gid,
+                                                                const uint32_t *__restrict__ pair_first,
+                                                                const uint32_t *__restrict__ n_pairs,
+                                                                const uint32_t *__restrict__ ntiles,
+                                                                float *__restrict__ dsplat) {
+    // one window of 64 records per wave, 5 float2 each
+    __shared__ float2 s_win[kPairWaves][64 * 5];
     const uint32_t np = *n_pairs;
     const int lane = __lane_id();
     const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    float2 *const win = s_win[threadIdx.x >> 6];
     // small pairs, one per lane
     for (uint32_t w0 = gw * 64; w0 < np; w0 += nwaves * 64) {
         const uint32_t q = w0 + lane;
-        if (q >= np) continue;
-        const uint32_t first = pair_first[q];
-        const uint32_t cnt = pair_count(pair_gid, pair_first, ntiles, q, np, first);
-        if (cnt > kSmallPair) continue;
-        const uint32_t gid = pair_gid[q];
-        const float2 *rec = reinterpret_cast<const float2 *>(dinst + (int64_t)first * GSR_SPLAT_GRAD_FLOATS);
+        const bool live = q < np;
+        const uint32_t first = live ? pair_first[q] : 0u;
+        const uint32_t cnt = live ? pair_count(pair_gid, pair_first, ntiles, q, np, first) : 0u;
+        const bool small = live && cnt <= kSmallPair;
+        // the run of records of the wave's pairs: from the first pair's first record to the end
+        // of the last live pair
+        const int lastl = np - w0 < 64u ? (int)(np - w0) - 1 : 63;
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)first);
+        const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)(first + cnt), lastl);
         float acc[GSR_SPLAT_GRAD_FLOATS];
 #pragma unroll
         for (int e = 0; e < GSR_SPLAT_GRAD_FLOATS; e++) acc[e] = 0.f;
-        uint32_t j = 0;
-        for (; j + 4 <= cnt; j += 4) {
-            float2 x[4][5];
+        for (uint32_t a = r0; a < r1; a += 64) {
+            // this lane's records inside the window [a, a + 64)
+            const uint32_t k0 = first > a ? first : a;
+            const uint32_t k1 = first + cnt < a + 64 ? first + cnt : a + 64;
+            const bool need = small && k0 < k1;
+            if (__ballot(need) == 0) continue;
+            if (a + lane < r1) {
+                const float2 *rec =
+                    reinterpret_cast<const float2 *>(dinst + (int64_t)(a + lane) * GSR_SPLAT_GRAD_FLOATS);
 #pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int e = 0; e < 5; e++) x[u][e] = rec[(j + u) * 5 + e];
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int e = 0; e < 5; e++) {
-                    acc[2 * e] += x[u][e].x;
-                    acc[2 * e + 1] += x[u][e].y;
-                }
-        }
-        for (; j < cnt; j++)
-#pragma unroll
-            for (int e = 0; e < 5; e++) {
-                const float2 x = rec[j * 5 + e];
-                acc[2 * e] += x.x;
-                acc[2 * e + 1] += x.y;
+                for (int e = 0; e < 5; e++) win[e * 64 + lane] = rec[e];
             }
-        float2 *out = reinterpret_cast<float2 *>(dsplat + (int64_t)gid * GSR_SPLAT_GRAD_FLOATS);
+            __builtin_amdgcn_wave_barrier();  // the wave reads back what its lanes just wrote
+            if (need)
+                for (uint32_t k = k0; k < k1; k++) {
+                    const int s = (int)(k - a);
 #pragma unroll
-        for (int e = 0; e < 5; e++) out[e] = make_float2(acc[2 * e], acc[2 * e + 1]);
+                    for (int e = 0; e < 5; e++) {
+                        const float2 x = win[e * 64 + s];
+                        acc[2 * e] += x.x;
+                        acc[2 * e + 1] += x.y;
+                    }
+                }
+            __builtin_amdgcn_wave_barrier();  // every read of the window precedes the next window's writes
+        }
+        if (small) {
+            float2 *out = reinterpret_cast<float2 *>(dsplat + (int64_t)pair_gid[q] * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+            for (int e = 0; e < 5; e++) out[e] = make_float2(acc[2 * e], acc[2 * e + 1]);
+        }
     }
     // large pairs, one per wave, dealt out across the grid
     for (uint32_t k0 = 0; (uint64_t)k0 * nwaves + gw < np; k0 += 64) {
@@ -128,8 +143,8 @@ extern "C" gsr_status gsr_pair_grads_launch(const float *dinst, const gsr_emissi
         const int nz = (int)(ceil_div(words, 256) < 16384 ? ceil_div(words, 256) : 16384);
         k_zero_f32<<<nz, 256, 0, st>>>(dsplat, words);
     }
-    const int nb = (int)(ceil_div(VN, 256) < 8192 ? ceil_div(VN, 256) : 8192);
-    k_pair_grads<<<nb, 256, 0, st>>>(dinst, em->pair_gid, em->pair_first, em->n_pairs, tile_info, dsplat);
+    const int nb = (int)(ceil_div(VN, 64 * kPairWaves) < 8192 ? ceil_div(VN, 64 * kPairWaves) : 8192);
+    k_pair_grads<<<nb, 64 * kPairWaves, 0, st>>>(dinst, em->pair_gid, em->pair_first, em->n_pairs, tile_info, dsplat);
     return last_launch();
 }
 

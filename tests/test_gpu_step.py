@@ -273,3 +273,43 @@ def test_step_prep_matches_torch(n):
     gsr.step_prep(pool, idx.flip(0).contiguous(), cams)
     assert torch.equal(cams, torch.index_select(pool.view(S, 96), 0, idx.flip(0)).reshape(-1))
     assert loss.item() == 3.0 and step.item() == 42
+
+
+def test_pair_sums_are_ordered_record_sums():
+    """gsr_pair_grads: the screen-space gradient of a (view, Gaussian) pair is the sum of its
+    instance records.  For pairs of at most 32 records the sum runs in emission order, so it
+    equals a sequential float32 sum bit for bit; larger pairs (a few Gaussians blown up to cover
+    most tiles) are summed by a lane tree and checked to float rounding."""
+    import paper_2604_12942_amd as gsr
+    g, cams, _, _ = _three_views(5)
+    g = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+    g["log_scales"][:, :16] += 2.5
+    V = len(cams)
+    H, W = cams[0]["height"], cams[0]["width"]
+    P = gsr.gaussians_to_device(g)
+    ct = gsr.camera_tensor(cams)
+    n = P["means"].shape[1]
+    r = gsr.Rasterizer(n, V, gsr.Raster(W, H))
+    r.forward(P, g["sh_degree"], ct)
+    rng = np.random.default_rng(2)
+    gC = torch.from_numpy(rng.standard_normal((V, 3, H, W)).astype(np.float32)).cuda()
+    gD = torch.from_numpy(rng.standard_normal((V, H, W)).astype(np.float32)).cuda()
+    r.render_backward(ct, gC, gD)
+    ds = r.screen_grads().cpu().numpy().reshape(-1, 10)
+    npairs = int(r.n_pairs.item())
+    first = r.pair_first[:npairs].cpu().numpy().astype(np.int64)
+    gid = r.pair_gid[:npairs].cpu().numpy().astype(np.int64)
+    ntiles = r.tile_info.view(4, -1)[0].cpu().numpy().astype(np.int64)
+    cnt = np.append(first[1:] - first[:-1], ntiles[gid[-1]])
+    total = int(first[-1] + cnt[-1])
+    rec = r.dinst[:total * 10].cpu().numpy().reshape(-1, 10)
+    small = cnt <= 32
+    assert small.any() and (~small).any(), (cnt.min(), cnt.max())
+    acc = np.zeros((npairs, 10), np.float32)
+    for j in range(32):
+        m = small & (cnt > j)
+        acc[m] += rec[first[m] + j]
+    assert np.array_equal(ds[gid[small]], acc[small])
+    for q in np.flatnonzero(~small):
+        part = rec[first[q]:first[q] + cnt[q]].astype(np.float64)
+        assert np.all(np.abs(ds[gid[q]] - part.sum(0)) <= 1e-5 * (np.abs(part).sum(0) + 1e-30)), q
