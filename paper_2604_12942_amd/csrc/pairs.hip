@@ -38,13 +38,15 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_grads(const float *__r
                                                                 const uint32_t *__restrict__ n_pairs,
                                                                 const uint32_t *__restrict__ ntiles,
                                                                 float *__restrict__ dsplat) {
-    // one window of 64 records per wave, 5 float2 each
-    __shared__ float2 s_win[kPairWaves][64 * 5];
+    // one window of 64 records per wave: floats 0-3 and 4-7 of each record as float4, 8-9 as float2
+    __shared__ float4 s_w4[kPairWaves][2][64];
+    __shared__ float2 s_w2[kPairWaves][64];
     const uint32_t np = *n_pairs;
     const int lane = __lane_id();
     const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    float2 *const win = s_win[threadIdx.x >> 6];
+    float4 *const w4a = s_w4[threadIdx.x >> 6][0], *const w4b = s_w4[threadIdx.x >> 6][1];
+    float2 *const w2 = s_w2[threadIdx.x >> 6];
     // small pairs, one per lane
     for (uint32_t w0 = gw * 64; w0 < np; w0 += nwaves * 64) {
         const uint32_t q = w0 + lane;
@@ -69,19 +71,27 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_grads(const float *__r
             if (a + lane < r1) {
                 const float2 *rec =
                     reinterpret_cast<const float2 *>(dinst + (int64_t)(a + lane) * GSR_SPLAT_GRAD_FLOATS);
-#pragma unroll
-                for (int e = 0; e < 5; e++) win[e * 64 + lane] = rec[e];
+                const float2 x0 = rec[0], x1 = rec[1], x2 = rec[2], x3 = rec[3], x4 = rec[4];
+                w4a[lane] = make_float4(x0.x, x0.y, x1.x, x1.y);
+                w4b[lane] = make_float4(x2.x, x2.y, x3.x, x3.y);
+                w2[lane] = x4;
             }
             __builtin_amdgcn_wave_barrier();  // the wave reads back what its lanes just wrote
             if (need)
                 for (uint32_t k = k0; k < k1; k++) {
                     const int s = (int)(k - a);
-#pragma unroll
-                    for (int e = 0; e < 5; e++) {
-                        const float2 x = win[e * 64 + s];
-                        acc[2 * e] += x.x;
-                        acc[2 * e + 1] += x.y;
-                    }
+                    const float4 xa = w4a[s], xb = w4b[s];
+                    const float2 xc = w2[s];
+                    acc[0] += xa.x;
+                    acc[1] += xa.y;
+                    acc[2] += xa.z;
+                    acc[3] += xa.w;
+                    acc[4] += xb.x;
+                    acc[5] += xb.y;
+                    acc[6] += xb.z;
+                    acc[7] += xb.w;
+                    acc[8] += xc.x;
+                    acc[9] += xc.y;
                 }
             __builtin_amdgcn_wave_barrier();  // every read of the window precedes the next window's writes
         }
