@@ -13,8 +13,8 @@ __global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
 // Per-pair screen-space gradient: the fixed-order sum of the pair's instance records.
 // Small pairs (at most kSmallPair records): each wave takes 64 consecutive visible pairs in
 // emission order.  Their records form one contiguous run, which the wave streams through LDS
-// 64 records at a time with coalesced loads (one record per lane; a window that holds no record
-// of a small pair is not loaded), and each lane adds its own pair's records from there, in order.
+// kWinRecs records at a time with coalesced loads (a window that holds no record of a small pair
+// is not loaded), and each lane adds its own pair's records from there, in order.
 // Large pairs (near Gaussians cover hundreds of tiles, and depth order puts them first): each is
 // summed by one whole wave, each lane striding over the records and a lane tree adding the 64
 // partial sums.  The large pairs are dealt out across the grid: lane l of wave w looks at pair
@@ -23,6 +23,7 @@ __global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
 // data, so the result repeats exactly.
 constexpr uint32_t kSmallPair = 32;
 constexpr int kPairWaves = 4;  // waves per workgroup
+constexpr int kWinRecs = 256;  // records per LDS window of a wave
 
 __device__ __forceinline__ uint32_t pair_count(const uint32_t *__restrict__ pair_gid,
                                                const uint32_t *__restrict__ pair_first,
@@ -38,9 +39,9 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_grads(const float *__r
                                                                 const uint32_t *__restrict__ n_pairs,
                                                                 const uint32_t *__restrict__ ntiles,
                                                                 float *__restrict__ dsplat) {
-    // one window of 64 records per wave: floats 0-3 and 4-7 of each record as float4, 8-9 as float2
-    __shared__ float4 s_w4[kPairWaves][2][64];
-    __shared__ float2 s_w2[kPairWaves][64];
+    // one window of records per wave: floats 0-3 and 4-7 of each record as float4, 8-9 as float2
+    __shared__ float4 s_w4[kPairWaves][2][kWinRecs];
+    __shared__ float2 s_w2[kPairWaves][kWinRecs];
     const uint32_t np = *n_pairs;
     const int lane = __lane_id();
     const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -62,20 +63,29 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_grads(const float *__r
         float acc[GSR_SPLAT_GRAD_FLOATS];
 #pragma unroll
         for (int e = 0; e < GSR_SPLAT_GRAD_FLOATS; e++) acc[e] = 0.f;
-        for (uint32_t a = r0; a < r1; a += 64) {
-            // this lane's records inside the window [a, a + 64)
+        for (uint32_t a = r0; a < r1; a += kWinRecs) {
+            // this lane's records inside the window [a, a + kWinRecs)
             const uint32_t k0 = first > a ? first : a;
-            const uint32_t k1 = first + cnt < a + 64 ? first + cnt : a + 64;
+            const uint32_t k1 = first + cnt < a + kWinRecs ? first + cnt : a + kWinRecs;
             const bool need = small && k0 < k1;
             if (__ballot(need) == 0) continue;
-            if (a + lane < r1) {
-                const float2 *rec =
-                    reinterpret_cast<const float2 *>(dinst + (int64_t)(a + lane) * GSR_SPLAT_GRAD_FLOATS);
-                const float2 x0 = rec[0], x1 = rec[1], x2 = rec[2], x3 = rec[3], x4 = rec[4];
-                w4a[lane] = make_float4(x0.x, x0.y, x1.x, x1.y);
-                w4b[lane] = make_float4(x2.x, x2.y, x3.x, x3.y);
-                w2[lane] = x4;
-            }
+            float2 x[kWinRecs / 64][5];
+#pragma unroll
+            for (int u = 0; u < kWinRecs / 64; u++)
+                if (a + u * 64 + lane < r1) {
+                    const float2 *rec = reinterpret_cast<const float2 *>(
+                        dinst + (int64_t)(a + u * 64 + lane) * GSR_SPLAT_GRAD_FLOATS);
+#pragma unroll
+                    for (int e = 0; e < 5; e++) x[u][e] = rec[e];
+                }
+#pragma unroll
+            for (int u = 0; u < kWinRecs / 64; u++)
+                if (a + u * 64 + lane < r1) {
+                    const int s = u * 64 + lane;
+                    w4a[s] = make_float4(x[u][0].x, x[u][0].y, x[u][1].x, x[u][1].y);
+                    w4b[s] = make_float4(x[u][2].x, x[u][2].y, x[u][3].x, x[u][3].y);
+                    w2[s] = x[u][4];
+                }
             __builtin_amdgcn_wave_barrier();  // the wave reads back what its lanes just wrote
             if (need)
                 for (uint32_t k = k0; k < k1; k++) {
