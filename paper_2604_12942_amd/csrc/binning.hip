@@ -143,12 +143,12 @@ __global__ __launch_bounds__(256) void k_scan_write(const uint32_t *__restrict__
 // ---- stable LSD radix sort, 8-bit digits -----------------------------------------------------
 // Block b sorts items [b*kRadixTile, (b+1)*kRadixTile); the histogram counts each block's digits,
 // and the scatter ranks them stably (input order) inside the block.
-constexpr int kRadixItems = 16;
+constexpr int kRadixItems = 12;
 constexpr int kRadixTile = kSortThreads * kRadixItems;
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                     uint32_t n_host, uint32_t cap, int shift, int nblocks,
                                                     uint32_t *__restrict__ hist) {
-    // Counts are order-free: each thread takes kRadixItems consecutive keys (four 16-byte loads)
+    // Counts are order-free: each thread takes kRadixItems consecutive keys (three 16-byte loads)
     // and adds a run of equal digits to the block's LDS count in one atomic, so nearly sorted
     // input (long runs) costs one add per run and shuffled input one per key.
     __shared__ uint32_t cnt[kRadix];
