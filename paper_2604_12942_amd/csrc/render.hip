@@ -223,20 +223,25 @@ __device__ __forceinline__ void write_null_slot(float4 *sA, float4 *sB, float4 *
 // instances.  Compositing is associative in the transmittance: the walk through
 // slice k starts from T_in(k), the product over the earlier slices of their own (1 - a)
 // products, and the pixel has terminated before slice k exactly when T_in(k) < 1e-4 (T never
-// increases).  So one pass computes every slice's product (a pixel whose product falls below
-// 1e-4 stops and records 0), a second composites all slices at once from their T_in, and a merge
-// sums each pixel's slice results in order, stopping after the slice in which it terminated.
-// The results are those of the whole-tile walk up to the float rounding of the transmittance
-// products (which are associated per slice).
+// increases).  So one pass computes every slice's product (as the product of its sub-slices'
+// products; a pixel whose product over a sub-slice falls below 1e-4 stops and records 0, which
+// can only happen when it terminates there), a second composites all slices at once from their
+// T_in, and a merge sums each pixel's slice results in order, stopping after the slice in which
+// it terminated.  The results are those of the whole-tile walk up to the float rounding of the
+// transmittance products (which are associated per sub-slice).
 constexpr uint32_t kSliceLen = 1024;
 constexpr uint32_t kSplitMin = 8 * kSliceLen;  // shorter tiles finish within the launch anyway
+// The product pass walks each slice as kSubs sub-slices of kSubLen instances (one LDS batch each)
+// in separate workgroups: shorter walks, spread over more workgroups.
+constexpr uint32_t kSubLen = 256;
+constexpr uint32_t kSubs = kSliceLen / kSubLen;
 constexpr uint32_t kNoSlice = 0xffffffffu;  // list entry of a slice that did not fit
 
 struct SliceArgs {
     const uint32_t *tile_slices;  // [V*T] number of slices of each view-tile (0: whole tile)
     const uint2 *info;            // [cap] (view-tile, slice index within the tile)
     const uint32_t *count;        // [1] number of slices
-    float *tprod;                 // [cap][256] per-pixel product of (1 - a) over the slice
+    float *tprod;                 // [cap][kSubs][256] per-pixel product of (1 - a) over each sub-slice
     float4 *part;                 // [cap][256] slice colour (3) and depth, already times T_in
     uint2 *part2;                 // [cap][256] (T after the slice, negated if it terminated there;
                                   //             last composited position)
@@ -266,9 +271,17 @@ __global__ void k_slice_emit(uint32_t *__restrict__ ns, const uint32_t *__restri
     }
 }
 
+// This pixel's product of (1 - a) over slice j, in sub-slice order.
+__device__ __forceinline__ float slice_prod(const SliceArgs &sl, uint32_t j) {
+    float P = 1.0f;
+#pragma unroll
+    for (uint32_t u = 0; u < kSubs; u++) P *= sl.tprod[((size_t)j * kSubs + u) * 256 + threadIdx.x];
+    return P;
+}
+
 __device__ __forceinline__ float slice_T_in(const SliceArgs &sl, uint32_t j, uint32_t k) {
     float T = 1.0f;
-    for (uint32_t q = 0; q < k; q++) T *= sl.tprod[(size_t)(j - k + q) * 256 + threadIdx.x];
+    for (uint32_t q = 0; q < k; q++) T *= slice_prod(sl, j - k + q);
     return T;
 }
 
@@ -281,15 +294,16 @@ __global__ __launch_bounds__(256) void k_slice_prod(const gsr_splat *__restrict_
     __shared__ float4 sA[257], sB[257], sC[257];
     write_null_slot(sA, sB, sC);
     const uint32_t n = min(*sl.count, sl.cap);
-    for (uint32_t j = blockIdx.x; j < n; j += gridDim.x) {
+    for (uint64_t ju = blockIdx.x; ju < (uint64_t)n * kSubs; ju += gridDim.x) {
+        const uint32_t j = (uint32_t)(ju / kSubs), u = (uint32_t)(ju % kSubs);
         const uint2 si = sl.info[j];
         if (si.x == kNoSlice || si.y + 1 == sl.tile_slices[si.x]) continue;
         const TileGeom t = tile_geom<TW, TH>(si.x, T, ntx, W, H);
         const uint32_t start = ranges[2 * si.x], end = ranges[2 * si.x + 1];
-        const uint32_t lo = start + si.y * kSliceLen, hi = min(lo + kSliceLen, end);
+        const uint32_t lo = min(start + si.y * kSliceLen + u * kSubLen, end), hi = min(lo + kSubLen, end);
         PixelWalk pw = walk_start(t, 1.0f);
         composite<kKeepTrans>(splats, inst, start, lo, hi, t, sA, sB, sC, pw, nullptr, 0u, 0u);
-        sl.tprod[(size_t)j * 256 + threadIdx.x] = (t.inside && pw.fxl == kGone) ? 0.0f : pw.Tr;
+        sl.tprod[(size_t)ju * 256 + threadIdx.x] = (t.inside && pw.fxl == kGone) ? 0.0f : pw.Tr;
     }
 }
 
@@ -332,7 +346,7 @@ __global__ __launch_bounds__(256) void k_slice_merge(const uint32_t *__restrict_
                 kt = k;
                 break;
             }
-            if (k + 1 < K) Tin *= sl.tprod[q];
+            if (k + 1 < K) Tin *= slice_prod(sl, j + k);
         }
         {
             float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1067,7 +1081,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     Tr = fabsf(To);
                     lst = p2.y ? p2.y : lst;
                     if (To < 0.0f) break;  // terminated in this slice
-                    if (k + 1 < K) Tin2 *= sl.tprod[q];
+                    if (k + 1 < K) Tin2 *= slice_prod(sl, j0 + k);
                 }
             }
             finish_pixels(t, item, cams[t.v], W, H, Tr, c0, c1, c2, dd, lst, rgb, depth, Tfin, last, a, pg, s_red);
@@ -1317,7 +1331,7 @@ SliceWs slice_layout(void *base, int64_t VT, int64_t capacity) {
     w.count = static_cast<uint32_t *>(take(4));
     w.scan = take(gsr_scan_ws_bytes(VT));
     w.info = static_cast<uint2 *>(take((size_t)w.cap * sizeof(uint2)));
-    w.tprod = static_cast<float *>(take((size_t)w.cap * 256 * sizeof(float)));
+    w.tprod = static_cast<float *>(take((size_t)w.cap * kSubs * 256 * sizeof(float)));
     w.part = static_cast<float4 *>(take((size_t)w.cap * 256 * sizeof(float4)));
     w.part2 = static_cast<uint2 *>(take((size_t)w.cap * 256 * sizeof(uint2)));
     w.bytes = off;
