@@ -21,7 +21,7 @@ __global__ void k_zero_f32(float *__restrict__ dst, int64_t n) {
 // w + l W (W waves in the grid), so the large pairs at the front of the list go to different waves
 // rather than queueing in the first ones.  Either way the order of the additions is fixed by the
 // data, so the result repeats exactly.
-constexpr uint32_t kSmallPair = 32;
+constexpr uint32_t kSmallPair = 64;
 constexpr int kPairWaves = 4;  // waves per workgroup
 constexpr int kWinRecs = 256;  // records per LDS window of a wave
 

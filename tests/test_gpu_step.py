@@ -277,9 +277,9 @@ def test_step_prep_matches_torch(n):
 
 def test_pair_sums_are_ordered_record_sums():
     """gsr_pair_grads: the screen-space gradient of a (view, Gaussian) pair is the sum of its
-    instance records.  For pairs of at most 32 records the sum runs in emission order, so it
-    equals a sequential float32 sum bit for bit; larger pairs (a few Gaussians blown up to cover
-    most tiles) are summed by a lane tree and checked to float rounding."""
+    instance records.  Pairs of at most 32 records (the kernel sums every pair of up to 64 in
+    emission order) equal a sequential float32 sum bit for bit; larger pairs (a few Gaussians
+    blown up to cover most tiles) are checked to float rounding."""
     import paper_2604_12942_amd as gsr
     g, cams, _, _ = _three_views(5)
     g = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
